@@ -1,0 +1,211 @@
+/*
+ * mnl.h - C ABI of the GPU Newton-Raphson multinomial-logit fitter.
+ *
+ * Method: Hasan, Wang, Mahani, "Fast Estimation of Multinomial Logit Models:
+ * R Package mnlogit" (arXiv:1404.3177).  One Newton-Raphson iteration is the
+ * fused utility / probability / log-likelihood / gradient pass (Eqs. 2-5, 9),
+ * the block-structured Hessian (Eq. 10), the Cholesky solve of the Newton
+ * system (Eq. 6) and the step-halving line search (Sec. 3.1).
+ *
+ * Data kinds (this ABI's letters; the paper swaps Y and Z):
+ *   X [N][p]     individual-specific data, alternative-specific coefficients
+ *                beta_k (paper: X_i . beta_k).  An intercept is a column of
+ *                ones supplied by the caller (Sec. 3.1: "another individual
+ *                specific variable" whose data is unity).
+ *   Y [N][K][g]  alternative-varying data, generic coefficients alpha
+ *                (paper: Z_ik . alpha).
+ *   Z [N][K][a]  alternative-varying data, alternative-specific coefficients
+ *                gamma_k (paper: Y_ik . gamma_k).
+ * Alternative 0 is the base: beta_0 = 0 (Sec. 2.1 normalisation).  theta has
+ * n_p = (K-1) p + K a + g entries in the Eq. 8 order
+ *   theta = (beta_1 .. beta_{K-1}, gamma_0 .. gamma_{K-1}, alpha),
+ * each chunk contiguous, features in column order within a chunk.
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller
+ * (row-major, float64 unless stated), except the host structs mnl_fit_opts
+ * and mnl_fit_info.  The library keeps no pointer to caller memory after the
+ * work it enqueued has completed.  It owns a per-context workspace in device
+ * memory that grows on demand (hipMalloc) and is freed by mnl_destroy.
+ * Work is enqueued on the given HIP stream (hipStream_t passed as void*,
+ * NULL = the default stream); mnl_loglik_grad and mnl_hessian return without
+ * synchronising, mnl_newton_step and mnl_fit synchronise the stream before
+ * they return.  A context is used by one host thread at a time.
+ *
+ * Errors: functions return MNL_OK (0) or a negative MNL_ERR_* code; the
+ * outputs are then unspecified.  mnl_strerror() names a code and
+ * mnl_last_error() gives the context's last message.
+ */
+#ifndef MNL_H
+#define MNL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MNL_VERSION_MAJOR 0
+#define MNL_VERSION_MINOR 1
+
+typedef struct mnl_ctx mnl_ctx;
+
+/* Return codes. */
+enum {
+    MNL_OK = 0,
+    MNL_ERR_ARG = -1,          /* bad dimension, NULL pointer, bad option,
+                                  choice out of range (when validating)   */
+    MNL_ERR_OOM = -2,          /* device allocation failed                */
+    MNL_ERR_NOT_PD = -3,       /* -H not numerically positive definite    */
+    MNL_ERR_NONFINITE = -4,    /* NaN/Inf in data or log-likelihood       */
+    MNL_ERR_LS_FAIL = -5,      /* line search exhausted its halvings      */
+    MNL_ERR_HIP = -6,          /* a HIP runtime call failed               */
+    MNL_ERR_UNSUPPORTED = -7   /* shape beyond the kernels' limits        */
+};
+
+/* Stop reasons reported in mnl_fit_info.stop_reason.  The first three are
+ * mnlogit's gtol / ftol / maxiter rules (Sec. 2.3 and its est.stat report). */
+enum {
+    MNL_STOP_NONE = 0,         /* a step was taken, no rule met (newton_step) */
+    MNL_STOP_GTOL = 1,         /* ||g||_2 <= gtol                          */
+    MNL_STOP_FTOL = 2,         /* |l_new - l_old| < ftol                   */
+    MNL_STOP_MAXITER = 3,      /* iteration cap reached                    */
+    MNL_STOP_LS_FAIL = 4,      /* no halving raised l; theta unchanged     */
+    MNL_STOP_NOT_PD = 5,       /* Cholesky pivot at or below round-off     */
+    MNL_STOP_NONFINITE = 6     /* l or g not finite                        */
+};
+
+/* Arithmetic of the Hessian contraction (Eq. 10).  The log-likelihood,
+ * gradient, Cholesky solve and line search are FP64 in every mode, so the
+ * fixed point g(theta) = 0 does not depend on this choice; a rounded Hessian
+ * only changes the convergence rate of the iteration. */
+typedef enum {
+    MNL_PREC_FP64 = 0,         /* FP64 MFMA, FP64 accumulation            */
+    MNL_PREC_FP32 = 1,         /* FP32 operands on MFMA, FP32 accumulation */
+    MNL_PREC_BF16 = 2          /* BF16 operands on MFMA, FP32 accumulation */
+} mnl_prec;
+
+/* One fitting problem (Sec. 3.1 notation). */
+typedef struct {
+    int64_t N;                 /* individuals, >= 1                        */
+    int32_t K;                 /* alternatives, >= 2 (K = 2: binary logit) */
+    int32_t p;                 /* columns of X (intercept included), >= 0  */
+    int32_t g;                 /* generic-coefficient variables, >= 0      */
+    int32_t a;                 /* alternative-specific-coef vars, >= 0     */
+    const double *X;           /* [N][p]; may be NULL iff p == 0           */
+    const double *Y;           /* [N][K][g]; may be NULL iff g == 0        */
+    const double *Z;           /* [N][K][a]; may be NULL iff a == 0        */
+    const int32_t *choice;     /* [N] observed alternative, 0..K-1         */
+    const double *w;           /* [N] frequency weights >= 0, NULL = ones  */
+} mnl_problem;
+
+/* Fit options; defaults (mnl_default_opts) are mnlogit's maxiter = 50,
+ * ftol = 1e-6, gtol = 1e-6 (Sec. 2.3), FP64 Hessian, 30 halvings, and a
+ * line-search acceptance slack of 64 ulps of |l|. */
+typedef struct {
+    int32_t maxiter;           /* >= 0                                     */
+    double ftol;               /* stop when |dl| < ftol (0 disables)       */
+    double gtol;               /* stop when ||g||_2 <= gtol                */
+    int32_t prec;              /* mnl_prec of the Hessian                  */
+    int32_t ls_max;            /* halvings before MNL_STOP_LS_FAIL, >= 0   */
+    double ls_tol_ulps;        /* accept l_t >= l - ls_tol_ulps*eps*|l|    */
+    int32_t validate;          /* nonzero: check choices and finiteness of
+                                  the data before fitting                  */
+} mnl_fit_opts;
+
+/* Report of a fit or of one Newton step (mnlogit's est.stat). Times in ms. */
+typedef struct {
+    int32_t iters;             /* Newton iterations taken                  */
+    int32_t ls_iters;          /* line-search trial evaluations            */
+    int32_t ls_backtracks;     /* halvings (trials beyond the full step)   */
+    int32_t stop_reason;       /* MNL_STOP_*                               */
+    int32_t hess_fallbacks;    /* mixed precision: Hessians recomputed in
+                                  FP64 after a failed factorisation       */
+    int32_t reserved;
+    double loglik;             /* l at the returned theta                  */
+    double grad_norm;          /* ||g||_2 at the returned theta (fit), at
+                                  the input theta (newton_step)            */
+    double loglik_diff;        /* l change of the last step                */
+    double t_total;            /* wall time of the call                    */
+    double t_loglik_grad;      /* first pass (l, g, P) before stepping     */
+    double t_hessian;          /* Hessian formation                        */
+    double t_chol;             /* Cholesky factorisation + solves          */
+    double t_ls;               /* line-search passes                       */
+} mnl_fit_info;
+
+/* Library version string ("major.minor"). */
+const char *mnl_version(void);
+
+/* Static name of a return code. */
+const char *mnl_strerror(int code);
+
+/* Fill *opts with the defaults above.  opts must not be NULL. */
+void mnl_default_opts(mnl_fit_opts *opts);
+
+/* n_p = (K-1) p + K a + g (Eq. 8), or -1 for K < 2 or negative sizes. */
+int64_t mnl_num_params(int32_t K, int32_t p, int32_t g, int32_t a);
+
+/* Create a context on HIP device `device`.  *ctx receives the handle.
+ * Returns MNL_ERR_ARG for ctx == NULL or an invalid device, MNL_ERR_HIP if
+ * the device cannot be selected. */
+int mnl_create(mnl_ctx **ctx, int device);
+
+/* Free the context and its workspace (NULL is ignored).  Waits for the
+ * context's outstanding work. */
+void mnl_destroy(mnl_ctx *ctx);
+
+/* Bytes of device workspace currently held by the context. */
+size_t mnl_workspace_bytes(const mnl_ctx *ctx);
+
+/* Last error message of the context (empty string if none). */
+const char *mnl_last_error(const mnl_ctx *ctx);
+
+/* Log-likelihood and gradient at theta (Eqs. 2-5 and 9), one fused pass.
+ *   theta   [n_p] device, input.
+ *   loglik  [1] device, output: weighted log-likelihood (Eq. 5).
+ *   grad    [n_p] device, output, may be NULL: dl/dtheta in Eq. 8 layout.
+ *   P       [N][K] device, output, may be NULL: choice probabilities
+ *           (Eqs. 3-4), alternative 0 in column 0.
+ * Asynchronous on `stream`. */
+int mnl_loglik_grad(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
+                    double *loglik, double *grad, double *P, void *stream);
+
+/* Full Hessian at theta (Eq. 10), Hessian sign (negative semidefinite).
+ *   theta   [n_p] device, input.
+ *   prec    mnl_prec of the contraction.
+ *   H       [n_p][n_p] device, output, full symmetric matrix.
+ * Asynchronous on `stream`. */
+int mnl_hessian(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
+                int32_t prec, double *H, void *stream);
+
+/* One Newton-Raphson iteration from theta (Eq. 6 with the halving line
+ * search).  If ||g(theta)||_2 <= opts->gtol no step is taken and
+ * step->stop_reason = MNL_STOP_GTOL.  Otherwise theta is replaced by the
+ * accepted trial theta + t delta, delta = -H^{-1} g, and stop_reason is
+ * MNL_STOP_NONE, or NOT_PD / LS_FAIL / NONFINITE with theta unchanged.
+ *   theta   [n_p] device, input and output.
+ *   opts    host, NULL = defaults.
+ *   step    host, output.
+ * Synchronises `stream`. */
+int mnl_newton_step(mnl_ctx *ctx, const mnl_problem *prob, double *theta,
+                    const mnl_fit_opts *opts, mnl_fit_info *step,
+                    void *stream);
+
+/* Newton-Raphson fit (Sec. 3.1): iterate until ||g||_2 <= gtol (checked at
+ * the top of each iteration), |dl| < ftol (after a step) or maxiter.
+ *   theta0     [n_p] device start, NULL = zeros (mnlogit's start = NULL).
+ *   theta_out  [n_p] device, output (may equal theta0).
+ *   opts       host, NULL = defaults.
+ *   info       host, output.
+ * NOT_PD, LS_FAIL and NONFINITE end the fit with that stop_reason and the
+ * last accepted theta; the call still returns MNL_OK.  Synchronises
+ * `stream`. */
+int mnl_fit(mnl_ctx *ctx, const mnl_problem *prob, const double *theta0,
+            const mnl_fit_opts *opts, double *theta_out, mnl_fit_info *info,
+            void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MNL_H */

@@ -1,0 +1,115 @@
+"""ctypes binding of libmnl.so (the C ABI declared in include/mnl.h).
+
+Argument marshalling only: torch tensors supply device memory and the
+current HIP stream; every step of the computation runs in the library's HIP
+kernels.  Importing this module never falls back to another implementation:
+if the library is missing, load() raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmnl.so")
+
+MNL_OK = 0
+ERRORS = {
+    -1: "MNL_ERR_ARG", -2: "MNL_ERR_OOM", -3: "MNL_ERR_NOT_PD",
+    -4: "MNL_ERR_NONFINITE", -5: "MNL_ERR_LS_FAIL", -6: "MNL_ERR_HIP",
+    -7: "MNL_ERR_UNSUPPORTED",
+}
+STOP_NONE, STOP_GTOL, STOP_FTOL, STOP_MAXITER = 0, 1, 2, 3
+STOP_LS_FAIL, STOP_NOT_PD, STOP_NONFINITE = 4, 5, 6
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+EXPORTS = [
+    "mnl_version", "mnl_strerror", "mnl_default_opts", "mnl_num_params",
+    "mnl_create", "mnl_destroy", "mnl_workspace_bytes", "mnl_last_error",
+    "mnl_loglik_grad", "mnl_hessian", "mnl_newton_step", "mnl_fit",
+]
+
+
+class MnlProblem(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64), ("K", ctypes.c_int32), ("p", ctypes.c_int32),
+        ("g", ctypes.c_int32), ("a", ctypes.c_int32),
+        ("X", ctypes.c_void_p), ("Y", ctypes.c_void_p), ("Z", ctypes.c_void_p),
+        ("choice", ctypes.c_void_p), ("w", ctypes.c_void_p),
+    ]
+
+
+class MnlFitOpts(ctypes.Structure):
+    _fields_ = [
+        ("maxiter", ctypes.c_int32), ("ftol", ctypes.c_double),
+        ("gtol", ctypes.c_double), ("prec", ctypes.c_int32),
+        ("ls_max", ctypes.c_int32), ("ls_tol_ulps", ctypes.c_double),
+        ("validate", ctypes.c_int32),
+    ]
+
+
+class MnlFitInfo(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32), ("ls_iters", ctypes.c_int32),
+        ("ls_backtracks", ctypes.c_int32), ("stop_reason", ctypes.c_int32),
+        ("hess_fallbacks", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("loglik", ctypes.c_double), ("grad_norm", ctypes.c_double),
+        ("loglik_diff", ctypes.c_double), ("t_total", ctypes.c_double),
+        ("t_loglik_grad", ctypes.c_double), ("t_hessian", ctypes.c_double),
+        ("t_chol", ctypes.c_double), ("t_ls", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmnl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with paper_1404_3177_amd/build.py")
+    # torch ships its own HIP runtime (same soname as ROCm's).  Loading torch
+    # first makes libmnl.so bind to that runtime, so both share one device
+    # context, one allocator view and the same stream objects.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.mnl_version.restype = ctypes.c_char_p
+    lib.mnl_strerror.restype = ctypes.c_char_p
+    lib.mnl_strerror.argtypes = [ctypes.c_int]
+    lib.mnl_default_opts.argtypes = [ctypes.POINTER(MnlFitOpts)]
+    lib.mnl_default_opts.restype = None
+    lib.mnl_num_params.argtypes = [I32, I32, I32, I32]
+    lib.mnl_num_params.restype = I64
+    lib.mnl_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+    lib.mnl_destroy.argtypes = [P]
+    lib.mnl_destroy.restype = None
+    lib.mnl_workspace_bytes.argtypes = [P]
+    lib.mnl_workspace_bytes.restype = ctypes.c_size_t
+    lib.mnl_last_error.argtypes = [P]
+    lib.mnl_last_error.restype = ctypes.c_char_p
+    prob = ctypes.POINTER(MnlProblem)
+    lib.mnl_loglik_grad.argtypes = [P, prob, P, P, P, P, P]
+    lib.mnl_hessian.argtypes = [P, prob, P, I32, P, P]
+    lib.mnl_newton_step.argtypes = [P, prob, P, ctypes.POINTER(MnlFitOpts),
+                                    ctypes.POINTER(MnlFitInfo), P]
+    lib.mnl_fit.argtypes = [P, prob, P, ctypes.POINTER(MnlFitOpts), P,
+                            ctypes.POINTER(MnlFitInfo), P]
+    for name in ("mnl_create", "mnl_loglik_grad", "mnl_hessian",
+                 "mnl_newton_step", "mnl_fit"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class MnlError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code

@@ -1,0 +1,497 @@
+// C ABI entry points and the Newton-Raphson driver (Sec. 3.1).
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <limits>
+
+#include "mnl_common.h"
+
+struct mnl_ctx {
+  mnl::Ctx c;
+};
+
+namespace mnl {
+
+int set_error(Ctx *c, int code, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->last_error = buf;
+  }
+  return code;
+}
+
+int ws_get(Ctx *c, int slot, size_t bytes, void **ptr) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~size_t(255);
+  Buf &b = c->bufs[slot];
+  if (b.bytes < bytes) {
+    if (b.ptr) {
+      // the old buffer may still be in use by enqueued work
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess)
+        return set_error(c, MNL_ERR_HIP, "hipDeviceSynchronize: %s",
+                         hipGetErrorString(e));
+      (void)hipFree(b.ptr);
+      c->total_bytes -= b.bytes;
+      b.ptr = nullptr;
+      b.bytes = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_error(c, MNL_ERR_OOM, "hipMalloc(%zu) failed", bytes);
+    }
+    b.ptr = p;
+    b.bytes = bytes;
+    c->total_bytes += bytes;
+  }
+  *ptr = b.ptr;
+  return MNL_OK;
+}
+
+namespace {
+
+int check_problem(Ctx *c, const mnl_problem *pr, Dims *d) {
+  if (!pr) return set_error(c, MNL_ERR_ARG, "problem is NULL");
+  if (pr->N < 1) return set_error(c, MNL_ERR_ARG, "N must be >= 1");
+  if (pr->K < 2) return set_error(c, MNL_ERR_ARG, "K must be >= 2");
+  if (pr->p < 0 || pr->g < 0 || pr->a < 0)
+    return set_error(c, MNL_ERR_ARG, "negative dimension");
+  if (pr->p > 0 && !pr->X) return set_error(c, MNL_ERR_ARG, "X is NULL");
+  if (pr->g > 0 && !pr->Y) return set_error(c, MNL_ERR_ARG, "Y is NULL");
+  if (pr->a > 0 && !pr->Z) return set_error(c, MNL_ERR_ARG, "Z is NULL");
+  if (!pr->choice) return set_error(c, MNL_ERR_ARG, "choice is NULL");
+  d->N = pr->N;
+  d->K = pr->K;
+  d->p = pr->p;
+  d->g = pr->g;
+  d->a = pr->a;
+  d->np = int64_t(pr->K - 1) * pr->p + int64_t(pr->K) * pr->a + pr->g;
+  if (d->np < 1) return set_error(c, MNL_ERR_ARG, "model has no coefficients");
+  if (int64_t(pr->K) * (pr->g + pr->a + 1) > (int64_t(1) << 24) ||
+      pr->p > 4096)
+    return set_error(c, MNL_ERR_UNSUPPORTED, "shape too large");
+  return MNL_OK;
+}
+
+int check_opts(Ctx *c, const mnl_fit_opts *o) {
+  if (o->maxiter < 0 || o->ls_max < 0 || o->ls_max > 1000 ||
+      !(o->gtol >= 0) || !(o->ftol >= 0) || !(o->ls_tol_ulps >= 0) ||
+      o->prec < MNL_PREC_FP64 || o->prec > MNL_PREC_BF16)
+    return set_error(c, MNL_ERR_ARG, "invalid fit options");
+  return MNL_OK;
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// One full pass (l, g, P, Ybar at theta) into the given workspace slots.
+int run_pass(Ctx *c, const Dims &d, const mnl_problem *pr, const double *theta,
+             double *lg, int slotP, int slotP32, int slotYbar, bool want_p32,
+             hipStream_t s) {
+  PassPlan plan;
+  int rc = pass_plan(d, &plan);
+  if (rc != MNL_OK)
+    return set_error(c, rc, "shape beyond the fused-pass limits");
+  void *partial, *P, *P32 = nullptr, *Ybar = nullptr;
+  MNL_TRY(ws_get(c, S_PARTIAL, size_t(plan.grid) * plan.stride * 8, &partial));
+  MNL_TRY(ws_get(c, slotP, size_t(d.N) * d.K * 8, &P));
+  if (want_p32) MNL_TRY(ws_get(c, slotP32, size_t(d.N) * d.K * 4, &P32));
+  if (d.g) MNL_TRY(ws_get(c, slotYbar, size_t(d.N) * d.g * 8, &Ybar));
+  PassArgs A;
+  A.d = d;
+  A.X = pr->X;
+  A.Y = pr->Y;
+  A.Z = pr->Z;
+  A.w = pr->w;
+  A.choice = pr->choice;
+  A.theta = theta;
+  A.P = (double *)P;
+  A.P32 = (float *)P32;
+  A.Ybar = (double *)Ybar;
+  A.partial = (double *)partial;
+  MNL_HIP(c, launch_pass(plan, A, s));
+  MNL_HIP(c, launch_pass_reduce(plan, (double *)partial, lg, lg + 1, d.np, s));
+  return MNL_OK;
+}
+
+struct StepState {
+  double *lg;        // [0] l, [1..] g at theta
+  double *lg_trial;
+  int cur;           // which P/Ybar slots hold theta's values (0 or 1)
+};
+
+// Hessian at the current theta (its P/Ybar in slot set `cur`) into S_H.
+int form_hessian(Ctx *c, const Dims &d, const mnl_problem *pr, int cur,
+                 int prec, double *H, hipStream_t s) {
+  void *P, *P32 = nullptr, *Ybar = nullptr;
+  MNL_TRY(ws_get(c, cur ? S_P_TRIAL : S_P, size_t(d.N) * d.K * 8, &P));
+  if (prec != MNL_PREC_FP64)
+    MNL_TRY(ws_get(c, cur ? S_P32_TRIAL : S_P32, size_t(d.N) * d.K * 4, &P32));
+  if (d.g)
+    MNL_TRY(ws_get(c, cur ? S_YBAR_TRIAL : S_YBAR, size_t(d.N) * d.g * 8,
+                   &Ybar));
+  HessArgs h;
+  h.d = d;
+  h.X = pr->X;
+  h.Y = pr->Y;
+  h.Z = pr->Z;
+  h.w = pr->w;
+  h.P = (const double *)P;
+  h.P32 = (const float *)P32;
+  h.Ybar = (const double *)Ybar;
+  h.H = H;
+  h.prec = prec;
+  return hessian_run(c, h, s);
+}
+
+int copy_d2h(Ctx *c, void *dst, const void *src, size_t n, hipStream_t s) {
+  MNL_HIP(c, hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, s));
+  MNL_HIP(c, hipStreamSynchronize(s));
+  return MNL_OK;
+}
+
+int validate_data(Ctx *c, const Dims &d, const mnl_problem *pr,
+                  hipStream_t s) {
+  void *f;
+  MNL_TRY(ws_get(c, S_SCAL, 256, &f));
+  int32_t *flags = (int32_t *)f + 16;
+  MNL_HIP(c, hipMemsetAsync(flags, 0, 8, s));
+  MNL_HIP(c, launch_validate(d, pr->X, pr->Y, pr->Z, pr->w, pr->choice, flags,
+                             s));
+  int32_t h[2];
+  MNL_TRY(copy_d2h(c, h, flags, 8, s));
+  if (h[0]) return set_error(c, MNL_ERR_ARG, "%d choices out of range", h[0]);
+  if (h[1])
+    return set_error(c, MNL_ERR_NONFINITE,
+                     "%d observations with non-finite data or bad weight",
+                     h[1]);
+  return MNL_OK;
+}
+
+// Core of one Newton iteration, given l and g at theta (in lg, P/Ybar in
+// slot set `cur`).  On an accepted step theta is updated in place and lg,
+// cur describe the new point.  Returns MNL_OK with *reason set.
+int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
+                const mnl_fit_opts &o, StepState &st, double l_old,
+                mnl_fit_info *info, int *reason, hipStream_t s) {
+  const bool mixed = o.prec != MNL_PREC_FP64;
+  void *Hv, *dv, *tv, *sv;
+  MNL_TRY(ws_get(c, S_H, size_t(d.np) * d.np * 8, &Hv));
+  MNL_TRY(ws_get(c, S_DELTA, size_t(d.np) * 8, &dv));
+  MNL_TRY(ws_get(c, S_THETA_TRIAL, size_t(d.np) * 8, &tv));
+  MNL_TRY(ws_get(c, S_SCAL, 256, &sv));
+  double *H = (double *)Hv, *delta = (double *)dv, *th_t = (double *)tv;
+  int32_t *cinfo = (int32_t *)sv + 32;
+
+  // Hessian and Newton direction (Eq. 6): delta = (-H)^{-1} g
+  double t0 = now_ms();
+  int prec = o.prec;
+  int32_t fail = 0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    MNL_TRY(form_hessian(c, d, pr, st.cur, prec, H, s));
+    MNL_HIP(c, hipStreamSynchronize(s));
+    double t1 = now_ms();
+    info->t_hessian += t1 - t0;
+    // the factorisation works on A = -H in place
+    MNL_TRY(chol_solve_run(c, H, d.np, st.lg + 1, delta, cinfo, s));
+    MNL_TRY(copy_d2h(c, &fail, cinfo, 4, s));
+    t0 = now_ms();
+    info->t_chol += t0 - t1;
+    if (fail == 0 || prec == MNL_PREC_FP64) break;
+    // a rounded Hessian that is not positive definite: redo it in FP64
+    prec = MNL_PREC_FP64;
+    info->hess_fallbacks += 1;
+  }
+  if (fail != 0) {
+    *reason = MNL_STOP_NOT_PD;
+    return MNL_OK;
+  }
+  (void)mixed;
+
+  // halving line search (Sec. 3.1)
+  const double tau =
+      o.ls_tol_ulps * std::numeric_limits<double>::epsilon() * std::fabs(l_old);
+  double t = 1.0;
+  const int nxt = st.cur ^ 1;
+  const bool want32 = o.prec != MNL_PREC_FP64;
+  double tl0 = now_ms();
+  for (int trial = 1; trial <= o.ls_max + 1; ++trial) {
+    MNL_HIP(c, launch_axpy(theta, delta, t, th_t, d.np, s));
+    MNL_TRY(run_pass(c, d, pr, th_t, st.lg_trial, nxt ? S_P_TRIAL : S_P,
+                     nxt ? S_P32_TRIAL : S_P32, nxt ? S_YBAR_TRIAL : S_YBAR,
+                     want32, s));
+    double l_new;
+    MNL_TRY(copy_d2h(c, &l_new, st.lg_trial, 8, s));
+    info->ls_iters += 1;
+    if (std::isfinite(l_new) && l_new >= l_old - tau) {
+      info->ls_backtracks += trial - 1;
+      MNL_HIP(c, hipMemcpyAsync(theta, th_t, size_t(d.np) * 8,
+                                hipMemcpyDeviceToDevice, s));
+      std::swap(st.lg, st.lg_trial);
+      st.cur = nxt;
+      info->loglik_diff = l_new - l_old;
+      info->loglik = l_new;
+      info->t_ls += now_ms() - tl0;
+      *reason = MNL_STOP_NONE;
+      return MNL_OK;
+    }
+    t *= 0.5;
+  }
+  info->ls_backtracks += o.ls_max;
+  info->t_ls += now_ms() - tl0;
+  *reason = MNL_STOP_LS_FAIL;
+  return MNL_OK;
+}
+
+}  // namespace
+}  // namespace mnl
+
+using namespace mnl;
+
+extern "C" {
+
+const char *mnl_version(void) { return "0.1"; }
+
+const char *mnl_strerror(int code) {
+  switch (code) {
+    case MNL_OK: return "ok";
+    case MNL_ERR_ARG: return "invalid argument";
+    case MNL_ERR_OOM: return "out of device memory";
+    case MNL_ERR_NOT_PD: return "Hessian not negative definite";
+    case MNL_ERR_NONFINITE: return "non-finite value";
+    case MNL_ERR_LS_FAIL: return "line search failed";
+    case MNL_ERR_HIP: return "HIP runtime error";
+    case MNL_ERR_UNSUPPORTED: return "unsupported shape";
+    default: return "unknown error";
+  }
+}
+
+void mnl_default_opts(mnl_fit_opts *o) {
+  if (!o) return;
+  o->maxiter = 50;
+  o->ftol = 1e-6;
+  o->gtol = 1e-6;
+  o->prec = MNL_PREC_FP64;
+  o->ls_max = 30;
+  o->ls_tol_ulps = 64.0;
+  o->validate = 0;
+}
+
+int64_t mnl_num_params(int32_t K, int32_t p, int32_t g, int32_t a) {
+  if (K < 2 || p < 0 || g < 0 || a < 0) return -1;
+  return int64_t(K - 1) * p + int64_t(K) * a + g;
+}
+
+int mnl_create(mnl_ctx **ctx, int device) {
+  if (!ctx) return MNL_ERR_ARG;
+  *ctx = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) {
+    (void)hipGetLastError();
+    return MNL_ERR_HIP;
+  }
+  if (device < 0 || device >= n) return MNL_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return MNL_ERR_HIP;
+  mnl_ctx *h = new mnl_ctx;
+  h->c.device = device;
+  h->c.bufs.resize(S_NSLOTS);
+  *ctx = h;
+  return MNL_OK;
+}
+
+void mnl_destroy(mnl_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->c.device);
+  (void)hipDeviceSynchronize();
+  for (auto &b : ctx->c.bufs)
+    if (b.ptr) (void)hipFree(b.ptr);
+  hessian_cache_free(&ctx->c);
+  delete ctx;
+}
+
+size_t mnl_workspace_bytes(const mnl_ctx *ctx) {
+  return ctx ? ctx->c.total_bytes : 0;
+}
+
+const char *mnl_last_error(const mnl_ctx *ctx) {
+  return ctx ? ctx->c.last_error.c_str() : "";
+}
+
+int mnl_loglik_grad(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
+                    double *loglik, double *grad, double *P, void *stream) {
+  if (!ctx) return MNL_ERR_ARG;
+  Ctx *c = &ctx->c;
+  Dims d;
+  MNL_TRY(check_problem(c, prob, &d));
+  if (!theta || !loglik) return set_error(c, MNL_ERR_ARG, "NULL output");
+  MNL_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  PassPlan plan;
+  int rc = pass_plan(d, &plan);
+  if (rc != MNL_OK) return set_error(c, rc, "shape beyond pass limits");
+  void *partial, *Pw = P, *Yb = nullptr;
+  MNL_TRY(ws_get(c, S_PARTIAL, size_t(plan.grid) * plan.stride * 8, &partial));
+  if (d.g) MNL_TRY(ws_get(c, S_YBAR, size_t(d.N) * d.g * 8, &Yb));
+  PassArgs A;
+  A.d = d;
+  A.X = prob->X;
+  A.Y = prob->Y;
+  A.Z = prob->Z;
+  A.w = prob->w;
+  A.choice = prob->choice;
+  A.theta = theta;
+  A.P = (double *)Pw;
+  A.P32 = nullptr;
+  A.Ybar = (double *)Yb;
+  A.partial = (double *)partial;
+  MNL_HIP(c, launch_pass(plan, A, s));
+  MNL_HIP(c, launch_pass_reduce(plan, (double *)partial, loglik, grad, d.np,
+                                s));
+  return MNL_OK;
+}
+
+int mnl_hessian(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
+                int32_t prec, double *H, void *stream) {
+  if (!ctx) return MNL_ERR_ARG;
+  Ctx *c = &ctx->c;
+  Dims d;
+  MNL_TRY(check_problem(c, prob, &d));
+  if (!theta || !H) return set_error(c, MNL_ERR_ARG, "NULL argument");
+  if (prec < MNL_PREC_FP64 || prec > MNL_PREC_BF16)
+    return set_error(c, MNL_ERR_ARG, "bad precision");
+  MNL_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  void *lg;
+  MNL_TRY(ws_get(c, S_LG, size_t(d.np + 1) * 8, &lg));
+  MNL_TRY(run_pass(c, d, prob, theta, (double *)lg, S_P, S_P32, S_YBAR,
+                   prec != MNL_PREC_FP64, s));
+  return form_hessian(c, d, prob, 0, prec, H, s);
+}
+
+static int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
+                    const mnl_fit_opts &o, mnl_fit_info *info, bool one_step,
+                    hipStream_t s) {
+  Dims d;
+  MNL_TRY(check_problem(c, prob, &d));
+  MNL_TRY(check_opts(c, &o));
+  MNL_HIP(c, hipSetDevice(c->device));
+  const double t_start = now_ms();
+  std::memset(info, 0, sizeof *info);
+  if (o.validate) MNL_TRY(validate_data(c, d, prob, s));
+  void *a, *b;
+  MNL_TRY(ws_get(c, S_LG, size_t(d.np + 1) * 8, &a));
+  MNL_TRY(ws_get(c, S_LG_TRIAL, size_t(d.np + 1) * 8, &b));
+  void *sv;
+  MNL_TRY(ws_get(c, S_SCAL, 256, &sv));
+  double *gn2 = (double *)sv;
+  StepState st{(double *)a, (double *)b, 0};
+
+  double t0 = now_ms();
+  MNL_TRY(run_pass(c, d, prob, theta, st.lg, S_P, S_P32, S_YBAR,
+                   o.prec != MNL_PREC_FP64, s));
+  double l = 0.0, gnorm = 0.0;
+  {
+    MNL_HIP(c, launch_sumsq(st.lg + 1, d.np, gn2, s));
+    double h[1];
+    MNL_TRY(copy_d2h(c, &l, st.lg, 8, s));
+    MNL_TRY(copy_d2h(c, h, gn2, 8, s));
+    gnorm = std::sqrt(h[0]);
+  }
+  info->t_loglik_grad = now_ms() - t0;
+  info->loglik_diff = std::numeric_limits<double>::quiet_NaN();
+  int reason = MNL_STOP_NONE;
+  for (;;) {
+    if (!std::isfinite(l) || !std::isfinite(gnorm)) {
+      reason = MNL_STOP_NONFINITE;
+      break;
+    }
+    if (gnorm <= o.gtol) {
+      reason = MNL_STOP_GTOL;
+      break;
+    }
+    if (!one_step && info->iters >= o.maxiter) {
+      reason = MNL_STOP_MAXITER;
+      break;
+    }
+    if (one_step && info->iters >= 1) break;
+    int r = MNL_STOP_NONE;
+    const double step_gnorm = gnorm;
+    MNL_TRY(newton_core(c, d, prob, theta, o, st, l, info, &r, s));
+    if (r != MNL_STOP_NONE) {
+      reason = r;
+      if (one_step) info->grad_norm = step_gnorm;
+      break;
+    }
+    info->iters += 1;
+    l = info->loglik;
+    MNL_HIP(c, launch_sumsq(st.lg + 1, d.np, gn2, s));
+    double h[1];
+    MNL_TRY(copy_d2h(c, h, gn2, 8, s));
+    gnorm = std::sqrt(h[0]);
+    if (one_step) {
+      info->grad_norm = step_gnorm;
+      info->loglik = l;
+      info->stop_reason = MNL_STOP_NONE;
+      info->t_total = now_ms() - t_start;
+      return MNL_OK;
+    }
+    if (std::fabs(info->loglik_diff) < o.ftol) {
+      reason = MNL_STOP_FTOL;
+      break;
+    }
+  }
+  info->stop_reason = reason;
+  info->loglik = l;
+  if (!one_step || reason == MNL_STOP_GTOL || reason == MNL_STOP_NONFINITE)
+    info->grad_norm = gnorm;
+  info->t_total = now_ms() - t_start;
+  return MNL_OK;
+}
+
+int mnl_newton_step(mnl_ctx *ctx, const mnl_problem *prob, double *theta,
+                    const mnl_fit_opts *opts, mnl_fit_info *step,
+                    void *stream) {
+  if (!ctx) return MNL_ERR_ARG;
+  Ctx *c = &ctx->c;
+  if (!theta || !step) return set_error(c, MNL_ERR_ARG, "NULL argument");
+  mnl_fit_opts o;
+  if (opts) o = *opts;
+  else mnl_default_opts(&o);
+  return fit_impl(c, prob, theta, o, step, true, (hipStream_t)stream);
+}
+
+int mnl_fit(mnl_ctx *ctx, const mnl_problem *prob, const double *theta0,
+            const mnl_fit_opts *opts, double *theta_out, mnl_fit_info *info,
+            void *stream) {
+  if (!ctx) return MNL_ERR_ARG;
+  Ctx *c = &ctx->c;
+  if (!theta_out || !info) return set_error(c, MNL_ERR_ARG, "NULL argument");
+  mnl_fit_opts o;
+  if (opts) o = *opts;
+  else mnl_default_opts(&o);
+  Dims d;
+  MNL_TRY(check_problem(c, prob, &d));
+  hipStream_t s = (hipStream_t)stream;
+  MNL_HIP(c, hipSetDevice(c->device));
+  if (theta0) {
+    if (theta0 != theta_out)
+      MNL_HIP(c, hipMemcpyAsync(theta_out, theta0, size_t(d.np) * 8,
+                                hipMemcpyDeviceToDevice, s));
+  } else {
+    MNL_HIP(c, hipMemsetAsync(theta_out, 0, size_t(d.np) * 8, s));
+  }
+  int rc = fit_impl(c, prob, theta_out, o, info, false, s);
+  (void)hipStreamSynchronize(s);
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/mnl.h"
+
+namespace mnl {
+
+constexpr int kWave = 64;
+
+// Dimensions of a problem, validated.
+struct Dims {
+  int64_t N;
+  int K, p, g, a;
+  int64_t np;      // number of coefficients (Eq. 8)
+  __host__ __device__ int64_t off_gamma() const { return int64_t(K - 1) * p; }
+  __host__ __device__ int64_t off_alpha() const { return int64_t(K - 1) * p + int64_t(K) * a; }
+};
+
+// Device workspace: one growing allocation per named slot.
+struct Buf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct Ctx;
+
+// Error helpers ---------------------------------------------------------------
+int set_error(Ctx *c, int code, const char *fmt, ...);
+
+#define MNL_HIP(ctx, call)                                                    \
+  do {                                                                        \
+    hipError_t _e = (call);                                                   \
+    if (_e != hipSuccess)                                                     \
+      return ::mnl::set_error((ctx), MNL_ERR_HIP, "%s failed: %s", #call,      \
+                              hipGetErrorString(_e));                         \
+  } while (0)
+
+#define MNL_TRY(expr)                                                         \
+  do {                                                                        \
+    int _r = (expr);                                                          \
+    if (_r != MNL_OK) return _r;                                              \
+  } while (0)
+
+// ---- fused pass (utility, probabilities, log-likelihood, gradient) ---------
+struct PassPlan {
+  int tb;            // observations per tile
+  int grid;          // workgroups (fixed by the shape: deterministic sums)
+  int beta_in_lds;   // beta staged in LDS (else read from global memory)
+  int jmax;          // gradient micro-tile slots per thread (8 or 32)
+  size_t lds_bytes;
+  int64_t stride;    // doubles per workgroup partial row
+};
+
+// Per-workgroup partial row layout: [0] loglik, [1 .. np] gradient.
+int pass_plan(const Dims &d, PassPlan *plan);
+
+struct PassArgs {
+  Dims d;
+  const double *X, *Y, *Z, *w;
+  const int32_t *choice;
+  const double *theta;
+  double *P;         // [N][K] f64 or null
+  float *P32;        // [N][K] f32 or null
+  double *Ybar;      // [N][g] or null
+  double *partial;   // [grid][stride]
+};
+
+hipError_t launch_pass(const PassPlan &plan, const PassArgs &a,
+                       hipStream_t s);
+// Sum the partial rows in a fixed order: out[0] = loglik, out[1..] = grad.
+hipError_t launch_pass_reduce(const PassPlan &plan, const double *partial,
+                              double *loglik, double *grad, int64_t np,
+                              hipStream_t s);
+
+// ---- small vector kernels ----------------------------------------------------
+// out = x + t * d
+hipError_t launch_axpy(const double *x, const double *d, double t, double *out,
+                       int64_t n, hipStream_t s);
+// out[0] = sum(x^2) in a fixed order (single workgroup)
+hipError_t launch_sumsq(const double *x, int64_t n, double *out,
+                        hipStream_t s);
+// Flags [0]: choice out of range count, [1]: non-finite data count.
+hipError_t launch_validate(const Dims &d, const double *X, const double *Y,
+                           const double *Z, const double *w,
+                           const int32_t *choice, int32_t *flags,
+                           hipStream_t s);
+
+// ---- Hessian -------------------------------------------------------------------
+struct HessPlan;
+struct HessArgs {
+  Dims d;
+  const double *X, *Y, *Z, *w;
+  const double *P;      // [N][K] f64
+  const float *P32;     // [N][K] f32 (mixed precision)
+  const double *Ybar;   // [N][g]
+  double *H;            // [np][np] output (Hessian sign)
+  int prec;
+};
+int hessian_run(Ctx *c, const HessArgs &a, hipStream_t s);
+void hessian_cache_free(Ctx *c);
+
+// ---- Cholesky and solves ------------------------------------------------------
+// Factor A = -H in place (lower triangle holds L) and solve L L^T delta = g.
+// info[0] receives 0 or (1 + index of the failed pivot).
+int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
+                   double *delta, int32_t *info, hipStream_t s);
+
+// Context ---------------------------------------------------------------------
+struct Ctx {
+  int device = 0;
+  std::string last_error;
+  std::vector<Buf> bufs;
+  size_t total_bytes = 0;
+  // event pool for timing
+  hipEvent_t ev[8] = {};
+  bool ev_ready = false;
+  // host-side caches of Hessian tile tables (keyed by shape)
+  void *hess_cache = nullptr;
+};
+
+// Workspace slots
+enum Slot {
+  S_PARTIAL = 0,   // pass partial rows
+  S_LG,            // [0] loglik, [1..np] grad (current)
+  S_LG_TRIAL,      // same for the line-search trial
+  S_P,             // P f64 [N][K] (current theta)
+  S_P_TRIAL,       // P f64 for the trial
+  S_P32,           // P f32
+  S_P32_TRIAL,
+  S_YBAR,          // Ybar [N][g]
+  S_YBAR_TRIAL,
+  S_H,             // Hessian / Cholesky factor [np][np]
+  S_DELTA,         // Newton direction [np]
+  S_THETA_TRIAL,   // trial theta [np]
+  S_SCAL,          // scalars (norms, flags)
+  S_HPART,         // Hessian split-K partials
+  S_HTAB,          // Hessian tile tables
+  S_CHOL,          // Cholesky scratch
+  S_THETA0,        // zero start
+  S_NSLOTS
+};
+
+int ws_get(Ctx *c, int slot, size_t bytes, void **ptr);
+
+}  // namespace mnl

@@ -1,0 +1,97 @@
+"""C-ABI library checks that need no GPU: it builds, loads, exports every
+function include/mnl.h declares, and its host-only functions behave."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from tests.conftest import ROOT, read_golden
+
+HEADER = os.path.join(ROOT, "include", "mnl.h")
+LIB = os.path.join(ROOT, "paper_1404_3177_amd", "libmnl.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mnl_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1404_3177_amd import build
+        build.build()
+    from paper_1404_3177_amd import _lib
+    return _lib.load(LIB)
+
+
+def test_header_declares_the_four_calls_and_helpers():
+    fns = declared_functions()
+    for f in ("mnl_fit", "mnl_loglik_grad", "mnl_hessian", "mnl_newton_step",
+              "mnl_create", "mnl_destroy", "mnl_num_params"):
+        assert f in fns
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (mnl_[a-z_0-9]+)$", out, flags=re.M))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    for f in declared_functions():
+        assert hasattr(lib, f)
+
+
+def test_binding_names_match_header():
+    from paper_1404_3177_amd import _lib
+    assert sorted(_lib.EXPORTS) == declared_functions()
+
+
+def test_num_params(lib):
+    for K, p, g, a, n_p, *_ in read_golden("num_params.txt"):
+        assert lib.mnl_num_params(int(K), int(p), int(g), int(a)) == int(n_p)
+    assert lib.mnl_num_params(1, 3, 0, 0) == -1
+    assert lib.mnl_num_params(3, -1, 0, 0) == -1
+
+
+def test_default_opts_are_mnlogit_defaults(lib):
+    from paper_1404_3177_amd import _lib
+    o = _lib.MnlFitOpts()
+    lib.mnl_default_opts(ctypes.byref(o))
+    assert (o.maxiter, o.ftol, o.gtol) == (50, 1e-6, 1e-6)
+    assert o.prec == 0 and o.ls_max == 30 and o.ls_tol_ulps == 64.0
+
+
+def test_strerror_and_version(lib):
+    assert lib.mnl_version().decode().count(".") == 1
+    assert lib.mnl_strerror(0) == b"ok"
+    assert b"Hessian" in lib.mnl_strerror(-3)
+    assert lib.mnl_strerror(-99) == b"unknown error"
+
+
+def test_null_context_is_rejected(lib):
+    # argument errors are caught before any device call
+    assert lib.mnl_create(None, 0) == -1
+    assert lib.mnl_loglik_grad(None, None, None, None, None, None, None) == -1
+    assert lib.mnl_fit(None, None, None, None, None, None, None) == -1
+    assert lib.mnl_workspace_bytes(None) == 0
+    lib.mnl_destroy(None)
+
+
+def test_struct_layouts_match_header():
+    # sizes of the ABI structs as laid out by the C compiler
+    from paper_1404_3177_amd import _lib
+    src = f'#include "{HEADER}"\n#include <stdio.h>\nint main(void){{' \
+          'printf("%zu %zu %zu\\n", sizeof(mnl_problem), sizeof(mnl_fit_opts),' \
+          ' sizeof(mnl_fit_info)); return 0;}'
+    exe = os.path.join("/tmp", "mnl_sizes")
+    subprocess.run(["gcc", "-x", "c", "-", "-o", exe], input=src, text=True,
+                   check=True)
+    sizes = [int(x) for x in subprocess.run([exe], capture_output=True,
+                                            text=True).stdout.split()]
+    assert sizes == [ctypes.sizeof(_lib.MnlProblem),
+                     ctypes.sizeof(_lib.MnlFitOpts),
+                     ctypes.sizeof(_lib.MnlFitInfo)]

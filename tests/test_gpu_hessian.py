@@ -1,0 +1,89 @@
+"""Parity of the GPU block Hessian (Eq. 10) with the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mnl_ref as R
+from tests.gpu_util import HESS_TOL, device_problem, hess_scale, theta_tensor
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [  # N, K, p, g, a, weights
+    (37, 4, 3, 2, 2, "uniform"),
+    (1, 3, 2, 1, 1, None),
+    (2049, 7, 5, 2, 1, None),
+    (513, 2, 4, 0, 0, "uniform"),
+    (777, 19, 3, 1, 0, "uniform"),
+    (300, 30, 2, 0, 2, None),
+    (1000, 5, 0, 3, 0, None),
+    (1000, 6, 0, 0, 3, "int"),
+    (1500, 13, 12, 2, 2, "uniform"),
+    (600, 66, 1, 1, 1, None),
+]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1404_3177_amd as mnl
+    return mnl.Context(0)
+
+
+def _gpu_h(ctx, pr, th, prec):
+    dp = device_problem(pr)
+    return ctx.hessian(dp, theta_tensor(th), prec=prec).cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_hessian_matches_oracle(ctx, shape, prec):
+    N, K, p, g, a, wk = shape
+    pr = synth.make_problem(N, K, p, g, a, seed=200 + N + K, weights=wk)
+    th = np.random.default_rng(N + K).normal(0, 0.6, pr.n_params)
+    H = _gpu_h(ctx, pr, th, prec)
+    H_ref = R.hessian(th, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
+    assert np.array_equal(H, H.T)
+    err = np.abs(H - H_ref) / hess_scale(pr)
+    assert err.max() <= HESS_TOL[prec], (prec, err.max(),
+                                         np.unravel_index(err.argmax(), H.shape))
+
+
+def test_hessian_deterministic(ctx):
+    import torch
+    pr = synth.make_problem(30000, 11, 7, 2, 2, seed=5, weights="uniform")
+    dp = device_problem(pr)
+    th = theta_tensor(np.random.default_rng(2).normal(0, 0.3, pr.n_params))
+    h1 = ctx.hessian(dp, th)
+    h2 = ctx.hessian(dp, th)
+    assert torch.equal(h1, h2)
+
+
+def test_hessian_c2_full(ctx):
+    pr = synth.make_config("c2")
+    th = 0.5 * pr.theta_true
+    H = _gpu_h(ctx, pr, th, "fp64")
+    H_ref = R.hessian(th, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
+    scale = np.abs(H_ref).max()
+    assert np.abs(H - H_ref).max() <= 1e-11 * scale
+    assert np.array_equal(H, H.T)
+
+
+@pytest.mark.parametrize("name", ["c3", "c5"])
+def test_hessian_config_sampled_blocks(ctx, name):
+    # full sizes: compare sampled blocks of Eq. 10 computed by the oracle
+    pr = synth.make_config(name)
+    th = 0.5 * pr.theta_true
+    H = _gpu_h(ctx, pr, th, "fp64")
+    assert np.array_equal(H, H.T)
+    P = R.probabilities(R.normalized_utility(th, pr.X, pr.Y, pr.Z))
+    w = np.ones(pr.N) if pr.w is None else pr.w
+    chunks = [c for c in R.chunk_list(pr.K, pr.p, pr.g, pr.a) if c[3] > 0]
+    rng = np.random.default_rng(0)
+    picks = [(0, 0), (0, 1), (len(chunks) - 1, len(chunks) - 1),
+             (len(chunks) - 2, len(chunks) - 1)]
+    picks += [tuple(sorted(rng.integers(0, len(chunks), 2))) for _ in range(6)]
+    for i, j in picks:
+        cn, cm = chunks[i], chunks[j]
+        B = R.hessian_block(P, pr.X, pr.Y, pr.Z, w, cn, cm)
+        G = H[cn[2]:cn[2] + cn[3], cm[2]:cm[2] + cm[3]]
+        scale = max(np.abs(B).max(), np.abs(np.diag(H)).max() * 1e-3)
+        assert np.abs(G - B).max() <= 1e-11 * scale, (name, cn, cm)
