@@ -1,0 +1,260 @@
+#!/usr/bin/env python
+"""Newton-Raphson multinomial-logit fits per second on one MI355X.
+
+One step = one whole fit (fused pass, block Hessian, Cholesky solve, halving
+line search, repeated until ||g||_2 <= 1e-8) of the 100,000-individual,
+50-alternative workload (21 individual-specific columns incl. intercept,
+5 generic and 5 alternative-specific alternative-varying variables), data
+already resident in HBM, started from theta = 0.
+
+    python bench.py [--steps K] [--warmup W] [--prec fp64|fp32|bf16]
+
+Prints one JSON line.  Besides the fit rate it reports the Hessian MFMA
+kernel's rate against the MFMA peak of its dtype (HIP events around every
+launch, on the stream it runs on), the fused pass kernel's HBM rate, the
+p50/p99 fit latency, the FP32-Hessian variant and the FP64 CPU oracle timed
+on the host cores over a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("NR fits/sec at 1e-8 grad tol + Hessian TFLOP/s (% MFMA peak); "
+          "p50/p99 fit latency")
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+HBM_GBPS = 8000.0
+GTOL = 1e-8
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def hess_kernel_flops(pr):
+    """Useful flops of the Hessian MFMA kernel per launch: 2 N per unique
+    entry of the blocks it forms (beta-beta, beta-gamma, gamma-gamma)."""
+    N, K, p, a = pr.N, pr.K, pr.p, pr.a
+    u_bb = (K - 1) * K // 2 * (p * (p + 1) // 2)
+    u_bg = (K - 1) * p * K * a
+    u_gg = K * (K - 1) // 2 * a * a + K * (a * (a + 1) // 2)
+    return 2.0 * N * (u_bb + u_bg + u_gg)
+
+
+def hess_total_flops(pr):
+    """Useful flops of the whole Hessian (all blocks, unique entries)."""
+    N, K, p, g, a = pr.N, pr.K, pr.p, pr.g, pr.a
+    u = ((K - 1) * K // 2 * (p * (p + 1) // 2) + (K - 1) * p * K * a +
+         K * (K - 1) // 2 * a * a + K * (a * (a + 1) // 2) +
+         (K - 1) * p * g + K * a * g + g * (g + 1) // 2)
+    return 2.0 * N * u
+
+
+def pass_bytes(pr):
+    """Algorithmic HBM bytes of one fused pass: read X, Y, Z, choice (and
+    weights), write P and Ybar."""
+    N, K, p, g, a = pr.N, pr.K, pr.p, pr.g, pr.a
+    b = N * (p + K * g + K * a) * 8 + 4 * N + N * K * 8 + N * g * 8
+    if pr.w is not None:
+        b += 8 * N
+    return float(b)
+
+
+def time_fits(ctx, dp, steps, warmup, prec):
+    import torch
+    for _ in range(warmup):
+        ctx.fit(dp, gtol=GTOL, ftol=0.0, prec=prec)
+    torch.cuda.synchronize()
+    lat, infos = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t = time.perf_counter()
+        theta, info = ctx.fit(dp, gtol=GTOL, ftol=0.0, prec=prec)
+        lat.append(time.perf_counter() - t)
+        infos.append(info)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    return theta, infos, lat, total
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    k = (len(xs) - 1) * q
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def kernel_stats(pr, infos, prec):
+    hk = sum(i["t_hess_kernel"] for i in infos)
+    nh = sum(i["n_hess"] for i in infos)
+    pk = sum(i["t_pass_kernel"] for i in infos)
+    npass = sum(i["n_pass"] for i in infos)
+    hess_ms = hk / max(nh, 1)
+    pass_ms = pk / max(npass, 1)
+    tflops = hess_kernel_flops(pr) / (hess_ms * 1e-3) / 1e12
+    gbps = pass_bytes(pr) / (pass_ms * 1e-3) / 1e9
+    return dict(hess_ms=hess_ms, n_hess=nh, pass_ms=pass_ms, n_pass=npass,
+                tflops=tflops, gbps=gbps,
+                peak=PEAK_TFLOPS[prec])
+
+
+def cpu_baseline(pr, iters, budget_s=30.0):
+    """The FP64 oracle on the host cores: one Newton iteration at theta = 0
+    (log-likelihood + gradient, Hessian of Eq. 10 block by block, Cholesky
+    solve, one line-search evaluation), scaled by the fit's iteration count
+    to fits/s."""
+    import numpy as np
+    from oracle import mnl_ref as R
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    th = np.zeros(pr.n_params)
+    t0 = time.perf_counter()
+    l0 = R.loglik(th, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
+    g0 = R.gradient(th, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
+    H = R.hessian(th, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
+    d = R.newton_direction(H, g0)
+    R.loglik(th + d, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
+    t_iter = time.perf_counter() - t0
+    del l0
+    return {"value": 1.0 / (t_iter * max(iters, 1)), "unit": "fits/s",
+            "cores": int(threads), "kind": "oracle",
+            "sample": f"one NR iteration of the same fit at theta=0 "
+                      f"({t_iter:.1f} s: loglik, gradient, Eq. 10 Hessian, "
+                      f"Cholesky solve, one line-search pass), scaled by the "
+                      f"fit's {iters} iterations",
+            "seconds_per_iteration": t_iter}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the "
+              "fit is not sharded across GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1404_3177_amd as mnl
+    import synth
+
+    log(f"generating workload {args.config}")
+    pr = synth.make_config(args.config)
+    ctx = mnl.Context(0)
+    dp = mnl.Problem.from_numpy(pr, device="cuda:0")
+    log(f"timing {args.steps} fits ({args.prec} Hessian) after "
+        f"{args.warmup} warmup fits")
+    theta, infos, lat, total = time_fits(ctx, dp, args.steps, args.warmup,
+                                         args.prec)
+    info = infos[-1]
+    ks = kernel_stats(pr, infos, args.prec)
+    log(f"fit: {total / args.steps * 1e3:.2f} ms, iters {info['iters']}, "
+        f"Hessian kernel {ks['hess_ms']:.3f} ms = {ks['tflops']:.2f} TFLOP/s")
+
+    gold_path = os.path.join(ROOT, "tests", "golden", f"fit_{args.config}.npz")
+    coef_err = None
+    if os.path.exists(gold_path):
+        gold = np.load(gold_path)
+        th = theta.cpu().numpy()
+        coef_err = float(np.linalg.norm(th - gold["theta"]) /
+                         np.linalg.norm(gold["theta"]))
+
+    variants = {}
+    if not args.no_variants and args.prec == "fp64":
+        for vp in ("fp32",):
+            log(f"variant: {vp} Hessian")
+            th_v, inf_v, lat_v, tot_v = time_fits(ctx, dp, max(3, args.steps // 2),
+                                                  1, vp)
+            kv = kernel_stats(pr, inf_v, vp)
+            ent = {"fits_per_s": len(lat_v) / tot_v,
+                   "ms_per_fit": tot_v / len(lat_v) * 1e3,
+                   "iters": inf_v[-1]["iters"],
+                   "hessian_kernel_ms": kv["hess_ms"],
+                   "hessian_tflops": kv["tflops"],
+                   "hessian_frac_of_peak": kv["tflops"] / kv["peak"],
+                   "peak_tflops": kv["peak"],
+                   "grad_norm": inf_v[-1]["grad_norm"],
+                   "stop_reason": inf_v[-1]["stop_reason"]}
+            if os.path.exists(gold_path):
+                ent["coef_rel_err_vs_oracle"] = float(
+                    np.linalg.norm(th_v.cpu().numpy() - gold["theta"]) /
+                    np.linalg.norm(gold["theta"]))
+            variants[f"{vp}_hessian"] = ent
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 CPU oracle (bounded sample)")
+        cpu = cpu_baseline(pr, info["iters"])
+
+    value = args.steps / total
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "fits/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else f"f64+{args.prec}-hessian",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{args.config}: N={pr.N} K={pr.K} p={pr.p} g={pr.g} "
+                         f"a={pr.a} (n_p={pr.n_params}), NR fit from theta=0 "
+                         f"to ||g||_2<=1e-8, {args.prec} Hessian"),
+            "N": pr.N, "K": pr.K, "p": pr.p, "g": pr.g, "a": pr.a,
+            "n_params": pr.n_params, "gtol": GTOL,
+        },
+        "roofline": {
+            "bound": "mfma",
+            "achieved": ks["tflops"],
+            "peak": ks["peak"],
+            "unit": "TFLOP/s",
+            "frac": ks["tflops"] / ks["peak"],
+            "traffic": None,
+            "kernel": f"k_hess_tiles<{ {'fp64': 0, 'fp32': 1, 'bf16': 2}[args.prec] }>",
+            "kernel_ms": ks["hess_ms"],
+            "launches": ks["n_hess"],
+            "flops_per_launch": hess_kernel_flops(pr),
+        },
+        "pass_kernel": {
+            "bound": "hbm", "achieved": ks["gbps"], "peak": HBM_GBPS,
+            "unit": "GB/s", "frac": ks["gbps"] / HBM_GBPS,
+            "kernel_ms": ks["pass_ms"], "launches": ks["n_pass"],
+            "bytes_per_launch": pass_bytes(pr),
+        },
+        "latency_ms": {"p50": percentile(lat, 0.5) * 1e3,
+                       "p99": percentile(lat, 0.99) * 1e3},
+        "fit": {"iters": info["iters"], "ls_iters": info["ls_iters"],
+                "stop_reason": info["stop_reason"],
+                "grad_norm": info["grad_norm"], "loglik": info["loglik"],
+                "coef_rel_err_vs_oracle": coef_err,
+                "hessian_total_flops": hess_total_flops(pr),
+                "phase_ms": {k: info[k] for k in ("t_loglik_grad", "t_hessian",
+                                                   "t_chol", "t_ls")}},
+        "variants": variants,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

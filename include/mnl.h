@@ -113,7 +113,11 @@ typedef struct {
                                   the data before fitting                  */
 } mnl_fit_opts;
 
-/* Report of a fit or of one Newton step (mnlogit's est.stat). Times in ms. */
+/* Report of a fit or of one Newton step (mnlogit's est.stat). Times in ms:
+ * t_* are host wall times of the phases; t_hess_kernel and t_pass_kernel
+ * are GPU times (HIP events on the caller's stream) of the Hessian MFMA
+ * kernel and of the fused pass kernel, summed over n_hess / n_pass
+ * launches. */
 typedef struct {
     int32_t iters;             /* Newton iterations taken                  */
     int32_t ls_iters;          /* line-search trial evaluations            */
@@ -121,7 +125,7 @@ typedef struct {
     int32_t stop_reason;       /* MNL_STOP_*                               */
     int32_t hess_fallbacks;    /* mixed precision: Hessians recomputed in
                                   FP64 after a failed factorisation       */
-    int32_t reserved;
+    int32_t n_hess;            /* Hessian formations                       */
     double loglik;             /* l at the returned theta                  */
     double grad_norm;          /* ||g||_2 at the returned theta (fit), at
                                   the input theta (newton_step)            */
@@ -131,6 +135,10 @@ typedef struct {
     double t_hessian;          /* Hessian formation                        */
     double t_chol;             /* Cholesky factorisation + solves          */
     double t_ls;               /* line-search passes                       */
+    double t_hess_kernel;      /* GPU time in the Hessian MFMA kernel      */
+    double t_pass_kernel;      /* GPU time in the fused pass kernel        */
+    int32_t n_pass;            /* fused passes run                         */
+    int32_t reserved;
 } mnl_fit_info;
 
 /* Library version string ("major.minor"). */

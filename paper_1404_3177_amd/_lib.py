@@ -53,11 +53,13 @@ class MnlFitInfo(ctypes.Structure):
     _fields_ = [
         ("iters", ctypes.c_int32), ("ls_iters", ctypes.c_int32),
         ("ls_backtracks", ctypes.c_int32), ("stop_reason", ctypes.c_int32),
-        ("hess_fallbacks", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("hess_fallbacks", ctypes.c_int32), ("n_hess", ctypes.c_int32),
         ("loglik", ctypes.c_double), ("grad_norm", ctypes.c_double),
         ("loglik_diff", ctypes.c_double), ("t_total", ctypes.c_double),
         ("t_loglik_grad", ctypes.c_double), ("t_hessian", ctypes.c_double),
         ("t_chol", ctypes.c_double), ("t_ls", ctypes.c_double),
+        ("t_hess_kernel", ctypes.c_double), ("t_pass_kernel", ctypes.c_double),
+        ("n_pass", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

@@ -812,16 +812,24 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   hd.ncombo = pl->ncombo;
   hd.nrow_xg = pl->nrow_xg;
   hd.ncol_xg = pl->ncol_xg;
+  if (c->ev_ready && pl->ntiles > 0) {
+    MNL_HIP(c, hipEventRecord(c->ev_h0, s));
+  }
   if (h.prec == 0) {
     MNL_HIP(c, launch_tiles<0>(*pl, hd, s));
-    MNL_HIP(c, (launch_assemble<double>(*pl, h, pbb, pxg, alt, s)));
   } else if (h.prec == 1) {
     MNL_HIP(c, launch_tiles<1>(*pl, hd, s));
-    MNL_HIP(c, (launch_assemble<float>(*pl, h, pbb, pxg, alt, s)));
   } else {
     MNL_HIP(c, launch_tiles<2>(*pl, hd, s));
-    MNL_HIP(c, (launch_assemble<float>(*pl, h, pbb, pxg, alt, s)));
   }
+  if (c->ev_ready && pl->ntiles > 0) {
+    MNL_HIP(c, hipEventRecord(c->ev_h1, s));
+    c->hess_pending = true;
+  }
+  if (h.prec == 0)
+    MNL_HIP(c, (launch_assemble<double>(*pl, h, pbb, pxg, alt, s)));
+  else
+    MNL_HIP(c, (launch_assemble<float>(*pl, h, pbb, pxg, alt, s)));
   return MNL_OK;
 }
 

@@ -118,8 +118,43 @@ int run_pass(Ctx *c, const Dims &d, const mnl_problem *pr, const double *theta,
   A.P32 = (float *)P32;
   A.Ybar = (double *)Ybar;
   A.partial = (double *)partial;
+  if (c->ev_ready) MNL_HIP(c, hipEventRecord(c->ev_p0, s));
   MNL_HIP(c, launch_pass(plan, A, s));
+  if (c->ev_ready) {
+    MNL_HIP(c, hipEventRecord(c->ev_p1, s));
+    c->pass_pending = true;
+  }
   MNL_HIP(c, launch_pass_reduce(plan, (double *)partial, lg, lg + 1, d.np, s));
+  return MNL_OK;
+}
+
+// Add the GPU times of the last bracketed kernels (call after a sync).
+void collect_timing(Ctx *c, mnl_fit_info *info) {
+  float ms = 0.0f;
+  if (c->hess_pending) {
+    if (hipEventElapsedTime(&ms, c->ev_h0, c->ev_h1) == hipSuccess) {
+      info->t_hess_kernel += ms;
+      info->n_hess += 1;
+    }
+    c->hess_pending = false;
+  }
+  if (c->pass_pending) {
+    if (hipEventElapsedTime(&ms, c->ev_p0, c->ev_p1) == hipSuccess) {
+      info->t_pass_kernel += ms;
+      info->n_pass += 1;
+    }
+    c->pass_pending = false;
+  }
+  (void)hipGetLastError();
+}
+
+int ensure_events(Ctx *c) {
+  if (c->ev_ready) return MNL_OK;
+  MNL_HIP(c, hipEventCreate(&c->ev_h0));
+  MNL_HIP(c, hipEventCreate(&c->ev_h1));
+  MNL_HIP(c, hipEventCreate(&c->ev_p0));
+  MNL_HIP(c, hipEventCreate(&c->ev_p1));
+  c->ev_ready = true;
   return MNL_OK;
 }
 
@@ -199,6 +234,7 @@ int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
   for (int attempt = 0; attempt < 2; ++attempt) {
     MNL_TRY(form_hessian(c, d, pr, st.cur, prec, H, s));
     MNL_HIP(c, hipStreamSynchronize(s));
+    collect_timing(c, info);
     double t1 = now_ms();
     info->t_hessian += t1 - t0;
     // the factorisation works on A = -H in place
@@ -231,6 +267,7 @@ int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
                      want32, s));
     double l_new;
     MNL_TRY(copy_d2h(c, &l_new, st.lg_trial, 8, s));
+    collect_timing(c, info);
     info->ls_iters += 1;
     if (std::isfinite(l_new) && l_new >= l_old - tau) {
       info->ls_backtracks += trial - 1;
@@ -315,6 +352,12 @@ void mnl_destroy(mnl_ctx *ctx) {
   for (auto &b : ctx->c.bufs)
     if (b.ptr) (void)hipFree(b.ptr);
   hessian_cache_free(&ctx->c);
+  if (ctx->c.ev_ready) {
+    (void)hipEventDestroy(ctx->c.ev_h0);
+    (void)hipEventDestroy(ctx->c.ev_h1);
+    (void)hipEventDestroy(ctx->c.ev_p0);
+    (void)hipEventDestroy(ctx->c.ev_p1);
+  }
   delete ctx;
 }
 
@@ -386,6 +429,8 @@ static int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
   MNL_HIP(c, hipSetDevice(c->device));
   const double t_start = now_ms();
   std::memset(info, 0, sizeof *info);
+  MNL_TRY(ensure_events(c));
+  c->hess_pending = c->pass_pending = false;
   if (o.validate) MNL_TRY(validate_data(c, d, prob, s));
   void *a, *b;
   MNL_TRY(ws_get(c, S_LG, size_t(d.np + 1) * 8, &a));
@@ -404,6 +449,7 @@ static int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
     double h[1];
     MNL_TRY(copy_d2h(c, &l, st.lg, 8, s));
     MNL_TRY(copy_d2h(c, h, gn2, 8, s));
+    collect_timing(c, info);
     gnorm = std::sqrt(h[0]);
   }
   info->t_loglik_grad = now_ms() - t0;

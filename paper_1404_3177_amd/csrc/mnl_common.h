@@ -118,9 +118,12 @@ struct Ctx {
   std::string last_error;
   std::vector<Buf> bufs;
   size_t total_bytes = 0;
-  // event pool for timing
-  hipEvent_t ev[8] = {};
+  // HIP events bracketing the Hessian MFMA kernel and the fused pass
+  // kernel on the caller's stream (read after the driver's next sync)
+  hipEvent_t ev_h0 = nullptr, ev_h1 = nullptr, ev_p0 = nullptr,
+             ev_p1 = nullptr;
   bool ev_ready = false;
+  bool hess_pending = false, pass_pending = false;
   // host-side caches of Hessian tile tables (keyed by shape)
   void *hess_cache = nullptr;
 };
