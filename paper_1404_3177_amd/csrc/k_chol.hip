@@ -1,19 +1,23 @@
 // Newton direction (Eq. 6): delta = (-H)^{-1} g through the Cholesky factor
 // of A = -H, always in FP64.
 //
-// Blocked right-looking factorisation with 64-wide panels on the lower
-// triangle of A (row-major, in place):
-//   diag  : one workgroup factors the 64x64 diagonal block in LDS and
-//           checks every pivot against the round-off floor
-//           n * eps * max_k A_kk (a pivot at or below it means -H is not
-//           numerically positive definite);
-//   trsm  : L21 = A21 L11^{-T}, one thread per row, L11 in LDS;
+// The matrix buffer has n + 1 rows: rows 0..n-1 hold H (row-major), row n
+// holds g^T.  Factoring the augmented lower triangle
+//     [ A    ]   [ L    ] [ L^T  z ]
+//     [ g^T  ] = [ z^T  ]
+// by blocked right-looking Cholesky leaves z = L^{-1} g in row n, so the
+// forward substitution comes out of the factorisation.  Per 32-wide panel:
+//   panel : every workgroup factors the small diagonal block in LDS (one
+//           barrier per column, LDL^T form then scaled), checks the pivots
+//           against the round-off floor n * eps * max_k A_kk (workgroup 0
+//           writes L11 and the failure flag) and solves its 64 rows
+//           x L11^T = a below the panel (one row per thread);
 //   update: A22 -= L21 L21^T on the lower 64x64 tiles, FP64 MFMA.
-// Then L z = g and L^T delta = z panel by panel: each workgroup re-solves
-// the small diagonal system itself and updates its share of the remaining
-// right-hand side, so one launch per panel suffices and no two workgroups
-// write the same entry.  A failure flag in device memory makes every later
-// launch return at once.
+// Then L^T delta = z by 64-wide panels from the bottom: each workgroup
+// re-solves the panel's small triangular system itself and updates its
+// share of the remaining right-hand side, so one launch per panel suffices
+// and no two workgroups write the same entry.  A failure flag in device
+// memory makes every later launch return at once.
 #include <cmath>
 
 #include "mnl_common.h"
@@ -23,7 +27,9 @@ namespace mnl {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int NB = 64;
+constexpr int NBF = 32;   // factorisation panel width
+constexpr int NBS = 64;   // backward-solve panel width
+constexpr int TILE = 64;  // trailing-update tile
 
 __device__ inline double wsum(double v) {
 #pragma unroll
@@ -31,7 +37,7 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
-// A <- -H on the lower triangle (the factorisation reads nothing else)
+// A <- -H on the lower triangle of rows 0..n-1 (nothing else is read)
 __global__ void k_negate_lower(double *A, int64_t n) {
   const int64_t r = blockIdx.y;
   const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -63,72 +69,74 @@ __global__ __launch_bounds__(256) void k_floor(const double *A, int64_t n,
   }
 }
 
-__global__ __launch_bounds__(256) void k_chol_diag(double *A, int64_t n,
-                                                   int64_t j0,
+// Panel j0 (width jb <= NBF): workgroup b factors the diagonal block and
+// solves rows j0 + jb + 64 (b - 1) .. + 63 (b >= 1).  64 threads.
+__global__ __launch_bounds__(64) void k_chol_panel(double *A, int64_t n,
+                                                   int64_t nrows, int64_t j0,
                                                    const double *floor_p,
                                                    int32_t *info) {
-  __shared__ double L[NB][NB + 1];
-  __shared__ int fail;
+  __shared__ double L[NBF][NBF + 1];
+  __shared__ double col[2][NBF];
   if (info[0]) return;
-  const int jb = (int)min<int64_t>(NB, n - j0);
+  const int jb = (int)min<int64_t>(NBF, n - j0);
   const int tid = threadIdx.x;
-  for (int e = tid; e < jb * jb; e += 256) {
-    const int i = e / jb, j = e - (e / jb) * jb;
-    L[i][j] = (j <= i) ? A[(j0 + i) * n + j0 + j] : 0.0;
+  for (int e = tid; e < NBF * NBF; e += 64) {
+    const int i = e / NBF, j = e - (e / NBF) * NBF;
+    L[i][j] = (i < jb && j <= i) ? A[(j0 + i) * n + j0 + j] : 0.0;
   }
-  if (tid == 0) fail = 0;
-  const double fl = *floor_p;
   __syncthreads();
+  // LDL^T: after step k the entries (i, j > k) hold the Schur complement;
+  // column k is final once step k starts (the workgroup is one wave, so the
+  // barriers are cheap)
   for (int k = 0; k < jb; ++k) {
-    if (tid == 0) {
-      const double d = L[k][k];
-      if (!(d > fl) || !isfinite(d)) {
-        fail = 1;
-        info[0] = int(j0 + k + 1);
-      } else {
-        L[k][k] = sqrt(d);
-      }
+    if (tid < jb) col[k & 1][tid] = L[tid][k];
+    __syncthreads();
+    const double dk = col[k & 1][k];
+    const double inv = 1.0 / dk;
+    for (int e = tid; e < NBF * NBF; e += 64) {
+      const int i = e / NBF, j = e - (e / NBF) * NBF;
+      if (j > k && j <= i && i < jb)
+        L[i][j] -= col[k & 1][i] * col[k & 1][j] * inv;
     }
-    __syncthreads();
-    if (fail) return;
-    const double dk = L[k][k];
-    for (int i = k + 1 + tid; i < jb; i += 256) L[i][k] /= dk;
-    __syncthreads();
-    const int m = jb - k - 1;
-    for (int e = tid; e < m * m; e += 256) {
-      const int i = k + 1 + e / m, j = k + 1 + (e - (e / m) * m);
-      if (j <= i) L[i][j] -= L[i][k] * L[j][k];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < jb * jb; e += 256) {
-    const int i = e / jb, j = e - (e / jb) * jb;
-    if (j <= i) A[(j0 + i) * n + j0 + j] = L[i][j];
-  }
-}
-
-// rows below the panel: x L11^T = a  ->  x_c = (a_c - sum_{k<c} x_k L_ck)/L_cc
-__global__ __launch_bounds__(64) void k_chol_trsm(double *A, int64_t n,
-                                                  int64_t j0,
-                                                  const int32_t *info) {
-  __shared__ double L[NB][NB + 1];
-  if (info[0]) return;
-  const int jb = (int)min<int64_t>(NB, n - j0);
-  const int64_t j1 = j0 + jb;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < jb * jb; e += 64) {
-    const int i = e / jb, j = e - (e / jb) * jb;
-    L[i][j] = (j <= i) ? A[(j0 + i) * n + j0 + j] : 0.0;
+    __syncthreads();   // column k + 1 is final before it is read
   }
   __syncthreads();
-  const int64_t r = j1 + int64_t(blockIdx.x) * 64 + tid;
-  if (r >= n) return;
-  double x[NB];
+  // pivots d_k = L[k][k]; L_ik = D_ik / sqrt(d_k)
+  const double fl = *floor_p;
+  bool bad = false;
+  for (int k = 0; k < jb; ++k) {
+    const double d = L[k][k];
+    if (!(d > fl) || !isfinite(d)) {
+      bad = true;
+      if (blockIdx.x == 0 && tid == 0 && !info[0]) info[0] = int(j0 + k + 1);
+      break;
+    }
+  }
+  if (bad) return;
+  __syncthreads();
+  for (int e = tid; e < NBF * NBF; e += 64) {
+    const int i = e / NBF, j = e - (e / NBF) * NBF;
+    if (i < jb && j < i) L[i][j] /= sqrt(L[j][j]);
+  }
+  __syncthreads();
+  if (tid < jb) L[tid][tid] = sqrt(L[tid][tid]);
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int e = tid; e < jb * jb; e += 64) {
+      const int i = e / jb, j = e - (e / jb) * jb;
+      if (j <= i) A[(j0 + i) * n + j0 + j] = L[i][j];
+    }
+    return;
+  }
+  // rows below: x L11^T = a  ->  x_c = (a_c - sum_{k<c} x_k L_ck) / L_cc
+  const int64_t r = j0 + jb + int64_t(blockIdx.x - 1) * 64 + tid;
+  if (r >= nrows) return;
+  double x[NBF];
   double *row = A + r * n + j0;
 #pragma unroll
-  for (int c = 0; c < NB; ++c) x[c] = c < jb ? row[c] : 0.0;
+  for (int c = 0; c < NBF; ++c) x[c] = c < jb ? row[c] : 0.0;
 #pragma unroll
-  for (int c = 0; c < NB; ++c) {
+  for (int c = 0; c < NBF; ++c) {
     if (c < jb) {
       double s = x[c];
 #pragma unroll
@@ -137,31 +145,31 @@ __global__ __launch_bounds__(64) void k_chol_trsm(double *A, int64_t n,
     }
   }
 #pragma unroll
-  for (int c = 0; c < NB; ++c)
+  for (int c = 0; c < NBF; ++c)
     if (c < jb) row[c] = x[c];
 }
 
-// trailing update on lower tiles: A[R][C] -= L21[R] . L21[C], FP64 MFMA
+// trailing update on lower tiles of rows/cols >= j0 + jb (rows up to
+// nrows - 1, columns up to n - 1): A[R][C] -= L21[R] . L21[C], FP64 MFMA
 __global__ __launch_bounds__(256) void k_chol_update(double *A, int64_t n,
-                                                     int64_t j0,
+                                                     int64_t nrows, int64_t j0,
                                                      const int32_t *info) {
-  __shared__ double Ar[NB][NB + 1];
-  __shared__ double Ac[NB][NB + 1];
+  __shared__ double Ar[TILE][NBF + 1];
+  __shared__ double Ac[TILE][NBF + 1];
   if (info[0]) return;
-  const int jb = (int)min<int64_t>(NB, n - j0);
+  const int jb = (int)min<int64_t>(NBF, n - j0);
   const int64_t j1 = j0 + jb;
-  // lower-triangular tile index
   const int64_t b = blockIdx.x;
   int64_t ti = (int64_t)((sqrt(8.0 * double(b) + 1.0) - 1.0) * 0.5);
   while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
   while (ti * (ti + 1) / 2 > b) --ti;
   const int64_t tj = b - ti * (ti + 1) / 2;
-  const int64_t R0 = j1 + ti * NB, C0 = j1 + tj * NB;
+  const int64_t R0 = j1 + ti * TILE, C0 = j1 + tj * TILE;
   const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e / NB, k = e - (e / NB) * NB;
+  for (int e = tid; e < TILE * NBF; e += 256) {
+    const int i = e / NBF, k = e - (e / NBF) * NBF;
     const int64_t rr = R0 + i, cc = C0 + i;
-    Ar[i][k] = (rr < n && k < jb) ? A[rr * n + j0 + k] : 0.0;
+    Ar[i][k] = (rr < nrows && k < jb) ? A[rr * n + j0 + k] : 0.0;
     Ac[i][k] = (cc < n && k < jb) ? A[cc * n + j0 + k] : 0.0;
   }
   __syncthreads();
@@ -170,7 +178,8 @@ __global__ __launch_bounds__(256) void k_chol_update(double *A, int64_t n,
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = d4{0, 0, 0, 0};
   const int ar = 16 * wv + (lane & 15);
-  for (int ks = 0; ks < (jb + 3) / 4; ++ks) {
+#pragma unroll
+  for (int ks = 0; ks < NBF / 4; ++ks) {
     const int k = 4 * ks + (lane >> 4);
     const double av = Ar[ar][k];
 #pragma unroll
@@ -185,44 +194,8 @@ __global__ __launch_bounds__(256) void k_chol_update(double *A, int64_t n,
     for (int r = 0; r < 4; ++r) {
       const int64_t rr = R0 + 16 * wv + (lane >> 4) + 4 * r;
       const int64_t cc = C0 + 16 * t + (lane & 15);
-      if (rr < n && cc < n && cc <= rr) A[rr * n + cc] -= acc[t][r];
+      if (rr < nrows && cc < n && cc <= rr) A[rr * n + cc] -= acc[t][r];
     }
-  }
-}
-
-// forward substitution, panel j0: z_p = L11^{-1} y_p, then y_r -= L_rp z_p
-__global__ __launch_bounds__(256) void k_chol_fwd(const double *A, int64_t n,
-                                                  int64_t j0, double *y,
-                                                  double *z,
-                                                  const int32_t *info) {
-  __shared__ double L[NB][NB + 1];
-  __shared__ double zp[NB];
-  if (info[0]) return;
-  const int jb = (int)min<int64_t>(NB, n - j0);
-  const int64_t j1 = j0 + jb;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < jb * jb; e += 256) {
-    const int i = e / jb, j = e - (e / jb) * jb;
-    L[i][j] = (j <= i) ? A[(j0 + i) * n + j0 + j] : 0.0;
-  }
-  __syncthreads();
-  if (tid < 64) {
-    // lane j holds unknown j; each step broadcasts one finished value
-    double zl = tid < jb ? y[j0 + tid] : 0.0;
-    for (int c = 0; c < jb; ++c) {
-      const double part = wsum((tid < c) ? L[c][tid] * zl : 0.0);
-      if (tid == c) zl = (zl - part) / L[c][c];
-    }
-    zp[tid] = zl;
-  }
-  __syncthreads();
-  if (blockIdx.x == 0 && tid < jb) z[j0 + tid] = zp[tid];
-  const int64_t r = j1 + int64_t(blockIdx.x) * 256 + tid;
-  if (r < n) {
-    const double *row = A + r * n + j0;
-    double s = 0.0;
-    for (int c = 0; c < jb; ++c) s = fma(row[c], zp[c], s);
-    y[r] -= s;
   }
 }
 
@@ -232,10 +205,10 @@ __global__ __launch_bounds__(256) void k_chol_bwd(const double *A, int64_t n,
                                                   int64_t j0, double *z,
                                                   double *delta,
                                                   const int32_t *info) {
-  __shared__ double L[NB][NB + 1];
-  __shared__ double dp[NB];
+  __shared__ double L[NBS][NBS + 1];
+  __shared__ double dp[NBS];
   if (info[0]) return;
-  const int jb = (int)min<int64_t>(NB, n - j0);
+  const int jb = (int)min<int64_t>(NBS, n - j0);
   const int tid = threadIdx.x;
   for (int e = tid; e < jb * jb; e += 256) {
     const int i = e / jb, j = e - (e / jb) * jb;
@@ -265,38 +238,31 @@ __global__ __launch_bounds__(256) void k_chol_bwd(const double *A, int64_t n,
 int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
                    double *delta, int32_t *info, hipStream_t s) {
   void *scr;
-  MNL_TRY(ws_get(c, S_CHOL, size_t(2 * n + 8) * 8, &scr));
-  double *y = static_cast<double *>(scr);
-  double *z = y + n;
+  MNL_TRY(ws_get(c, S_CHOL, size_t(n + 8) * 8, &scr));
+  double *z = static_cast<double *>(scr);
   double *floor_p = z + n;
-  MNL_HIP(c, hipMemcpyAsync(y, g, size_t(n) * 8, hipMemcpyDeviceToDevice, s));
+  const int64_t nrows = n + 1;
+  // g^T as row n of the augmented matrix
+  MNL_HIP(c, hipMemcpyAsync(A + n * n, g, size_t(n) * 8,
+                            hipMemcpyDeviceToDevice, s));
   {
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)n);
     hipLaunchKernelGGL(k_negate_lower, grid, dim3(256), 0, s, A, n);
   }
   hipLaunchKernelGGL(k_floor, dim3(1), dim3(256), 0, s, A, n, floor_p, info);
-  for (int64_t j0 = 0; j0 < n; j0 += NB) {
-    const int64_t jb = std::min<int64_t>(NB, n - j0);
-    const int64_t rest = n - j0 - jb;
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, A, n, j0,
-                       floor_p, info);
-    if (rest > 0) {
-      hipLaunchKernelGGL(k_chol_trsm, dim3((unsigned)((rest + 63) / 64)),
-                         dim3(64), 0, s, A, n, j0, info);
-      const int64_t T = (rest + NB - 1) / NB;
-      hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(T * (T + 1) / 2)),
-                         dim3(256), 0, s, A, n, j0, info);
-    }
+  for (int64_t j0 = 0; j0 < n; j0 += NBF) {
+    const int64_t jb = std::min<int64_t>(NBF, n - j0);
+    const int64_t rest = nrows - j0 - jb;   // >= 1: the g row
+    hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)(1 + (rest + 63) / 64)),
+                       dim3(64), 0, s, A, n, nrows, j0, floor_p, info);
+    const int64_t T = (rest + TILE - 1) / TILE;
+    hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(T * (T + 1) / 2)),
+                       dim3(256), 0, s, A, n, nrows, j0, info);
   }
-  for (int64_t j0 = 0; j0 < n; j0 += NB) {
-    const int64_t jb = std::min<int64_t>(NB, n - j0);
-    const int64_t rest = n - j0 - jb;
-    const unsigned gr = (unsigned)std::max<int64_t>(1, (rest + 255) / 256);
-    hipLaunchKernelGGL(k_chol_fwd, dim3(gr), dim3(256), 0, s, A, n, j0, y, z,
-                       info);
-  }
-  const int64_t last = ((n - 1) / NB) * NB;
-  for (int64_t j0 = last; j0 >= 0; j0 -= NB) {
+  MNL_HIP(c, hipMemcpyAsync(z, A + n * n, size_t(n) * 8,
+                            hipMemcpyDeviceToDevice, s));
+  const int64_t last = ((n - 1) / NBS) * NBS;
+  for (int64_t j0 = last; j0 >= 0; j0 -= NBS) {
     const unsigned gr = (unsigned)std::max<int64_t>(1, (j0 + 255) / 256);
     hipLaunchKernelGGL(k_chol_bwd, dim3(gr), dim3(256), 0, s, A, n, j0, z,
                        delta, info);

@@ -38,39 +38,44 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int kThreads = 256;
-constexpr int kRows = 64;        // rows per workgroup tile (4 waves x 16)
-constexpr int kTN = 4;           // 16-column MFMA tiles per wave
-constexpr int kCols = 16 * kTN;  // columns per workgroup tile
-constexpr int kMaxCols = 128;    // staged alternatives per BB row tile
+constexpr int kThreads = 256;    // small kernels
+constexpr int kMaxCols = 512;    // staged alternatives per BB row tile
 
 enum TileType { T_BB = 0, T_XG = 1 };
 
 struct Tile {
   int32_t type, row0, col0, split;
-  int32_t obs0, obs1, pad0, pad1;
+  int32_t obs0, obs1, tn, pad1;   // tn: 16-column MFMA tiles of this tile
 };
 
 // MFMA traits --------------------------------------------------------------
+// T: staged input type; OT: operand type in LDS; KCB / KCX: most
+// observations per round for BB / XG tiles (a multiple of KSTEP, the
+// observations per MFMA); TN: most 16-column MFMA tiles per wave; NW: waves
+// per workgroup (16 rows each), chosen so that accumulators plus operands
+// fit the register file at NW / 4 waves per SIMD.
 template <int PREC> struct MF;
 template <> struct MF<0> {
-  using T = double;       // staged operand type
+  using T = double;
+  using OT = double;
   using Acc = d4;
-  static constexpr int KSTEP = 4, KC = 16;
+  static constexpr int KSTEP = 4, KCB = 16, KCX = 16, TN = 8, NW = 16;
   __device__ static int out_row(int l, int r) { return (l >> 4) + 4 * r; }
   __device__ static Acc zero() { return Acc{0, 0, 0, 0}; }
 };
 template <> struct MF<1> {
   using T = float;
+  using OT = float;
   using Acc = f4;
-  static constexpr int KSTEP = 4, KC = 32;
+  static constexpr int KSTEP = 4, KCB = 32, KCX = 16, TN = 16, NW = 8;
   __device__ static int out_row(int l, int r) { return 4 * (l >> 4) + r; }
   __device__ static Acc zero() { return Acc{0, 0, 0, 0}; }
 };
 template <> struct MF<2> {
   using T = float;
+  using OT = __bf16;
   using Acc = f4;
-  static constexpr int KSTEP = 32, KC = 64;
+  static constexpr int KSTEP = 32, KCB = 64, KCX = 32, TN = 16, NW = 8;
   __device__ static int out_row(int l, int r) { return 4 * (l >> 4) + r; }
   __device__ static Acc zero() { return Acc{0, 0, 0, 0}; }
 };
@@ -84,18 +89,17 @@ struct HessDev {
   // BB tables
   const int32_t *bb_cols;    // [n_row_tiles][kMaxCols]
   const int32_t *bb_ncol;    // [n_row_tiles]
-  const uint32_t *bb_row;    // per pair row: ln | lm << 8 | diag << 16 | valid << 17
-  const uint32_t *bb_combo;  // per combo col: a | b << 16 (0xffffffff = pad)
+  const uint32_t *bb_row;    // per pair row: ln | lm << 12 | diag << 24 | valid << 25
+  const uint32_t *bb_combo;  // per combo col: a | b << 16
   int64_t bb_M, bb_N;        // padded partial dims
   int64_t xg_M, xg_N;
   void *part_bb, *part_xg;   // [S][M][N] accumulator type
   int64_t nrow_bb, ncombo;   // valid rows / cols
   int64_t nrow_xg, ncol_xg;
+  int kc_bb, kc_xg;          // observations per round
+  int pstride_bb;            // staged P columns per observation (BB)
+  int bb_full;               // BB stages whole P rows (K <= kMaxCols)
 };
-
-template <int PREC>
-__device__ inline typename MF<PREC>::Acc mfma_step(
-    typename MF<PREC>::Acc c, const float *av, const float *bv);
 
 template <typename T>
 __device__ inline T ldg_op(const double *p64, const float *p32, int64_t idx);
@@ -110,215 +114,254 @@ __device__ inline float ldg_op<float>(const double *p64, const float *p32,
   return p32 ? p32[idx] : (float)p64[idx];
 }
 
-// Generated-operand GEMM over a tile list.
+__host__ __device__ constexpr int align16(int bytes) {
+  return (bytes + 15) & ~15;
+}
+
+// LDS layout of one workgroup (bytes); shared by the kernel and the host.
+// The raw region is P columns, X, Z and w of one round, back to back.
+struct TileLds {
+  int raw_p, raw_x, raw_z, raw_w, tab, opa, opb, total;
+};
+
 template <int PREC>
-__global__ __launch_bounds__(kThreads) void k_hess_tiles(HessDev H) {
+__host__ __device__ inline TileLds tile_lds(int type, int KC, int K, int p,
+                                            int a, int bn, int pcols) {
   using M = MF<PREC>;
+  constexpr int kRows = 16 * M::NW;
+  const int tsz = sizeof(typename M::T), osz = sizeof(typename M::OT);
+  const int kp = PREC == 2 ? KC + 8 : KC;   // padded k extent (bf16 rows)
+  TileLds L;
+  int o = 0;
+  L.raw_p = o; o += KC * pcols * tsz;
+  L.raw_x = o; o += KC * p * tsz;
+  L.raw_z = o; o += (type == 0 ? 0 : KC * K * a * tsz);
+  L.raw_w = o; o = align16(o + KC * tsz);
+  L.tab = o;   o = align16(o + (kRows + bn) * 4);
+  L.opa = o;   o = align16(o + kRows * kp * osz);
+  L.opb = o;   o = align16(o + bn * kp * osz);
+  L.total = o;
+  return L;
+}
+
+// Generated-operand GEMM over a tile list.  Per round of KC observations:
+// the raw inputs (P columns, X, Z, w) sit in LDS; the workgroup forms the
+// A tile (64 rows x KC) and the B tile (16 tn columns x KC) in the MFMA
+// operand type, then each wave runs 16 rows x 16 tn columns of MFMAs from
+// LDS.  Several workgroups share a CU, so one's loads overlap another's
+// MFMAs.
+template <int PREC>
+__global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
+  using M = MF<PREC>;
+  constexpr int kRows = 16 * M::NW, NT = 64 * M::NW;
   using T = typename M::T;
+  using OT = typename M::OT;
+  constexpr int TNM = M::TN;
   extern __shared__ double smd[];
-  T *sm = reinterpret_cast<T *>(smd);
+  char *smb = reinterpret_cast<char *>(smd);
   const Tile tile = H.tiles[blockIdx.x];
   const Dims d = H.d;
   const int K = d.K, p = d.p, a = d.a;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  constexpr int KC = M::KC;
-  const int lrow = 16 * wv + (lane & 15);      // generation row in tile
-  const int row = tile.row0 + lrow;
-  typename M::Acc acc[kTN];
-#pragma unroll
-  for (int t = 0; t < kTN; ++t) acc[t] = M::zero();
+  const int tn = tile.tn, bn = 16 * tn;
+  const bool is_bb = tile.type == T_BB;
+  const int KC = is_bb ? H.kc_bb : H.kc_xg;
+  const int kp = PREC == 2 ? KC + 8 : KC;
+  const TileLds L = tile_lds<PREC>(tile.type, KC, K, p, a, bn,
+                                   is_bb ? H.pstride_bb : K);
+  const T *Ps = reinterpret_cast<const T *>(smb + L.raw_p);
+  const T *Xs = reinterpret_cast<const T *>(smb + L.raw_x);
+  const T *Zs = reinterpret_cast<const T *>(smb + L.raw_z);
+  const T *Ws = reinterpret_cast<const T *>(smb + L.raw_w);
+  uint32_t *tab = reinterpret_cast<uint32_t *>(smb + L.tab);
+  OT *opa = reinterpret_cast<OT *>(smb + L.opa);
+  OT *opb = reinterpret_cast<OT *>(smb + L.opb);
+  const int pstride = is_bb ? H.pstride_bb : K;
 
-  if (tile.type == T_BB) {
+  // tile tables: BB row info and feature pairs, cached in LDS
+  int ncol = K;
+  const int32_t *cols = nullptr;
+  if (is_bb) {
     const int rt = tile.row0 / kRows;
-    const int ncol = H.bb_ncol[rt];
-    const int32_t *cols = H.bb_cols + int64_t(rt) * kMaxCols;
-    // LDS: Ps[KC][kMaxCols], Xs[KC][p], ws[KC]
-    T *Ps = sm;
-    T *Xs = Ps + KC * kMaxCols;
-    T *Ws = Xs + KC * p;
-    const uint32_t rinfo = (row < H.nrow_bb) ? H.bb_row[row] : 0u;
-    const int ln = rinfo & 0xff, lm = (rinfo >> 8) & 0xff;
-    const T dg = (rinfo >> 16) & 1 ? T(1) : T(0);
-    const bool rvalid = (rinfo >> 17) & 1;
-    int ca[kTN], cb[kTN];
-#pragma unroll
-    for (int t = 0; t < kTN; ++t) {
-      const int col = tile.col0 + 16 * t + (lane & 15);
-      uint32_t ci = (col < H.ncombo) ? H.bb_combo[col] : 0xffffffffu;
-      ca[t] = (ci == 0xffffffffu) ? -1 : int(ci & 0xffff);
-      cb[t] = (ci == 0xffffffffu) ? -1 : int(ci >> 16);
+    ncol = H.bb_ncol[rt];
+    cols = H.bb_cols + int64_t(rt) * kMaxCols;
+    for (int r = tid; r < kRows; r += NT) {
+      const int row = tile.row0 + r;
+      tab[r] = row < H.nrow_bb ? H.bb_row[row] : 0u;
     }
-    for (int i0 = tile.obs0; i0 < tile.obs1; i0 += KC) {
-      const int nobs = min(KC, tile.obs1 - i0);
-      for (int idx = tid; idx < KC * ncol; idx += kThreads) {
-        const int j = idx / ncol, c = idx - j * ncol;
-        Ps[j * kMaxCols + c] =
+    for (int c = tid; c < bn; c += NT) {
+      const int col = tile.col0 + c;
+      tab[kRows + c] = col < H.ncombo ? H.bb_combo[col] : 0xffffffffu;
+    }
+  }
+  __syncthreads();  // tile tables visible to every thread
+  // stage one round of raw inputs (coalesced where the data are contiguous)
+  auto stage = [&](int i0, int nobs) {
+    T *Pw = reinterpret_cast<T *>(smb + L.raw_p);
+    T *Xw = reinterpret_cast<T *>(smb + L.raw_x);
+    T *Zw = reinterpret_cast<T *>(smb + L.raw_z);
+    T *Ww = reinterpret_cast<T *>(smb + L.raw_w);
+    if (is_bb && !H.bb_full) {
+      for (int e = tid; e < KC * ncol; e += NT) {
+        const int j = e / ncol, c = e - j * ncol;
+        Pw[j * pstride + c] =
             j < nobs ? ldg_op<T>(H.P, H.P32, int64_t(i0 + j) * K + cols[c])
                      : T(0);
       }
-      for (int idx = tid; idx < KC * p; idx += kThreads) {
-        const int j = idx / p, f = idx - j * p;
-        Xs[idx] = j < nobs ? T(d.N > 0 ? H.X[int64_t(i0 + j) * p + f] : 0)
-                           : T(0);
-      }
-      for (int j = tid; j < KC; j += kThreads)
-        Ws[j] = j < nobs ? T(H.w ? H.w[i0 + j] : 1.0) : T(0);
-      __syncthreads();
-#pragma unroll
-      for (int ks = 0; ks < KC / M::KSTEP; ++ks) {
-        if constexpr (PREC == 2) {
-          const int jb = ks * 32 + 8 * (lane >> 4);
-          bf8 av;
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const int j = jb + q;
-            float om = rvalid ? Ws[j] * Ps[j * kMaxCols + ln] *
-                                    (dg - Ps[j * kMaxCols + lm])
-                              : 0.0f;
-            av[q] = (__bf16)om;
-          }
-#pragma unroll
-          for (int t = 0; t < kTN; ++t) {
-            bf8 bv;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const int j = jb + q;
-              float xx = ca[t] >= 0 ? Xs[j * p + ca[t]] * Xs[j * p + cb[t]]
-                                    : 0.0f;
-              bv[q] = (__bf16)xx;
-            }
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t],
-                                                             0, 0, 0);
-          }
-        } else {
-          const int j = ks * 4 + (lane >> 4);
-          const T om = rvalid ? Ws[j] * Ps[j * kMaxCols + ln] *
-                                    (dg - Ps[j * kMaxCols + lm])
-                              : T(0);
-#pragma unroll
-          for (int t = 0; t < kTN; ++t) {
-            const T xx = ca[t] >= 0 ? Xs[j * p + ca[t]] * Xs[j * p + cb[t]]
-                                    : T(0);
-            if constexpr (PREC == 0)
-              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(om, xx, acc[t], 0,
-                                                            0, 0);
-            else
-              acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(om, xx, acc[t], 0,
-                                                            0, 0);
-          }
-        }
-      }
-      __syncthreads();
-    }
-  } else {  // T_XG
-    // LDS: Ps[KC][K], Xs[KC][p], Zs[KC][K*a], ws[KC]
-    T *Ps = sm;
-    T *Xs = Ps + KC * K;
-    T *Zs = Xs + KC * p;
-    T *Ws = Zs + KC * K * a;
-    const int64_t nbrow = int64_t(K - 1) * p;
-    // A row: w P_n phi_nf
-    int an = 0, af = 0;
-    bool arow_z = false, avalid = row < H.nrow_xg;
-    if (avalid) {
-      if (row < nbrow) {
-        an = 1 + row / p;
-        af = row - (an - 1) * p;
-      } else {
-        const int r2 = int(row - nbrow);
-        an = r2 / a;
-        af = r2 - an * a;
-        arow_z = true;
-      }
-    }
-    int bm[kTN], bc[kTN];
-#pragma unroll
-    for (int t = 0; t < kTN; ++t) {
-      const int col = tile.col0 + 16 * t + (lane & 15);
-      if (col < H.ncol_xg) {
-        bm[t] = col / a;
-        bc[t] = col - bm[t] * a;
-      } else {
-        bm[t] = -1;
-        bc[t] = 0;
-      }
-    }
-    for (int i0 = tile.obs0; i0 < tile.obs1; i0 += KC) {
-      const int nobs = min(KC, tile.obs1 - i0);
-      for (int idx = tid; idx < KC * K; idx += kThreads) {
-        const int j = idx / K;
-        Ps[idx] = j < nobs ? ldg_op<T>(H.P, H.P32, int64_t(i0) * K + idx)
-                           : T(0);
-      }
-      for (int idx = tid; idx < KC * p; idx += kThreads) {
-        const int j = idx / p;
-        Xs[idx] = j < nobs ? T(H.X[int64_t(i0) * p + idx]) : T(0);
-      }
-      const int za = K * a;
-      for (int idx = tid; idx < KC * za; idx += kThreads) {
-        const int j = idx / za;
-        Zs[idx] = j < nobs ? T(H.Z[int64_t(i0) * za + idx]) : T(0);
-      }
-      for (int j = tid; j < KC; j += kThreads)
-        Ws[j] = j < nobs ? T(H.w ? H.w[i0 + j] : 1.0) : T(0);
-      __syncthreads();
-#pragma unroll
-      for (int ks = 0; ks < KC / M::KSTEP; ++ks) {
-        if constexpr (PREC == 2) {
-          const int jb = ks * 32 + 8 * (lane >> 4);
-          bf8 av;
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const int j = jb + q;
-            float v = 0.0f;
-            if (avalid)
-              v = Ws[j] * Ps[j * K + an] *
-                  (arow_z ? Zs[(j * K + an) * a + af] : Xs[j * p + af]);
-            av[q] = (__bf16)v;
-          }
-#pragma unroll
-          for (int t = 0; t < kTN; ++t) {
-            bf8 bv;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const int j = jb + q;
-              float v = bm[t] >= 0
-                            ? Ps[j * K + bm[t]] * Zs[(j * K + bm[t]) * a + bc[t]]
-                            : 0.0f;
-              bv[q] = (__bf16)v;
-            }
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t],
-                                                             0, 0, 0);
-          }
-        } else {
-          const int j = ks * 4 + (lane >> 4);
-          T av = T(0);
-          if (avalid)
-            av = Ws[j] * Ps[j * K + an] *
-                 (arow_z ? Zs[(j * K + an) * a + af] : Xs[j * p + af]);
-#pragma unroll
-          for (int t = 0; t < kTN; ++t) {
-            const T bv = bm[t] >= 0
-                             ? Ps[j * K + bm[t]] * Zs[(j * K + bm[t]) * a + bc[t]]
+    } else if (is_bb) {
+      for (int e = tid; e < KC * K; e += NT)
+        Pw[e] = e < nobs * K ? ldg_op<T>(H.P, H.P32, int64_t(i0) * K + e)
                              : T(0);
-            if constexpr (PREC == 0)
-              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0,
-                                                            0, 0);
-            else
-              acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0,
-                                                            0, 0);
+    } else {
+      for (int e = tid; e < KC * K; e += NT)
+        Pw[e] = e < nobs * K ? ldg_op<T>(H.P, H.P32, int64_t(i0) * K + e)
+                             : T(0);
+      const int za = K * a;
+      for (int e = tid; e < KC * za; e += NT)
+        Zw[e] = e < nobs * za ? T(H.Z[int64_t(i0) * za + e]) : T(0);
+    }
+    for (int e = tid; e < KC * p; e += NT)
+      Xw[e] = e < nobs * p ? T(H.X[int64_t(i0) * p + e]) : T(0);
+    for (int e = tid; e < KC; e += NT)
+      Ww[e] = e < nobs ? (H.w ? T(H.w[i0 + e]) : T(1)) : T(0);
+  };
+
+  typename M::Acc acc[TNM];
+#pragma unroll
+  for (int t = 0; t < TNM; ++t) acc[t] = M::zero();
+
+  stage(tile.obs0, min(KC, tile.obs1 - tile.obs0));
+  __syncthreads();
+  // per-thread operand roles, fixed for the tile (no division in the loop)
+  const int nb_rows = int(int64_t(K - 1) * p);
+  const int ra = tid & (kRows - 1), ka0 = tid / kRows;  // NT / kRows = 4
+  bool a_ok = false, a_z = false;
+  int a_ln = 0, a_lm = 0, a_f = 0;
+  T a_dg = T(0);
+  if (is_bb) {
+    const uint32_t ri = tab[ra];
+    a_ok = (ri >> 25) & 1;
+    a_ln = ri & 0xfff;
+    a_lm = (ri >> 12) & 0xfff;
+    a_dg = (ri >> 24) & 1 ? T(1) : T(0);
+  } else {
+    const int row = tile.row0 + ra;
+    if (row < H.nrow_xg) {
+      a_ok = true;
+      if (row < nb_rows) {
+        a_ln = 1 + row / p;
+        a_f = row - (a_ln - 1) * p;
+      } else {
+        const int r2 = row - nb_rows;
+        a_ln = r2 / a;
+        a_f = r2;
+        a_z = true;
+      }
+    }
+  }
+  // B: kbs threads share a column when bn divides the workgroup
+  const int kbs = (NT % bn == 0) ? NT / bn : 1;
+  const int cbx = (NT % bn == 0) ? tid % bn : tid;
+  const int kb0 = (NT % bn == 0) ? tid / bn : 0;
+  bool b_ok = false;
+  int b_f1 = 0, b_f2 = 0;
+  if (cbx < bn) {
+    if (is_bb) {
+      const uint32_t ci = tab[kRows + cbx];
+      b_ok = ci != 0xffffffffu;
+      b_f1 = int(ci & 0xffff);
+      b_f2 = int(ci >> 16);
+    } else {
+      const int col = tile.col0 + cbx;
+      b_ok = col < H.ncol_xg;
+      b_f1 = col / a;
+      b_f2 = col;
+    }
+  }
+  for (int i0 = tile.obs0; i0 < tile.obs1; i0 += KC) {
+    // ---- form the operand tiles for this round ------------------------------
+    // A: thread -> row ra, observations ka0, ka0 + 4, ...
+    if (a_ok) {
+      for (int k = ka0; k < KC; k += NT / kRows) {
+        T v;
+        if (is_bb)
+          v = Ws[k] * Ps[k * pstride + a_ln] * (a_dg - Ps[k * pstride + a_lm]);
+        else
+          v = Ws[k] * Ps[k * pstride + a_ln] *
+              (a_z ? Zs[k * K * a + a_f] : Xs[k * p + a_f]);
+        if constexpr (PREC == 2) opa[ra * kp + k] = (__bf16)v;
+        else opa[k * kRows + ra] = v;
+      }
+    } else {
+      for (int k = ka0; k < KC; k += NT / kRows) {
+        if constexpr (PREC == 2) opa[ra * kp + k] = (__bf16)0.0f;
+        else opa[k * kRows + ra] = OT(0);
+      }
+    }
+    // B: thread -> column cbx, observations kb0, kb0 + kbs, ...
+    if (cbx < bn) {
+      for (int k = kb0; k < KC; k += kbs) {
+        T v = T(0);
+        if (b_ok) {
+          if (is_bb) v = Xs[k * p + b_f1] * Xs[k * p + b_f2];
+          else v = Ps[k * pstride + b_f1] * Zs[k * K * a + b_f2];
+        }
+        if constexpr (PREC == 2) opb[cbx * kp + k] = (__bf16)v;
+        else opb[k * bn + cbx] = v;
+      }
+    }
+    __syncthreads();
+
+    // ---- MFMAs from LDS --------------------------------------------------------
+    const int i1 = i0 + KC;
+    const bool more = i1 < tile.obs1;
+    const int nobs1 = more ? min(KC, tile.obs1 - i1) : 0;
+
+    const int arow = 16 * wv + (lane & 15);
+    if constexpr (PREC == 2) {
+      for (int ks = 0; ks < KC / 32; ++ks) {
+        const int kb = 32 * ks + 8 * (lane >> 4);
+        const bf8 av = *reinterpret_cast<const bf8 *>(opa + arow * kp + kb);
+        const OT *bp = opb + (lane & 15) * kp + kb;
+#pragma unroll
+        for (int t = 0; t < TNM; ++t) {
+          if (t < tn) {
+            const bf8 bv = *reinterpret_cast<const bf8 *>(bp + 16 * t * kp);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t],
+                                                             0, 0, 0);
           }
         }
       }
-      __syncthreads();
+    } else {
+#pragma unroll 4
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        const int k = 4 * ks + (lane >> 4);
+        const OT av = opa[k * kRows + arow];
+        const OT *bp = opb + k * bn + (lane & 15);
+#pragma unroll
+        for (int t = 0; t < TNM; ++t) {
+          if (t < tn) {
+            if constexpr (PREC == 0)
+              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bp[16 * t],
+                                                            acc[t], 0, 0, 0);
+            else
+              acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bp[16 * t],
+                                                            acc[t], 0, 0, 0);
+          }
+        }
+      }
     }
+    // the raw region is free since the operand tiles were formed
+    if (more) stage(i1, nobs1);
+    // every wave is done with the operand tiles and the next round is staged
+    __syncthreads();
   }
 
   // epilogue: this split's partial tile
   using AccT = typename std::conditional<PREC == 0, double, float>::type;
   AccT *part;
   int64_t Mp, Np;
-  if (tile.type == T_BB) {
+  if (is_bb) {
     part = reinterpret_cast<AccT *>(H.part_bb);
     Mp = H.bb_M;
     Np = H.bb_N;
@@ -330,12 +373,14 @@ __global__ __launch_bounds__(kThreads) void k_hess_tiles(HessDev H) {
   AccT *base = part + (int64_t(tile.split) * Mp + tile.row0 + 16 * wv) * Np +
                tile.col0;
 #pragma unroll
-  for (int t = 0; t < kTN; ++t) {
+  for (int t = 0; t < TNM; ++t) {
+    if (t < tn) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int orow = M::out_row(lane, r);
-      const int ocol = 16 * t + (lane & 15);
-      base[int64_t(orow) * Np + ocol] = acc[t][r];
+      for (int r = 0; r < 4; ++r) {
+        const int orow = M::out_row(lane, r);
+        const int ocol = 16 * t + (lane & 15);
+        base[int64_t(orow) * Np + ocol] = acc[t][r];
+      }
     }
   }
 }
@@ -343,10 +388,13 @@ __global__ __launch_bounds__(kThreads) void k_hess_tiles(HessDev H) {
 // Per-alternative sums for the delta_nm parts and the alpha blocks:
 //   out[n][r][s] = sum_i w_i P_in L_in[r] R_in[s]
 // with L = (x_i, z_in, y_in - ybar_i), R = (z_in, y_in - ybar_i).
-// Workgroup: alternatives [n0, n0 + nb) x one observation range; each
-// thread owns up to kJ outputs.
-constexpr int kJ = 8;
+// Workgroup: nb alternatives x one observation range.  Per tile of kAltTB
+// observations the raw X, Z, Y - Ybar and w P of those alternatives are
+// staged in LDS (contiguous slices); each thread owns kAltRB rows r of one
+// alternative against all nr columns, accumulated in registers.
 constexpr int kAltTB = 16;
+constexpr int kAltRB = 4;
+constexpr int kAltNR = 16;   // most a + g handled
 
 __global__ __launch_bounds__(kThreads) void k_hess_alt(
     Dims d, const double *X, const double *Y, const double *Z,
@@ -359,64 +407,91 @@ __global__ __launch_bounds__(kThreads) void k_hess_alt(
   const int nbe = min(nb, K - n0);
   const int64_t i_begin = int64_t(blockIdx.y) * obs_chunk;
   const int64_t i_end = min(d.N, i_begin + obs_chunk);
-  // LDS: L[kAltTB][nb][nl] (u * L) and R[kAltTB][nb][nr]
-  double *Ls = sm;
-  double *Rs = Ls + kAltTB * nb * nl;
+  // LDS: Xs[TB][p], Zs[TB][nb][a], Ys[TB][nb][g] (centred), Us[TB][nb]
+  double *Xs = sm;
+  double *Zs = Xs + kAltTB * p;
+  double *Ys = Zs + kAltTB * nb * a;
+  double *Us = Ys + kAltTB * nb * g;
   const int tid = threadIdx.x;
-  const int nout = nbe * nl * nr;
-  double acc[kJ];
+  const int nrb = (nl + kAltRB - 1) / kAltRB;
+  const int q = tid / nrb, rb = tid - q * nrb;
+  const bool own = q < nbe;
+  const int r0 = rb * kAltRB;
+  double acc[kAltRB][kAltNR];
 #pragma unroll
-  for (int j = 0; j < kJ; ++j) acc[j] = 0.0;
+  for (int i = 0; i < kAltRB; ++i)
+#pragma unroll
+    for (int j = 0; j < kAltNR; ++j) acc[i][j] = 0.0;
+
   for (int64_t i0 = i_begin; i0 < i_end; i0 += kAltTB) {
     const int nobs = (int)min<int64_t>(kAltTB, i_end - i0);
-    // stage u*L and R for every (obs, alternative)
-    for (int idx = tid; idx < kAltTB * nbe; idx += kThreads) {
-      const int j = idx / nbe, q = idx - j * nbe;
-      const int n = n0 + q;
-      double *L = Ls + (j * nb + q) * nl;
-      double *Rr = Rs + (j * nb + q) * nr;
-      if (j >= nobs) {
-        for (int r = 0; r < nl; ++r) L[r] = 0.0;
-        for (int r = 0; r < nr; ++r) Rr[r] = 0.0;
-        continue;
-      }
-      const int64_t i = i0 + j;
-      const double u = (w ? w[i] : 1.0) * P[i * K + n];
-      for (int f = 0; f < p; ++f) L[f] = u * X[i * p + f];
-      for (int c = 0; c < a; ++c) {
-        const double z = Z[(i * K + n) * a + c];
-        L[p + c] = u * z;
-        Rr[c] = z;
-      }
-      for (int c = 0; c < g; ++c) {
-        const double yc = Y[(i * K + n) * g + c] - Ybar[i * g + c];
-        L[p + a + c] = u * yc;
-        Rr[a + c] = yc;
-      }
+    for (int e = tid; e < kAltTB * p; e += kThreads)
+      Xs[e] = e < nobs * p ? X[i0 * p + e] : 0.0;
+    for (int e = tid; e < kAltTB * nb * a; e += kThreads) {
+      const int j = e / (nb * a), rem = e - j * nb * a;
+      const int qq = rem / a;
+      Zs[e] = (j < nobs && qq < nbe) ? Z[(i0 + j) * K * a + n0 * a + rem] : 0.0;
+    }
+    for (int e = tid; e < kAltTB * nb * g; e += kThreads) {
+      const int j = e / (nb * g), rem = e - j * nb * g;
+      const int qq = rem / g, c = rem - qq * g;
+      Ys[e] = (j < nobs && qq < nbe)
+                  ? Y[(i0 + j) * K * g + n0 * g + rem] - Ybar[(i0 + j) * g + c]
+                  : 0.0;
+    }
+    for (int e = tid; e < kAltTB * nb; e += kThreads) {
+      const int j = e / nb, qq = e - j * nb;
+      Us[e] = (j < nobs && qq < nbe)
+                  ? (w ? w[i0 + j] : 1.0) * P[(i0 + j) * K + n0 + qq]
+                  : 0.0;
     }
     __syncthreads();
+    if (own) {
+      for (int j = 0; j < nobs; ++j) {
+        const double u = Us[j * nb + q];
+        const double *zq = Zs + (j * nb + q) * a;
+        const double *yq = Ys + (j * nb + q) * g;
+        double Rv[kAltNR];
 #pragma unroll
-    for (int jj = 0; jj < kJ; ++jj) {
-      const int o = tid + jj * kThreads;
-      if (o < nout) {
-        const int q = o / (nl * nr);
-        const int rem = o - q * nl * nr;
-        const int r = rem / nr, s = rem - (rem / nr) * nr;
-        double sacc = acc[jj];
-        for (int j = 0; j < nobs; ++j)
-          sacc = fma(Ls[(j * nb + q) * nl + r], Rs[(j * nb + q) * nr + s],
-                     sacc);
-        acc[jj] = sacc;
+        for (int s2 = 0; s2 < kAltNR; ++s2)
+          Rv[s2] = s2 < a ? zq[s2] : (s2 < nr ? yq[s2 - a] : 0.0);
+#pragma unroll
+        for (int i = 0; i < kAltRB; ++i) {
+          const int r = r0 + i;
+          double lv = 0.0;
+          if (r < p) lv = Xs[j * p + r];
+          else if (r < p + a) lv = zq[r - p];
+          else if (r < nl) lv = yq[r - p - a];
+          lv *= u;
+#pragma unroll
+          for (int s2 = 0; s2 < kAltNR; ++s2)
+            acc[i][s2] = fma(lv, Rv[s2], acc[i][s2]);
+        }
       }
     }
     __syncthreads();
   }
-  double *ob = out + (int64_t(blockIdx.y) * K + n0) * nl * nr;
+  if (own) {
+    double *ob = out + ((int64_t(blockIdx.y) * K + n0 + q) * nl) * nr;
 #pragma unroll
-  for (int jj = 0; jj < kJ; ++jj) {
-    const int o = tid + jj * kThreads;
-    if (o < nout) ob[o] = acc[jj];
+    for (int i = 0; i < kAltRB; ++i) {
+      const int r = r0 + i;
+      if (r >= nl) continue;
+#pragma unroll
+      for (int s2 = 0; s2 < kAltNR; ++s2)
+        if (s2 < nr) ob[r * nr + s2] = acc[i][s2];
+    }
   }
+}
+
+// sum the observation splits of the per-alternative sums in a fixed order
+__global__ void k_alt_reduce(const double *alt, int S, int64_t n,
+                             double *red) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double v = 0.0;
+  for (int s2 = 0; s2 < S; ++s2) v += alt[int64_t(s2) * n + e];
+  red[e] = v;
 }
 
 // ---- assembly into H (Hessian sign) ----------------------------------------------
@@ -527,6 +602,7 @@ struct Plan {
   int64_t bb_M = 0, bb_N = 0, xg_M = 0, xg_N = 0;
   int64_t nrow_bb = 0, ncombo = 0, nrow_xg = 0, ncol_xg = 0;
   size_t lds = 0;
+  int kc_bb = 4, kc_xg = 4, pstride_bb = 1, bb_full = 0;
   // alt kernel
   int alt_nb = 1, alt_S = 1;
   int64_t alt_chunk = 0;
@@ -559,8 +635,25 @@ int build_plan(Ctx *c, const Dims &d, int prec, Plan **out) {
   Plan *pl = new Plan;
   pl->d = d;
   pl->prec = prec;
-  const int KC = prec == 0 ? MF<0>::KC : (prec == 1 ? MF<1>::KC : MF<2>::KC);
+  const int KSTEP = prec == 2 ? 32 : 4;
+  const int kRows = 16 * (prec == 0 ? MF<0>::NW : (prec == 1 ? MF<1>::NW : MF<2>::NW));
+  const int NT = 4 * kRows;
+  const int KCB0 = prec == 0 ? MF<0>::KCB : (prec == 1 ? MF<1>::KCB : MF<2>::KCB);
+  const int KCX0 = prec == 0 ? MF<0>::KCX : (prec == 1 ? MF<1>::KCX : MF<2>::KCX);
+  const int TNMAX = prec == 0 ? MF<0>::TN : (prec == 1 ? MF<1>::TN : MF<2>::TN);
   const int K = d.K, p = d.p, a = d.a, g = d.g;
+  // column tiling: as few 16-column MFMA tiles of padding as possible with
+  // at most TNMAX per workgroup tile
+  auto col_tiling = [&](int64_t ncols, int *tn_out) -> int64_t {
+    const int64_t n16 = (ncols + 15) / 16;
+    if (n16 == 0) {
+      *tn_out = 1;
+      return 0;
+    }
+    const int64_t nct = (n16 + TNMAX - 1) / TNMAX;
+    *tn_out = int((n16 + nct - 1) / nct);
+    return nct;
+  };
 
   // BB rows: pairs n <= m over alternatives 1..K-1, row-major
   std::vector<int32_t> pair_nm;
@@ -572,16 +665,27 @@ int build_plan(Ctx *c, const Dims &d, int prec, Plan **out) {
     for (int fb = fa; fb < p; ++fb) combo.push_back(uint32_t(fa) | (uint32_t(fb) << 16));
   const int64_t ncombo = int64_t(combo.size());
   const int64_t nrt_bb = (nrow_bb + kRows - 1) / kRows;
-  const int64_t nct_bb = (ncombo + kCols - 1) / kCols;
+  int tn_bb = 1;
+  const int64_t nct_bb = col_tiling(ncombo, &tn_bb);
+  const int cw_bb = 16 * tn_bb;
   std::vector<int32_t> bb_cols(std::max<int64_t>(nrt_bb, 1) * kMaxCols, 0);
   std::vector<int32_t> bb_ncol(std::max<int64_t>(nrt_bb, 1), 0);
   std::vector<uint32_t> bb_row(std::max<int64_t>(nrow_bb, 1), 0);
+  pl->bb_full = K <= kMaxCols ? 1 : 0;
+  if (K > 4095) {
+    delete pl;
+    return set_error(c, MNL_ERR_UNSUPPORTED, "Hessian tiles need K < 4096");
+  }
   for (int64_t t = 0; t < nrt_bb; ++t) {
     std::vector<int> alts;
     const int64_t r1 = std::min<int64_t>(nrow_bb, (t + 1) * kRows);
-    for (int64_t r = t * kRows; r < r1; ++r) {
-      alts.push_back(pair_nm[r] & 0xffff);
-      alts.push_back(pair_nm[r] >> 16);
+    if (pl->bb_full) {
+      for (int k = 0; k < K; ++k) alts.push_back(k);
+    } else {
+      for (int64_t r = t * kRows; r < r1; ++r) {
+        alts.push_back(pair_nm[r] & 0xffff);
+        alts.push_back(pair_nm[r] >> 16);
+      }
     }
     std::sort(alts.begin(), alts.end());
     alts.erase(std::unique(alts.begin(), alts.end()), alts.end());
@@ -591,95 +695,153 @@ int build_plan(Ctx *c, const Dims &d, int prec, Plan **out) {
       const int n = pair_nm[r] & 0xffff, m = pair_nm[r] >> 16;
       const uint32_t ln = uint32_t(std::lower_bound(alts.begin(), alts.end(), n) - alts.begin());
       const uint32_t lm = uint32_t(std::lower_bound(alts.begin(), alts.end(), m) - alts.begin());
-      bb_row[r] = ln | (lm << 8) | (uint32_t(n == m) << 16) | (1u << 17);
+      bb_row[r] = ln | (lm << 12) | (uint32_t(n == m) << 24) | (1u << 25);
     }
   }
   pl->nrow_bb = nrow_bb;
   pl->ncombo = ncombo;
   pl->bb_M = nrt_bb * kRows;
-  pl->bb_N = nct_bb * kCols;
+  pl->bb_N = std::max<int64_t>(nct_bb * cw_bb, 16);
 
   // XG rows: all alternative-specific coefficients; columns: gamma ones
   const int64_t offg = d.off_gamma();
   const int64_t nrow_xg = a > 0 ? offg + int64_t(K) * a : 0;
   const int64_t ncol_xg = a > 0 ? int64_t(K) * a : 0;
   const int64_t nrt_xg = (nrow_xg + kRows - 1) / kRows;
-  const int64_t nct_xg = (ncol_xg + kCols - 1) / kCols;
+  int tn_xg = 1;
+  const int64_t nct_xg = col_tiling(ncol_xg, &tn_xg);
+  const int cw_xg = 16 * tn_xg;
   pl->nrow_xg = nrow_xg;
   pl->ncol_xg = ncol_xg;
   pl->xg_M = nrt_xg * kRows;
-  pl->xg_N = nct_xg * kCols;
+  pl->xg_N = std::max<int64_t>(nct_xg * cw_xg, 16);
 
   // output tiles, then observation splits
-  std::vector<std::pair<int, std::pair<int, int>>> out_tiles;
+  struct OutTile { int type, row0, col0, tn; };
+  std::vector<OutTile> out_tiles;
   for (int64_t rt = 0; rt < nrt_bb; ++rt)
     for (int64_t ct = 0; ct < nct_bb; ++ct)
-      out_tiles.push_back({T_BB, {int(rt * kRows), int(ct * kCols)}});
+      out_tiles.push_back({T_BB, int(rt * kRows), int(ct * cw_bb), tn_bb});
   for (int64_t rt = 0; rt < nrt_xg; ++rt)
     for (int64_t ct = 0; ct < nct_xg; ++ct) {
-      const int64_t r0 = rt * kRows, c0 = ct * kCols;
+      const int64_t r0 = rt * kRows, c0 = ct * cw_xg;
       // gamma-gamma below the diagonal is mirrored, not computed
-      if (r0 >= offg && r0 > offg + c0 + kCols - 1) continue;
-      out_tiles.push_back({T_XG, {int(r0), int(c0)}});
+      if (r0 >= offg && r0 > offg + c0 + cw_xg - 1) continue;
+      out_tiles.push_back({T_XG, int(r0), int(c0), tn_xg});
     }
   const int64_t nout = int64_t(out_tiles.size());
   int S = 1;
   if (nout > 0) {
-    const int64_t target = 1024;
+    // about two rounds of workgroups over 256 CUs
+    const int64_t target = 512 * 256 / NT;
     S = int(std::max<int64_t>(1, (target + nout - 1) / nout));
-    const int64_t max_s = std::max<int64_t>(1, d.N / 256);
-    S = int(std::min<int64_t>(S, max_s));
+    const int64_t max_s = std::max<int64_t>(1, d.N / 1024);
+    S = int(std::min<int64_t>({int64_t(S), max_s, int64_t(64)}));
+    if (S >= 8) S = S / 8 * 8;
   }
   int64_t chunk = (d.N + S - 1) / S;
-  chunk = (chunk + KC - 1) / KC * KC;
+  const int KCR = std::max(KCB0, KCX0);
+  chunk = (chunk + KCR - 1) / KCR * KCR;
   S = int((d.N + chunk - 1) / chunk);
   pl->S = S;
+  // XCD-aware order: workgroup b runs on XCD b % 8, so the tiles of one
+  // observation split are given ids of one residue and share that XCD's L2
   std::vector<Tile> tiles;
-  for (int s = 0; s < S; ++s)
-    for (auto &ot : out_tiles) {
-      Tile t{};
-      t.type = ot.first;
-      t.row0 = ot.second.first;
-      t.col0 = ot.second.second;
-      t.split = s;
-      t.obs0 = int(s * chunk);
-      t.obs1 = int(std::min<int64_t>(d.N, (s + 1) * chunk));
-      tiles.push_back(t);
+  {
+    std::vector<std::vector<Tile>> q(8);
+    for (int sp = 0; sp < S; ++sp)
+      for (auto &ot : out_tiles) {
+        Tile t{};
+        t.type = ot.type;
+        t.row0 = ot.row0;
+        t.col0 = ot.col0;
+        t.tn = ot.tn;
+        t.split = sp;
+        t.obs0 = int(sp * chunk);
+        t.obs1 = int(std::min<int64_t>(d.N, (sp + 1) * chunk));
+        q[sp % 8].push_back(t);
+      }
+    size_t pos[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    size_t left = size_t(S) * out_tiles.size();
+    while (left) {
+      for (int x = 0; x < 8 && left; ++x) {
+        // an exhausted queue lends its slot to the longest remaining one
+        int src = x;
+        if (pos[src] >= q[src].size()) {
+          size_t best = 0;
+          for (int y = 0; y < 8; ++y)
+            if (q[y].size() - pos[y] > best) { best = q[y].size() - pos[y]; src = y; }
+        }
+        tiles.push_back(q[src][pos[src]++]);
+        --left;
+      }
     }
-  if (d.N > (int64_t(1) << 31) - 1024)
+  }
+  if (d.N > (int64_t(1) << 31) - 1024) {
+    delete pl;
     return set_error(c, MNL_ERR_UNSUPPORTED, "N too large for Hessian tiles");
+  }
   pl->ntiles = int(tiles.size());
 
-  // LDS per workgroup (max over tile kinds)
-  const size_t esz = prec == 0 ? 8 : 4;
-  size_t lds_bb = nrow_bb ? size_t(KC) * (kMaxCols + p + 1) * esz : 0;
-  size_t lds_xg = nrow_xg ? size_t(KC) * (K + p + size_t(K) * a + 1) * esz : 0;
-  pl->lds = std::max(lds_bb, lds_xg);
-  if (pl->lds > 150 * 1024) {
+  // observations per round: as many as the prefetch registers and LDS
+  // allow (a multiple of the MFMA's observation count)
+  int max_ncol = 0;
+  for (int64_t t = 0; t < nrt_bb; ++t) max_ncol = std::max(max_ncol, bb_ncol[t]);
+  pl->pstride_bb = std::max(max_ncol, 1);
+  auto lds_of = [&](int type, int kc, int bn) -> size_t {
+    const int pc = type == T_BB ? pl->pstride_bb : K;
+    if (prec == 0) return tile_lds<0>(type, kc, K, p, a, bn, pc).total;
+    if (prec == 1) return tile_lds<1>(type, kc, K, p, a, bn, pc).total;
+    return tile_lds<2>(type, kc, K, p, a, bn, pc).total;
+  };
+  // observations per round: the largest multiple of the MFMA's observation
+  // count that keeps LDS small enough for several workgroups per CU
+  auto pick_kc = [&](int type, int kc0, int bn) -> int {
+    int kc = kc0;
+    // 16-wave workgroups own a CU; 8-wave ones share it with a second
+    const size_t budget = kRows >= 256 ? size_t(150 * 1024) : size_t(78 * 1024);
+    while (kc > KSTEP && lds_of(type, kc, bn) > budget) kc -= KSTEP;
+    return lds_of(type, kc, bn) > 150 * 1024 ? 0 : kc;
+  };
+  pl->kc_bb = nrow_bb ? pick_kc(T_BB, KCB0, cw_bb) : KSTEP;
+  pl->kc_xg = nrow_xg ? pick_kc(T_XG, KCX0, cw_xg) : KSTEP;
+  if (pl->kc_bb == 0 || pl->kc_xg == 0) {
     delete pl;
-    return set_error(c, MNL_ERR_UNSUPPORTED, "Hessian tile LDS too large");
+    return set_error(c, MNL_ERR_UNSUPPORTED,
+                     "Hessian tile exceeds LDS (p=%d K=%d a=%d)", p, K, a);
   }
+  pl->lds = std::max(nrow_bb ? lds_of(T_BB, pl->kc_bb, cw_bb) : size_t(0),
+                     nrow_xg ? lds_of(T_XG, pl->kc_xg, cw_xg) : size_t(0));
 
   // per-alternative kernel
   pl->need_alt = (a + g) > 0;
   if (pl->need_alt) {
     const int nl = p + a + g, nr = a + g;
-    int nb = std::max(1, (kJ * kThreads) / (nl * nr));
-    nb = std::min(nb, K);
-    while (nb > 1 && size_t(kAltTB) * nb * (nl + nr) * 8 > 64 * 1024) --nb;
-    if (nl * nr > kJ * kThreads) {
+    if (nr > kAltNR) {
       delete pl;
-      return set_error(c, MNL_ERR_UNSUPPORTED, "too many alpha/gamma features");
+      return set_error(c, MNL_ERR_UNSUPPORTED,
+                       "more than %d alternative-varying variables", kAltNR);
     }
+    const int nrb = (nl + kAltRB - 1) / kAltRB;
+    if (nrb > kThreads) {
+      delete pl;
+      return set_error(c, MNL_ERR_UNSUPPORTED, "too many features");
+    }
+    int nb = std::max(1, std::min(kThreads / nrb, K));
+    auto lds_alt = [&](int b2) {
+      return size_t(kAltTB) * (p + size_t(b2) * (a + g + 1)) * 8;
+    };
+    while (nb > 1 && lds_alt(nb) > 64 * 1024) --nb;
     pl->alt_nb = nb;
     const int ngrp = (K + nb - 1) / nb;
     int Sa = std::max(1, 512 / ngrp);
-    Sa = int(std::min<int64_t>(Sa, std::max<int64_t>(1, d.N / 256)));
+    Sa = int(std::min<int64_t>(Sa, std::max<int64_t>(1, d.N / 128)));
     int64_t ch = (d.N + Sa - 1) / Sa;
+    ch = (ch + kAltTB - 1) / kAltTB * kAltTB;
     Sa = int((d.N + ch - 1) / ch);
     pl->alt_S = Sa;
     pl->alt_chunk = ch;
-    pl->alt_lds = size_t(kAltTB) * nb * (nl + nr) * 8;
+    pl->alt_lds = lds_alt(nb);
   }
 
   // device tables
@@ -729,7 +891,8 @@ hipError_t launch_tiles(const Plan &pl, const HessDev &hd, hipStream_t s) {
       reinterpret_cast<const void *>(&k_hess_tiles<PREC>),
       hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_hess_tiles<PREC>, dim3(pl.ntiles), dim3(kThreads),
+  hipLaunchKernelGGL(k_hess_tiles<PREC>, dim3(pl.ntiles),
+                     dim3(64 * MF<PREC>::NW),
                      pl.lds, s, hd);
   return hipGetLastError();
 }
@@ -749,12 +912,12 @@ hipError_t launch_assemble(const Plan &pl, const HessArgs &h, void *pbb,
     const int64_t n = pl.nrow_xg * pl.ncol_xg;
     hipLaunchKernelGGL(k_assemble_xg<AccT>, dim3((unsigned)((n + 255) / 256)),
                        dim3(256), 0, s, d, (const AccT *)pxg, pl.S, pl.xg_M,
-                       pl.xg_N, alt, pl.alt_S, h.H);
+                       pl.xg_N, alt, 1, h.H);
   }
   if (d.g > 0) {
     const int64_t n = d.off_alpha() * d.g + int64_t(d.g) * d.g;
     hipLaunchKernelGGL(k_assemble_alpha, dim3((unsigned)((n + 255) / 256)),
-                       dim3(256), 0, s, d, alt, pl.alt_S, h.H);
+                       dim3(256), 0, s, d, alt, 1, h.H);
   }
   return hipGetLastError();
 }
@@ -769,15 +932,17 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   const size_t bytes_bb = size_t(pl->S) * pl->bb_M * pl->bb_N * asz;
   const size_t bytes_xg = size_t(pl->S) * pl->xg_M * pl->xg_N * asz;
   const int nl = d.p + d.a + d.g, nr = d.a + d.g;
-  const size_t bytes_alt =
-      pl->need_alt ? size_t(pl->alt_S) * d.K * nl * nr * 8 : 0;
+  const size_t n_alt = pl->need_alt ? size_t(d.K) * nl * nr : 0;
+  const size_t bytes_alt = size_t(pl->alt_S) * n_alt * 8;
   const size_t o_xg = (bytes_bb + 255) & ~size_t(255);
   const size_t o_alt = (o_xg + bytes_xg + 255) & ~size_t(255);
+  const size_t o_red = (o_alt + bytes_alt + 255) & ~size_t(255);
   void *ws;
-  MNL_TRY(ws_get(c, S_HPART, o_alt + bytes_alt, &ws));
+  MNL_TRY(ws_get(c, S_HPART, o_red + n_alt * 8 + 256, &ws));
   char *wb = static_cast<char *>(ws);
   void *pbb = wb, *pxg = wb + o_xg;
-  double *alt = reinterpret_cast<double *>(wb + o_alt);
+  double *alt_part = reinterpret_cast<double *>(wb + o_alt);
+  double *alt = reinterpret_cast<double *>(wb + o_red);
 
   if (pl->need_alt) {
     const int ngrp = (d.K + pl->alt_nb - 1) / pl->alt_nb;
@@ -787,7 +952,10 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
                    (int)pl->alt_lds));
     hipLaunchKernelGGL(k_hess_alt, dim3(ngrp, pl->alt_S), dim3(kThreads),
                        pl->alt_lds, s, d, h.X, h.Y, h.Z, h.w, h.P, h.Ybar,
-                       pl->alt_nb, pl->alt_chunk, alt);
+                       pl->alt_nb, pl->alt_chunk, alt_part);
+    hipLaunchKernelGGL(k_alt_reduce, dim3((unsigned)((n_alt + 255) / 256)),
+                       dim3(256), 0, s, alt_part, pl->alt_S, int64_t(n_alt),
+                       alt);
     MNL_HIP(c, hipGetLastError());
   }
   HessDev hd;
@@ -812,6 +980,10 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   hd.ncombo = pl->ncombo;
   hd.nrow_xg = pl->nrow_xg;
   hd.ncol_xg = pl->ncol_xg;
+  hd.kc_bb = pl->kc_bb;
+  hd.kc_xg = pl->kc_xg;
+  hd.pstride_bb = pl->pstride_bb;
+  hd.bb_full = pl->bb_full;
   if (c->ev_ready && pl->ntiles > 0) {
     MNL_HIP(c, hipEventRecord(c->ev_h0, s));
   }

@@ -220,7 +220,8 @@ int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
                 mnl_fit_info *info, int *reason, hipStream_t s) {
   const bool mixed = o.prec != MNL_PREC_FP64;
   void *Hv, *dv, *tv, *sv;
-  MNL_TRY(ws_get(c, S_H, size_t(d.np) * d.np * 8, &Hv));
+  // n_p + 1 rows: the factorisation carries g as an extra row
+  MNL_TRY(ws_get(c, S_H, size_t(d.np + 1) * d.np * 8, &Hv));
   MNL_TRY(ws_get(c, S_DELTA, size_t(d.np) * 8, &dv));
   MNL_TRY(ws_get(c, S_THETA_TRIAL, size_t(d.np) * 8, &tv));
   MNL_TRY(ws_get(c, S_SCAL, 256, &sv));

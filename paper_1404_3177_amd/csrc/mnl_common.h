@@ -107,7 +107,8 @@ int hessian_run(Ctx *c, const HessArgs &a, hipStream_t s);
 void hessian_cache_free(Ctx *c);
 
 // ---- Cholesky and solves ------------------------------------------------------
-// Factor A = -H in place (lower triangle holds L) and solve L L^T delta = g.
+// Factor A = -H in place (lower triangle holds L) and solve L L^T delta = g;
+// A has n + 1 rows of n (row n is scratch for g).
 // info[0] receives 0 or (1 + index of the failed pivot).
 int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
                    double *delta, int32_t *info, hipStream_t s);
