@@ -10,9 +10,10 @@
 //   panel : every workgroup factors the small diagonal block in LDS (one
 //           barrier per column, LDL^T form then scaled), checks the pivots
 //           against the round-off floor n * eps * max_k A_kk (workgroup 0
-//           writes L11 and the failure flag) and solves its 64 rows
-//           x L11^T = a below the panel (one row per thread);
-//   update: A22 -= L21 L21^T on the lower 64x64 tiles, FP64 MFMA.
+//           writes L11 to scratch and the failure flag) and solves its 64
+//           rows x L11^T = a below the panel (one row per thread);
+//   update: puts L11 in place, then A22 -= L21 L21^T on the lower 64x64
+//           tiles, FP64 MFMA.
 // Then L^T delta = z by 64-wide panels from the bottom: each workgroup
 // re-solves the panel's small triangular system itself and updates its
 // share of the remaining right-hand side, so one launch per panel suffices
@@ -70,42 +71,54 @@ __global__ __launch_bounds__(256) void k_floor(const double *A, int64_t n,
 }
 
 // Panel j0 (width jb <= NBF): workgroup b factors the diagonal block and
-// solves rows j0 + jb + 64 (b - 1) .. + 63 (b >= 1).  64 threads.
+// solves rows j0 + jb + 64 (b - 1) .. + 63 (b >= 1).  One wave: lane i
+// keeps row i of the diagonal block in registers; each step broadcasts the
+// finished column through LDS.
 __global__ __launch_bounds__(64) void k_chol_panel(double *A, int64_t n,
                                                    int64_t nrows, int64_t j0,
                                                    const double *floor_p,
+                                                   double *l11,
                                                    int32_t *info) {
   __shared__ double L[NBF][NBF + 1];
-  __shared__ double col[2][NBF];
+  __shared__ double col[NBF];
   if (info[0]) return;
   const int jb = (int)min<int64_t>(NBF, n - j0);
   const int tid = threadIdx.x;
-  for (int e = tid; e < NBF * NBF; e += 64) {
-    const int i = e / NBF, j = e - (e / NBF) * NBF;
-    L[i][j] = (i < jb && j <= i) ? A[(j0 + i) * n + j0 + j] : 0.0;
+  const bool mine = tid < jb;
+  double a[NBF];
+  {
+    const double *src = A + (j0 + (mine ? tid : 0)) * n + j0;
+#pragma unroll
+    for (int j = 0; j < NBF; ++j)
+      a[j] = (mine && j <= tid && j < jb) ? src[j] : 0.0;
   }
-  __syncthreads();
-  // LDL^T: after step k the entries (i, j > k) hold the Schur complement;
-  // column k is final once step k starts (the workgroup is one wave, so the
-  // barriers are cheap)
-  for (int k = 0; k < jb; ++k) {
-    if (tid < jb) col[k & 1][tid] = L[tid][k];
-    __syncthreads();
-    const double dk = col[k & 1][k];
-    const double inv = 1.0 / dk;
-    for (int e = tid; e < NBF * NBF; e += 64) {
-      const int i = e / NBF, j = e - (e / NBF) * NBF;
-      if (j > k && j <= i && i < jb)
-        L[i][j] -= col[k & 1][i] * col[k & 1][j] * inv;
+  // LDL^T on the lower triangle: a[j] of lane i is D_ij, a[i] of lane i d_i
+#pragma unroll
+  for (int k = 0; k < NBF; ++k) {
+    if (k < jb) {
+      if (tid < jb) col[tid] = a[k];
+      __syncthreads();
+      const double inv = 1.0 / col[k];
+      const double lik = a[k] * inv;
+#pragma unroll
+      for (int j = k + 1; j < NBF; ++j)
+        if (j <= tid) a[j] = fma(-lik, col[j], a[j]);
+      __syncthreads();
     }
-    __syncthreads();   // column k + 1 is final before it is read
   }
-  __syncthreads();
-  // pivots d_k = L[k][k]; L_ik = D_ik / sqrt(d_k)
+  // pivots and the scaled factor L_ij = D_ij / sqrt(d_j)
   const double fl = *floor_p;
+  if (tid < jb) col[tid] = a[tid];   // placeholder, replaced below
+  __syncthreads();
+  double dself = 0.0;
+#pragma unroll
+  for (int j = 0; j < NBF; ++j)
+    if (j == tid) dself = a[j];
+  if (tid < jb) col[tid] = dself;
+  __syncthreads();
   bool bad = false;
   for (int k = 0; k < jb; ++k) {
-    const double d = L[k][k];
+    const double d = col[k];
     if (!(d > fl) || !isfinite(d)) {
       bad = true;
       if (blockIdx.x == 0 && tid == 0 && !info[0]) info[0] = int(j0 + k + 1);
@@ -113,52 +126,64 @@ __global__ __launch_bounds__(64) void k_chol_panel(double *A, int64_t n,
     }
   }
   if (bad) return;
-  __syncthreads();
-  for (int e = tid; e < NBF * NBF; e += 64) {
-    const int i = e / NBF, j = e - (e / NBF) * NBF;
-    if (i < jb && j < i) L[i][j] /= sqrt(L[j][j]);
+  if (mine) {
+#pragma unroll
+    for (int j = 0; j < NBF; ++j) {
+      if (j < tid) L[tid][j] = a[j] / sqrt(col[j]);
+      else if (j == tid) L[tid][j] = sqrt(col[j]);
+      else L[tid][j] = 0.0;
+    }
+  } else if (tid < NBF) {
+    // padding rows of a narrow last panel: identity, so the solve below
+    // needs no bounds on the column index
+#pragma unroll
+    for (int j = 0; j < NBF; ++j) L[tid][j] = (j == tid) ? 1.0 : 0.0;
   }
   __syncthreads();
-  if (tid < jb) L[tid][tid] = sqrt(L[tid][tid]);
-  __syncthreads();
   if (blockIdx.x == 0) {
-    for (int e = tid; e < jb * jb; e += 64) {
-      const int i = e / jb, j = e - (e / jb) * jb;
-      if (j <= i) A[(j0 + i) * n + j0 + j] = L[i][j];
+    // L11 goes to scratch, not into A: other workgroups of this launch may
+    // still be reading the original diagonal block; the next launch
+    // (k_chol_update) copies it into place
+    if (mine) {
+#pragma unroll
+      for (int j = 0; j < NBF; ++j) l11[tid * NBF + j] = L[tid][j];
     }
     return;
   }
-  // rows below: x L11^T = a  ->  x_c = (a_c - sum_{k<c} x_k L_ck) / L_cc
+  // rows below: x L11^T = a, column by column; each lane's row sits in LDS
+  // (padded columns stay zero: their row of L11 is the identity)
+  __shared__ double Xr[64][NBF + 1];
   const int64_t r = j0 + jb + int64_t(blockIdx.x - 1) * 64 + tid;
-  if (r >= nrows) return;
-  double x[NBF];
-  double *row = A + r * n + j0;
-#pragma unroll
-  for (int c = 0; c < NBF; ++c) x[c] = c < jb ? row[c] : 0.0;
-#pragma unroll
-  for (int c = 0; c < NBF; ++c) {
-    if (c < jb) {
-      double s = x[c];
-#pragma unroll
-      for (int k = 0; k < c; ++k) s = fma(-x[k], L[c][k], s);
-      x[c] = s / L[c][c];
-    }
+  const bool live = r < nrows;
+  double *row = A + (live ? r : j0) * n + j0;
+  for (int c = 0; c < NBF; ++c) Xr[tid][c] = (live && c < jb) ? row[c] : 0.0;
+  for (int c = 0; c < jb; ++c) {
+    const double xc = Xr[tid][c] / L[c][c];
+    Xr[tid][c] = xc;
+    for (int j = c + 1; j < jb; ++j) Xr[tid][j] = fma(-xc, L[j][c], Xr[tid][j]);
   }
-#pragma unroll
-  for (int c = 0; c < NBF; ++c)
-    if (c < jb) row[c] = x[c];
+  if (live)
+    for (int c = 0; c < jb; ++c) row[c] = Xr[tid][c];
 }
 
 // trailing update on lower tiles of rows/cols >= j0 + jb (rows up to
 // nrows - 1, columns up to n - 1): A[R][C] -= L21[R] . L21[C], FP64 MFMA
 __global__ __launch_bounds__(256) void k_chol_update(double *A, int64_t n,
                                                      int64_t nrows, int64_t j0,
+                                                     const double *l11,
                                                      const int32_t *info) {
   __shared__ double Ar[TILE][NBF + 1];
   __shared__ double Ac[TILE][NBF + 1];
   if (info[0]) return;
   const int jb = (int)min<int64_t>(NBF, n - j0);
   const int64_t j1 = j0 + jb;
+  if (blockIdx.x == 0) {
+    // the panel's factored diagonal block, written by k_chol_panel
+    for (int e = threadIdx.x; e < jb * jb; e += 256) {
+      const int i = e / jb, j = e - (e / jb) * jb;
+      if (j <= i) A[(j0 + i) * n + j0 + j] = l11[i * NBF + j];
+    }
+  }
   const int64_t b = blockIdx.x;
   int64_t ti = (int64_t)((sqrt(8.0 * double(b) + 1.0) - 1.0) * 0.5);
   while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
@@ -227,9 +252,12 @@ __global__ __launch_bounds__(256) void k_chol_bwd(const double *A, int64_t n,
   if (blockIdx.x == 0 && tid < jb) delta[j0 + tid] = dp[tid];
   const int64_t c = int64_t(blockIdx.x) * 256 + tid;
   if (c < j0) {
-    double s = 0.0;
-    for (int r = 0; r < jb; ++r) s = fma(A[(j0 + r) * n + c], dp[r], s);
-    z[c] -= s;
+    // independent partial sums keep many loads in flight
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    const double *colp = A + j0 * n + c;
+#pragma unroll 16
+    for (int r = 0; r < jb; ++r) s[r & 3] = fma(colp[int64_t(r) * n], dp[r], s[r & 3]);
+    z[c] -= (s[0] + s[1]) + (s[2] + s[3]);
   }
 }
 
@@ -238,9 +266,10 @@ __global__ __launch_bounds__(256) void k_chol_bwd(const double *A, int64_t n,
 int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
                    double *delta, int32_t *info, hipStream_t s) {
   void *scr;
-  MNL_TRY(ws_get(c, S_CHOL, size_t(n + 8) * 8, &scr));
+  MNL_TRY(ws_get(c, S_CHOL, size_t(n + 8 + NBF * NBF) * 8, &scr));
   double *z = static_cast<double *>(scr);
   double *floor_p = z + n;
+  double *l11 = floor_p + 8;
   const int64_t nrows = n + 1;
   // g^T as row n of the augmented matrix
   MNL_HIP(c, hipMemcpyAsync(A + n * n, g, size_t(n) * 8,
@@ -254,10 +283,10 @@ int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
     const int64_t jb = std::min<int64_t>(NBF, n - j0);
     const int64_t rest = nrows - j0 - jb;   // >= 1: the g row
     hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)(1 + (rest + 63) / 64)),
-                       dim3(64), 0, s, A, n, nrows, j0, floor_p, info);
+                       dim3(64), 0, s, A, n, nrows, j0, floor_p, l11, info);
     const int64_t T = (rest + TILE - 1) / TILE;
     hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(T * (T + 1) / 2)),
-                       dim3(256), 0, s, A, n, nrows, j0, info);
+                       dim3(256), 0, s, A, n, nrows, j0, l11, info);
   }
   MNL_HIP(c, hipMemcpyAsync(z, A + n * n, size_t(n) * 8,
                             hipMemcpyDeviceToDevice, s));

@@ -427,23 +427,28 @@ __global__ __launch_bounds__(kThreads) void k_hess_alt(
     const int nobs = (int)min<int64_t>(kAltTB, i_end - i0);
     for (int e = tid; e < kAltTB * p; e += kThreads)
       Xs[e] = e < nobs * p ? X[i0 * p + e] : 0.0;
-    for (int e = tid; e < kAltTB * nb * a; e += kThreads) {
-      const int j = e / (nb * a), rem = e - j * nb * a;
-      const int qq = rem / a;
-      Zs[e] = (j < nobs && qq < nbe) ? Z[(i0 + j) * K * a + n0 * a + rem] : 0.0;
+    // per observation the slices of Z, Y (alternatives n0..n0+nb) and P
+    // are contiguous: thread tid covers element tid (+ multiples of the
+    // workgroup size) of each slice, with no division in the loop
+    for (int j = 0; j < kAltTB; ++j) {
+      const bool ok = j < nobs;
+      const int64_t i = i0 + j;
+      for (int e = tid; e < nb * a; e += kThreads)
+        Zs[j * nb * a + e] = (ok && e < nbe * a) ? Z[i * K * a + n0 * a + e]
+                                                 : 0.0;
+      for (int e = tid; e < nb * g; e += kThreads)
+        Ys[j * nb * g + e] = (ok && e < nbe * g) ? Y[i * K * g + n0 * g + e]
+                                                 : 0.0;
+      for (int e = tid; e < nb; e += kThreads)
+        Us[j * nb + e] =
+            (ok && e < nbe) ? (w ? w[i] : 1.0) * P[i * K + n0 + e] : 0.0;
     }
+    __syncthreads();
+    // centre the generic data: y - ybar (ybar per observation and variable)
     for (int e = tid; e < kAltTB * nb * g; e += kThreads) {
-      const int j = e / (nb * g), rem = e - j * nb * g;
-      const int qq = rem / g, c = rem - qq * g;
-      Ys[e] = (j < nobs && qq < nbe)
-                  ? Y[(i0 + j) * K * g + n0 * g + rem] - Ybar[(i0 + j) * g + c]
-                  : 0.0;
-    }
-    for (int e = tid; e < kAltTB * nb; e += kThreads) {
-      const int j = e / nb, qq = e - j * nb;
-      Us[e] = (j < nobs && qq < nbe)
-                  ? (w ? w[i0 + j] : 1.0) * P[(i0 + j) * K + n0 + qq]
-                  : 0.0;
+      const int j = e / (nb * g);
+      const int c = (e - j * nb * g) % g;
+      if (j < nobs) Ys[e] -= Ybar[(i0 + j) * g + c];
     }
     __syncthreads();
     if (own) {
