@@ -7,11 +7,10 @@
 //     [ g^T  ] = [ z^T  ]
 // by blocked right-looking Cholesky leaves z = L^{-1} g in row n, so the
 // forward substitution comes out of the factorisation.  Per 32-wide panel:
-//   panel : every workgroup factors the small diagonal block in LDS (one
-//           barrier per column, LDL^T form then scaled), checks the pivots
-//           against the round-off floor n * eps * max_k A_kk (workgroup 0
-//           writes L11 to scratch and the failure flag) and solves its 64
-//           rows x L11^T = a below the panel (one row per thread);
+//   diag  : one wave factors the diagonal block in registers (LDL^T form,
+//           then scaled), checks the pivots against the round-off floor
+//           n * eps * max_k A_kk and writes L11 to scratch;
+//   trsm  : rows below the panel solve x L11^T = a, one row per thread;
 //   update: puts L11 in place, then A22 -= L21 L21^T on the lower 64x64
 //           tiles, FP64 MFMA.
 // Then L^T delta = z by 64-wide panels from the bottom: each workgroup
@@ -70,16 +69,15 @@ __global__ __launch_bounds__(256) void k_floor(const double *A, int64_t n,
   }
 }
 
-// Panel j0 (width jb <= NBF): workgroup b factors the diagonal block and
-// solves rows j0 + jb + 64 (b - 1) .. + 63 (b >= 1).  One wave: lane i
-// keeps row i of the diagonal block in registers; each step broadcasts the
-// finished column through LDS.
-__global__ __launch_bounds__(64) void k_chol_panel(double *A, int64_t n,
-                                                   int64_t nrows, int64_t j0,
-                                                   const double *floor_p,
-                                                   double *l11,
-                                                   int32_t *info) {
-  __shared__ double L[NBF][NBF + 1];
+// Diagonal block of panel j0 (width jb <= NBF), one wave: lane i keeps row
+// i in registers; each LDL^T step broadcasts the finished column through
+// LDS.  Pivots are checked against the round-off floor; L11 goes to
+// scratch (l11, row-major NBF x NBF, identity rows past jb) and is put into
+// A by the next trailing-update launch.
+__global__ __launch_bounds__(64) void k_chol_diag(const double *A, int64_t n,
+                                                  int64_t j0,
+                                                  const double *floor_p,
+                                                  double *l11, int32_t *info) {
   __shared__ double col[NBF];
   if (info[0]) return;
   const int jb = (int)min<int64_t>(NBF, n - j0);
@@ -92,78 +90,80 @@ __global__ __launch_bounds__(64) void k_chol_panel(double *A, int64_t n,
     for (int j = 0; j < NBF; ++j)
       a[j] = (mine && j <= tid && j < jb) ? src[j] : 0.0;
   }
-  // LDL^T on the lower triangle: a[j] of lane i is D_ij, a[i] of lane i d_i
 #pragma unroll
   for (int k = 0; k < NBF; ++k) {
     if (k < jb) {
       if (tid < jb) col[tid] = a[k];
       __syncthreads();
-      const double inv = 1.0 / col[k];
-      const double lik = a[k] * inv;
+      const double lik = a[k] / col[k];
 #pragma unroll
       for (int j = k + 1; j < NBF; ++j)
         if (j <= tid) a[j] = fma(-lik, col[j], a[j]);
       __syncthreads();
     }
   }
-  // pivots and the scaled factor L_ij = D_ij / sqrt(d_j)
-  const double fl = *floor_p;
-  if (tid < jb) col[tid] = a[tid];   // placeholder, replaced below
-  __syncthreads();
-  double dself = 0.0;
+  double d = 0.0;
 #pragma unroll
   for (int j = 0; j < NBF; ++j)
-    if (j == tid) dself = a[j];
-  if (tid < jb) col[tid] = dself;
+    if (j == tid) d = a[j];
+  if (tid < jb) col[tid] = d;
   __syncthreads();
-  bool bad = false;
+  const double fl = *floor_p;
   for (int k = 0; k < jb; ++k) {
-    const double d = col[k];
-    if (!(d > fl) || !isfinite(d)) {
-      bad = true;
-      if (blockIdx.x == 0 && tid == 0 && !info[0]) info[0] = int(j0 + k + 1);
-      break;
+    const double dk = col[k];
+    if (!(dk > fl) || !isfinite(dk)) {
+      if (tid == 0) info[0] = int(j0 + k + 1);
+      return;
     }
   }
-  if (bad) return;
-  if (mine) {
+  if (tid < NBF) {
+    double *dst = l11 + tid * NBF;
 #pragma unroll
     for (int j = 0; j < NBF; ++j) {
-      if (j < tid) L[tid][j] = a[j] / sqrt(col[j]);
-      else if (j == tid) L[tid][j] = sqrt(col[j]);
-      else L[tid][j] = 0.0;
+      double v;
+      if (!mine) v = (j == tid) ? 1.0 : 0.0;
+      else if (j < tid) v = a[j] / sqrt(col[j]);
+      else if (j == tid) v = sqrt(col[j]);
+      else v = 0.0;
+      dst[j] = v;
     }
-  } else if (tid < NBF) {
-    // padding rows of a narrow last panel: identity, so the solve below
-    // needs no bounds on the column index
-#pragma unroll
-    for (int j = 0; j < NBF; ++j) L[tid][j] = (j == tid) ? 1.0 : 0.0;
   }
+}
+
+// rows below panel j0: x L11^T = a, one row per thread in registers, L11
+// broadcast from LDS (its padding rows are the identity, so no bounds on
+// the column index are needed)
+__global__ __launch_bounds__(64) void k_chol_trsm(double *A, int64_t n,
+                                                  int64_t nrows, int64_t j0,
+                                                  const double *l11,
+                                                  const int32_t *info) {
+  __shared__ double L[NBF][NBF + 1];
+  if (info[0]) return;
+  const int jb = (int)min<int64_t>(NBF, n - j0);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NBF * NBF; e += 64)
+    L[e / NBF][e % NBF] = l11[e];
   __syncthreads();
-  if (blockIdx.x == 0) {
-    // L11 goes to scratch, not into A: other workgroups of this launch may
-    // still be reading the original diagonal block; the next launch
-    // (k_chol_update) copies it into place
-    if (mine) {
+  const int64_t r = j0 + jb + int64_t(blockIdx.x) * 64 + tid;
+  if (r >= nrows) return;
+  double x[NBF];
+  double *row = A + r * n + j0;
 #pragma unroll
-      for (int j = 0; j < NBF; ++j) l11[tid * NBF + j] = L[tid][j];
+  for (int c = 0; c < NBF; ++c) x[c] = c < jb ? row[c] : 0.0;
+  // the runtime bound keeps the compiler from hoisting all of L11 into
+  // registers ahead of the substitution
+#pragma unroll
+  for (int c = 0; c < NBF; ++c) {
+    if (c < jb) {
+      double s0 = x[c];
+#pragma unroll
+      for (int k = 0; k < c; ++k) s0 = fma(-x[k], L[c][k], s0);
+      x[c] = s0 / L[c][c];
     }
-    return;
   }
-  // rows below: x L11^T = a, column by column; each lane's row sits in LDS
-  // (padded columns stay zero: their row of L11 is the identity)
-  __shared__ double Xr[64][NBF + 1];
-  const int64_t r = j0 + jb + int64_t(blockIdx.x - 1) * 64 + tid;
-  const bool live = r < nrows;
-  double *row = A + (live ? r : j0) * n + j0;
-  for (int c = 0; c < NBF; ++c) Xr[tid][c] = (live && c < jb) ? row[c] : 0.0;
-  for (int c = 0; c < jb; ++c) {
-    const double xc = Xr[tid][c] / L[c][c];
-    Xr[tid][c] = xc;
-    for (int j = c + 1; j < jb; ++j) Xr[tid][j] = fma(-xc, L[j][c], Xr[tid][j]);
-  }
-  if (live)
-    for (int c = 0; c < jb; ++c) row[c] = Xr[tid][c];
+#pragma unroll
+  for (int c = 0; c < NBF; ++c)
+    if (c < jb) row[c] = x[c];
 }
 
 // trailing update on lower tiles of rows/cols >= j0 + jb (rows up to
@@ -282,8 +282,10 @@ int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
   for (int64_t j0 = 0; j0 < n; j0 += NBF) {
     const int64_t jb = std::min<int64_t>(NBF, n - j0);
     const int64_t rest = nrows - j0 - jb;   // >= 1: the g row
-    hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)(1 + (rest + 63) / 64)),
-                       dim3(64), 0, s, A, n, nrows, j0, floor_p, l11, info);
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, s, A, n, j0,
+                       floor_p, l11, info);
+    hipLaunchKernelGGL(k_chol_trsm, dim3((unsigned)((rest + 63) / 64)),
+                       dim3(64), 0, s, A, n, nrows, j0, l11, info);
     const int64_t T = (rest + TILE - 1) / TILE;
     hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(T * (T + 1) / 2)),
                        dim3(256), 0, s, A, n, nrows, j0, l11, info);

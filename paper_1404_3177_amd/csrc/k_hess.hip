@@ -208,14 +208,12 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
             j < nobs ? ldg_op<T>(H.P, H.P32, int64_t(i0 + j) * K + cols[c])
                      : T(0);
       }
-    } else if (is_bb) {
-      for (int e = tid; e < KC * K; e += NT)
-        Pw[e] = e < nobs * K ? ldg_op<T>(H.P, H.P32, int64_t(i0) * K + e)
-                             : T(0);
     } else {
       for (int e = tid; e < KC * K; e += NT)
         Pw[e] = e < nobs * K ? ldg_op<T>(H.P, H.P32, int64_t(i0) * K + e)
                              : T(0);
+    }
+    if (!is_bb) {
       const int za = K * a;
       for (int e = tid; e < KC * za; e += NT)
         Zw[e] = e < nobs * za ? T(H.Z[int64_t(i0) * za + e]) : T(0);
@@ -425,30 +423,43 @@ __global__ __launch_bounds__(kThreads) void k_hess_alt(
 
   for (int64_t i0 = i_begin; i0 < i_end; i0 += kAltTB) {
     const int nobs = (int)min<int64_t>(kAltTB, i_end - i0);
-    for (int e = tid; e < kAltTB * p; e += kThreads)
-      Xs[e] = e < nobs * p ? X[i0 * p + e] : 0.0;
-    // per observation the slices of Z, Y (alternatives n0..n0+nb) and P
-    // are contiguous: thread tid covers element tid (+ multiples of the
-    // workgroup size) of each slice, with no division in the loop
-    for (int j = 0; j < kAltTB; ++j) {
-      const bool ok = j < nobs;
-      const int64_t i = i0 + j;
-      for (int e = tid; e < nb * a; e += kThreads)
-        Zs[j * nb * a + e] = (ok && e < nbe * a) ? Z[i * K * a + n0 * a + e]
-                                                 : 0.0;
-      for (int e = tid; e < nb * g; e += kThreads)
-        Ys[j * nb * g + e] = (ok && e < nbe * g) ? Y[i * K * g + n0 * g + e]
-                                                 : 0.0;
-      for (int e = tid; e < nb; e += kThreads)
-        Us[j * nb + e] =
-            (ok && e < nbe) ? (w ? w[i] : 1.0) * P[i * K + n0 + e] : 0.0;
-    }
-    __syncthreads();
-    // centre the generic data: y - ybar (ybar per observation and variable)
-    for (int e = tid; e < kAltTB * nb * g; e += kThreads) {
-      const int j = e / (nb * g);
-      const int c = (e - j * nb * g) % g;
-      if (j < nobs) Ys[e] -= Ybar[(i0 + j) * g + c];
+    {
+      const int nx = nobs * p;
+      const double *srx = X + i0 * p;
+      batched_copy<8>(
+          kAltTB * p, tid, kThreads,
+          [&](int e) { return e < nx ? srx[e] : 0.0; },
+          [&](int e, double v) { Xs[e] = v; });
+      // per observation the slices of Z, Y (alternatives n0..n0+nb) and P
+      // are contiguous; element idx of a staged array is observation
+      // idx / slice, offset idx % slice
+      const int za = nb * a, zg = nb * g;
+      batched_copy<8>(
+          kAltTB * za, tid, kThreads,
+          [&](int idx) {
+            const int j = idx / za, e = idx - j * za;
+            return (j < nobs && e < nbe * a)
+                       ? Z[(i0 + j) * K * a + n0 * a + e] : 0.0;
+          },
+          [&](int idx, double v) { Zs[idx] = v; });
+      batched_copy<8>(
+          kAltTB * zg, tid, kThreads,
+          [&](int idx) {
+            const int j = idx / zg, e = idx - j * zg;
+            if (j >= nobs || e >= nbe * g) return 0.0;
+            const int c = e % g;   // generic variable of this element
+            return Y[(i0 + j) * K * g + n0 * g + e] - Ybar[(i0 + j) * g + c];
+          },
+          [&](int idx, double v) { Ys[idx] = v; });
+      batched_copy<8>(
+          kAltTB * nb, tid, kThreads,
+          [&](int idx) {
+            const int j = idx / nb, e = idx - j * nb;
+            return (j < nobs && e < nbe)
+                       ? (w ? w[i0 + j] : 1.0) * P[(i0 + j) * K + n0 + e]
+                       : 0.0;
+          },
+          [&](int idx, double v) { Us[idx] = v; });
     }
     __syncthreads();
     if (own) {
@@ -494,9 +505,15 @@ __global__ void k_alt_reduce(const double *alt, int S, int64_t n,
                              double *red) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  double v = 0.0;
-  for (int s2 = 0; s2 < S; ++s2) v += alt[int64_t(s2) * n + e];
-  red[e] = v;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int s2 = 0;
+  for (; s2 + 8 <= S; s2 += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += alt[int64_t(s2 + u) * n + e];
+  }
+  for (; s2 < S; ++s2) acc[s2 & 7] += alt[int64_t(s2) * n + e];
+  red[e] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) +
+           ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 }
 
 // ---- assembly into H (Hessian sign) ----------------------------------------------

@@ -115,17 +115,24 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs A, int tb,
     const int nobs = (int)((d.N - i0) < tb ? (d.N - i0) : tb);
 
     // ---- 1. stage the tile ---------------------------------------------
-    for (int idx = tid; idx < tb * p; idx += kThreads) {
-      int i = idx / p, aa = idx - i * p;
-      xs[aa * tb + i] = (i < nobs) ? A.X[(i0 + i) * p + aa] : 0.0;
-    }
     {
-      const int64_t ny = int64_t(nobs) * K * g;
+      const double *srx = A.X + i0 * p;
+      const int nx = nobs * p;
+      batched_copy<8>(
+          tb * p, tid, kThreads,
+          [&](int e) { return e < nx ? srx[e] : 0.0; },
+          [&](int e, double v) {
+            const int i = e / p;
+            xs[(e - i * p) * tb + i] = v;
+          });
       const double *src = A.Y + i0 * K * g;
-      for (int64_t idx = tid; idx < ny; idx += kThreads) ys[idx] = src[idx];
-      const int64_t nz = int64_t(nobs) * K * a;
+      batched_copy<8>(
+          nobs * K * g, tid, kThreads, [&](int e) { return src[e]; },
+          [&](int e, double v) { ys[e] = v; });
       const double *srz = A.Z + i0 * K * a;
-      for (int64_t idx = tid; idx < nz; idx += kThreads) zs[idx] = srz[idx];
+      batched_copy<8>(
+          nobs * K * a, tid, kThreads, [&](int e) { return srz[e]; },
+          [&](int e, double v) { zs[e] = v; });
     }
     for (int i = tid; i < tb; i += kThreads) {
       ws[i] = (i < nobs) ? (A.w ? A.w[i0 + i] : 1.0) : 0.0;
@@ -289,8 +296,17 @@ __global__ void k_pass_reduce(const double *__restrict__ partial, int grid,
                               double *grad) {
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j > np) return;
-  double s = 0.0;
-  for (int b = 0; b < grid; ++b) s += partial[int64_t(b) * stride + j];
+  // eight independent partial sums in a fixed order: deterministic, and
+  // many loads in flight
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int b = 0;
+  for (; b + 8 <= grid; b += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += partial[int64_t(b + u) * stride + j];
+  }
+  for (; b < grid; ++b) acc[b & 7] += partial[int64_t(b) * stride + j];
+  const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) +
+                   ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   if (j == 0) {
     if (loglik) *loglik = s;
   } else if (grad) {

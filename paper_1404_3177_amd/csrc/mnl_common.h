@@ -14,6 +14,28 @@ namespace mnl {
 
 constexpr int kWave = 64;
 
+// Copy n elements with nthr threads keeping U loads in flight per thread:
+// all U loads of a batch are issued before any store, so a staging loop is
+// not one memory latency per element.  ld(e) returns element e, st(e, v)
+// stores it.
+template <int U, typename Load, typename Store>
+__device__ inline void batched_copy(int n, int tid, int nthr, Load ld,
+                                    Store st) {
+  for (int base = 0; base < n; base += U * nthr) {
+    decltype(ld(0)) v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + tid + u * nthr;
+      if (e < n) v[u] = ld(e);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + tid + u * nthr;
+      if (e < n) st(e, v[u]);
+    }
+  }
+}
+
 // Dimensions of a problem, validated.
 struct Dims {
   int64_t N;
