@@ -212,6 +212,94 @@ int mnl_fit(mnl_ctx *ctx, const mnl_problem *prob, const double *theta0,
             const mnl_fit_opts *opts, double *theta_out, mnl_fit_info *info,
             void *stream);
 
+/* ---- Serving: continuous batching of independent fits -------------------
+ *
+ * A server runs many fits at once on one device.  Requests arrive with
+ * their data in HOST memory; each is admitted, in arrival order, as soon as
+ * a slot is free and its device footprint (mnl_fit_footprint) fits in what
+ * the HBM budget has left, so requests that arrive while others are on the
+ * GPU join the running mix.  An admitted fit copies its data to the device
+ * and keeps all of its state there (data, P, H, workspace) until it ends;
+ * each slot runs its fit on a HIP stream of its own, so the fits' kernels
+ * overlap on the device.  Every fit's reductions use partitions fixed by
+ * its own shape, so its result is bitwise the same alone and in any mix.
+ * A request whose footprint exceeds the whole budget is refused at submit.
+ * Device memory comes from a stream-ordered pool owned by the server; the
+ * budget bounds the bytes that admitted fits have requested from it.
+ */
+typedef struct mnl_server mnl_server;
+
+typedef struct {
+    int32_t device;            /* HIP device                               */
+    int32_t slots;             /* fits in flight at once, 1..256            */
+    size_t hbm_budget;         /* bytes admitted fits may hold; 0 = 80 % of
+                                  the device memory free at creation       */
+} mnl_server_opts;
+
+/* One finished request (mnl_server_wait).  Times in ms on the server clock
+ * (mnl_server_now_ms): t_arrival as given at submit, t_admit when a slot
+ * took it, t_done when theta was in host memory.  Latency is t_done -
+ * t_arrival (queueing, host-to-device copies and the fit). */
+typedef struct {
+    int64_t id;                /* from mnl_server_submit                   */
+    int32_t status;            /* MNL_OK or the MNL_ERR_* of the fit        */
+    int32_t slot;              /* slot that ran it                          */
+    double t_arrival, t_admit, t_done;
+    size_t footprint;          /* device bytes reserved for it              */
+    mnl_fit_info info;         /* as from mnl_fit                           */
+} mnl_server_result;
+
+/* Counters of a server (mnl_server_stats). */
+typedef struct {
+    int64_t submitted, completed;
+    int32_t queued, running;
+    int32_t max_running;       /* most fits in flight at one time           */
+    int32_t reserved;
+    size_t budget, in_use, peak_in_use; /* footprint bytes                 */
+} mnl_server_stats;
+
+/* Device bytes a fit of this shape holds while it runs: its data copy plus
+ * the library's workspace (an upper bound).  Only the sizes (N, K, p, g,
+ * a) and whether w is NULL are read.  Returns -1 for an invalid shape. */
+int64_t mnl_fit_footprint(const mnl_problem *shape, int32_t prec);
+
+/* Milliseconds on the server clock (a monotonic host clock). */
+double mnl_server_now_ms(void);
+
+/* Create a server and its slot threads.  Returns MNL_ERR_ARG for bad
+ * options, MNL_ERR_HIP / MNL_ERR_OOM if streams or the pool fail. */
+int mnl_server_create(mnl_server **srv, const mnl_server_opts *opts);
+
+/* Stop the server: queued requests that were not admitted are dropped
+ * (never reported), running fits finish, then all resources are freed.
+ * NULL is ignored. */
+void mnl_server_destroy(mnl_server *srv);
+
+/* Queue a fit.
+ *   prob       host struct whose array pointers are HOST memory (page-
+ *              locked memory makes the copies faster); the arrays must stay
+ *              valid and unchanged until the request's result is returned
+ *              by mnl_server_wait.
+ *   theta0     host [n_p] start or NULL (zeros); same lifetime rule.
+ *   opts       fit options (copied), NULL = defaults.
+ *   theta_out  host [n_p], written before the result is reported.
+ *   t_arrival  arrival time on the server clock; < 0 means now.
+ *   id         receives the request id (>= 0).
+ * Returns MNL_ERR_ARG for an invalid problem or options and MNL_ERR_OOM if
+ * the footprint exceeds the whole budget; nothing is queued then. */
+int mnl_server_submit(mnl_server *srv, const mnl_problem *prob,
+                      const double *theta0, const mnl_fit_opts *opts,
+                      double *theta_out, double t_arrival, int64_t *id);
+
+/* Move up to max_results finished requests into out[] (completion order)
+ * and set *n_out.  Blocks until at least one is available or timeout_ms has
+ * passed (0 = do not block, < 0 = no limit). */
+int mnl_server_wait(mnl_server *srv, mnl_server_result *out,
+                    int32_t max_results, double timeout_ms, int32_t *n_out);
+
+/* Snapshot of the server's counters. */
+int mnl_server_get_stats(mnl_server *srv, mnl_server_stats *st);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,11 +19,13 @@ import ctypes
 from typing import Optional
 
 from . import _lib
-from ._lib import (MnlError, MnlFitInfo, MnlFitOpts, MnlProblem, PREC,  # noqa
+from ._lib import (MnlError, MnlFitInfo, MnlFitOpts, MnlProblem,  # noqa
+                   MnlServerOpts, MnlServerResult, MnlServerStats, PREC,
                    STOP_FTOL, STOP_GTOL, STOP_LS_FAIL, STOP_MAXITER,
                    STOP_NONE, STOP_NONFINITE, STOP_NOT_PD)
 
-__all__ = ["Context", "Problem", "num_params", "default_opts", "MnlError"]
+__all__ = ["Context", "Problem", "HostProblem", "Server", "num_params",
+           "default_opts", "fit_footprint", "MnlError"]
 
 
 def num_params(K: int, p: int, g: int, a: int) -> int:
@@ -178,3 +180,132 @@ class Context:
             ctypes.byref(o), theta.data_ptr(), ctypes.byref(info),
             _stream_handle(stream)))
         return theta, info.as_dict()
+
+
+def fit_footprint(N: int, K: int, p: int, g: int, a: int, prec="fp64",
+                  weights: bool = False) -> int:
+    """Device bytes a served fit of this shape holds (data + workspace)."""
+    pr = PREC[prec] if isinstance(prec, str) else int(prec)
+    shape = MnlProblem(N=N, K=K, p=p, g=g, a=a, X=None, Y=None, Z=None,
+                       choice=None, w=1 if weights else None)
+    return int(_lib.load().mnl_fit_footprint(ctypes.byref(shape), pr))
+
+
+class HostProblem:
+    """Problem whose arrays live in host memory (the server's input).
+    Arrays are made contiguous float64 / int32; with pinned=True they are
+    copied into page-locked torch tensors, which the device reads faster."""
+
+    def __init__(self, X, Y, Z, choice, w=None, pinned: bool = False):
+        import numpy as np
+        N, p = X.shape
+        K, g, a = Y.shape[1], Y.shape[2], Z.shape[2]
+        if Y.shape[0] != N or Z.shape[0] != N or Z.shape[1] != K or \
+                choice.shape[0] != N:
+            raise ValueError("inconsistent shapes")
+
+        def host(x, dt):
+            x = np.ascontiguousarray(x, dtype=dt)
+            if not pinned:
+                return x, x.ctypes.data
+            import torch
+            t = torch.from_numpy(x).pin_memory()
+            return t, t.data_ptr()
+        self.N, self.K, self.p, self.g, self.a = N, K, p, g, a
+        hx, px = host(X, np.float64)
+        hy, py = host(Y, np.float64)
+        hz, pz = host(Z, np.float64)
+        hc, pc = host(choice, np.int32)
+        hw, pw = host(w, np.float64) if w is not None else (None, None)
+        self._refs = (hx, hy, hz, hc, hw)
+        self.c = MnlProblem(N=N, K=K, p=p, g=g, a=a,
+                            X=px if p else None, Y=py if g else None,
+                            Z=pz if a else None, choice=pc, w=pw)
+
+    @property
+    def n_params(self) -> int:
+        return (self.K - 1) * self.p + self.K * self.a + self.g
+
+    @classmethod
+    def from_numpy(cls, prob, pinned: bool = False):
+        """From a synth.Problem."""
+        return cls(prob.X, prob.Y, prob.Z, prob.choice, prob.w, pinned=pinned)
+
+
+class Server:
+    """Continuous-batching fit server (mnl_server_* in include/mnl.h).
+
+    submit() queues a HostProblem and returns its id; wait() returns
+    finished requests as dicts with the fitted theta (numpy), status, the
+    fit report and the arrival / admission / completion times (ms on the
+    server clock, now_ms())."""
+
+    def __init__(self, slots: int = 8, hbm_budget: int = 0, device: int = 0):
+        self.lib = _lib.load()
+        o = MnlServerOpts(device=device, slots=slots, hbm_budget=hbm_budget)
+        h = ctypes.c_void_p()
+        rc = self.lib.mnl_server_create(ctypes.byref(h), ctypes.byref(o))
+        if rc != 0:
+            raise MnlError(rc, "mnl_server_create failed")
+        self.h = h
+        self._live = {}
+
+    def now_ms(self) -> float:
+        return float(self.lib.mnl_server_now_ms())
+
+    def submit(self, prob: HostProblem, theta0=None, t_arrival: float = -1.0,
+               **opts) -> int:
+        import numpy as np
+        o = Context._opts(**opts)
+        theta = np.empty(prob.n_params, dtype=np.float64)
+        th0 = None
+        if theta0 is not None:
+            th0 = np.ascontiguousarray(theta0, dtype=np.float64)
+        rid = ctypes.c_int64()
+        rc = self.lib.mnl_server_submit(
+            self.h, ctypes.byref(prob.c),
+            th0.ctypes.data if th0 is not None else None, ctypes.byref(o),
+            theta.ctypes.data, float(t_arrival), ctypes.byref(rid))
+        if rc != 0:
+            raise MnlError(rc, "mnl_server_submit refused the request")
+        self._live[rid.value] = (prob, theta, th0)
+        return rid.value
+
+    def wait(self, max_results: int = 256, timeout_ms: float = -1.0) -> list:
+        buf = (MnlServerResult * max_results)()
+        n = ctypes.c_int32()
+        rc = self.lib.mnl_server_wait(self.h, buf, max_results,
+                                      float(timeout_ms), ctypes.byref(n))
+        if rc != 0:
+            raise MnlError(rc, "mnl_server_wait failed")
+        out = []
+        for r in buf[:n.value]:
+            _, theta, _ = self._live.pop(r.id)
+            out.append(dict(id=r.id, status=r.status, slot=r.slot,
+                            t_arrival=r.t_arrival, t_admit=r.t_admit,
+                            t_done=r.t_done, footprint=r.footprint,
+                            info=r.info.as_dict(), theta=theta))
+        return out
+
+    def stats(self) -> dict:
+        st = MnlServerStats()
+        rc = self.lib.mnl_server_get_stats(self.h, ctypes.byref(st))
+        if rc != 0:
+            raise MnlError(rc, "mnl_server_get_stats failed")
+        return st.as_dict()
+
+    @property
+    def pending(self) -> int:
+        return len(self._live)
+
+    def close(self):
+        if self.h:
+            self.lib.mnl_server_destroy(self.h)
+            self.h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -28,6 +28,9 @@ EXPORTS = [
     "mnl_version", "mnl_strerror", "mnl_default_opts", "mnl_num_params",
     "mnl_create", "mnl_destroy", "mnl_workspace_bytes", "mnl_last_error",
     "mnl_loglik_grad", "mnl_hessian", "mnl_newton_step", "mnl_fit",
+    "mnl_fit_footprint", "mnl_server_now_ms", "mnl_server_create",
+    "mnl_server_destroy", "mnl_server_submit", "mnl_server_wait",
+    "mnl_server_get_stats",
 ]
 
 
@@ -60,6 +63,33 @@ class MnlFitInfo(ctypes.Structure):
         ("t_chol", ctypes.c_double), ("t_ls", ctypes.c_double),
         ("t_hess_kernel", ctypes.c_double), ("t_pass_kernel", ctypes.c_double),
         ("n_pass", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class MnlServerOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_size_t)]
+
+
+class MnlServerResult(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_int64), ("status", ctypes.c_int32),
+        ("slot", ctypes.c_int32), ("t_arrival", ctypes.c_double),
+        ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+        ("footprint", ctypes.c_size_t), ("info", MnlFitInfo),
+    ]
+
+
+class MnlServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+        ("queued", ctypes.c_int32), ("running", ctypes.c_int32),
+        ("max_running", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("budget", ctypes.c_size_t), ("in_use", ctypes.c_size_t),
+        ("peak_in_use", ctypes.c_size_t),
     ]
 
     def as_dict(self) -> dict:
@@ -104,8 +134,24 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                     ctypes.POINTER(MnlFitInfo), P]
     lib.mnl_fit.argtypes = [P, prob, P, ctypes.POINTER(MnlFitOpts), P,
                             ctypes.POINTER(MnlFitInfo), P]
+    lib.mnl_fit_footprint.argtypes = [prob, I32]
+    lib.mnl_fit_footprint.restype = I64
+    lib.mnl_server_now_ms.argtypes = []
+    lib.mnl_server_now_ms.restype = ctypes.c_double
+    lib.mnl_server_create.argtypes = [ctypes.POINTER(P),
+                                      ctypes.POINTER(MnlServerOpts)]
+    lib.mnl_server_destroy.argtypes = [P]
+    lib.mnl_server_destroy.restype = None
+    lib.mnl_server_submit.argtypes = [P, prob, P, ctypes.POINTER(MnlFitOpts),
+                                      P, ctypes.c_double,
+                                      ctypes.POINTER(I64)]
+    lib.mnl_server_wait.argtypes = [P, ctypes.POINTER(MnlServerResult), I32,
+                                    ctypes.c_double, ctypes.POINTER(I32)]
+    lib.mnl_server_get_stats.argtypes = [P, ctypes.POINTER(MnlServerStats)]
     for name in ("mnl_create", "mnl_loglik_grad", "mnl_hessian",
-                 "mnl_newton_step", "mnl_fit"):
+                 "mnl_newton_step", "mnl_fit", "mnl_server_create",
+                 "mnl_server_submit", "mnl_server_wait",
+                 "mnl_server_get_stats"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -9,10 +9,12 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmnl.so")
-SOURCES = ["mnl_api.hip", "k_pass.hip", "k_hess.hip", "k_chol.hip"]
+SOURCES = ["mnl_api.hip", "mnl_serve.hip", "k_pass.hip", "k_hess.hip",
+           "k_chol.hip"]
+OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "-fPIC", "-pthread",
     "--offload-arch=gfx950",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -29,21 +31,38 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source into libmnl.so (always recompiles)."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    """Compile every source (in parallel) and link libmnl.so; always
+    recompiles."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    cc = hipcc()
+    noise = "is not a recognized feature for this target"
+    procs = []
+    for src in SOURCES:
+        obj = os.path.join(OBJDIR, src.replace(".hip", ".o"))
+        cmd = [cc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, obj, subprocess.Popen(
+            cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    failed, objs = [], []
+    for src, obj, p in procs:
+        out, _ = p.communicate()
+        msgs = [ln for ln in out.splitlines() if ln.strip() and noise not in ln]
+        if p.returncode != 0:
+            failed.append(src)
+            sys.stderr.write(out)
+        elif msgs and verbose:
+            print("\n".join(msgs))
+        objs.append(obj)
+    if failed:
+        raise RuntimeError(f"hipcc failed on {failed}")
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *srcs, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+    cmd = [cc, "-shared", "-fPIC", "-pthread", "--offload-arch=gfx950", *objs,
+           "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libmnl.so")
-    noise = "is not a recognized feature for this target"
-    msgs = [ln for ln in (res.stdout + res.stderr).splitlines()
-            if ln.strip() and noise not in ln]
-    if msgs and verbose:
-        print("\n".join(msgs))
+        raise RuntimeError("linking libmnl.so failed")
     os.replace(tmp, LIB)
     return LIB
 

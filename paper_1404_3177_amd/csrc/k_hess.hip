@@ -630,7 +630,12 @@ struct Plan {
   int64_t alt_chunk = 0;
   size_t alt_lds = 0;
   bool need_alt = false;
-  // device tables (one allocation)
+  // tables: host copies (kept until the plan is freed, so an asynchronous
+  // upload never reads freed memory) and one device allocation
+  std::vector<Tile> h_tiles;
+  std::vector<int32_t> h_cols, h_ncol, h_pair;
+  std::vector<uint32_t> h_row, h_combo;
+  size_t o_cols = 0, o_ncol = 0, o_row = 0, o_combo = 0, o_pair = 0;
   void *dev = nullptr;
   size_t dev_bytes = 0;
   Tile *tiles = nullptr;
@@ -643,18 +648,11 @@ struct Cache {
   std::map<Key, Plan *> plans;
 };
 
-int build_plan(Ctx *c, const Dims &d, int prec, Plan **out) {
-  if (!c->hess_cache) c->hess_cache = new Cache;
-  Cache *cache = static_cast<Cache *>(c->hess_cache);
-  Key key{d.N, d.K, d.p, d.g, d.a, prec};
-  auto it = cache->plans.find(key);
-  if (it != cache->plans.end()) {
-    *out = it->second;
-    return MNL_OK;
-  }
+// Host part of a plan: tiling, split counts, LDS sizes and the tile tables
+// (in pl's host vectors).  On error the caller deletes pl.
+int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
   if (d.p > 255 || d.K > 32767)
     return set_error(c, MNL_ERR_UNSUPPORTED, "Hessian tiles need p <= 255");
-  Plan *pl = new Plan;
   pl->d = d;
   pl->prec = prec;
   const int KSTEP = prec == 2 ? 32 : 4;
@@ -695,7 +693,6 @@ int build_plan(Ctx *c, const Dims &d, int prec, Plan **out) {
   std::vector<uint32_t> bb_row(std::max<int64_t>(nrow_bb, 1), 0);
   pl->bb_full = K <= kMaxCols ? 1 : 0;
   if (K > 4095) {
-    delete pl;
     return set_error(c, MNL_ERR_UNSUPPORTED, "Hessian tiles need K < 4096");
   }
   for (int64_t t = 0; t < nrt_bb; ++t) {
@@ -800,7 +797,6 @@ int build_plan(Ctx *c, const Dims &d, int prec, Plan **out) {
     }
   }
   if (d.N > (int64_t(1) << 31) - 1024) {
-    delete pl;
     return set_error(c, MNL_ERR_UNSUPPORTED, "N too large for Hessian tiles");
   }
   pl->ntiles = int(tiles.size());
@@ -828,7 +824,6 @@ int build_plan(Ctx *c, const Dims &d, int prec, Plan **out) {
   pl->kc_bb = nrow_bb ? pick_kc(T_BB, KCB0, cw_bb) : KSTEP;
   pl->kc_xg = nrow_xg ? pick_kc(T_XG, KCX0, cw_xg) : KSTEP;
   if (pl->kc_bb == 0 || pl->kc_xg == 0) {
-    delete pl;
     return set_error(c, MNL_ERR_UNSUPPORTED,
                      "Hessian tile exceeds LDS (p=%d K=%d a=%d)", p, K, a);
   }
@@ -840,13 +835,11 @@ int build_plan(Ctx *c, const Dims &d, int prec, Plan **out) {
   if (pl->need_alt) {
     const int nl = p + a + g, nr = a + g;
     if (nr > kAltNR) {
-      delete pl;
       return set_error(c, MNL_ERR_UNSUPPORTED,
                        "more than %d alternative-varying variables", kAltNR);
     }
     const int nrb = (nl + kAltRB - 1) / kAltRB;
     if (nrb > kThreads) {
-      delete pl;
       return set_error(c, MNL_ERR_UNSUPPORTED, "too many features");
     }
     int nb = std::max(1, std::min(kThreads / nrb, K));
@@ -866,52 +859,117 @@ int build_plan(Ctx *c, const Dims &d, int prec, Plan **out) {
     pl->alt_lds = lds_alt(nb);
   }
 
-  // device tables
+  // table layout (one allocation)
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  size_t o_tiles = 0;
-  size_t o_cols = al(o_tiles + tiles.size() * sizeof(Tile));
-  size_t o_ncol = al(o_cols + bb_cols.size() * 4);
-  size_t o_row = al(o_ncol + bb_ncol.size() * 4);
-  size_t o_combo = al(o_row + bb_row.size() * 4);
-  size_t o_pair = al(o_combo + std::max<size_t>(combo.size(), 1) * 4);
-  size_t total = al(o_pair + std::max<size_t>(pair_nm.size(), 1) * 4);
-  if (hipMalloc(&pl->dev, total) != hipSuccess) {
+  pl->o_cols = al(tiles.size() * sizeof(Tile));
+  pl->o_ncol = al(pl->o_cols + bb_cols.size() * 4);
+  pl->o_row = al(pl->o_ncol + bb_ncol.size() * 4);
+  pl->o_combo = al(pl->o_row + bb_row.size() * 4);
+  pl->o_pair = al(pl->o_combo + std::max<size_t>(combo.size(), 1) * 4);
+  pl->dev_bytes = al(pl->o_pair + std::max<size_t>(pair_nm.size(), 1) * 4);
+  pl->h_tiles = std::move(tiles);
+  pl->h_cols = std::move(bb_cols);
+  pl->h_ncol = std::move(bb_ncol);
+  pl->h_row = std::move(bb_row);
+  pl->h_combo = std::move(combo);
+  pl->h_pair = std::move(pair_nm);
+  return MNL_OK;
+}
+
+// Device copy of a plan's tables.  A context in stream-ordered mode takes
+// the memory from its pool and uploads on its stream; otherwise the upload
+// is synchronous.
+int plan_upload(Ctx *c, Plan *pl) {
+  hipError_t e;
+  if (c->pool)
+    e = hipMallocFromPoolAsync(&pl->dev, pl->dev_bytes, c->pool, c->ostream);
+  else
+    e = hipMalloc(&pl->dev, pl->dev_bytes);
+  if (e != hipSuccess) {
     (void)hipGetLastError();
-    delete pl;
+    pl->dev = nullptr;
     return set_error(c, MNL_ERR_OOM, "Hessian tables");
   }
-  pl->dev_bytes = total;
   char *base = static_cast<char *>(pl->dev);
-  pl->tiles = reinterpret_cast<Tile *>(base + o_tiles);
-  pl->bb_cols = reinterpret_cast<int32_t *>(base + o_cols);
-  pl->bb_ncol = reinterpret_cast<int32_t *>(base + o_ncol);
-  pl->bb_row = reinterpret_cast<uint32_t *>(base + o_row);
-  pl->bb_combo = reinterpret_cast<uint32_t *>(base + o_combo);
-  pl->pair_nm = reinterpret_cast<int32_t *>(base + o_pair);
+  pl->tiles = reinterpret_cast<Tile *>(base);
+  pl->bb_cols = reinterpret_cast<int32_t *>(base + pl->o_cols);
+  pl->bb_ncol = reinterpret_cast<int32_t *>(base + pl->o_ncol);
+  pl->bb_row = reinterpret_cast<uint32_t *>(base + pl->o_row);
+  pl->bb_combo = reinterpret_cast<uint32_t *>(base + pl->o_combo);
+  pl->pair_nm = reinterpret_cast<int32_t *>(base + pl->o_pair);
   auto up = [&](void *dst, const void *src, size_t n) {
-    return n ? hipMemcpy(dst, src, n, hipMemcpyHostToDevice) : hipSuccess;
+    if (!n) return hipSuccess;
+    return c->pool ? hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice,
+                                    c->ostream)
+                   : hipMemcpy(dst, src, n, hipMemcpyHostToDevice);
   };
-  if (up(pl->tiles, tiles.data(), tiles.size() * sizeof(Tile)) != hipSuccess ||
-      up(pl->bb_cols, bb_cols.data(), bb_cols.size() * 4) != hipSuccess ||
-      up(pl->bb_ncol, bb_ncol.data(), bb_ncol.size() * 4) != hipSuccess ||
-      up(pl->bb_row, bb_row.data(), bb_row.size() * 4) != hipSuccess ||
-      up(pl->bb_combo, combo.data(), combo.size() * 4) != hipSuccess ||
-      up(pl->pair_nm, pair_nm.data(), pair_nm.size() * 4) != hipSuccess) {
-    (void)hipFree(pl->dev);
-    delete pl;
+  if (up(pl->tiles, pl->h_tiles.data(), pl->h_tiles.size() * sizeof(Tile)) !=
+          hipSuccess ||
+      up(pl->bb_cols, pl->h_cols.data(), pl->h_cols.size() * 4) != hipSuccess ||
+      up(pl->bb_ncol, pl->h_ncol.data(), pl->h_ncol.size() * 4) != hipSuccess ||
+      up(pl->bb_row, pl->h_row.data(), pl->h_row.size() * 4) != hipSuccess ||
+      up(pl->bb_combo, pl->h_combo.data(), pl->h_combo.size() * 4) !=
+          hipSuccess ||
+      up(pl->pair_nm, pl->h_pair.data(), pl->h_pair.size() * 4) != hipSuccess)
     return set_error(c, MNL_ERR_HIP, "uploading Hessian tables");
+  return MNL_OK;
+}
+
+void plan_free(Ctx *c, Plan *pl) {
+  if (pl->dev) {
+    if (c->pool) (void)hipFreeAsync(pl->dev, c->ostream);
+    else (void)hipFree(pl->dev);
+  }
+  delete pl;
+}
+
+int build_plan(Ctx *c, const Dims &d, int prec, Plan **out) {
+  if (!c->hess_cache) c->hess_cache = new Cache;
+  Cache *cache = static_cast<Cache *>(c->hess_cache);
+  Key key{d.N, d.K, d.p, d.g, d.a, prec};
+  auto it = cache->plans.find(key);
+  if (it != cache->plans.end()) {
+    *out = it->second;
+    return MNL_OK;
+  }
+  Plan *pl = new Plan;
+  int rc = plan_host(c, d, prec, pl);
+  if (rc == MNL_OK) rc = plan_upload(c, pl);
+  if (rc != MNL_OK) {
+    plan_free(c, pl);
+    return rc;
   }
   cache->plans[key] = pl;
   *out = pl;
   return MNL_OK;
 }
 
+// Split-partial workspace of hessian_run: offsets of the XG partials, the
+// per-alternative partials and their reduction, and the total.
+struct PartLayout {
+  size_t o_xg, o_alt, o_red, total, n_alt;
+};
+PartLayout part_layout(const Plan &pl) {
+  const Dims &d = pl.d;
+  const size_t asz = pl.prec == 0 ? 8 : 4;
+  const size_t bytes_bb = size_t(pl.S) * pl.bb_M * pl.bb_N * asz;
+  const size_t bytes_xg = size_t(pl.S) * pl.xg_M * pl.xg_N * asz;
+  const int nl = d.p + d.a + d.g, nr = d.a + d.g;
+  PartLayout L;
+  L.n_alt = pl.need_alt ? size_t(d.K) * nl * nr : 0;
+  const size_t bytes_alt = size_t(pl.alt_S) * L.n_alt * 8;
+  L.o_xg = (bytes_bb + 255) & ~size_t(255);
+  L.o_alt = (L.o_xg + bytes_xg + 255) & ~size_t(255);
+  L.o_red = (L.o_alt + bytes_alt + 255) & ~size_t(255);
+  L.total = L.o_red + L.n_alt * 8 + 256;
+  return L;
+}
+
 template <int PREC>
 hipError_t launch_tiles(const Plan &pl, const HessDev &hd, hipStream_t s) {
   if (pl.ntiles == 0) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute(
-      reinterpret_cast<const void *>(&k_hess_tiles<PREC>),
-      hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
+  hipError_t e = raise_lds_limit(
+      reinterpret_cast<const void *>(&k_hess_tiles<PREC>), (int)pl.lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_hess_tiles<PREC>, dim3(pl.ntiles),
                      dim3(64 * MF<PREC>::NW),
@@ -950,28 +1008,19 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   Plan *pl;
   MNL_TRY(build_plan(c, h.d, h.prec, &pl));
   const Dims &d = h.d;
-  const size_t asz = h.prec == 0 ? 8 : 4;
-  const size_t bytes_bb = size_t(pl->S) * pl->bb_M * pl->bb_N * asz;
-  const size_t bytes_xg = size_t(pl->S) * pl->xg_M * pl->xg_N * asz;
-  const int nl = d.p + d.a + d.g, nr = d.a + d.g;
-  const size_t n_alt = pl->need_alt ? size_t(d.K) * nl * nr : 0;
-  const size_t bytes_alt = size_t(pl->alt_S) * n_alt * 8;
-  const size_t o_xg = (bytes_bb + 255) & ~size_t(255);
-  const size_t o_alt = (o_xg + bytes_xg + 255) & ~size_t(255);
-  const size_t o_red = (o_alt + bytes_alt + 255) & ~size_t(255);
+  const PartLayout L = part_layout(*pl);
+  const size_t n_alt = L.n_alt;
   void *ws;
-  MNL_TRY(ws_get(c, S_HPART, o_red + n_alt * 8 + 256, &ws));
+  MNL_TRY(ws_get(c, S_HPART, L.total, &ws));
   char *wb = static_cast<char *>(ws);
-  void *pbb = wb, *pxg = wb + o_xg;
-  double *alt_part = reinterpret_cast<double *>(wb + o_alt);
-  double *alt = reinterpret_cast<double *>(wb + o_red);
+  void *pbb = wb, *pxg = wb + L.o_xg;
+  double *alt_part = reinterpret_cast<double *>(wb + L.o_alt);
+  double *alt = reinterpret_cast<double *>(wb + L.o_red);
 
   if (pl->need_alt) {
     const int ngrp = (d.K + pl->alt_nb - 1) / pl->alt_nb;
-    MNL_HIP(c, hipFuncSetAttribute(
-                   reinterpret_cast<const void *>(&k_hess_alt),
-                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                   (int)pl->alt_lds));
+    MNL_HIP(c, raise_lds_limit(reinterpret_cast<const void *>(&k_hess_alt),
+                               (int)pl->alt_lds));
     hipLaunchKernelGGL(k_hess_alt, dim3(ngrp, pl->alt_S), dim3(kThreads),
                        pl->alt_lds, s, d, h.X, h.Y, h.Z, h.w, h.P, h.Ybar,
                        pl->alt_nb, pl->alt_chunk, alt_part);
@@ -1030,12 +1079,18 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
 void hessian_cache_free(Ctx *c) {
   if (!c->hess_cache) return;
   Cache *cache = static_cast<Cache *>(c->hess_cache);
-  for (auto &kv : cache->plans) {
-    if (kv.second->dev) (void)hipFree(kv.second->dev);
-    delete kv.second;
-  }
+  for (auto &kv : cache->plans) plan_free(c, kv.second);
   delete cache;
   c->hess_cache = nullptr;
+}
+
+int hessian_footprint(Ctx *c, const Dims &d, int prec, size_t *part_bytes,
+                      size_t *table_bytes) {
+  Plan pl;
+  MNL_TRY(plan_host(c, d, prec, &pl));
+  *part_bytes = part_layout(pl).total;
+  *table_bytes = pl.dev_bytes;
+  return MNL_OK;
 }
 
 }  // namespace mnl

@@ -350,9 +350,8 @@ hipError_t launch_pass(const PassPlan &plan, const PassArgs &a,
   const size_t lds = plan.lds_bytes;
 #define MNL_PASS_LAUNCH(BL, J)                                                \
   do {                                                                        \
-    hipError_t e_ = hipFuncSetAttribute(                                      \
-        reinterpret_cast<const void *>(&k_pass<BL, J>),                       \
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
+    hipError_t e_ = raise_lds_limit(                                          \
+        reinterpret_cast<const void *>(&k_pass<BL, J>), (int)lds);            \
     if (e_ != hipSuccess) return e_;                                          \
     hipLaunchKernelGGL((k_pass<BL, J>), grid, block, lds, s, a, plan.tb,      \
                        plan.stride);                                          \

@@ -4,6 +4,9 @@
 #include <cstdarg>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "mnl_common.h"
 
@@ -31,20 +34,29 @@ int ws_get(Ctx *c, int slot, size_t bytes, void **ptr) {
   Buf &b = c->bufs[slot];
   if (b.bytes < bytes) {
     if (b.ptr) {
-      // the old buffer may still be in use by enqueued work
-      hipError_t e = hipDeviceSynchronize();
-      if (e != hipSuccess)
-        return set_error(c, MNL_ERR_HIP, "hipDeviceSynchronize: %s",
-                         hipGetErrorString(e));
-      (void)hipFree(b.ptr);
+      if (c->pool) {
+        // stream-ordered: later work on ostream cannot see the old buffer
+        MNL_HIP(c, hipFreeAsync(b.ptr, c->ostream));
+      } else {
+        // the old buffer may still be in use by enqueued work
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess)
+          return set_error(c, MNL_ERR_HIP, "hipDeviceSynchronize: %s",
+                           hipGetErrorString(e));
+        (void)hipFree(b.ptr);
+      }
       c->total_bytes -= b.bytes;
       b.ptr = nullptr;
       b.bytes = 0;
     }
     void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    const hipError_t e =
+        c->pool ? hipMallocFromPoolAsync(&p, bytes, c->pool, c->ostream)
+                : hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
       (void)hipGetLastError();
-      return set_error(c, MNL_ERR_OOM, "hipMalloc(%zu) failed", bytes);
+      return set_error(c, MNL_ERR_OOM, "device allocation of %zu bytes failed",
+                       bytes);
     }
     b.ptr = p;
     b.bytes = bytes;
@@ -54,7 +66,32 @@ int ws_get(Ctx *c, int slot, size_t bytes, void **ptr) {
   return MNL_OK;
 }
 
-namespace {
+void ctx_release(Ctx *c) {
+  for (auto &b : c->bufs) {
+    if (!b.ptr) continue;
+    if (c->pool) (void)hipFreeAsync(b.ptr, c->ostream);
+    else (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  c->total_bytes = 0;
+  hessian_cache_free(c);
+}
+
+hipError_t raise_lds_limit(const void *kernel, int bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<const void *, int>, int> limit;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  int &cur = limit[{kernel, dev}];
+  if (cur >= bytes) return hipSuccess;
+  e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          bytes);
+  if (e == hipSuccess) cur = bytes;
+  return e;
+}
 
 int check_problem(Ctx *c, const mnl_problem *pr, Dims *d) {
   if (!pr) return set_error(c, MNL_ERR_ARG, "problem is NULL");
@@ -92,6 +129,8 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch())
       .count();
 }
+
+namespace {
 
 // One full pass (l, g, P, Ybar at theta) into the given workspace slots.
 int run_pass(Ctx *c, const Dims &d, const mnl_problem *pr, const double *theta,
@@ -291,6 +330,120 @@ int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
 }
 
 }  // namespace
+int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
+             const mnl_fit_opts &o, mnl_fit_info *info, bool one_step,
+             hipStream_t s) {
+  Dims d;
+  MNL_TRY(check_problem(c, prob, &d));
+  MNL_TRY(check_opts(c, &o));
+  MNL_HIP(c, hipSetDevice(c->device));
+  const double t_start = now_ms();
+  std::memset(info, 0, sizeof *info);
+  MNL_TRY(ensure_events(c));
+  c->hess_pending = c->pass_pending = false;
+  if (o.validate) MNL_TRY(validate_data(c, d, prob, s));
+  void *a, *b;
+  MNL_TRY(ws_get(c, S_LG, size_t(d.np + 1) * 8, &a));
+  MNL_TRY(ws_get(c, S_LG_TRIAL, size_t(d.np + 1) * 8, &b));
+  void *sv;
+  MNL_TRY(ws_get(c, S_SCAL, 256, &sv));
+  double *gn2 = (double *)sv;
+  StepState st{(double *)a, (double *)b, 0};
+
+  double t0 = now_ms();
+  MNL_TRY(run_pass(c, d, prob, theta, st.lg, S_P, S_P32, S_YBAR,
+                   o.prec != MNL_PREC_FP64, s));
+  double l = 0.0, gnorm = 0.0;
+  {
+    MNL_HIP(c, launch_sumsq(st.lg + 1, d.np, gn2, s));
+    double h[1];
+    MNL_TRY(copy_d2h(c, &l, st.lg, 8, s));
+    MNL_TRY(copy_d2h(c, h, gn2, 8, s));
+    collect_timing(c, info);
+    gnorm = std::sqrt(h[0]);
+  }
+  info->t_loglik_grad = now_ms() - t0;
+  info->loglik_diff = std::numeric_limits<double>::quiet_NaN();
+  int reason = MNL_STOP_NONE;
+  for (;;) {
+    if (!std::isfinite(l) || !std::isfinite(gnorm)) {
+      reason = MNL_STOP_NONFINITE;
+      break;
+    }
+    if (gnorm <= o.gtol) {
+      reason = MNL_STOP_GTOL;
+      break;
+    }
+    if (!one_step && info->iters >= o.maxiter) {
+      reason = MNL_STOP_MAXITER;
+      break;
+    }
+    if (one_step && info->iters >= 1) break;
+    int r = MNL_STOP_NONE;
+    const double step_gnorm = gnorm;
+    MNL_TRY(newton_core(c, d, prob, theta, o, st, l, info, &r, s));
+    if (r != MNL_STOP_NONE) {
+      reason = r;
+      if (one_step) info->grad_norm = step_gnorm;
+      break;
+    }
+    info->iters += 1;
+    l = info->loglik;
+    MNL_HIP(c, launch_sumsq(st.lg + 1, d.np, gn2, s));
+    double h[1];
+    MNL_TRY(copy_d2h(c, h, gn2, 8, s));
+    gnorm = std::sqrt(h[0]);
+    if (one_step) {
+      info->grad_norm = step_gnorm;
+      info->loglik = l;
+      info->stop_reason = MNL_STOP_NONE;
+      info->t_total = now_ms() - t_start;
+      return MNL_OK;
+    }
+    if (std::fabs(info->loglik_diff) < o.ftol) {
+      reason = MNL_STOP_FTOL;
+      break;
+    }
+  }
+  info->stop_reason = reason;
+  info->loglik = l;
+  if (!one_step || reason == MNL_STOP_GTOL || reason == MNL_STOP_NONFINITE)
+    info->grad_norm = gnorm;
+  info->t_total = now_ms() - t_start;
+  return MNL_OK;
+}
+
+
+int fit_workspace_footprint(Ctx *c, const Dims &d, int prec, size_t *bytes) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  PassPlan plan;
+  if (pass_plan(d, &plan) != MNL_OK)
+    return set_error(c, MNL_ERR_UNSUPPORTED, "shape beyond the fused-pass limits");
+  const size_t np = size_t(d.np), N = size_t(d.N), K = size_t(d.K);
+  size_t t = al(size_t(plan.grid) * plan.stride * 8);  // S_PARTIAL
+  t += 2 * al((np + 1) * 8);                            // S_LG, S_LG_TRIAL
+  t += 2 * al(N * K * 8);                               // S_P, S_P_TRIAL
+  if (prec != MNL_PREC_FP64) t += 2 * al(N * K * 4);   // S_P32 pair
+  if (d.g) t += 2 * al(N * size_t(d.g) * 8);            // S_YBAR pair
+  t += al((np + 1) * np * 8);                           // S_H
+  t += 2 * al(np * 8) + al(256);                        // delta, trial, scalars
+  t += al((np + 8 + 32 * 32) * 8);                      // Cholesky scratch
+  // Hessian partials and tables; a mixed fit may redo the Hessian in FP64
+  size_t part = 0, tab = 0;
+  MNL_TRY(hessian_footprint(c, d, prec, &part, &tab));
+  t += al(part) + al(tab);
+  if (prec != MNL_PREC_FP64) {
+    size_t part64 = 0, tab64 = 0;
+    MNL_TRY(hessian_footprint(c, d, MNL_PREC_FP64, &part64, &tab64));
+    // the FP64 partials replace the mixed ones (the slot grows), the FP64
+    // tables come on top
+    if (part64 > part) t += al(part64);
+    t += al(tab64);
+  }
+  *bytes = t;
+  return MNL_OK;
+}
+
 }  // namespace mnl
 
 using namespace mnl;
@@ -419,89 +572,6 @@ int mnl_hessian(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
   MNL_TRY(run_pass(c, d, prob, theta, (double *)lg, S_P, S_P32, S_YBAR,
                    prec != MNL_PREC_FP64, s));
   return form_hessian(c, d, prob, 0, prec, H, s);
-}
-
-static int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
-                    const mnl_fit_opts &o, mnl_fit_info *info, bool one_step,
-                    hipStream_t s) {
-  Dims d;
-  MNL_TRY(check_problem(c, prob, &d));
-  MNL_TRY(check_opts(c, &o));
-  MNL_HIP(c, hipSetDevice(c->device));
-  const double t_start = now_ms();
-  std::memset(info, 0, sizeof *info);
-  MNL_TRY(ensure_events(c));
-  c->hess_pending = c->pass_pending = false;
-  if (o.validate) MNL_TRY(validate_data(c, d, prob, s));
-  void *a, *b;
-  MNL_TRY(ws_get(c, S_LG, size_t(d.np + 1) * 8, &a));
-  MNL_TRY(ws_get(c, S_LG_TRIAL, size_t(d.np + 1) * 8, &b));
-  void *sv;
-  MNL_TRY(ws_get(c, S_SCAL, 256, &sv));
-  double *gn2 = (double *)sv;
-  StepState st{(double *)a, (double *)b, 0};
-
-  double t0 = now_ms();
-  MNL_TRY(run_pass(c, d, prob, theta, st.lg, S_P, S_P32, S_YBAR,
-                   o.prec != MNL_PREC_FP64, s));
-  double l = 0.0, gnorm = 0.0;
-  {
-    MNL_HIP(c, launch_sumsq(st.lg + 1, d.np, gn2, s));
-    double h[1];
-    MNL_TRY(copy_d2h(c, &l, st.lg, 8, s));
-    MNL_TRY(copy_d2h(c, h, gn2, 8, s));
-    collect_timing(c, info);
-    gnorm = std::sqrt(h[0]);
-  }
-  info->t_loglik_grad = now_ms() - t0;
-  info->loglik_diff = std::numeric_limits<double>::quiet_NaN();
-  int reason = MNL_STOP_NONE;
-  for (;;) {
-    if (!std::isfinite(l) || !std::isfinite(gnorm)) {
-      reason = MNL_STOP_NONFINITE;
-      break;
-    }
-    if (gnorm <= o.gtol) {
-      reason = MNL_STOP_GTOL;
-      break;
-    }
-    if (!one_step && info->iters >= o.maxiter) {
-      reason = MNL_STOP_MAXITER;
-      break;
-    }
-    if (one_step && info->iters >= 1) break;
-    int r = MNL_STOP_NONE;
-    const double step_gnorm = gnorm;
-    MNL_TRY(newton_core(c, d, prob, theta, o, st, l, info, &r, s));
-    if (r != MNL_STOP_NONE) {
-      reason = r;
-      if (one_step) info->grad_norm = step_gnorm;
-      break;
-    }
-    info->iters += 1;
-    l = info->loglik;
-    MNL_HIP(c, launch_sumsq(st.lg + 1, d.np, gn2, s));
-    double h[1];
-    MNL_TRY(copy_d2h(c, h, gn2, 8, s));
-    gnorm = std::sqrt(h[0]);
-    if (one_step) {
-      info->grad_norm = step_gnorm;
-      info->loglik = l;
-      info->stop_reason = MNL_STOP_NONE;
-      info->t_total = now_ms() - t_start;
-      return MNL_OK;
-    }
-    if (std::fabs(info->loglik_diff) < o.ftol) {
-      reason = MNL_STOP_FTOL;
-      break;
-    }
-  }
-  info->stop_reason = reason;
-  info->loglik = l;
-  if (!one_step || reason == MNL_STOP_GTOL || reason == MNL_STOP_NONFINITE)
-    info->grad_norm = gnorm;
-  info->t_total = now_ms() - t_start;
-  return MNL_OK;
 }
 
 int mnl_newton_step(mnl_ctx *ctx, const mnl_problem *prob, double *theta,

@@ -127,6 +127,10 @@ struct HessArgs {
 };
 int hessian_run(Ctx *c, const HessArgs &a, hipStream_t s);
 void hessian_cache_free(Ctx *c);
+// Device bytes hessian_run takes for a shape: split partials (workspace
+// slot S_HPART) and tile tables.
+int hessian_footprint(Ctx *c, const Dims &d, int prec, size_t *part_bytes,
+                      size_t *table_bytes);
 
 // ---- Cholesky and solves ------------------------------------------------------
 // Factor A = -H in place (lower triangle holds L) and solve L L^T delta = g;
@@ -149,7 +153,31 @@ struct Ctx {
   bool hess_pending = false, pass_pending = false;
   // host-side caches of Hessian tile tables (keyed by shape)
   void *hess_cache = nullptr;
+  // stream-ordered mode (server slots): device memory comes from `pool`,
+  // allocated and freed in the order of `ostream`, the only stream the
+  // context's work runs on
+  hipMemPool_t pool = nullptr;
+  hipStream_t ostream = nullptr;
 };
+
+// Raise a kernel's dynamic-LDS limit on the current device to at least
+// `bytes`.  The limit only grows, so launches from several host threads
+// never see it lowered under them.
+hipError_t raise_lds_limit(const void *kernel, int bytes);
+
+// Validate a problem description and fill its dimensions.
+int check_problem(Ctx *c, const mnl_problem *pr, Dims *d);
+int check_opts(Ctx *c, const mnl_fit_opts *o);
+// Newton-Raphson loop on device data (theta in/out on the device).
+int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
+             const mnl_fit_opts &o, mnl_fit_info *info, bool one_step,
+             hipStream_t s);
+// Upper bound of the device bytes a fit of this shape allocates in its
+// context (workspace and tables; not the caller's data).
+int fit_workspace_footprint(Ctx *c, const Dims &d, int prec, size_t *bytes);
+// Free the context's workspace and tables (stream-ordered in pool mode).
+void ctx_release(Ctx *c);
+double now_ms();
 
 // Workspace slots
 enum Slot {

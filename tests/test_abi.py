@@ -84,9 +84,12 @@ def test_null_context_is_rejected(lib):
 def test_struct_layouts_match_header():
     # sizes of the ABI structs as laid out by the C compiler
     from paper_1404_3177_amd import _lib
+    names = ["mnl_problem", "mnl_fit_opts", "mnl_fit_info",
+             "mnl_server_opts", "mnl_server_result", "mnl_server_stats"]
+    fmt = " ".join(["%zu"] * len(names))
+    args = ", ".join(f"sizeof({n})" for n in names)
     src = f'#include "{HEADER}"\n#include <stdio.h>\nint main(void){{' \
-          'printf("%zu %zu %zu\\n", sizeof(mnl_problem), sizeof(mnl_fit_opts),' \
-          ' sizeof(mnl_fit_info)); return 0;}'
+          f'printf("{fmt}\\n", {args}); return 0;}}'
     exe = os.path.join("/tmp", "mnl_sizes")
     subprocess.run(["gcc", "-x", "c", "-", "-o", exe], input=src, text=True,
                    check=True)
@@ -94,4 +97,40 @@ def test_struct_layouts_match_header():
                                             text=True).stdout.split()]
     assert sizes == [ctypes.sizeof(_lib.MnlProblem),
                      ctypes.sizeof(_lib.MnlFitOpts),
-                     ctypes.sizeof(_lib.MnlFitInfo)]
+                     ctypes.sizeof(_lib.MnlFitInfo),
+                     ctypes.sizeof(_lib.MnlServerOpts),
+                     ctypes.sizeof(_lib.MnlServerResult),
+                     ctypes.sizeof(_lib.MnlServerStats)]
+
+
+def test_server_null_arguments_are_rejected(lib):
+    assert lib.mnl_server_create(None, None) == -1
+    assert lib.mnl_server_submit(None, None, None, None, None, 0.0, None) == -1
+    assert lib.mnl_server_wait(None, None, 0, 0.0, None) == -1
+    assert lib.mnl_server_get_stats(None, None) == -1
+    lib.mnl_server_destroy(None)
+    t0 = lib.mnl_server_now_ms()
+    assert lib.mnl_server_now_ms() >= t0
+
+
+def _footprint(N, K, p, g, a, prec="fp64", weights=False):
+    import paper_1404_3177_amd as mnl
+    return mnl.fit_footprint(N, K, p, g, a, prec, weights)
+
+
+def test_fit_footprint_covers_data_and_grows_with_the_shape(lib):
+    # host-only: the footprint comes from the kernels' plans, no device
+    N, K, p, g, a = 100_000, 50, 21, 5, 5
+    n_p = (K - 1) * p + K * a + g
+    f = _footprint(N, K, p, g, a)
+    data = 8 * N * (p + K * g + K * a) + 4 * N
+    # data, two FP64 probability arrays and the Hessian at least
+    assert f >= data + 2 * 8 * N * K + 8 * n_p * n_p
+    assert _footprint(2 * N, K, p, g, a) > f
+    assert _footprint(N, K + 1, p, g, a) > f
+    assert _footprint(N, K, p, g, a, weights=True) >= f + 8 * N
+    # mixed precision adds the FP32 copies of P (and keeps FP64 room)
+    assert _footprint(N, K, p, g, a, "bf16") > f
+    assert _footprint(N, 1, p, g, a) == -1
+    assert _footprint(0, K, p, g, a) == -1
+    assert lib.mnl_fit_footprint(None, 0) == -1
