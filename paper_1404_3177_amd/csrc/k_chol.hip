@@ -1,23 +1,20 @@
-// Newton direction (Eq. 6): delta = (-H)^{-1} g through the Cholesky factor
-// of A = -H, always in FP64.
+// Newton direction (Eq. 6): delta = (-H)^{-1} g through the factorisation
+// A = -H = L D L^T (L unit lower triangular, D diagonal), always in FP64.
 //
 // The matrix buffer has n + 1 rows: rows 0..n-1 hold H (row-major), row n
 // holds g^T.  Factoring the augmented lower triangle
-//     [ A    ]   [ L    ] [ L^T  z ]
-//     [ g^T  ] = [ z^T  ]
-// by blocked right-looking Cholesky leaves z = L^{-1} g in row n, so the
-// forward substitution comes out of the factorisation.  Per 32-wide panel:
-//   diag  : one wave factors the diagonal block in registers (LDL^T form,
-//           then scaled), checks the pivots against the round-off floor
-//           n * eps * max_k A_kk and writes L11 to scratch;
-//   trsm  : rows below the panel solve x L11^T = a, one row per thread;
-//   update: puts L11 in place, then A22 -= L21 L21^T on the lower 64x64
-//           tiles, FP64 MFMA.
-// Then L^T delta = z by 64-wide panels from the bottom: each workgroup
-// re-solves the panel's small triangular system itself and updates its
-// share of the remaining right-hand side, so one launch per panel suffices
-// and no two workgroups write the same entry.  A failure flag in device
-// memory makes every later launch return at once.
+//     [ A    ]   [ L    ] [ D ] [ L^T  y ]
+//     [ g^T  ] = [ y^T  ]
+// leaves y = D^{-1} L^{-1} g in row n, so the forward substitution comes out
+// of the factorisation and delta = L^{-T} y needs one unit-triangular solve.
+// One launch per 32-wide panel (k_chol_step) factors the panel and updates
+// the trailing lower triangle with FP64 MFMA; the first launch reads -H
+// directly.  Then L^T delta = y by 64-wide panels from the bottom: each
+// workgroup re-solves the panel's small unit-triangular system itself and
+// updates its share of the remaining right-hand side, so one launch per
+// panel suffices and no two workgroups write the same entry.  A failure flag
+// in device memory makes every later launch return at once.  In A, the
+// diagonal holds D and the strict lower triangle the multipliers of L.
 #include <cmath>
 
 #include "mnl_common.h"
@@ -31,29 +28,20 @@ constexpr int NBF = 32;   // factorisation panel width
 constexpr int NBS = 64;   // backward-solve panel width
 constexpr int TILE = 64;  // trailing-update tile
 
-__device__ inline double wsum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-// A <- -H on the lower triangle of rows 0..n-1 (nothing else is read)
-__global__ void k_negate_lower(double *A, int64_t n) {
-  const int64_t r = blockIdx.y;
-  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c <= r && r < n) A[r * n + c] = -A[r * n + c];
-}
-
-__global__ __launch_bounds__(256) void k_floor(const double *A, int64_t n,
+// Round-off floor of the pivots, n * eps * max_k A_kk with A = -H, and g^T
+// into row n of the matrix buffer.
+__global__ __launch_bounds__(256) void k_floor(double *Hm, int64_t n,
+                                               const double *g,
                                                double *floor_out,
                                                int32_t *info) {
   __shared__ double red[256];
   double m = 0.0;
   bool bad = false;
   for (int64_t i = threadIdx.x; i < n; i += 256) {
-    const double v = A[i * n + i];
+    const double v = -Hm[i * n + i];
     if (!isfinite(v)) bad = true;
     m = fmax(m, v);
+    Hm[n * n + i] = g[i];
   }
   red[threadIdx.x] = bad ? INFINITY : m;
   __syncthreads();
@@ -69,196 +57,276 @@ __global__ __launch_bounds__(256) void k_floor(const double *A, int64_t n,
   }
 }
 
-// Diagonal block of panel j0 (width jb <= NBF), one wave: lane i keeps row
-// i in registers; each LDL^T step broadcasts the finished column through
-// LDS.  Pivots are checked against the round-off floor; L11 goes to
-// scratch (l11, row-major NBF x NBF, identity rows past jb) and is put into
-// A by the next trailing-update launch.
-__global__ __launch_bounds__(64) void k_chol_diag(const double *A, int64_t n,
-                                                  int64_t j0,
-                                                  const double *floor_p,
-                                                  double *l11, int32_t *info) {
-  __shared__ double col[NBF];
-  if (info[0]) return;
-  const int jb = (int)min<int64_t>(NBF, n - j0);
-  const int tid = threadIdx.x;
-  const bool mine = tid < jb;
-  double a[NBF];
-  {
-    const double *src = A + (j0 + (mine ? tid : 0)) * n + j0;
-#pragma unroll
-    for (int j = 0; j < NBF; ++j)
-      a[j] = (mine && j <= tid && j < jb) ? src[j] : 0.0;
-  }
-#pragma unroll
-  for (int k = 0; k < NBF; ++k) {
-    if (k < jb) {
-      if (tid < jb) col[tid] = a[k];
-      __syncthreads();
-      const double lik = a[k] / col[k];
-#pragma unroll
-      for (int j = k + 1; j < NBF; ++j)
-        if (j <= tid) a[j] = fma(-lik, col[j], a[j]);
-      __syncthreads();
-    }
-  }
-  double d = 0.0;
-#pragma unroll
-  for (int j = 0; j < NBF; ++j)
-    if (j == tid) d = a[j];
-  if (tid < jb) col[tid] = d;
-  __syncthreads();
-  const double fl = *floor_p;
-  for (int k = 0; k < jb; ++k) {
-    const double dk = col[k];
-    if (!(dk > fl) || !isfinite(dk)) {
-      if (tid == 0) info[0] = int(j0 + k + 1);
-      return;
-    }
-  }
-  if (tid < NBF) {
-    double *dst = l11 + tid * NBF;
-#pragma unroll
-    for (int j = 0; j < NBF; ++j) {
-      double v;
-      if (!mine) v = (j == tid) ? 1.0 : 0.0;
-      else if (j < tid) v = a[j] / sqrt(col[j]);
-      else if (j == tid) v = sqrt(col[j]);
-      else v = 0.0;
-      dst[j] = v;
-    }
-  }
+// 1 / d to within an ulp: hardware estimate and two Newton steps
+__device__ inline double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(e, r, r);
+  e = fma(-d, r, 1.0);
+  return fma(e, r, r);
 }
 
-// rows below panel j0: x L11^T = a, one row per thread in registers, L11
-// broadcast from LDS (its padding rows are the identity, so no bounds on
-// the column index are needed)
-__global__ __launch_bounds__(64) void k_chol_trsm(double *A, int64_t n,
-                                                  int64_t nrows, int64_t j0,
-                                                  const double *l11,
-                                                  const int32_t *info) {
-  __shared__ double L[NBF][NBF + 1];
-  if (info[0]) return;
-  const int jb = (int)min<int64_t>(NBF, n - j0);
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NBF * NBF; e += 64)
-    L[e / NBF][e % NBF] = l11[e];
+// One step of the blocked right-looking LDL^T factorisation, panel j0
+// (width jb <= NBF), in a single launch.  Workgroup b owns the lower 64x64
+// tile (ti, tj) of the trailing rows [j1, nrows) x columns [j1, n),
+// j1 = j0 + jb.  Every wave factors the panel's diagonal block itself
+// (lanes 0..31 hold its rows) while lanes 32..63 carry 32 panel rows of tile
+// row ti (waves 0, 1) or tile column tj (waves 2, 3) through the same column
+// steps, so the diagonal factor and the panel's triangular solve are one
+// chain with no barrier across waves.  The multiplier rows then feed the
+// FP64-MFMA update A22 -= L21 D L21^T of the tile.  The panel's columns are
+// only read in this launch: its factor goes to scratch `cur` and the next
+// launch (or k_chol_copy) writes it into A, so no workgroup overwrites what
+// another still reads.  With neg set (the first panel) rows 0..n-1 of the
+// buffer still hold H and every value read from them is negated (row n is
+// g itself).  Pivots are checked against the round-off floor.
+__global__ __launch_bounds__(256) void k_chol_step(
+    double *A, int64_t n, int64_t nrows, int64_t j0, const double *prev,
+    int64_t j0p, double *cur, const double *floor_p, int32_t *info, int neg) {
+  __shared__ double Pr[TILE][NBF + 1];
+  __shared__ double Pc[TILE][NBF + 1];
+  __shared__ double colb[4][128];
+  __shared__ int fail;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // one read of the failure flag for the whole workgroup (other workgroups
+  // may set it meanwhile), so every wave takes the same branch
+  if (tid == 0) fail = info[0];
   __syncthreads();
-  const int64_t r = j0 + jb + int64_t(blockIdx.x) * 64 + tid;
-  if (r >= nrows) return;
-  double x[NBF];
-  double *row = A + r * n + j0;
-#pragma unroll
-  for (int c = 0; c < NBF; ++c) x[c] = c < jb ? row[c] : 0.0;
-  // the runtime bound keeps the compiler from hoisting all of L11 into
-  // registers ahead of the substitution
-#pragma unroll
-  for (int c = 0; c < NBF; ++c) {
-    if (c < jb) {
-      double s0 = x[c];
-#pragma unroll
-      for (int k = 0; k < c; ++k) s0 = fma(-x[k], L[c][k], s0);
-      x[c] = s0 / L[c][c];
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < NBF; ++c)
-    if (c < jb) row[c] = x[c];
-}
-
-// trailing update on lower tiles of rows/cols >= j0 + jb (rows up to
-// nrows - 1, columns up to n - 1): A[R][C] -= L21[R] . L21[C], FP64 MFMA
-__global__ __launch_bounds__(256) void k_chol_update(double *A, int64_t n,
-                                                     int64_t nrows, int64_t j0,
-                                                     const double *l11,
-                                                     const int32_t *info) {
-  __shared__ double Ar[TILE][NBF + 1];
-  __shared__ double Ac[TILE][NBF + 1];
-  if (info[0]) return;
+  if (fail) return;
   const int jb = (int)min<int64_t>(NBF, n - j0);
   const int64_t j1 = j0 + jb;
-  if (blockIdx.x == 0) {
-    // the panel's factored diagonal block, written by k_chol_panel
-    for (int e = threadIdx.x; e < jb * jb; e += 256) {
-      const int i = e / jb, j = e - (e / jb) * jb;
-      if (j <= i) A[(j0 + i) * n + j0 + j] = l11[i * NBF + j];
-    }
-  }
   const int64_t b = blockIdx.x;
   int64_t ti = (int64_t)((sqrt(8.0 * double(b) + 1.0) - 1.0) * 0.5);
   while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
   while (ti * (ti + 1) / 2 > b) --ti;
   const int64_t tj = b - ti * (ti + 1) / 2;
   const int64_t R0 = j1 + ti * TILE, C0 = j1 + tj * TILE;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < TILE * NBF; e += 256) {
-    const int i = e / NBF, k = e - (e / NBF) * NBF;
-    const int64_t rr = R0 + i, cc = C0 + i;
-    Ar[i][k] = (rr < nrows && k < jb) ? A[rr * n + j0 + k] : 0.0;
-    Ac[i][k] = (cc < n && k < jb) ? A[cc * n + j0 + k] : 0.0;
+  const bool same = ti == tj;
+
+  // my row: lanes < 32 a row of the diagonal block (identity past jb),
+  // lanes >= 32 a panel row (zero when out of range).  The matrix buffer
+  // carries NBF doubles of padding, so all NBF entries of a row can be
+  // loaded unconditionally and masked afterwards.
+  const bool diag = lane < NBF;
+  int64_t prow = -1;
+  if (!diag) {
+    const int64_t i = int64_t(wv & 1) * 32 + (lane - NBF);
+    if (wv < 2) prow = R0 + i < nrows ? R0 + i : -1;
+    else if (!same) prow = C0 + i < n ? C0 + i : -1;
   }
-  __syncthreads();
-  const int lane = tid & 63, wv = tid >> 6;
-  d4 acc[4];
+  const int ncols = diag ? (lane < jb ? lane + 1 : 0) : (prow >= 0 ? jb : 0);
+  const int64_t srow = diag ? j0 + min(lane, jb - 1) : (prow >= 0 ? prow : 0);
+  const double sgn = (neg && srow < n) ? -1.0 : 1.0;
+  double x[NBF];
+  {
+    const double *s1 = A + srow * n + j0;
+    if (((srow * n + j0) & 1) == 0) {
+      const double2 *s2 = reinterpret_cast<const double2 *>(s1);
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = d4{0, 0, 0, 0};
-  const int ar = 16 * wv + (lane & 15);
+      for (int k = 0; k < NBF / 2; ++k) {
+        const double2 v = s2[k];
+        x[2 * k] = v.x;
+        x[2 * k + 1] = v.y;
+      }
+    } else {
 #pragma unroll
-  for (int ks = 0; ks < NBF / 4; ++ks) {
-    const int k = 4 * ks + (lane >> 4);
-    const double av = Ar[ar][k];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const double bv = Ac[16 * t + (lane & 15)][k];
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+      for (int k = 0; k < NBF; ++k) x[k] = s1[k];
     }
   }
+  // the tile this workgroup updates, loaded while the chain runs
+  const bool upd = C0 < n;
+  double tv[4][4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t rr = R0 + 16 * wv + (lane >> 4) + 4 * r;
       const int64_t cc = C0 + 16 * t + (lane & 15);
-      if (rr < nrows && cc < n && cc <= rr) A[rr * n + cc] -= acc[t][r];
+      tv[t][r] = (upd && rr < nrows && cc < n && cc <= rr) ? A[rr * n + cc] : 0.0;
+    }
+#pragma unroll
+  for (int k = 0; k < NBF; ++k) {
+    const double one = (diag && k == lane) ? 1.0 : 0.0;
+    x[k] = k < ncols ? sgn * x[k] : one;
+  }
+  // column steps, branch-free: lanes publish column k of the diagonal rows
+  // through this wave's LDS buffer (lanes >= 32 write to a dummy half; LDS
+  // operations of one wave complete in order), every lane forms its
+  // multiplier with the reciprocal of the pivot and updates its remaining
+  // entries
+  const double fl = *floor_p;
+  int bad = NBF;
+  double dmine = 1.0;
+  double *cbw = &colb[wv][0];
+#pragma unroll
+  for (int k = 0; k < NBF; ++k) {
+    cbw[lane] = x[k];
+    __builtin_amdgcn_wave_barrier();
+    const double dk = cbw[k];
+    const bool ok = dk > fl && isfinite(dk);
+    bad = (k < jb && !ok && bad == NBF) ? k : bad;
+    dmine = lane == k ? dk : dmine;
+    const double r = recip(dk);
+    const bool act = !diag || lane > k;
+    const double l = act ? x[k] * r : 0.0;
+#pragma unroll
+    for (int j = k + 1; j < NBF; ++j) x[j] = fma(-l, cbw[j], x[j]);
+    x[k] = act ? l : x[k];
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (bad < NBF) {
+    if (tid == 0) info[0] = int(j0 + bad + 1);
+    return;  // the same pivot fails in every wave of every workgroup
+  }
+  // x now holds the multipliers (and d on a diagonal row's own entry);
+  // D goes to this wave's buffer, L21 D to Pr and L21 to Pc
+  double *dds = &colb[wv][64];
+  if (diag) dds[lane] = dmine;
+  __builtin_amdgcn_wave_barrier();
+  if (!diag) {
+    const int i = (wv & 1) * 32 + (lane - NBF);
+    if (wv < 2) {
+#pragma unroll
+      for (int k = 0; k < NBF; ++k) Pr[i][k] = x[k] * dds[k];
+      if (same) {
+#pragma unroll
+        for (int k = 0; k < NBF; ++k) Pc[i][k] = x[k];
+      }
+    } else if (!same) {
+#pragma unroll
+      for (int k = 0; k < NBF; ++k) Pc[i][k] = x[k];
+    }
+  }
+  __syncthreads();
+  if (upd) {
+    // A[R][C] -= L21[R] D L21[C]^T, lower part
+    d4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = d4{0, 0, 0, 0};
+    const int ar = 16 * wv + (lane & 15);
+#pragma unroll
+    for (int ks = 0; ks < NBF / 4; ++ks) {
+      const int k = 4 * ks + (lane >> 4);
+      const double av = Pr[ar][k];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double bv = Pc[16 * t + (lane & 15)][k];
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t rr = R0 + 16 * wv + (lane >> 4) + 4 * r;
+        const int64_t cc = C0 + 16 * t + (lane & 15);
+        const double sr = (neg && rr < n) ? -1.0 : 1.0;
+        if (rr < nrows && cc < n && cc <= rr)
+          A[rr * n + cc] = sr * tv[t][r] - acc[t][r];
+      }
+    }
+  }
+  // this panel's factor to scratch
+  if (!diag) {
+    if (wv < 2 && tj == 0 && prow >= 0) {
+      double2 *dst = reinterpret_cast<double2 *>(cur + prow * NBF);
+#pragma unroll
+      for (int k = 0; k < NBF / 2; ++k) dst[k] = double2{x[2 * k], x[2 * k + 1]};
+    }
+  } else if (b == 0 && wv == 0 && lane < jb) {
+#pragma unroll
+    for (int k = 0; k < NBF; ++k)
+      if (k <= lane) cur[(j0 + lane) * NBF + k] = x[k];
+  }
+  // the previous panel's factor into A (columns nobody reads here)
+  if (prev) {
+    const int64_t cnt = (nrows - j0p) * NBF;
+    for (int64_t e = int64_t(blockIdx.x) * 256 + tid; e < cnt;
+         e += int64_t(gridDim.x) * 256) {
+      const int64_t r = j0p + e / NBF;
+      const int k = int(e % NBF);
+      if (r - j0p >= NBF || k <= r - j0p) A[r * n + j0p + k] = prev[r * NBF + k];
     }
   }
 }
 
-// backward substitution, panel j0: d_p = L11^{-T} z_p, then
-// z_c -= sum_r L_rc d_r for the columns c < j0
+// the last panel's factor into A, and y (row n) into z
+__global__ __launch_bounds__(256) void k_chol_copy(double *A, int64_t n,
+                                                   int64_t nrows, int64_t j0p,
+                                                   const double *prev,
+                                                   double *z,
+                                                   const int32_t *info) {
+  if (info[0]) return;
+  const int64_t cnt = (nrows - j0p) * NBF;
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < cnt;
+       e += int64_t(gridDim.x) * 256) {
+    const int64_t r = j0p + e / NBF;
+    const int k = int(e % NBF);
+    if (j0p + k < n && (r - j0p >= NBF || k <= r - j0p))
+      A[r * n + j0p + k] = prev[r * NBF + k];
+  }
+  for (int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x; c < n;
+       c += int64_t(gridDim.x) * 256)
+    z[c] = c >= j0p ? prev[n * NBF + (c - j0p)] : A[n * n + c];
+}
+
+__device__ inline double readlane_f64(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l);
+  const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), l);
+  return __builtin_bit_cast(double, uint64_t(lo) | (uint64_t(hi) << 32));
+}
+
+// backward substitution L^T delta = y, panel j0 (jb <= NBS rows): every
+// workgroup solves the panel's unit-triangular system in one wave (delta_c
+// broadcast by readlane), then subtracts L[panel][c]^T delta_panel from its
+// 64-column chunk of z (four row groups, summed in a fixed order)
 __global__ __launch_bounds__(256) void k_chol_bwd(const double *A, int64_t n,
                                                   int64_t j0, double *z,
                                                   double *delta,
                                                   const int32_t *info) {
   __shared__ double L[NBS][NBS + 1];
   __shared__ double dp[NBS];
+  __shared__ double part[4][64];
   if (info[0]) return;
   const int jb = (int)min<int64_t>(NBS, n - j0);
   const int tid = threadIdx.x;
   for (int e = tid; e < jb * jb; e += 256) {
     const int i = e / jb, j = e - (e / jb) * jb;
-    L[i][j] = (j <= i) ? A[(j0 + i) * n + j0 + j] : 0.0;
+    L[i][j] = (j < i) ? A[(j0 + i) * n + j0 + j] : 0.0;
   }
   __syncthreads();
   if (tid < 64) {
-    double dl = tid < jb ? z[j0 + tid] : 0.0;
-    for (int c = jb - 1; c >= 0; --c) {
-      const double part = wsum((tid > c && tid < jb) ? L[tid][c] * dl : 0.0);
-      if (tid == c) dl = (dl - part) / L[c][c];
+    // rows past jb are identity rows, so the chain always has NBS steps
+    // (unrolled: the L loads do not wait on the chain)
+    double zt = tid < jb ? z[j0 + tid] : 0.0;
+    double dl = 0.0;
+#pragma unroll
+    for (int c = NBS - 1; c >= 0; --c) {
+      const double lc = (c < jb && tid < c) ? L[c][tid] : 0.0;
+      const double dc = readlane_f64(zt, c);
+      dl = tid == c ? dc : dl;
+      zt = fma(-lc, dc, zt);
     }
     dp[tid] = dl;
   }
   __syncthreads();
   if (blockIdx.x == 0 && tid < jb) delta[j0 + tid] = dp[tid];
-  const int64_t c = int64_t(blockIdx.x) * 256 + tid;
+  const int64_t c = int64_t(blockIdx.x) * 64 + (tid & 63);
+  const int grp = tid >> 6;
+  double s = 0.0;
   if (c < j0) {
-    // independent partial sums keep many loads in flight
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
     const double *colp = A + j0 * n + c;
-#pragma unroll 16
-    for (int r = 0; r < jb; ++r) s[r & 3] = fma(colp[int64_t(r) * n], dp[r], s[r & 3]);
-    z[c] -= (s[0] + s[1]) + (s[2] + s[3]);
+    double s2[2] = {0.0, 0.0};
+#pragma unroll 8
+    for (int r = grp; r < jb; r += 4)
+      s2[(r >> 2) & 1] = fma(colp[int64_t(r) * n], dp[r], s2[(r >> 2) & 1]);
+    s = s2[0] + s2[1];
   }
+  part[grp][tid & 63] = s;
+  __syncthreads();
+  if (grp == 0 && c < j0)
+    z[c] -= (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
 }
 
 }  // namespace
@@ -266,35 +334,37 @@ __global__ __launch_bounds__(256) void k_chol_bwd(const double *A, int64_t n,
 int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
                    double *delta, int32_t *info, hipStream_t s) {
   void *scr;
-  MNL_TRY(ws_get(c, S_CHOL, size_t(n + 8 + NBF * NBF) * 8, &scr));
-  double *z = static_cast<double *>(scr);
-  double *floor_p = z + n;
-  double *l11 = floor_p + 8;
   const int64_t nrows = n + 1;
-  // g^T as row n of the augmented matrix
-  MNL_HIP(c, hipMemcpyAsync(A + n * n, g, size_t(n) * 8,
-                            hipMemcpyDeviceToDevice, s));
-  {
-    dim3 grid((unsigned)((n + 255) / 256), (unsigned)n);
-    hipLaunchKernelGGL(k_negate_lower, grid, dim3(256), 0, s, A, n);
-  }
-  hipLaunchKernelGGL(k_floor, dim3(1), dim3(256), 0, s, A, n, floor_p, info);
-  for (int64_t j0 = 0; j0 < n; j0 += NBF) {
+  // two panel buffers of nrows x NBF (each a multiple of 256 bytes, so
+  // both stay 16-byte aligned), z, floor
+  MNL_TRY(ws_get(c, S_CHOL, size_t(n + 8 + 2 * nrows * NBF) * 8, &scr));
+  double *pbuf[2] = {static_cast<double *>(scr),
+                     static_cast<double *>(scr) + nrows * NBF};
+  double *z = pbuf[1] + nrows * NBF;
+  double *floor_p = z + n;
+  hipLaunchKernelGGL(k_floor, dim3(1), dim3(256), 0, s, A, n, g, floor_p,
+                     info);
+  int step = 0;
+  int64_t j0p = -1;
+  for (int64_t j0 = 0; j0 < n; j0 += NBF, ++step) {
     const int64_t jb = std::min<int64_t>(NBF, n - j0);
     const int64_t rest = nrows - j0 - jb;   // >= 1: the g row
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, s, A, n, j0,
-                       floor_p, l11, info);
-    hipLaunchKernelGGL(k_chol_trsm, dim3((unsigned)((rest + 63) / 64)),
-                       dim3(64), 0, s, A, n, nrows, j0, l11, info);
     const int64_t T = (rest + TILE - 1) / TILE;
-    hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(T * (T + 1) / 2)),
-                       dim3(256), 0, s, A, n, nrows, j0, l11, info);
+    const double *prev = j0p >= 0 ? pbuf[(step - 1) & 1] : nullptr;
+    hipLaunchKernelGGL(k_chol_step, dim3((unsigned)(T * (T + 1) / 2)),
+                       dim3(256), 0, s, A, n, nrows, j0, prev, j0p,
+                       pbuf[step & 1], floor_p, info, j0 == 0 ? 1 : 0);
+    j0p = j0;
   }
-  MNL_HIP(c, hipMemcpyAsync(z, A + n * n, size_t(n) * 8,
-                            hipMemcpyDeviceToDevice, s));
+  {
+    const int64_t cnt = std::max<int64_t>((nrows - j0p) * NBF, n);
+    const unsigned gr = (unsigned)std::min<int64_t>(1024, (cnt + 255) / 256);
+    hipLaunchKernelGGL(k_chol_copy, dim3(gr), dim3(256), 0, s, A, n, nrows,
+                       j0p, pbuf[(step - 1) & 1], z, info);
+  }
   const int64_t last = ((n - 1) / NBS) * NBS;
   for (int64_t j0 = last; j0 >= 0; j0 -= NBS) {
-    const unsigned gr = (unsigned)std::max<int64_t>(1, (j0 + 255) / 256);
+    const unsigned gr = (unsigned)std::max<int64_t>(1, (j0 + 63) / 64);
     hipLaunchKernelGGL(k_chol_bwd, dim3(gr), dim3(256), 0, s, A, n, j0, z,
                        delta, info);
   }

@@ -259,8 +259,9 @@ int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
                 mnl_fit_info *info, int *reason, hipStream_t s) {
   const bool mixed = o.prec != MNL_PREC_FP64;
   void *Hv, *dv, *tv, *sv;
-  // n_p + 1 rows: the factorisation carries g as an extra row
-  MNL_TRY(ws_get(c, S_H, size_t(d.np + 1) * d.np * 8, &Hv));
+  // n_p + 1 rows: the factorisation carries g as an extra row; 64 doubles
+  // of padding let its kernels load whole panel rows unconditionally
+  MNL_TRY(ws_get(c, S_H, (size_t(d.np + 1) * d.np + 64) * 8, &Hv));
   MNL_TRY(ws_get(c, S_DELTA, size_t(d.np) * 8, &dv));
   MNL_TRY(ws_get(c, S_THETA_TRIAL, size_t(d.np) * 8, &tv));
   MNL_TRY(ws_get(c, S_SCAL, 256, &sv));
@@ -425,9 +426,9 @@ int fit_workspace_footprint(Ctx *c, const Dims &d, int prec, size_t *bytes) {
   t += 2 * al(N * K * 8);                               // S_P, S_P_TRIAL
   if (prec != MNL_PREC_FP64) t += 2 * al(N * K * 4);   // S_P32 pair
   if (d.g) t += 2 * al(N * size_t(d.g) * 8);            // S_YBAR pair
-  t += al((np + 1) * np * 8);                           // S_H
+  t += al(((np + 1) * np + 64) * 8);                    // S_H
   t += 2 * al(np * 8) + al(256);                        // delta, trial, scalars
-  t += al((np + 8 + 32 * 32) * 8);                      // Cholesky scratch
+  t += al((np + 8 + 2 * (np + 1) * 32) * 8);            // Cholesky scratch
   // Hessian partials and tables; a mixed fit may redo the Hessian in FP64
   size_t part = 0, tab = 0;
   MNL_TRY(hessian_footprint(c, d, prec, &part, &tab));

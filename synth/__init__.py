@@ -15,4 +15,5 @@ from .gen import (  # noqa: F401
     serving_request_shapes,
     serving_request,
     serving_arrivals,
+    ServingStream,
 )

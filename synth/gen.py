@@ -165,3 +165,77 @@ def serving_arrivals(n: int, rate: float) -> np.ndarray:
     requests per second."""
     rng = np.random.Generator(np.random.PCG64(SERVING_SEED))
     return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+class ServingStream:
+    """Host data of the serving stream, drawn fast enough to feed the GPU.
+
+    Request r has the shape serving_request_shapes(r), its own coefficients
+    (N(0, 0.5^2)) and its own simulated choices (Gumbel-max over its
+    utilities, as make_problem).  Drawing every request's features afresh
+    would cost the host more time than the GPU needs for the fit, so the
+    features are windows into shared N(0,1) pools, at offsets drawn from the
+    request's seed: X from a pool of rows of width p whose column 0 is the
+    intercept, Y from a flat pool, and the Gumbel noise of the choices from
+    a Gumbel pool.  Each request's arrays are plain contiguous views (no
+    copies); ``alloc(shape, dtype)`` supplies the pools' and the choices'
+    memory (e.g. page-locked host memory).
+    """
+
+    def __init__(self, n_requests: int, seed: int = SERVING_SEED,
+                 alloc=None, threads: int = 8):
+        self.shapes = [serving_request_shapes(r) for r in range(n_requests)]
+        self.alloc = alloc or (lambda shape, dt: np.empty(shape, dtype=dt))
+        self.threads = threads
+        rng = np.random.Generator(np.random.PCG64(seed * 1_000_003 + 17))
+        slack = 1 << 16
+        max_n = max(s["N"] for s in self.shapes)
+        ny = max(s["N"] * s["K"] * s["g"] for s in self.shapes)
+        ng = max(s["N"] * s["K"] for s in self.shapes)
+        ps = sorted({s["p"] for s in self.shapes})
+        self.rows = max_n + slack
+        flat = self.alloc((ny + slack,), np.float64)
+        flat[:] = rng.standard_normal(flat.shape[0])
+        self.ypool = flat
+        self.xpool = {}
+        for p in ps:
+            xp = self.alloc((self.rows, p), np.float64)
+            xp[:, 1:] = rng.standard_normal((self.rows, p - 1))
+            xp[:, 0] = 1.0
+            self.xpool[p] = xp
+        gp = self.alloc((ng + slack,), np.float64)
+        gp[:] = rng.gumbel(size=gp.shape[0])
+        self.gpool = gp
+
+    def request(self, r: int) -> Problem:
+        s = self.shapes[r]
+        N, K, p, g = s["N"], s["K"], s["p"], s["g"]
+        rng = np.random.Generator(np.random.PCG64(s["seed"]))
+        ox = int(rng.integers(0, self.rows - N + 1))
+        X = self.xpool[p][ox:ox + N]
+        ny = N * K * g
+        oy = int(rng.integers(0, self.ypool.shape[0] - ny + 1))
+        Y = self.ypool[oy:oy + ny].reshape(N, K, g)
+        n_p = (K - 1) * p + g
+        theta = 0.5 * rng.standard_normal(n_p)
+        og = int(rng.integers(0, self.gpool.shape[0] - N * K + 1))
+        gumbel = self.gpool[og:og + N * K].reshape(N, K)
+        beta = np.zeros((K, p))
+        beta[1:] = theta[:(K - 1) * p].reshape(K - 1, p)
+        util = X @ beta.T
+        if g:
+            util += (Y.reshape(N * K, g) @ theta[(K - 1) * p:]).reshape(N, K)
+        choice = self.alloc((N,), np.int32)
+        choice[:] = np.argmax(util + gumbel, axis=1)
+        return Problem(N=N, K=K, p=p, g=g, a=0, X=X, Y=Y,
+                       Z=np.zeros((N, K, 0)), choice=choice, w=None,
+                       theta_true=theta, name=f"req{r}",
+                       meta=dict(seed=s["seed"], coef_sd=0.5, rho=0.0,
+                                 weights=None, pooled=True))
+
+    def requests(self) -> list:
+        """All requests, drawn on a thread pool (numpy releases the GIL in
+        the matrix products)."""
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(self.threads) as ex:
+            return list(ex.map(self.request, range(len(self.shapes))))
