@@ -13,7 +13,10 @@ Prints one JSON line.  Besides the fit rate it reports the Hessian MFMA
 kernel's rate against the MFMA peak of its dtype (HIP events around every
 launch, on the stream it runs on), the fused pass kernel's HBM rate, the
 p50/p99 fit latency, the FP32-Hessian variant and the FP64 CPU oracle timed
-on the host cores over a bounded sample.
+on the host cores over a bounded sample, and the continuous-batching
+server on a stream of uneven fits: saturated fits/s (mixed-precision and
+FP64 Hessians), p50/p99 latency under Poisson arrivals, and a batch of 1024
+small fits.
 """
 import argparse
 import json
@@ -150,6 +153,104 @@ def cpu_baseline(pr, iters, target_s=12.0):
             "seconds_per_iteration_full_N": t_iter}
 
 
+STOP_NAMES = {0: "none", 1: "gtol", 2: "ftol", 3: "maxiter", 4: "ls_fail",
+              5: "not_pd", 6: "nonfinite"}
+
+
+def serve_run(hps, slots, prec, arrivals_s=None):
+    """Run host problems through a fresh continuous-batching server.  With
+    arrivals_s (seconds from the start) requests are submitted at those
+    times (open loop); without, all at once (closed loop, the saturated
+    rate).  Latency = completion (theta in host memory) - arrival."""
+    import threading
+    import paper_1404_3177_amd as mnl
+    srv = mnl.Server(slots=slots)
+    n = len(hps)
+    res = []
+
+    def collect():
+        while len(res) < n:
+            res.extend(srv.wait(timeout_ms=200.0))
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = srv.now_ms() + 20.0
+    for i, h in enumerate(hps):
+        t_arr = t0 + (arrivals_s[i] * 1e3 if arrivals_s is not None else 0.0)
+        while True:
+            dt = t_arr - srv.now_ms()
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 2.0) * 1e-3)
+        srv.submit(h, gtol=GTOL, ftol=0.0, prec=prec, t_arrival=t_arr)
+    th.join()
+    st = srv.stats()
+    srv.close()
+    span = max(r["t_done"] for r in res) - t0
+    lat = [r["t_done"] - r["t_arrival"] for r in res]
+    stops = {}
+    for r in res:
+        k = STOP_NAMES.get(r["info"]["stop_reason"], "error") \
+            if r["status"] == 0 else f"error{r['status']}"
+        stops[k] = stops.get(k, 0) + 1
+    conv = sum(1 for r in res if r["status"] == 0 and
+               r["info"]["stop_reason"] == 1)
+    return {"requests": n, "fits_per_s": n / span * 1e3,
+            "converged_fits_per_s": conv / span * 1e3,
+            "span_s": span * 1e-3,
+            "latency_ms": {"p50": percentile(lat, 0.5),
+                           "p99": percentile(lat, 0.99),
+                           "max": max(lat)},
+            "iters_mean": sum(r["info"]["iters"] for r in res) / n,
+            "stop_reasons": stops, "max_running": st["max_running"],
+            "peak_footprint_gb": st["peak_in_use"] / 1e9}
+
+
+def serving(n_req, slots, load):
+    """The serving stream (uneven fits, mixed-precision Hessian): saturated
+    rate, Poisson arrivals at load x that rate, the FP64 path at saturation
+    for comparison, and a batch of 1024 independent small fits."""
+    import numpy as np
+    import torch
+    import paper_1404_3177_amd as mnl
+    import synth
+
+    def pinned(shape, dt):
+        tdt = {np.dtype(np.float64): torch.float64,
+               np.dtype(np.int32): torch.int32}[np.dtype(dt)]
+        return torch.empty(shape, dtype=tdt, pin_memory=True).numpy()
+    log(f"serving: drawing {n_req} requests")
+    t = time.perf_counter()
+    reqs = synth.ServingStream(n_req, alloc=pinned).requests()
+    hps = [mnl.HostProblem.from_numpy(r) for r in reqs]
+    log(f"serving: requests ready in {time.perf_counter() - t:.1f} s")
+    out = {"workload": (f"{n_req} requests: N log-uniform in [1e3, 2e5], K in "
+                        f"5..60, p = 1 + 5..30, g in 0..5, a = 0; fit to "
+                        f"||g||_2<=1e-8 from theta=0"),
+           "slots": slots}
+    log("serving: closed loop, bf16 Hessian")
+    sat = serve_run(hps, slots, "bf16")
+    log(f"serving: saturated {sat['fits_per_s']:.1f} fits/s")
+    out["bf16_saturated"] = sat
+    log("serving: closed loop, fp64 Hessian")
+    out["fp64_saturated"] = serve_run(hps, slots, "fp64")
+    rate = load * sat["fits_per_s"]
+    arr = synth.serving_arrivals(n_req, rate)
+    log(f"serving: Poisson arrivals at {rate:.1f} requests/s, bf16 Hessian")
+    ol = serve_run(hps, slots, "bf16", arrivals_s=arr)
+    ol["arrival_rate"] = rate
+    ol["load"] = load
+    out["bf16_poisson"] = ol
+    out["mixed_vs_fp64_saturated"] = (sat["fits_per_s"] /
+                                      out["fp64_saturated"]["fits_per_s"])
+    log("serving: 1024 independent c1 fits (fp64)")
+    c1 = [synth.make_problem(2000, 10, 6, 1, 0, seed=1000 + i, coef_sd=0.5)
+          for i in range(1024)]
+    out["c1_batch_1024_fp64"] = serve_run(
+        [mnl.HostProblem.from_numpy(p, pinned=True) for p in c1], slots,
+        "fp64")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +260,10 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the serving stream (0: skip serving)")
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-load", type=float, default=0.8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the "
@@ -214,6 +319,10 @@ def main():
                     np.linalg.norm(gold["theta"]))
             variants[f"{vp}_hessian"] = ent
 
+    serve = None
+    if args.serve_requests > 0:
+        serve = serving(args.serve_requests, args.serve_slots, args.serve_load)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 CPU oracle (bounded sample)")
@@ -268,6 +377,7 @@ def main():
                 "phase_ms": {k: info[k] for k in ("t_loglik_grad", "t_hessian",
                                                    "t_chol", "t_ls")}},
         "variants": variants,
+        "serving": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

@@ -249,6 +249,10 @@ class Server:
             raise MnlError(rc, "mnl_server_create failed")
         self.h = h
         self._live = {}
+        import threading
+        # submit() and wait() may run on different threads: a result is
+        # matched to its request only after submit() has recorded it
+        self._lock = threading.Lock()
 
     def now_ms(self) -> float:
         return float(self.lib.mnl_server_now_ms())
@@ -262,13 +266,15 @@ class Server:
         if theta0 is not None:
             th0 = np.ascontiguousarray(theta0, dtype=np.float64)
         rid = ctypes.c_int64()
-        rc = self.lib.mnl_server_submit(
-            self.h, ctypes.byref(prob.c),
-            th0.ctypes.data if th0 is not None else None, ctypes.byref(o),
-            theta.ctypes.data, float(t_arrival), ctypes.byref(rid))
-        if rc != 0:
-            raise MnlError(rc, "mnl_server_submit refused the request")
-        self._live[rid.value] = (prob, theta, th0)
+        with self._lock:
+            rc = self.lib.mnl_server_submit(
+                self.h, ctypes.byref(prob.c),
+                th0.ctypes.data if th0 is not None else None,
+                ctypes.byref(o), theta.ctypes.data, float(t_arrival),
+                ctypes.byref(rid))
+            if rc != 0:
+                raise MnlError(rc, "mnl_server_submit refused the request")
+            self._live[rid.value] = (prob, theta, th0)
         return rid.value
 
     def wait(self, max_results: int = 256, timeout_ms: float = -1.0) -> list:
@@ -280,7 +286,8 @@ class Server:
             raise MnlError(rc, "mnl_server_wait failed")
         out = []
         for r in buf[:n.value]:
-            _, theta, _ = self._live.pop(r.id)
+            with self._lock:
+                _, theta, _ = self._live.pop(r.id)
             out.append(dict(id=r.id, status=r.status, slot=r.slot,
                             t_arrival=r.t_arrival, t_admit=r.t_admit,
                             t_done=r.t_done, footprint=r.footprint,
