@@ -150,20 +150,20 @@ __host__ __device__ inline TileLds tile_lds(int type, int KC, int K, int p,
 // operand type, then each wave runs 16 rows x 16 tn columns of MFMAs from
 // LDS.  Several workgroups share a CU, so one's loads overlap another's
 // MFMAs.
-template <int PREC>
+template <int PREC, int TNV>
 __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
   using M = MF<PREC>;
   constexpr int kRows = 16 * M::NW, NT = 64 * M::NW;
   using T = typename M::T;
   using OT = typename M::OT;
-  constexpr int TNM = M::TN;
+  constexpr int TNM = TNV;
   extern __shared__ double smd[];
   char *smb = reinterpret_cast<char *>(smd);
   const Tile tile = H.tiles[blockIdx.x];
   const Dims d = H.d;
   const int K = d.K, p = d.p, a = d.a;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int tn = tile.tn, bn = 16 * tn;
+  constexpr int bn = 16 * TNV;
   const bool is_bb = tile.type == T_BB;
   const int KC = is_bb ? H.kc_bb : H.kc_xg;
   const int kp = PREC == 2 ? KC + 8 : KC;
@@ -321,32 +321,43 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
         const int kb = 32 * ks + 8 * (lane >> 4);
         const bf8 av = *reinterpret_cast<const bf8 *>(opa + arow * kp + kb);
         const OT *bp = opb + (lane & 15) * kp + kb;
+        bf8 bv[TNM];
 #pragma unroll
-        for (int t = 0; t < TNM; ++t) {
-          if (t < tn) {
-            const bf8 bv = *reinterpret_cast<const bf8 *>(bp + 16 * t * kp);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t],
-                                                             0, 0, 0);
-          }
-        }
+        for (int t = 0; t < TNM; ++t)
+          bv[t] = *reinterpret_cast<const bf8 *>(bp + 16 * t * kp);
+#pragma unroll
+        for (int t = 0; t < TNM; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[t], acc[t],
+                                                           0, 0, 0);
       }
     } else {
-#pragma unroll 4
-      for (int ks = 0; ks < KC / 4; ++ks) {
-        const int k = 4 * ks + (lane >> 4);
-        const OT av = opa[k * kRows + arow];
-        const OT *bp = opb + k * bn + (lane & 15);
+      // operands of k-step ks + 1 are loaded while those of ks feed the
+      // MFMAs (the last step reloads its own, unused)
+      const int nks = KC / 4;
+      const OT *ap = opa + (lane >> 4) * kRows + arow;
+      const OT *bp = opb + (lane >> 4) * bn + (lane & 15);
+      OT av = ap[0];
+      OT bv[TNM];
+#pragma unroll
+      for (int t = 0; t < TNM; ++t) bv[t] = bp[16 * t];
+      for (int ks = 0; ks < nks; ++ks) {
+        const int kn = ks + 1 < nks ? ks + 1 : ks;
+        const OT avn = ap[kn * 4 * kRows];
+        OT bvn[TNM];
+#pragma unroll
+        for (int t = 0; t < TNM; ++t) bvn[t] = bp[kn * 4 * bn + 16 * t];
 #pragma unroll
         for (int t = 0; t < TNM; ++t) {
-          if (t < tn) {
-            if constexpr (PREC == 0)
-              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bp[16 * t],
-                                                            acc[t], 0, 0, 0);
-            else
-              acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bp[16 * t],
-                                                            acc[t], 0, 0, 0);
-          }
+          if constexpr (PREC == 0)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[t], acc[t],
+                                                          0, 0, 0);
+          else
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[t], acc[t],
+                                                          0, 0, 0);
         }
+        av = avn;
+#pragma unroll
+        for (int t = 0; t < TNM; ++t) bv[t] = bvn[t];
       }
     }
     // the raw region is free since the operand tiles were formed
@@ -372,13 +383,11 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
                tile.col0;
 #pragma unroll
   for (int t = 0; t < TNM; ++t) {
-    if (t < tn) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int orow = M::out_row(lane, r);
-        const int ocol = 16 * t + (lane & 15);
-        base[int64_t(orow) * Np + ocol] = acc[t][r];
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int orow = M::out_row(lane, r);
+      const int ocol = 16 * t + (lane & 15);
+      base[int64_t(orow) * Np + ocol] = acc[t][r];
     }
   }
 }
@@ -625,6 +634,7 @@ struct Plan {
   int64_t nrow_bb = 0, ncombo = 0, nrow_xg = 0, ncol_xg = 0;
   size_t lds = 0;
   int kc_bb = 4, kc_xg = 4, pstride_bb = 1, bb_full = 0;
+  int tn = 1;                    // 16-column MFMA tiles per workgroup tile
   // alt kernel
   int alt_nb = 1, alt_S = 1;
   int64_t alt_chunk = 0;
@@ -648,6 +658,20 @@ struct Cache {
   std::map<Key, Plan *> plans;
 };
 
+// Compute units of the context's device (256 on MI355X when the device
+// cannot be queried, e.g. for host-only footprint queries).
+int device_cus(Ctx *c) {
+  if (c->ncu > 0) return c->ncu;
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount,
+                            c->device) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return 256;
+  }
+  c->ncu = n;
+  return n;
+}
+
 // Host part of a plan: tiling, split counts, LDS sizes and the tile tables
 // (in pl's host vectors).  On error the caller deletes pl.
 int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
@@ -662,17 +686,24 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
   const int KCX0 = prec == 0 ? MF<0>::KCX : (prec == 1 ? MF<1>::KCX : MF<2>::KCX);
   const int TNMAX = prec == 0 ? MF<0>::TN : (prec == 1 ? MF<1>::TN : MF<2>::TN);
   const int K = d.K, p = d.p, a = d.a, g = d.g;
-  // column tiling: as few 16-column MFMA tiles of padding as possible with
-  // at most TNMAX per workgroup tile
-  auto col_tiling = [&](int64_t ncols, int *tn_out) -> int64_t {
-    const int64_t n16 = (ncols + 15) / 16;
-    if (n16 == 0) {
-      *tn_out = 1;
-      return 0;
+  // column tiling: one width (tn 16-column MFMA tiles) for both tile kinds,
+  // as the kernel is specialised on it; per kind, as few tiles of padding as
+  // possible with at most TNMAX per workgroup tile, and the wider of the two
+  auto n16_of = [](int64_t ncols) { return (ncols + 15) / 16; };
+  int tnu = 1;
+  {
+    const int64_t ncombo0 = p > 0 ? int64_t(p) * (p + 1) / 2 : 0;
+    const int64_t ncolxg0 = a > 0 ? int64_t(K) * a : 0;
+    for (const int64_t n16 : {n16_of(ncombo0), n16_of(ncolxg0)}) {
+      if (n16 == 0) continue;
+      const int64_t nct = (n16 + TNMAX - 1) / TNMAX;
+      tnu = std::max(tnu, int((n16 + nct - 1) / nct));
     }
-    const int64_t nct = (n16 + TNMAX - 1) / TNMAX;
-    *tn_out = int((n16 + nct - 1) / nct);
-    return nct;
+  }
+  pl->tn = tnu;
+  auto col_tiling = [&](int64_t ncols, int *tn_out) -> int64_t {
+    *tn_out = tnu;
+    return (n16_of(ncols) + tnu - 1) / tnu;
   };
 
   // BB rows: pairs n <= m over alternatives 1..K-1, row-major
@@ -751,12 +782,23 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
   const int64_t nout = int64_t(out_tiles.size());
   int S = 1;
   if (nout > 0) {
-    // about two rounds of workgroups over 256 CUs
-    const int64_t target = 512 * 256 / NT;
-    S = int(std::max<int64_t>(1, (target + nout - 1) / nout));
-    const int64_t max_s = std::max<int64_t>(1, d.N / 1024);
-    S = int(std::min<int64_t>({int64_t(S), max_s, int64_t(64)}));
-    if (S >= 8) S = S / 8 * 8;
+    // observation splits: the count whose workgroups fill the device's
+    // resident slots (CUs x workgroups per CU) best in whole rounds; a
+    // larger count must gain 2 points of fill to be taken (each split adds
+    // a partial tile to write and reduce)
+    const int64_t slots = int64_t(device_cus(c)) * std::max(1, 2048 / NT);
+    const int64_t max_s =
+        std::max<int64_t>(1, std::min<int64_t>(64, d.N / 1024));
+    double best = -1.0;
+    for (int sc = 1; sc <= max_s; ++sc) {
+      const int64_t wg = int64_t(sc) * nout;
+      const int64_t rounds = (wg + slots - 1) / slots;
+      const double fill = double(wg) / double(rounds * slots);
+      if (fill > best + 0.02) {
+        best = fill;
+        S = sc;
+      }
+    }
   }
   int64_t chunk = (d.N + S - 1) / S;
   const int KCR = std::max(KCB0, KCX0);
@@ -965,16 +1007,23 @@ PartLayout part_layout(const Plan &pl) {
   return L;
 }
 
-template <int PREC>
+template <int PREC, int TNV>
+hipError_t launch_tiles_tn(const Plan &pl, const HessDev &hd, hipStream_t s) {
+  hipError_t e = raise_lds_limit(
+      reinterpret_cast<const void *>(&k_hess_tiles<PREC, TNV>), (int)pl.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_hess_tiles<PREC, TNV>), dim3(pl.ntiles),
+                     dim3(64 * MF<PREC>::NW), pl.lds, s, hd);
+  return hipGetLastError();
+}
+
+// the instantiation for the plan's column-tile width
+template <int PREC, int TNV = MF<PREC>::TN>
 hipError_t launch_tiles(const Plan &pl, const HessDev &hd, hipStream_t s) {
   if (pl.ntiles == 0) return hipSuccess;
-  hipError_t e = raise_lds_limit(
-      reinterpret_cast<const void *>(&k_hess_tiles<PREC>), (int)pl.lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_hess_tiles<PREC>, dim3(pl.ntiles),
-                     dim3(64 * MF<PREC>::NW),
-                     pl.lds, s, hd);
-  return hipGetLastError();
+  if (pl.tn == TNV) return launch_tiles_tn<PREC, TNV>(pl, hd, s);
+  if constexpr (TNV > 1) return launch_tiles<PREC, TNV - 1>(pl, hd, s);
+  return hipErrorInvalidValue;
 }
 
 template <typename AccT>

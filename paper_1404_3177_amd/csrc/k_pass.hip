@@ -10,16 +10,18 @@
 //   Ybar_i = sum_k P_ik y_ik                            (used by the centred
 //          alpha blocks of the Hessian)
 //
-// One workgroup (4 waves) walks tiles of TB observations with a fixed
-// stride, so every sum has a fixed partition for a given shape and the
-// result is bitwise reproducible.  Per tile:
-//   1. stage X (transposed), Y, Z, w, choice of the tile in LDS (coalesced);
-//   2. U = X beta^T as a register-blocked product from LDS, plus the Y/Z
-//      terms;
-//   3. one wave per row: max / exp / sum by wave reductions, P and Ybar to
-//      HBM, residual R_ik = w_i (e_ik - P_ik) back into LDS;
-//   4. gradient partials: beta (X^T R) and gamma (sum_i R_ik z_ik) live in
-//      registers owned by fixed threads across tiles; alpha in LDS.
+// A workgroup (4 waves) walks tiles of 16 observations with a fixed stride,
+// so every sum has a fixed partition for a given shape and the result is
+// bitwise reproducible.  Per tile:
+//   1. X of the tile goes to LDS transposed (one coalesced read);
+//   2. X beta for the 16 observations on FP64 MFMA (16 x 16 output tiles,
+//      beta gathered from theta), into LDS;
+//   3. one wave per observation, lanes over alternatives: the Y and Z terms
+//      (read straight from HBM), max / exp / sum by DPP reductions, P and
+//      Ybar to HBM, residual R_ik = w_i (e_ik - P_ik) back into LDS, the
+//      gamma gradient into per-wave LDS sums;
+//   4. the beta gradient X^T R on FP64 MFMA, accumulated in registers
+//      across all of the workgroup's tiles.
 // At the end each workgroup writes one partial row, reduced in a fixed
 // order by k_pass_reduce.
 #include "mnl_common.h"
@@ -28,318 +30,350 @@ namespace mnl {
 
 namespace {
 
+typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
+constexpr int kTB = 16;           // observations per tile (MFMA rows)
+constexpr int kXS = kTB + 1;      // LDS row stride of the transposed X tile
 
-__device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
+// Lane permutation of a double by DPP (both 32-bit halves).
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(u)), CTRL, 0xf,
+                                             0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(u >> 32)), CTRL,
+                                             0xf, 0xf, false);
+  return __builtin_bit_cast(double,
+                            (uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
 }
+__device__ inline double readlane_f64(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l);
+  const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), l);
+  return __builtin_bit_cast(double, uint64_t(lo) | (uint64_t(hi) << 32));
+}
+// Wave-wide sum / max: butterflies within each 16-lane row (lane xor 1,
+// xor 2, then the mirrored half-row and row: every lane of a row combines
+// the same two values, so the row agrees bitwise), then the four row
+// results in a fixed order.  Every lane must be active.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) +
+         (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+__device__ inline double wave_max(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x140>(v));
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
+              fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
 struct Lay {  // LDS layout, offsets in doubles
-  int Kp, tb;
-  int bs, gs, as, xs, us, ys, zs, ws, gacc, lacc, ch;  // ch: int offset
-  int total;                                           // doubles
+  int Kp, p16;
+  int xs, us, ws, gz, gam, alf, red, ch;
+  int total;
 };
 
-__host__ __device__ inline Lay make_lay(const Dims &d, int tb, bool beta_lds) {
+__host__ __device__ inline Lay make_lay(const Dims &d) {
   Lay L;
-  L.Kp = (d.K + 1) & ~1;
-  L.tb = tb;
+  L.Kp = (d.K + 15) & ~15;
+  L.p16 = (d.p + 15) & ~15;
   int o = 0;
-  L.bs = o; o += beta_lds ? d.p * L.Kp : 0;
-  L.gs = o; o += d.K * d.a;
-  L.as = o; o += d.g;
-  L.xs = o; o += d.p * tb;
-  L.us = o; o += tb * L.Kp;
-  L.ys = o; o += tb * d.K * d.g;
-  L.zs = o; o += tb * d.K * d.a;
-  L.ws = o; o += tb;
-  L.gacc = o; o += kWaves * d.g;
-  L.lacc = o; o += kWaves;
-  L.ch = o;  o += (tb + 1) / 2;  // int32 choices packed two per double
+  L.xs = o;  o += L.p16 * kXS;                // X^T tile [p16][kXS]
+  L.us = o;  o += kTB * L.Kp;                 // U, then e, then R [kTB][Kp]
+  L.ws = o;  o += kTB;                        // weights
+  L.gz = o;  o += kWaves * d.K * d.a;         // gamma gradient per wave
+  L.gam = o; o += d.K * d.a;                  // gamma
+  L.alf = o; o += d.g;                        // alpha
+  L.red = o; o += kWaves * (1 + d.g);         // loglik, alpha grad per wave
+  L.ch = o;  o += kTB / 2;                    // choices, two per double
   L.total = o;
   return L;
 }
 
-template <bool BETA_LDS, int JMAX>
-__global__ __launch_bounds__(kThreads) void k_pass(PassArgs A, int tb,
+// NTW: beta-gradient MFMA tiles per wave; CAP: register slots for the z
+// and y values of one alternative (>= a and >= g)
+template <int NTW, int CAP>
+__global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
                                                    int64_t stride) {
   extern __shared__ double sm[];
   const Dims d = A.d;
-  const Lay L = make_lay(d, tb, BETA_LDS);
-  const int K = d.K, p = d.p, g = d.g, a = d.a, Kp = L.Kp;
+  const Lay L = make_lay(d);
+  const int K = d.K, p = d.p, g = d.g, a = d.a, Kp = L.Kp, p16 = L.p16;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  double *bs = sm + L.bs, *gs = sm + L.gs, *as = sm + L.as, *xs = sm + L.xs,
-         *us = sm + L.us, *ys = sm + L.ys, *zs = sm + L.zs, *ws = sm + L.ws,
-         *gacc = sm + L.gacc, *lacc = sm + L.lacc;
+  double *xs = sm + L.xs, *us = sm + L.us, *ws = sm + L.ws, *gz = sm + L.gz,
+         *gam = sm + L.gam, *alf = sm + L.alf, *red = sm + L.red;
   int32_t *chs = reinterpret_cast<int32_t *>(sm + L.ch);
   const double *th = A.theta;
   const int64_t offg = d.off_gamma(), offa = d.off_alpha();
-
-  // coefficients: beta_s[a][k] (k = 0 column is the base, all zero)
-  if (BETA_LDS) {
-    for (int idx = tid; idx < p * Kp; idx += kThreads) {
-      int aa = idx / Kp, k = idx - aa * Kp;
-      bs[idx] = (k >= 1 && k < K) ? th[int64_t(k - 1) * p + aa] : 0.0;
-    }
-  }
-  for (int idx = tid; idx < K * a; idx += kThreads) gs[idx] = th[offg + idx];
-  for (int idx = tid; idx < g; idx += kThreads) as[idx] = th[offa + idx];
-  for (int idx = tid; idx < kWaves * g; idx += kThreads) gacc[idx] = 0.0;
-  if (tid < kWaves) lacc[tid] = 0.0;
-
-  // gradient accumulators owned by this thread
-  const int pp2 = (p + 1) / 2, kp2 = Kp / 2;
-  const int nub = pp2 * kp2;       // beta 2x2 units
-  const int nug = K * a;           // gamma units
-  double gb[JMAX][4];
-  double gg[JMAX];
+  const int Ka = K * a;
+  for (int e = tid; e < Ka; e += kThreads) gam[e] = th[offg + e];
+  for (int e = tid; e < g; e += kThreads) alf[e] = th[offa + e];
+  for (int e = tid; e < kWaves * Ka; e += kThreads) gz[e] = 0.0;
+  for (int e = tid; e < kWaves * (1 + g); e += kThreads) red[e] = 0.0;
+  // beta-gradient tiles (16 features x 16 alternatives), wave wv owns
+  // tiles wv, wv + 4, ... of the row-major tile grid
+  const int nct = Kp / 16, nbt = (p16 / 16) * nct;
+  d4 acc[NTW];
 #pragma unroll
-  for (int j = 0; j < JMAX; ++j) {
-    gb[j][0] = gb[j][1] = gb[j][2] = gb[j][3] = 0.0;
-    gg[j] = 0.0;
-  }
-  double lsum = 0.0;  // wave-uniform
+  for (int j = 0; j < NTW; ++j) acc[j] = d4{0, 0, 0, 0};
+  double lsum = 0.0;  // per lane: choice terms of its alternatives, and
+                      // on lane 0 the log-normalisers
+  const int p4 = (p + 3) / 4;
   __syncthreads();
 
-  const int64_t ntiles = (d.N + tb - 1) / tb;
+  const int64_t ntiles = (d.N + kTB - 1) / kTB;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t i0 = t * tb;
-    const int nobs = (int)((d.N - i0) < tb ? (d.N - i0) : tb);
+    const int64_t i0 = t * kTB;
+    const int nobs = (int)((d.N - i0) < kTB ? (d.N - i0) : kTB);
 
-    // ---- 1. stage the tile ---------------------------------------------
+    // ---- 1. X^T, w and choices of the tile -----------------------------------
     {
       const double *srx = A.X + i0 * p;
       const int nx = nobs * p;
-      batched_copy<8>(
-          tb * p, tid, kThreads,
-          [&](int e) { return e < nx ? srx[e] : 0.0; },
-          [&](int e, double v) {
-            const int i = e / p;
-            xs[(e - i * p) * tb + i] = v;
-          });
-      const double *src = A.Y + i0 * K * g;
-      batched_copy<8>(
-          nobs * K * g, tid, kThreads, [&](int e) { return src[e]; },
-          [&](int e, double v) { ys[e] = v; });
-      const double *srz = A.Z + i0 * K * a;
-      batched_copy<8>(
-          nobs * K * a, tid, kThreads, [&](int e) { return srz[e]; },
-          [&](int e, double v) { zs[e] = v; });
-    }
-    for (int i = tid; i < tb; i += kThreads) {
-      ws[i] = (i < nobs) ? (A.w ? A.w[i0 + i] : 1.0) : 0.0;
-      // an out-of-range choice (rejected when validation is on) is clamped
-      // so that no access leaves the tile
-      int c = (i < nobs) ? A.choice[i0 + i] : 0;
-      chs[i] = c < 0 ? 0 : (c >= K ? K - 1 : c);
-    }
-    __syncthreads();
-
-    // ---- 2. utilities ------------------------------------------------------
-    {
-      const int tb2 = tb / 2;
-      const int nu = tb2 * kp2;
-      for (int u = tid; u < nu; u += kThreads) {
-        const int iu = u % tb2, ku = u / tb2;
-        const int i = 2 * iu, k = 2 * ku;
-        double c00 = 0, c01 = 0, c10 = 0, c11 = 0;
-        for (int aa = 0; aa < p; ++aa) {
-          const double x0 = xs[aa * tb + i], x1 = xs[aa * tb + i + 1];
-          double b0, b1;
-          if (BETA_LDS) {
-            b0 = bs[aa * Kp + k];
-            b1 = bs[aa * Kp + k + 1];
-          } else {
-            b0 = (k >= 1 && k < K) ? th[int64_t(k - 1) * p + aa] : 0.0;
-            b1 = (k + 1 < K) ? th[int64_t(k) * p + aa] : 0.0;
-          }
-          c00 = fma(x0, b0, c00);
-          c01 = fma(x0, b1, c01);
-          c10 = fma(x1, b0, c10);
-          c11 = fma(x1, b1, c11);
-        }
-        double cc[2][2] = {{c00, c01}, {c10, c11}};
-#pragma unroll
-        for (int di = 0; di < 2; ++di) {
-#pragma unroll
-          for (int dk = 0; dk < 2; ++dk) {
-            const int ii = i + di, kk = k + dk;
-            double v = cc[di][dk];
-            if (kk < K && ii < nobs) {
-              for (int c = 0; c < a; ++c)
-                v = fma(zs[(ii * K + kk) * a + c], gs[kk * a + c], v);
-              for (int c = 0; c < g; ++c)
-                v = fma(ys[(ii * K + kk) * g + c], as[c], v);
-            }
-            us[ii * Kp + kk] = v;
-          }
-        }
+      for (int e = tid; e < kTB * p16; e += kThreads) {
+        const int i = e / p16, aa = e - i * p16;
+        xs[aa * kXS + i] = (aa < p && i < nobs) ? srx[i * p + aa] : 0.0;
+      }
+      (void)nx;
+      if (tid < kTB) {
+        ws[tid] = tid < nobs ? (A.w ? A.w[i0 + tid] : 1.0) : 0.0;
+        // an out-of-range choice (rejected when validation is on) is
+        // clamped so that no access leaves the tile
+        int c = tid < nobs ? A.choice[i0 + tid] : 0;
+        chs[tid] = c < 0 ? 0 : (c >= K ? K - 1 : c);
       }
     }
     __syncthreads();
 
-    // ---- 3. softmax, log-likelihood, residuals, Ybar --------------------------
+    // ---- 2. X beta on MFMA -----------------------------------------------------
+    for (int ct = wv; ct < nct; ct += kWaves) {
+      d4 u = d4{0, 0, 0, 0};
+      const int kc = ct * 16 + (lane & 15);
+      for (int ks = 0; ks < p4; ++ks) {
+        const int aa = 4 * ks + (lane >> 4);
+        const double av = xs[aa * kXS + (lane & 15)];
+        const double bv = (aa < p && kc >= 1 && kc < K)
+                              ? th[int64_t(kc - 1) * p + aa] : 0.0;
+        u = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, u, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) us[((lane >> 4) + 4 * r) * Kp + kc] = u[r];
+    }
+    __syncthreads();
+
+    // ---- 3. softmax, log-likelihood, residuals, Ybar, gamma gradient ----------
+    // Lane k holds alternative k of the first 64 (its z and y values in
+    // registers, loaded once); alternatives past 64 are revisited in chunks.
     for (int i = wv; i < nobs; i += kWaves) {
       const double wi = ws[i];
       const int ci = chs[i];
+      const int64_t gi = i0 + i;
+      const double *yr = A.Y + gi * K * g;
+      const double *zr = A.Z + gi * Ka;
+      double *ui = us + i * Kp;
+      double zv[CAP], yv[CAP];
+      const bool own = lane < K;
+#pragma unroll
+      for (int c = 0; c < CAP; ++c) {
+        zv[c] = (c < a && own) ? zr[lane * a + c] : 0.0;
+        yv[c] = (c < g && own) ? yr[lane * g + c] : 0.0;
+      }
       double m = -INFINITY;
-      for (int k = lane; k < K; k += kWave) m = fmax(m, us[i * Kp + k]);
+      {
+        double u = -INFINITY;
+        if (own) {
+          u = ui[lane];
+#pragma unroll
+          for (int c = 0; c < CAP; ++c) {
+            if (c < a) u = fma(zv[c], gam[lane * a + c], u);
+            if (c < g) u = fma(yv[c], alf[c], u);
+          }
+          ui[lane] = u;
+        }
+        m = u;
+      }
+      for (int k0 = kWave; k0 < K; k0 += kWave) {
+        const int k = k0 + lane;
+        if (k < K) {
+          double u = ui[k];
+          for (int c = 0; c < a; ++c) u = fma(zr[k * a + c], gam[k * a + c], u);
+          for (int c = 0; c < g; ++c) u = fma(yr[k * g + c], alf[c], u);
+          ui[k] = u;
+          m = fmax(m, u);
+        }
+      }
       m = wave_max(m);
-      const double uci = us[i * Kp + ci];
       double s = 0.0;
-      for (int k = lane; k < K; k += kWave) {
-        const double e = exp(us[i * Kp + k] - m);
-        us[i * Kp + k] = e;
-        s += e;
+      for (int k0 = 0; k0 < K; k0 += kWave) {
+        const int k = k0 + lane;
+        if (k < K) {
+          const double u = ui[k];
+          const double e = exp(u - m);
+          if (k == ci) lsum += wi * u;  // U at the choice, one lane
+          s += e;
+          ui[k] = e;
+        }
       }
       s = wave_sum(s);
-      lsum += wi * (uci - (m + log(s)));
+      if (lane == 0) lsum -= wi * (m + log(s));
       const double inv = 1.0 / s;
-      const int64_t row = (i0 + i) * K;
-      for (int c = 0; c < g; ++c) {
-        double yb = 0.0;
-        for (int k = lane; k < K; k += kWave)
-          yb = fma(us[i * Kp + k] * inv, ys[(i * K + k) * g + c], yb);
-        yb = wave_sum(yb);
-        if (lane == 0) {
-          if (A.Ybar) A.Ybar[(i0 + i) * g + c] = yb;
-          // alpha gradient: w_i (y_{i,c_i} - ybar_i)   (Eq. 9, centred)
-          gacc[wv * g + c] += wi * (ys[(i * K + ci) * g + c] - yb);
+      if (g > 0) {
+        // Ybar_c = sum_k P_k y_kc, all c reduced together
+        double part[CAP];
+        const double P0 = own ? ui[lane] * inv : 0.0;
+#pragma unroll
+        for (int c = 0; c < CAP; ++c) part[c] = (c < g) ? P0 * yv[c] : 0.0;
+        for (int k0 = kWave; k0 < K; k0 += kWave) {
+          const int k = k0 + lane;
+          if (k < K) {
+            const double P = ui[k] * inv;
+#pragma unroll
+            for (int c = 0; c < CAP; ++c)
+              if (c < g) part[c] = fma(P, yr[k * g + c], part[c]);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < CAP; ++c) {
+          if (c < g) {
+            const double yb = wave_sum(part[c]);
+            // y at the choice, from its lane or from memory
+            const double ych = ci < kWave ? readlane_f64(yv[c], ci)
+                                          : yr[ci * g + c];
+            if (lane == 0) {
+              if (A.Ybar) A.Ybar[gi * g + c] = yb;
+              // alpha gradient: w_i (y_{i,c_i} - ybar_i)   (Eq. 9, centred)
+              red[wv * (1 + g) + 1 + c] += wi * (ych - yb);
+            }
+          }
         }
       }
-      for (int k = lane; k < K; k += kWave) {
-        const double P = us[i * Kp + k] * inv;
-        if (A.P) A.P[row + k] = P;
-        if (A.P32) A.P32[row + k] = (float)P;
-        us[i * Kp + k] = wi * ((k == ci ? 1.0 : 0.0) - P);
+      const int64_t row = gi * K;
+      for (int k0 = 0; k0 < K; k0 += kWave) {
+        const int k = k0 + lane;
+        if (k < K) {
+          const double P = ui[k] * inv;
+          if (A.P) A.P[row + k] = P;
+          if (A.P32) A.P32[row + k] = (float)P;
+          const double R = wi * ((k == ci ? 1.0 : 0.0) - P);
+          ui[k] = R;
+          double *gzk = gz + wv * Ka + k * a;
+          if (k0 == 0) {
+#pragma unroll
+            for (int c = 0; c < CAP; ++c)
+              if (c < a) gzk[c] = fma(R, zv[c], gzk[c]);
+          } else {
+            for (int c = 0; c < a; ++c) gzk[c] = fma(R, zr[k * a + c], gzk[c]);
+          }
+        }
       }
-      if (Kp > K && lane == 0) us[i * Kp + K] = 0.0;
     }
-    // rows beyond nobs contribute nothing
-    for (int idx = nobs * Kp + tid; idx < tb * Kp; idx += kThreads)
-      us[idx] = 0.0;
     __syncthreads();
 
-    // ---- 4. gradient partials ------------------------------------------------
+    // ---- 4. beta gradient X^T R on MFMA ---------------------------------------
 #pragma unroll
-    for (int j = 0; j < JMAX; ++j) {
-      const int u = tid + j * kThreads;
-      if (u < nub) {
-        const int ku = u % kp2, au = u / kp2;
-        const int k = 2 * ku, a0 = 2 * au;
-        const bool has1 = (a0 + 1) < p;
-        double s00 = gb[j][0], s01 = gb[j][1], s10 = gb[j][2], s11 = gb[j][3];
-        for (int i = 0; i < nobs; ++i) {
-          const double r0 = us[i * Kp + k], r1 = us[i * Kp + k + 1];
-          const double x0 = xs[a0 * tb + i];
-          const double x1 = has1 ? xs[(a0 + 1) * tb + i] : 0.0;
-          s00 = fma(x0, r0, s00);
-          s01 = fma(x0, r1, s01);
-          s10 = fma(x1, r0, s10);
-          s11 = fma(x1, r1, s11);
-        }
-        gb[j][0] = s00; gb[j][1] = s01; gb[j][2] = s10; gb[j][3] = s11;
-      }
-      if (u < nug) {
-        const int k = u / a, c = u - (u / a) * a;
-        double s0 = gg[j];
-        for (int i = 0; i < nobs; ++i)
-          s0 = fma(us[i * Kp + k], zs[(i * K + k) * a + c], s0);
-        gg[j] = s0;
+    for (int j = 0; j < NTW; ++j) {
+      const int bt = wv + kWaves * j;
+      if (bt < nbt) {
+        const int rt = bt / nct, ct = bt - rt * nct;
+        const double *xa = xs + (16 * rt + (lane & 15)) * kXS + (lane >> 4);
+        const double *rb = us + (lane >> 4) * Kp + 16 * ct + (lane & 15);
+#pragma unroll
+        for (int ks = 0; ks < kTB / 4; ++ks)
+          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              xa[4 * ks], rb[4 * ks * Kp], acc[j], 0, 0, 0);
       }
     }
     __syncthreads();
   }
 
-  // ---- write this workgroup's partial row ---------------------------------------
+  // ---- this workgroup's partial row --------------------------------------------
   double *out = A.partial + int64_t(blockIdx.x) * stride;
-  if (lane == 0) lacc[wv] = lsum;
+  lsum = wave_sum(lsum);
+  if (lane == 0) red[wv * (1 + g)] = lsum;
   __syncthreads();
   if (tid == 0) {
     double l = 0.0;
-    for (int v = 0; v < kWaves; ++v) l += lacc[v];
+    for (int v = 0; v < kWaves; ++v) l += red[v * (1 + g)];
     out[0] = l;
-  }
-#pragma unroll
-  for (int j = 0; j < JMAX; ++j) {
-    const int u = tid + j * kThreads;
-    if (u < nub) {
-      const int ku = u % kp2, au = u / kp2;
-      const int k = 2 * ku, a0 = 2 * au;
-      const double v[4] = {gb[j][0], gb[j][1], gb[j][2], gb[j][3]};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int aa = a0 + (q >> 1), kk = k + (q & 1);
-        if (aa < p && kk >= 1 && kk < K)
-          out[1 + int64_t(kk - 1) * p + aa] = v[q];
-      }
-    }
-    if (u < nug) out[1 + offg + u] = gg[j];
   }
   for (int c = tid; c < g; c += kThreads) {
     double s = 0.0;
-    for (int v = 0; v < kWaves; ++v) s += gacc[v * g + c];
+    for (int v = 0; v < kWaves; ++v) s += red[v * (1 + g) + 1 + c];
     out[1 + offa + c] = s;
+  }
+  for (int e = tid; e < Ka; e += kThreads) {
+    double s = 0.0;
+    for (int v = 0; v < kWaves; ++v) s += gz[v * Ka + e];
+    out[1 + offg + e] = s;
+  }
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) {
+    const int bt = wv + kWaves * j;
+    if (bt < nbt) {
+      const int rt = bt / nct, ct = bt - rt * nct;
+      const int kk = 16 * ct + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int aa = 16 * rt + (lane >> 4) + 4 * r;
+        if (aa < p && kk >= 1 && kk < K)
+          out[1 + int64_t(kk - 1) * p + aa] = acc[j][r];
+      }
+    }
   }
 }
 
-__global__ void k_pass_reduce(const double *__restrict__ partial, int grid,
-                              int64_t stride, int64_t np, double *loglik,
-                              double *grad) {
-  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j > np) return;
-  // eight independent partial sums in a fixed order: deterministic, and
-  // many loads in flight
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int b = 0;
-  for (; b + 8 <= grid; b += 8) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] += partial[int64_t(b + u) * stride + j];
+// Sum the partial rows: 64 columns per workgroup, 16 groups of rows each
+// summed with four accumulators, the group sums added in a fixed order.
+__global__ __launch_bounds__(1024) void k_pass_reduce(
+    const double *__restrict__ partial, int grid, int64_t stride, int64_t np,
+    double *loglik, double *grad) {
+  __shared__ double red[16][64];
+  const int col = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t j = int64_t(blockIdx.x) * 64 + col;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (j <= np) {
+    int q = 0;
+    for (int b = grp; b < grid; b += 16, ++q)
+      acc[q & 3] += partial[int64_t(b) * stride + j];
   }
-  for (; b < grid; ++b) acc[b & 7] += partial[int64_t(b) * stride + j];
-  const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) +
-                   ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-  if (j == 0) {
-    if (loglik) *loglik = s;
-  } else if (grad) {
-    grad[j - 1] = s;
+  red[grp][col] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (grp == 0 && j <= np) {
+    double s = 0.0;
+    for (int q = 0; q < 16; ++q) s += red[q][col];
+    if (j == 0) {
+      if (loglik) *loglik = s;
+    } else if (grad) {
+      grad[j - 1] = s;
+    }
   }
 }
 
 }  // namespace
 
 int pass_plan(const Dims &d, PassPlan *plan) {
-  const int Kp = (d.K + 1) & ~1;
-  const int pp2 = (d.p + 1) / 2;
-  const int64_t nub = int64_t(pp2) * (Kp / 2);
-  const int64_t nug = int64_t(d.K) * d.a;
-  const int64_t need = nub > nug ? nub : nug;
-  if (need <= 8 * kThreads) plan->jmax = 8;
-  else if (need <= 16 * kThreads) plan->jmax = 16;
-  else return MNL_ERR_UNSUPPORTED;
-  const bool beta_lds = int64_t(d.p) * Kp * 8 <= 64 * 1024;
-  plan->beta_in_lds = beta_lds;
-  const size_t budget = 80 * 1024;
-  int tb = 64;
-  while (tb > 2) {
-    Lay L = make_lay(d, tb, beta_lds);
-    if (size_t(L.total) * 8 <= budget) break;
-    tb /= 2;
-  }
-  Lay L = make_lay(d, tb, beta_lds);
-  if (size_t(L.total) * 8 > 150 * 1024) return MNL_ERR_UNSUPPORTED;
-  plan->tb = tb;
+  const Lay L = make_lay(d);
+  const int nbt = (L.p16 / 16) * (L.Kp / 16);
+  const int per_wave = (nbt + kWaves - 1) / kWaves;
+  int ntw = 1;
+  while (ntw < per_wave) ntw *= 2;
+  if (ntw > 32) return MNL_ERR_UNSUPPORTED;
+  const int mx = d.a > d.g ? d.a : d.g;
+  if (mx > 16) return MNL_ERR_UNSUPPORTED;
+  plan->cap = mx <= 4 ? 4 : (mx <= 8 ? 8 : 16);
+  if (size_t(L.total) * 8 > 160 * 1024) return MNL_ERR_UNSUPPORTED;
+  plan->ntw = ntw;
+  plan->tb = kTB;
   plan->lds_bytes = size_t(L.total) * 8;
-  const int64_t ntiles = (d.N + tb - 1) / tb;
-  plan->grid = (int)(ntiles < 512 ? ntiles : 512);
+  const int64_t ntiles = (d.N + kTB - 1) / kTB;
+  plan->grid = (int)(ntiles < 1024 ? ntiles : 1024);
   plan->stride = 1 + d.np;
   return MNL_OK;
 }
@@ -348,21 +382,28 @@ hipError_t launch_pass(const PassPlan &plan, const PassArgs &a,
                        hipStream_t s) {
   dim3 grid(plan.grid), block(kThreads);
   const size_t lds = plan.lds_bytes;
-#define MNL_PASS_LAUNCH(BL, J)                                                \
+#define MNL_PASS_LAUNCH(J, C)                                                 \
   do {                                                                        \
     hipError_t e_ = raise_lds_limit(                                          \
-        reinterpret_cast<const void *>(&k_pass<BL, J>), (int)lds);            \
+        reinterpret_cast<const void *>(&k_pass<J, C>), (int)lds);             \
     if (e_ != hipSuccess) return e_;                                          \
-    hipLaunchKernelGGL((k_pass<BL, J>), grid, block, lds, s, a, plan.tb,      \
-                       plan.stride);                                          \
+    hipLaunchKernelGGL((k_pass<J, C>), grid, block, lds, s, a, plan.stride);  \
   } while (0)
-  if (plan.beta_in_lds) {
-    if (plan.jmax == 8) MNL_PASS_LAUNCH(true, 8);
-    else MNL_PASS_LAUNCH(true, 16);
-  } else {
-    if (plan.jmax == 8) MNL_PASS_LAUNCH(false, 8);
-    else MNL_PASS_LAUNCH(false, 16);
+#define MNL_PASS_CAP(J)                                                       \
+  do {                                                                        \
+    if (plan.cap == 4) MNL_PASS_LAUNCH(J, 4);                                 \
+    else if (plan.cap == 8) MNL_PASS_LAUNCH(J, 8);                            \
+    else MNL_PASS_LAUNCH(J, 16);                                              \
+  } while (0)
+  switch (plan.ntw) {
+    case 1: MNL_PASS_CAP(1); break;
+    case 2: MNL_PASS_CAP(2); break;
+    case 4: MNL_PASS_CAP(4); break;
+    case 8: MNL_PASS_CAP(8); break;
+    case 16: MNL_PASS_CAP(16); break;
+    default: MNL_PASS_CAP(32); break;
   }
+#undef MNL_PASS_CAP
 #undef MNL_PASS_LAUNCH
   return hipGetLastError();
 }
@@ -371,7 +412,7 @@ hipError_t launch_pass_reduce(const PassPlan &plan, const double *partial,
                               double *loglik, double *grad, int64_t np,
                               hipStream_t s) {
   const int64_t n = np + 1;
-  dim3 block(256), grid((unsigned)((n + 255) / 256));
+  dim3 block(1024), grid((unsigned)((n + 63) / 64));
   hipLaunchKernelGGL(k_pass_reduce, grid, block, 0, s, partial, plan.grid,
                      plan.stride, np, loglik, grad);
   return hipGetLastError();

@@ -74,8 +74,8 @@ int set_error(Ctx *c, int code, const char *fmt, ...);
 struct PassPlan {
   int tb;            // observations per tile
   int grid;          // workgroups (fixed by the shape: deterministic sums)
-  int beta_in_lds;   // beta staged in LDS (else read from global memory)
-  int jmax;          // gradient micro-tile slots per thread (8 or 32)
+  int ntw;           // beta-gradient MFMA tiles per wave (power of two)
+  int cap;           // register slots for one alternative's z / y values
   size_t lds_bytes;
   int64_t stride;    // doubles per workgroup partial row
 };
@@ -158,6 +158,7 @@ struct Ctx {
   // context's work runs on
   hipMemPool_t pool = nullptr;
   hipStream_t ostream = nullptr;
+  int ncu = 0;   // compute units of `device` (0: not queried yet)
 };
 
 // Raise a kernel's dynamic-LDS limit on the current device to at least
