@@ -97,6 +97,7 @@ struct HessDev {
   int64_t nrow_bb, ncombo;   // valid rows / cols
   int64_t nrow_xg, ncol_xg;
   int kc_bb, kc_xg;          // observations per round
+  int nbuf_bb, nbuf_xg;      // raw input buffers (2: next round streams in)
   int pstride_bb;            // staged P columns per observation (BB)
   int bb_full;               // BB stages whole P rows (K <= kMaxCols)
 };
@@ -121,27 +122,41 @@ __host__ __device__ constexpr int align16(int bytes) {
 // LDS layout of one workgroup (bytes); shared by the kernel and the host.
 // The raw region is P columns, X, Z and w of one round, back to back.
 struct TileLds {
-  int raw_p, raw_x, raw_z, raw_w, tab, opa, opb, total;
+  // raw inputs of a round: P columns and Z (operand precision; P as P /
+  // P32 are stored) and X and w in FP64; two buffers
+  int rx, rz, rw, rawsz;
+  int raw0, tab, opa, opb, total;
 };
 
 template <int PREC>
 __host__ __device__ inline TileLds tile_lds(int type, int KC, int K, int p,
-                                            int a, int bn, int pcols) {
+                                            int a, int bn, int pcols,
+                                            int nbuf) {
   using M = MF<PREC>;
   constexpr int kRows = 16 * M::NW;
   const int tsz = sizeof(typename M::T), osz = sizeof(typename M::OT);
   const int kp = PREC == 2 ? KC + 8 : KC;   // padded k extent (bf16 rows)
   TileLds L;
+  L.rx = align16(KC * pcols * tsz);
+  L.rz = L.rx + KC * p * 8;
+  L.rw = L.rz + (type == 0 ? 0 : align16(KC * K * a * tsz));
+  L.rawsz = align16(L.rw + KC * 8);
   int o = 0;
-  L.raw_p = o; o += KC * pcols * tsz;
-  L.raw_x = o; o += KC * p * tsz;
-  L.raw_z = o; o += (type == 0 ? 0 : KC * K * a * tsz);
-  L.raw_w = o; o = align16(o + KC * tsz);
-  L.tab = o;   o = align16(o + (kRows + bn) * 4);
-  L.opa = o;   o = align16(o + kRows * kp * osz);
-  L.opb = o;   o = align16(o + bn * kp * osz);
+  L.raw0 = o; o += nbuf * L.rawsz;
+  L.tab = o;  o = align16(o + (kRows + bn) * 4);
+  L.opa = o;  o = align16(o + kRows * kp * osz);
+  L.opb = o;  o = align16(o + bn * kp * osz);
   L.total = o;
   return L;
+}
+
+// Wait for this wave's LDS operations, then the workgroup barrier; global
+// loads still in flight (asynchronous copies into LDS) are not waited for.
+__device__ inline void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0), vmcnt / expcnt untouched
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // Generated-operand GEMM over a tile list.  Per round of KC observations:
@@ -167,16 +182,20 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
   const bool is_bb = tile.type == T_BB;
   const int KC = is_bb ? H.kc_bb : H.kc_xg;
   const int kp = PREC == 2 ? KC + 8 : KC;
+  const int nbuf = is_bb ? H.nbuf_bb : H.nbuf_xg;
   const TileLds L = tile_lds<PREC>(tile.type, KC, K, p, a, bn,
-                                   is_bb ? H.pstride_bb : K);
-  const T *Ps = reinterpret_cast<const T *>(smb + L.raw_p);
-  const T *Xs = reinterpret_cast<const T *>(smb + L.raw_x);
-  const T *Zs = reinterpret_cast<const T *>(smb + L.raw_z);
-  const T *Ws = reinterpret_cast<const T *>(smb + L.raw_w);
+                                   is_bb ? H.pstride_bb : K, nbuf);
   uint32_t *tab = reinterpret_cast<uint32_t *>(smb + L.tab);
   OT *opa = reinterpret_cast<OT *>(smb + L.opa);
   OT *opb = reinterpret_cast<OT *>(smb + L.opb);
   const int pstride = is_bb ? H.pstride_bb : K;
+  // raw buffer b of the round: P columns, then X, Z, w (FP64)
+  auto rawp = [&](int b) {
+    return reinterpret_cast<T *>(smb + L.raw0 + b * L.rawsz);
+  };
+  auto rawd = [&](int b, int off) {
+    return reinterpret_cast<double *>(smb + L.raw0 + b * L.rawsz + off);
+  };
 
   // tile tables: BB row info and feature pairs, cached in LDS
   int ncol = K;
@@ -194,13 +213,26 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
       tab[kRows + c] = col < H.ncombo ? H.bb_combo[col] : 0xffffffffu;
     }
   }
-  __syncthreads();  // tile tables visible to every thread
-  // stage one round of raw inputs (coalesced where the data are contiguous)
-  auto stage = [&](int i0, int nobs) {
-    T *Pw = reinterpret_cast<T *>(smb + L.raw_p);
-    T *Xw = reinterpret_cast<T *>(smb + L.raw_x);
-    T *Zw = reinterpret_cast<T *>(smb + L.raw_z);
-    T *Ww = reinterpret_cast<T *>(smb + L.raw_w);
+  // start from zeros in both raw buffers: the slots past the last
+  // observation keep stale (finite) values that meet a zero weight
+  for (int e = tid; e < nbuf * L.rawsz / 4; e += NT)
+    reinterpret_cast<uint32_t *>(smb + L.raw0)[e] = 0u;
+  __syncthreads();  // tile tables and zeroed buffers visible to every thread
+  // stage one round of raw inputs into buffer b: the contiguous blocks (P
+  // rows, X, Z) stream straight into LDS asynchronously, split over the
+  // waves in 64-dword pieces; gathered P columns and w are copied directly
+  auto stage = [&](int b, int i0, int nobs) {
+    auto wg_copy = [&](const void *src, void *dst, int ndw) {
+      const uint32_t *s32 = static_cast<const uint32_t *>(src);
+      char *d8 = static_cast<char *>(dst);
+      for (int c = 64 * wv; c < ndw; c += 64 * (NT / 64)) {
+        if (c + lane < ndw)
+          __builtin_amdgcn_global_load_lds(s32 + c + lane,
+                                           (lds_void_t *)(d8 + 4 * c), 4, 0,
+                                           0);
+      }
+    };
+    T *Pw = rawp(b);
     if (is_bb && !H.bb_full) {
       for (int e = tid; e < KC * ncol; e += NT) {
         const int j = e / ncol, c = e - j * ncol;
@@ -208,27 +240,39 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
             j < nobs ? ldg_op<T>(H.P, H.P32, int64_t(i0 + j) * K + cols[c])
                      : T(0);
       }
+    } else if (PREC == 0 || !H.P32) {
+      if (PREC == 0) {
+        wg_copy(H.P + int64_t(i0) * K, Pw, 2 * nobs * K);
+      } else {
+        for (int e = tid; e < nobs * K; e += NT)
+          Pw[e] = T(H.P[int64_t(i0) * K + e]);
+      }
     } else {
-      for (int e = tid; e < KC * K; e += NT)
-        Pw[e] = e < nobs * K ? ldg_op<T>(H.P, H.P32, int64_t(i0) * K + e)
-                             : T(0);
+      wg_copy(H.P32 + int64_t(i0) * K, Pw, nobs * K);
     }
+    wg_copy(H.X + int64_t(i0) * p, rawd(b, L.rx), 2 * nobs * p);
     if (!is_bb) {
-      const int za = K * a;
-      for (int e = tid; e < KC * za; e += NT)
-        Zw[e] = e < nobs * za ? T(H.Z[int64_t(i0) * za + e]) : T(0);
+      if constexpr (PREC == 0) {
+        wg_copy(H.Z + int64_t(i0) * K * a, rawd(b, L.rz), 2 * nobs * K * a);
+      } else {
+        T *Zw = reinterpret_cast<T *>(smb + L.raw0 + b * L.rawsz + L.rz);
+        const int za = K * a;
+        batched_copy<8>(
+            nobs * za, tid, NT,
+            [&](int e) { return T(H.Z[int64_t(i0) * za + e]); },
+            [&](int e, T v) { Zw[e] = v; });
+      }
     }
-    for (int e = tid; e < KC * p; e += NT)
-      Xw[e] = e < nobs * p ? T(H.X[int64_t(i0) * p + e]) : T(0);
+    double *Ww = rawd(b, L.rw);
     for (int e = tid; e < KC; e += NT)
-      Ww[e] = e < nobs ? (H.w ? T(H.w[i0 + e]) : T(1)) : T(0);
+      Ww[e] = e < nobs ? (H.w ? H.w[i0 + e] : 1.0) : 0.0;
   };
 
   typename M::Acc acc[TNM];
 #pragma unroll
   for (int t = 0; t < TNM; ++t) acc[t] = M::zero();
 
-  stage(tile.obs0, min(KC, tile.obs1 - tile.obs0));
+  stage(0, tile.obs0, min(KC, tile.obs1 - tile.obs0));
   __syncthreads();
   // per-thread operand roles, fixed for the tile (no division in the loop)
   const int nb_rows = int(int64_t(K - 1) * p);
@@ -276,17 +320,25 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
       b_f2 = col;
     }
   }
-  for (int i0 = tile.obs0; i0 < tile.obs1; i0 += KC) {
+  int cur = 0;
+  for (int i0 = tile.obs0; i0 < tile.obs1;
+       i0 += KC, cur = nbuf == 2 ? cur ^ 1 : 0) {
+    const T *Ps = rawp(cur);
+    const double *Xs = rawd(cur, L.rx);
+    const T *Zs = reinterpret_cast<const T *>(smb + L.raw0 +
+                                              cur * L.rawsz + L.rz);
+    const double *Ws = rawd(cur, L.rw);
     // ---- form the operand tiles for this round ------------------------------
     // A: thread -> row ra, observations ka0, ka0 + 4, ...
     if (a_ok) {
       for (int k = ka0; k < KC; k += NT / kRows) {
         T v;
         if (is_bb)
-          v = Ws[k] * Ps[k * pstride + a_ln] * (a_dg - Ps[k * pstride + a_lm]);
+          v = T(Ws[k]) * Ps[k * pstride + a_ln] *
+              (a_dg - Ps[k * pstride + a_lm]);
         else
-          v = Ws[k] * Ps[k * pstride + a_ln] *
-              (a_z ? Zs[k * K * a + a_f] : Xs[k * p + a_f]);
+          v = T(Ws[k]) * Ps[k * pstride + a_ln] *
+              T(a_z ? Zs[k * K * a + a_f] : Xs[k * p + a_f]);
         if constexpr (PREC == 2) opa[ra * kp + k] = (__bf16)v;
         else opa[k * kRows + ra] = v;
       }
@@ -301,19 +353,19 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
       for (int k = kb0; k < KC; k += kbs) {
         T v = T(0);
         if (b_ok) {
-          if (is_bb) v = Xs[k * p + b_f1] * Xs[k * p + b_f2];
-          else v = Ps[k * pstride + b_f1] * Zs[k * K * a + b_f2];
+          if (is_bb) v = T(Xs[k * p + b_f1] * Xs[k * p + b_f2]);
+          else v = Ps[k * pstride + b_f1] * T(Zs[k * K * a + b_f2]);
         }
         if constexpr (PREC == 2) opb[cbx * kp + k] = (__bf16)v;
         else opb[k * bn + cbx] = v;
       }
     }
-    __syncthreads();
+    // the next round streams into the other raw buffer during the MFMAs
+    const int i1 = i0 + KC;
+    if (nbuf == 2 && i1 < tile.obs1) stage(cur ^ 1, i1, min(KC, tile.obs1 - i1));
+    lds_barrier();
 
     // ---- MFMAs from LDS --------------------------------------------------------
-    const int i1 = i0 + KC;
-    const bool more = i1 < tile.obs1;
-    const int nobs1 = more ? min(KC, tile.obs1 - i1) : 0;
 
     const int arow = 16 * wv + (lane & 15);
     if constexpr (PREC == 2) {
@@ -360,10 +412,13 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
         for (int t = 0; t < TNM; ++t) bv[t] = bvn[t];
       }
     }
-    // the raw region is free since the operand tiles were formed
-    if (more) stage(i1, nobs1);
-    // every wave is done with the operand tiles and the next round is staged
+    // every wave is done with the operand tiles and the next round landed
     __syncthreads();
+    if (nbuf == 1 && i1 < tile.obs1) {
+      // one raw buffer: the next round is staged after this round's MFMAs
+      stage(0, i1, min(KC, tile.obs1 - i1));
+      __syncthreads();
+    }
   }
 
   // epilogue: this split's partial tile
@@ -393,118 +448,120 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
 }
 
 // Per-alternative sums for the delta_nm parts and the alpha blocks:
-//   out[n][r][s] = sum_i w_i P_in L_in[r] R_in[s]
-// with L = (x_i, z_in, y_in - ybar_i), R = (z_in, y_in - ybar_i).
-// Workgroup: nb alternatives x one observation range.  Per tile of kAltTB
-// observations the raw X, Z, Y - Ybar and w P of those alternatives are
-// staged in LDS (contiguous slices); each thread owns kAltRB rows r of one
-// alternative against all nr columns, accumulated in registers.
+//   out[n][l][r] = sum_i w_i P_in L_in[l] R_in[r]
+// with L = (x_i, z_in, y_in - ybar_i), R = (z_in, y_in - ybar_i): for each
+// alternative n a small GEMM over the observations, on FP64 MFMA.
+// Workgroup: nb = 4 NQ alternatives x one observation range; wave w owns
+// alternatives w, w + 4, ... with all NRT 16-row tiles of L for each, so
+// per k-step the R operand and w P_n are read once for NRT MFMAs.  Per tile
+// of 16 observations X, the Z and Y slices of the workgroup's alternatives,
+// Ybar and w P are staged in LDS with contiguous row copies.
 constexpr int kAltTB = 16;
-constexpr int kAltRB = 4;
-constexpr int kAltNR = 16;   // most a + g handled
+constexpr int kAltNR = 16;   // most a + g handled (one MFMA column tile)
 
+template <int NRT>
 __global__ __launch_bounds__(kThreads) void k_hess_alt(
     Dims d, const double *X, const double *Y, const double *Z,
-    const double *w, const double *P, const double *Ybar, int nb,
+    const double *w, const double *P, const double *Ybar, int nb, int ngrp,
     int64_t obs_chunk, double *out /* [S][K][nl][nr] */) {
+  constexpr int NQ = NRT == 1 ? 8 : (NRT == 2 ? 4 : (NRT <= 4 ? 2 : 1));
   extern __shared__ double sm[];
   const int K = d.K, p = d.p, g = d.g, a = d.a;
   const int nl = p + a + g, nr = a + g;
-  const int n0 = blockIdx.x * nb;
+  const int grp = blockIdx.x % ngrp, split = blockIdx.x / ngrp;
+  const int n0 = grp * nb;
   const int nbe = min(nb, K - n0);
-  const int64_t i_begin = int64_t(blockIdx.y) * obs_chunk;
+  const int64_t i_begin = int64_t(split) * obs_chunk;
   const int64_t i_end = min(d.N, i_begin + obs_chunk);
-  // LDS: Xs[TB][p], Zs[TB][nb][a], Ys[TB][nb][g] (centred), Us[TB][nb]
-  double *Xs = sm;
-  double *Zs = Xs + kAltTB * p;
-  double *Ys = Zs + kAltTB * nb * a;
-  double *Us = Ys + kAltTB * nb * g;
-  const int tid = threadIdx.x;
-  const int nrb = (nl + kAltRB - 1) / kAltRB;
-  const int q = tid / nrb, rb = tid - q * nrb;
-  const bool own = q < nbe;
-  const int r0 = rb * kAltRB;
-  double acc[kAltRB][kAltNR];
-#pragma unroll
-  for (int i = 0; i < kAltRB; ++i)
-#pragma unroll
-    for (int j = 0; j < kAltNR; ++j) acc[i][j] = 0.0;
-
-  for (int64_t i0 = i_begin; i0 < i_end; i0 += kAltTB) {
+  // two LDS buffers, each: Xs [TB][p], Zs [TB][nb][a], Ys [TB][nb][g],
+  // Yb [TB][g] (Ybar), Ps [TB][nb] (P), Ws [TB] (weights, 0 past the end)
+  const int oZ = kAltTB * p, oY = oZ + kAltTB * nb * a,
+            oB = oY + kAltTB * nb * g, oP = oB + kAltTB * g,
+            oW = oP + kAltTB * nb, bsz = oW + kAltTB;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // stale values are multiplied by a zero weight, so start from zeros
+  // (never NaN) and load only whole rows of real observations
+  for (int e = tid; e < 2 * bsz; e += kThreads) sm[e] = 0.0;
+  __syncthreads();
+  auto stage = [&](int b, int64_t i0) {
+    double *B = sm + b * bsz;
     const int nobs = (int)min<int64_t>(kAltTB, i_end - i0);
-    {
-      const int nx = nobs * p;
-      const double *srx = X + i0 * p;
-      batched_copy<8>(
-          kAltTB * p, tid, kThreads,
-          [&](int e) { return e < nx ? srx[e] : 0.0; },
-          [&](int e, double v) { Xs[e] = v; });
-      // per observation the slices of Z, Y (alternatives n0..n0+nb) and P
-      // are contiguous; element idx of a staged array is observation
-      // idx / slice, offset idx % slice
-      const int za = nb * a, zg = nb * g;
-      batched_copy<8>(
-          kAltTB * za, tid, kThreads,
-          [&](int idx) {
-            const int j = idx / za, e = idx - j * za;
-            return (j < nobs && e < nbe * a)
-                       ? Z[(i0 + j) * K * a + n0 * a + e] : 0.0;
-          },
-          [&](int idx, double v) { Zs[idx] = v; });
-      batched_copy<8>(
-          kAltTB * zg, tid, kThreads,
-          [&](int idx) {
-            const int j = idx / zg, e = idx - j * zg;
-            if (j >= nobs || e >= nbe * g) return 0.0;
-            const int c = e % g;   // generic variable of this element
-            return Y[(i0 + j) * K * g + n0 * g + e] - Ybar[(i0 + j) * g + c];
-          },
-          [&](int idx, double v) { Ys[idx] = v; });
-      batched_copy<8>(
-          kAltTB * nb, tid, kThreads,
-          [&](int idx) {
-            const int j = idx / nb, e = idx - j * nb;
-            return (j < nobs && e < nbe)
-                       ? (w ? w[i0 + j] : 1.0) * P[(i0 + j) * K + n0 + e]
-                       : 0.0;
-          },
-          [&](int idx, double v) { Us[idx] = v; });
+    for (int j = wv; j < kAltTB; j += kThreads / kWave) {
+      const int64_t ii = i0 + j;
+      if (j < nobs) {
+        wave_copy_lds(X + ii * p, B + j * p, 2 * p, lane);
+        wave_copy_lds(Z + (ii * K + n0) * a, B + oZ + j * nb * a,
+                      2 * nbe * a, lane);
+        wave_copy_lds(Y + (ii * K + n0) * g, B + oY + j * nb * g,
+                      2 * nbe * g, lane);
+        wave_copy_lds(Ybar + ii * g, B + oB + j * g, 2 * g, lane);
+        wave_copy_lds(P + ii * K + n0, B + oP + j * nb, 2 * nbe, lane);
+      }
+      if (lane == 0) B[oW + j] = j < nobs ? (w ? w[ii] : 1.0) : 0.0;
     }
-    __syncthreads();
-    if (own) {
-      for (int j = 0; j < nobs; ++j) {
-        const double u = Us[j * nb + q];
-        const double *zq = Zs + (j * nb + q) * a;
-        const double *yq = Ys + (j * nb + q) * g;
-        double Rv[kAltNR];
+  };
+  d4 acc[NQ][NRT];
 #pragma unroll
-        for (int s2 = 0; s2 < kAltNR; ++s2)
-          Rv[s2] = s2 < a ? zq[s2] : (s2 < nr ? yq[s2 - a] : 0.0);
+  for (int j = 0; j < NQ; ++j)
 #pragma unroll
-        for (int i = 0; i < kAltRB; ++i) {
-          const int r = r0 + i;
-          double lv = 0.0;
-          if (r < p) lv = Xs[j * p + r];
-          else if (r < p + a) lv = zq[r - p];
-          else if (r < nl) lv = yq[r - p - a];
-          lv *= u;
+    for (int r = 0; r < NRT; ++r) acc[j][r] = d4{0, 0, 0, 0};
+
+  const int ntile = (int)((i_end - i_begin + kAltTB - 1) / kAltTB);
+  if (ntile > 0) stage(0, i_begin);
+  __syncthreads();
+  const int rl = lane & 15;
+  for (int t = 0; t < ntile; ++t) {
+    const int cur = t & 1;
+    // the next tile streams into the other buffer while this one is used
+    if (t + 1 < ntile) stage(cur ^ 1, i_begin + int64_t(t + 1) * kAltTB);
+    const double *B = sm + cur * bsz;
+    const double *Xs = B, *Zs = B + oZ, *Ys = B + oY, *Yb = B + oB,
+                 *Ps = B + oP, *Ws = B + oW;
+#pragma unroll 1
+    for (int ks = 0; ks < kAltTB / 4; ++ks) {
+      const int ob = 4 * ks + (lane >> 4);
+      const double wo = Ws[ob];
 #pragma unroll
-          for (int s2 = 0; s2 < kAltNR; ++s2)
-            acc[i][s2] = fma(lv, Rv[s2], acc[i][s2]);
+      for (int jq = 0; jq < NQ; ++jq) {
+        const int q = wv + 4 * jq;
+        if (q < nbe) {
+          const double u = wo * Ps[ob * nb + q];
+          const double *zq = Zs + (ob * nb + q) * a;
+          const double *yq = Ys + (ob * nb + q) * g;
+          const double *ybq = Yb + ob * g;
+          // R operand: column r = rl
+          double bv = 0.0;
+          if (rl < a) bv = zq[rl];
+          else if (rl < nr) bv = yq[rl - a] - ybq[rl - a];
+#pragma unroll
+          for (int rt = 0; rt < NRT; ++rt) {
+            const int l = 16 * rt + rl;
+            double lv = 0.0;
+            if (l < p) lv = Xs[ob * p + l];
+            else if (l < p + a) lv = zq[l - p];
+            else if (l < nl) lv = yq[l - p - a] - ybq[l - p - a];
+            acc[jq][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                u * lv, bv, acc[jq][rt], 0, 0, 0);
+          }
         }
       }
     }
+    // this tile's reads are done and the next tile has landed
     __syncthreads();
   }
-  if (own) {
-    double *ob = out + ((int64_t(blockIdx.y) * K + n0 + q) * nl) * nr;
 #pragma unroll
-    for (int i = 0; i < kAltRB; ++i) {
-      const int r = r0 + i;
-      if (r >= nl) continue;
+  for (int jq = 0; jq < NQ; ++jq) {
+    const int q = wv + 4 * jq;
+    if (q >= nbe) continue;
+    double *ob = out + ((int64_t(split) * K + n0 + q) * nl) * nr;
+    const int r = lane & 15;
 #pragma unroll
-      for (int s2 = 0; s2 < kAltNR; ++s2)
-        if (s2 < nr) ob[r * nr + s2] = acc[i][s2];
+    for (int rt = 0; rt < NRT; ++rt) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int l = 16 * rt + (lane >> 4) + 4 * i;
+        if (l < nl && r < nr) ob[l * nr + r] = acc[jq][rt][i];
+      }
     }
   }
 }
@@ -634,9 +691,10 @@ struct Plan {
   int64_t nrow_bb = 0, ncombo = 0, nrow_xg = 0, ncol_xg = 0;
   size_t lds = 0;
   int kc_bb = 4, kc_xg = 4, pstride_bb = 1, bb_full = 0;
+  int nbuf_bb = 1, nbuf_xg = 1;
   int tn = 1;                    // 16-column MFMA tiles per workgroup tile
   // alt kernel
-  int alt_nb = 1, alt_S = 1;
+  int alt_nb = 1, alt_S = 1, alt_nrt = 1, alt_ngrp = 1;
   int64_t alt_chunk = 0;
   size_t alt_lds = 0;
   bool need_alt = false;
@@ -786,7 +844,7 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
     // resident slots (CUs x workgroups per CU) best in whole rounds; a
     // larger count must gain 2 points of fill to be taken (each split adds
     // a partial tile to write and reduce)
-    const int64_t slots = int64_t(device_cus(c)) * std::max(1, 2048 / NT);
+    const int64_t slots = int64_t(device_cus(c)) * std::max(1, 16 * 64 / NT);
     const int64_t max_s =
         std::max<int64_t>(1, std::min<int64_t>(64, d.N / 1024));
     double best = -1.0;
@@ -848,57 +906,69 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
   int max_ncol = 0;
   for (int64_t t = 0; t < nrt_bb; ++t) max_ncol = std::max(max_ncol, bb_ncol[t]);
   pl->pstride_bb = std::max(max_ncol, 1);
-  auto lds_of = [&](int type, int kc, int bn) -> size_t {
+  auto lds_of = [&](int type, int kc, int bn, int nbuf) -> size_t {
     const int pc = type == T_BB ? pl->pstride_bb : K;
-    if (prec == 0) return tile_lds<0>(type, kc, K, p, a, bn, pc).total;
-    if (prec == 1) return tile_lds<1>(type, kc, K, p, a, bn, pc).total;
-    return tile_lds<2>(type, kc, K, p, a, bn, pc).total;
+    if (prec == 0) return tile_lds<0>(type, kc, K, p, a, bn, pc, nbuf).total;
+    if (prec == 1) return tile_lds<1>(type, kc, K, p, a, bn, pc, nbuf).total;
+    return tile_lds<2>(type, kc, K, p, a, bn, pc, nbuf).total;
   };
   // observations per round: the largest multiple of the MFMA's observation
   // count that keeps LDS small enough for several workgroups per CU
-  auto pick_kc = [&](int type, int kc0, int bn) -> int {
-    int kc = kc0;
+  // (double-buffered raw inputs if they fit; one buffer otherwise)
+  auto pick_kc = [&](int type, int kc0, int bn, int *nbuf) -> int {
     // 16-wave workgroups own a CU; 8-wave ones share it with a second
-    const size_t budget = kRows >= 256 ? size_t(150 * 1024) : size_t(78 * 1024);
-    while (kc > KSTEP && lds_of(type, kc, bn) > budget) kc -= KSTEP;
-    return lds_of(type, kc, bn) > 150 * 1024 ? 0 : kc;
+    const size_t budget = kRows >= 192 ? size_t(150 * 1024) : size_t(78 * 1024);
+    for (int nb2 = 2; nb2 >= 1; --nb2) {
+      for (int kc = kc0; kc >= KSTEP; kc -= KSTEP) {
+        if (lds_of(type, kc, bn, nb2) <= budget) {
+          *nbuf = nb2;
+          return kc;
+        }
+      }
+    }
+    *nbuf = 1;
+    return lds_of(type, KSTEP, bn, 1) > 150 * 1024 ? 0 : KSTEP;
   };
-  pl->kc_bb = nrow_bb ? pick_kc(T_BB, KCB0, cw_bb) : KSTEP;
-  pl->kc_xg = nrow_xg ? pick_kc(T_XG, KCX0, cw_xg) : KSTEP;
+  pl->nbuf_bb = pl->nbuf_xg = 1;
+  pl->kc_bb = nrow_bb ? pick_kc(T_BB, KCB0, cw_bb, &pl->nbuf_bb) : KSTEP;
+  pl->kc_xg = nrow_xg ? pick_kc(T_XG, KCX0, cw_xg, &pl->nbuf_xg) : KSTEP;
   if (pl->kc_bb == 0 || pl->kc_xg == 0) {
     return set_error(c, MNL_ERR_UNSUPPORTED,
                      "Hessian tile exceeds LDS (p=%d K=%d a=%d)", p, K, a);
   }
-  pl->lds = std::max(nrow_bb ? lds_of(T_BB, pl->kc_bb, cw_bb) : size_t(0),
-                     nrow_xg ? lds_of(T_XG, pl->kc_xg, cw_xg) : size_t(0));
+  pl->lds = std::max(
+      nrow_bb ? lds_of(T_BB, pl->kc_bb, cw_bb, pl->nbuf_bb) : size_t(0),
+      nrow_xg ? lds_of(T_XG, pl->kc_xg, cw_xg, pl->nbuf_xg) : size_t(0));
 
   // per-alternative kernel
   pl->need_alt = (a + g) > 0;
   if (pl->need_alt) {
     const int nl = p + a + g, nr = a + g;
-    if (nr > kAltNR) {
+    if (nr > kAltNR)
       return set_error(c, MNL_ERR_UNSUPPORTED,
                        "more than %d alternative-varying variables", kAltNR);
-    }
-    const int nrb = (nl + kAltRB - 1) / kAltRB;
-    if (nrb > kThreads) {
-      return set_error(c, MNL_ERR_UNSUPPORTED, "too many features");
-    }
-    int nb = std::max(1, std::min(kThreads / nrb, K));
-    auto lds_alt = [&](int b2) {
-      return size_t(kAltTB) * (p + size_t(b2) * (a + g + 1)) * 8;
-    };
-    while (nb > 1 && lds_alt(nb) > 64 * 1024) --nb;
+    int nrt = (nl + 15) / 16;
+    if (nrt > 8)
+      return set_error(c, MNL_ERR_UNSUPPORTED, "more than 128 features");
+    if (nrt == 5) nrt = 6;
+    if (nrt == 7) nrt = 8;
+    const int nq = nrt == 1 ? 8 : (nrt == 2 ? 4 : (nrt <= 4 ? 2 : 1));
+    const int nb = 4 * nq;
+    pl->alt_nrt = nrt;
     pl->alt_nb = nb;
     const int ngrp = (K + nb - 1) / nb;
-    int Sa = std::max(1, 512 / ngrp);
-    Sa = int(std::min<int64_t>(Sa, std::max<int64_t>(1, d.N / 128)));
+    pl->alt_ngrp = ngrp;
+    int Sa = std::max(1, 1024 / ngrp);
+    Sa = int(std::min<int64_t>(Sa, std::max<int64_t>(1, d.N / 64)));
     int64_t ch = (d.N + Sa - 1) / Sa;
     ch = (ch + kAltTB - 1) / kAltTB * kAltTB;
     Sa = int((d.N + ch - 1) / ch);
     pl->alt_S = Sa;
     pl->alt_chunk = ch;
-    pl->alt_lds = lds_alt(nb);
+    pl->alt_lds = 2 * size_t(kAltTB) *
+                  (p + size_t(nb) * a + size_t(nb) * g + g + nb + 1) * 8;
+    if (pl->alt_lds > 150 * 1024)
+      return set_error(c, MNL_ERR_UNSUPPORTED, "per-alternative tile too big");
   }
 
   // table layout (one allocation)
@@ -1026,6 +1096,30 @@ hipError_t launch_tiles(const Plan &pl, const HessDev &hd, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+template <int NRT>
+hipError_t launch_alt_nrt(const Plan &pl, const HessArgs &h, double *part,
+                          hipStream_t s) {
+  hipError_t e = raise_lds_limit(
+      reinterpret_cast<const void *>(&k_hess_alt<NRT>), (int)pl.alt_lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_hess_alt<NRT>), dim3(pl.alt_ngrp * pl.alt_S),
+                     dim3(kThreads), pl.alt_lds, s, pl.d, h.X, h.Y, h.Z, h.w,
+                     h.P, h.Ybar, pl.alt_nb, pl.alt_ngrp, pl.alt_chunk, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_alt(const Plan &pl, const HessArgs &h, double *part,
+                      hipStream_t s) {
+  switch (pl.alt_nrt) {
+    case 1: return launch_alt_nrt<1>(pl, h, part, s);
+    case 2: return launch_alt_nrt<2>(pl, h, part, s);
+    case 3: return launch_alt_nrt<3>(pl, h, part, s);
+    case 4: return launch_alt_nrt<4>(pl, h, part, s);
+    case 6: return launch_alt_nrt<6>(pl, h, part, s);
+    default: return launch_alt_nrt<8>(pl, h, part, s);
+  }
+}
+
 template <typename AccT>
 hipError_t launch_assemble(const Plan &pl, const HessArgs &h, void *pbb,
                            void *pxg, const double *alt, hipStream_t s) {
@@ -1067,12 +1161,7 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   double *alt = reinterpret_cast<double *>(wb + L.o_red);
 
   if (pl->need_alt) {
-    const int ngrp = (d.K + pl->alt_nb - 1) / pl->alt_nb;
-    MNL_HIP(c, raise_lds_limit(reinterpret_cast<const void *>(&k_hess_alt),
-                               (int)pl->alt_lds));
-    hipLaunchKernelGGL(k_hess_alt, dim3(ngrp, pl->alt_S), dim3(kThreads),
-                       pl->alt_lds, s, d, h.X, h.Y, h.Z, h.w, h.P, h.Ybar,
-                       pl->alt_nb, pl->alt_chunk, alt_part);
+    MNL_HIP(c, launch_alt(*pl, h, alt_part, s));
     hipLaunchKernelGGL(k_alt_reduce, dim3((unsigned)((n_alt + 255) / 256)),
                        dim3(256), 0, s, alt_part, pl->alt_S, int64_t(n_alt),
                        alt);
@@ -1102,6 +1191,8 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   hd.ncol_xg = pl->ncol_xg;
   hd.kc_bb = pl->kc_bb;
   hd.kc_xg = pl->kc_xg;
+  hd.nbuf_bb = pl->nbuf_bb;
+  hd.nbuf_xg = pl->nbuf_xg;
   hd.pstride_bb = pl->pstride_bb;
   hd.bb_full = pl->bb_full;
   if (c->ev_ready && pl->ntiles > 0) {

@@ -36,6 +36,22 @@ __device__ inline void batched_copy(int n, int tid, int nthr, Load ld,
   }
 }
 
+// Asynchronous copy of n dwords from global memory to LDS by one wave: each
+// instruction moves 64 consecutive dwords straight into LDS (no registers);
+// the copy has landed after s_waitcnt vmcnt(0) (which __syncthreads
+// includes).  src: 4-byte aligned; dst: LDS, 4-byte aligned.
+typedef __attribute__((address_space(3))) void lds_void_t;
+__device__ inline void wave_copy_lds(const void *src, void *dst, int n,
+                                     int lane) {
+  const uint32_t *s = static_cast<const uint32_t *>(src);
+  char *dc = static_cast<char *>(dst);
+  for (int c = 0; c < n; c += 64) {
+    if (c + lane < n)
+      __builtin_amdgcn_global_load_lds(s + c + lane,
+                                       (lds_void_t *)(dc + 4 * c), 4, 0, 0);
+  }
+}
+
 // Dimensions of a problem, validated.
 struct Dims {
   int64_t N;

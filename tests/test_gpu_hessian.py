@@ -81,6 +81,13 @@ def test_hessian_config_sampled_blocks(ctx, name):
     picks = [(0, 0), (0, 1), (len(chunks) - 1, len(chunks) - 1),
              (len(chunks) - 2, len(chunks) - 1)]
     picks += [tuple(sorted(rng.integers(0, len(chunks), 2))) for _ in range(6)]
+    last_is_alpha = pr.g > 0
+    if last_is_alpha and pr.K > 50:
+        # the literal alpha-alpha block of Eq. 10 sums K^2 products of N-row
+        # matrices (minutes at this size); it is compared in full at the
+        # c2 size and on the small shapes
+        a_idx = len(chunks) - 1
+        picks = [pk for pk in picks if pk != (a_idx, a_idx)]
     for i, j in picks:
         cn, cm = chunks[i], chunks[j]
         B = R.hessian_block(P, pr.X, pr.Y, pr.Z, w, cn, cm)
