@@ -59,7 +59,7 @@ template <> struct MF<0> {
   using T = double;
   using OT = double;
   using Acc = d4;
-  static constexpr int KSTEP = 4, KCB = 16, KCX = 16, TN = 8, NW = 16;
+  static constexpr int KSTEP = 4, KCB = 32, KCX = 32, TN = 8, NW = 16;
   __device__ static int out_row(int l, int r) { return (l >> 4) + 4 * r; }
   __device__ static Acc zero() { return Acc{0, 0, 0, 0}; }
 };
@@ -143,7 +143,7 @@ __host__ __device__ inline TileLds tile_lds(int type, int KC, int K, int p,
   L.rawsz = align16(L.rw + KC * 8);
   int o = 0;
   L.raw0 = o; o += nbuf * L.rawsz;
-  L.tab = o;  o = align16(o + (kRows + bn) * 4);
+  L.tab = o;  o = align16(o + (kRows + bn + pcols) * 4);
   L.opa = o;  o = align16(o + kRows * kp * osz);
   L.opb = o;  o = align16(o + bn * kp * osz);
   L.total = o;
@@ -189,6 +189,7 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
   OT *opa = reinterpret_cast<OT *>(smb + L.opa);
   OT *opb = reinterpret_cast<OT *>(smb + L.opb);
   const int pstride = is_bb ? H.pstride_bb : K;
+  const bool gather = is_bb && !H.bb_full;
   // raw buffer b of the round: P columns, then X, Z, w (FP64)
   auto rawp = [&](int b) {
     return reinterpret_cast<T *>(smb + L.raw0 + b * L.rawsz);
@@ -212,7 +213,12 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
       const int col = tile.col0 + c;
       tab[kRows + c] = col < H.ncombo ? H.bb_combo[col] : 0xffffffffu;
     }
+    if (gather)
+      for (int c = tid; c < ncol; c += NT) tab[kRows + bn + c] = cols[c];
   }
+  // staged P columns per observation of this tile
+  const int pst = gather ? ncol : pstride;
+  const uint32_t *colt = tab + kRows + bn;
   // start from zeros in both raw buffers: the slots past the last
   // observation keep stale (finite) values that meet a zero weight
   for (int e = tid; e < nbuf * L.rawsz / 4; e += NT)
@@ -233,12 +239,29 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
       }
     };
     T *Pw = rawp(b);
-    if (is_bb && !H.bb_full) {
-      for (int e = tid; e < KC * ncol; e += NT) {
+    if (gather && (PREC == 0 || H.P32)) {
+      // the tile's columns of each row, [obs][ncol] in LDS, element by
+      // element (dword by dword) straight into LDS
+      constexpr int DW = sizeof(T) / 4;
+      const uint32_t *b32 =
+          PREC == 0 ? reinterpret_cast<const uint32_t *>(H.P)
+                    : reinterpret_cast<const uint32_t *>(H.P32);
+      const int ndw = nobs * ncol * DW;
+      char *d8 = reinterpret_cast<char *>(Pw);
+      for (int c0 = 64 * wv; c0 < ndw; c0 += 64 * (NT / 64)) {
+        const int t = c0 + lane;
+        if (t < ndw) {
+          const int e = t / DW, hf = t - e * DW;
+          const int j = e / ncol, c = e - j * ncol;
+          __builtin_amdgcn_global_load_lds(
+              b32 + (int64_t(i0 + j) * K + int(colt[c])) * DW + hf,
+              (lds_void_t *)(d8 + 4 * c0), 4, 0, 0);
+        }
+      }
+    } else if (gather) {
+      for (int e = tid; e < nobs * ncol; e += NT) {
         const int j = e / ncol, c = e - j * ncol;
-        Pw[j * pstride + c] =
-            j < nobs ? ldg_op<T>(H.P, H.P32, int64_t(i0 + j) * K + cols[c])
-                     : T(0);
+        Pw[j * pst + c] = ldg_op<T>(H.P, H.P32, int64_t(i0 + j) * K + colt[c]);
       }
     } else if (PREC == 0 || !H.P32) {
       if (PREC == 0) {
@@ -334,10 +357,9 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
       for (int k = ka0; k < KC; k += NT / kRows) {
         T v;
         if (is_bb)
-          v = T(Ws[k]) * Ps[k * pstride + a_ln] *
-              (a_dg - Ps[k * pstride + a_lm]);
+          v = T(Ws[k]) * Ps[k * pst + a_ln] * (a_dg - Ps[k * pst + a_lm]);
         else
-          v = T(Ws[k]) * Ps[k * pstride + a_ln] *
+          v = T(Ws[k]) * Ps[k * pst + a_ln] *
               T(a_z ? Zs[k * K * a + a_f] : Xs[k * p + a_f]);
         if constexpr (PREC == 2) opa[ra * kp + k] = (__bf16)v;
         else opa[k * kRows + ra] = v;
@@ -354,7 +376,7 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
         T v = T(0);
         if (b_ok) {
           if (is_bb) v = T(Xs[k * p + b_f1] * Xs[k * p + b_f2]);
-          else v = Ps[k * pstride + b_f1] * T(Zs[k * K * a + b_f2]);
+          else v = Ps[k * pst + b_f1] * T(Zs[k * K * a + b_f2]);
         }
         if constexpr (PREC == 2) opb[cbx * kp + k] = (__bf16)v;
         else opb[k * bn + cbx] = v;
@@ -594,6 +616,7 @@ __global__ void k_assemble_bb(Dims d, const AccT *part, int S, int64_t Mp,
   const int64_t r = e / ncombo, q = e - (e / ncombo) * ncombo;
   double v = 0.0;
   for (int s = 0; s < S; ++s) v += (double)part[(int64_t(s) * Mp + r) * Np + q];
+  if (pair_nm[r] == 0) return;  // padding row of a pair block
   const int n = pair_nm[r] & 0xffff, m = pair_nm[r] >> 16;
   const int fa = combo[q] & 0xffff, fb = combo[q] >> 16;
   const int64_t np = d.np, p = d.p;
@@ -764,10 +787,36 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
     return (n16_of(ncols) + tnu - 1) / tnu;
   };
 
-  // BB rows: pairs n <= m over alternatives 1..K-1, row-major
+  // BB rows: pairs n <= m over alternatives 1..K-1.  Row-major, or, when
+  // there are many alternatives, in blocks of (kRows / 16) x 16
+  // alternatives, one block per row tile, so that a tile stages the P
+  // columns of its two blocks only (padding rows are 0)
   std::vector<int32_t> pair_nm;
-  for (int n = 1; n < K; ++n)
-    for (int m = n; m < K; ++m) pair_nm.push_back(n | (m << 16));
+  bool blocked = false;
+  {
+    const int Lk = K - 1, bh = kRows / 16, bw = 16;
+    int64_t rows_blk = 0;
+    for (int bi = 0; 1 + bi * bh <= Lk; ++bi)
+      for (int bj = 0; 1 + bj * bw <= Lk; ++bj)
+        if (1 + bi * bh <= bj * bw + bw) rows_blk += kRows;
+    const double pairs = double(Lk) * (Lk + 1) / 2.0;
+    blocked = p > 0 && Lk > 2 * bw && double(rows_blk) <= 1.15 * pairs;
+    if (blocked) {
+      for (int bi = 0; 1 + bi * bh <= Lk; ++bi)
+        for (int bj = 0; 1 + bj * bw <= Lk; ++bj) {
+          if (1 + bi * bh > bj * bw + bw) continue;
+          for (int dn = 0; dn < bh; ++dn)
+            for (int dm = 0; dm < bw; ++dm) {
+              const int n = 1 + bi * bh + dn, m = 1 + bj * bw + dm;
+              pair_nm.push_back((n <= Lk && m <= Lk && n <= m)
+                                    ? (n | (m << 16)) : 0);
+            }
+        }
+    } else {
+      for (int n = 1; n < K; ++n)
+        for (int m = n; m < K; ++m) pair_nm.push_back(n | (m << 16));
+    }
+  }
   const int64_t nrow_bb = p > 0 ? int64_t(pair_nm.size()) : 0;
   std::vector<uint32_t> combo;
   for (int fa = 0; fa < p; ++fa)
@@ -780,7 +829,7 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
   std::vector<int32_t> bb_cols(std::max<int64_t>(nrt_bb, 1) * kMaxCols, 0);
   std::vector<int32_t> bb_ncol(std::max<int64_t>(nrt_bb, 1), 0);
   std::vector<uint32_t> bb_row(std::max<int64_t>(nrow_bb, 1), 0);
-  pl->bb_full = K <= kMaxCols ? 1 : 0;
+  pl->bb_full = (!blocked && K <= kMaxCols) ? 1 : 0;
   if (K > 4095) {
     return set_error(c, MNL_ERR_UNSUPPORTED, "Hessian tiles need K < 4096");
   }
@@ -791,6 +840,7 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
       for (int k = 0; k < K; ++k) alts.push_back(k);
     } else {
       for (int64_t r = t * kRows; r < r1; ++r) {
+        if (pair_nm[r] == 0) continue;
         alts.push_back(pair_nm[r] & 0xffff);
         alts.push_back(pair_nm[r] >> 16);
       }
@@ -800,6 +850,7 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
     bb_ncol[t] = int(alts.size());
     for (size_t q = 0; q < alts.size(); ++q) bb_cols[t * kMaxCols + q] = alts[q];
     for (int64_t r = t * kRows; r < r1; ++r) {
+      if (pair_nm[r] == 0) continue;   // padding row: not valid
       const int n = pair_nm[r] & 0xffff, m = pair_nm[r] >> 16;
       const uint32_t ln = uint32_t(std::lower_bound(alts.begin(), alts.end(), n) - alts.begin());
       const uint32_t lm = uint32_t(std::lower_bound(alts.begin(), alts.end(), m) - alts.begin());

@@ -19,6 +19,7 @@ SHAPES = [  # N, K, p, g, a, weights
     (1000, 6, 0, 0, 3, "int"),
     (1500, 13, 12, 2, 2, "uniform"),
     (600, 66, 1, 1, 1, None),
+    (300, 129, 3, 1, 1, "uniform"),   # many alternatives: blocked pair rows
 ]
 
 
