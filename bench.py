@@ -251,6 +251,53 @@ def serving(n_req, slots, load):
     return out
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "c2_fp64_hessian_traffic.md")
+HESS_SRC = os.path.join(ROOT, "paper_1404_3177_amd", "csrc", "k_hess.hip")
+
+
+def source_digest(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the Hessian tile kernel from the committed
+    counter profile (FETCH_SIZE / WRITE_SIZE, scaled by a plain copy of
+    known size), or None when the kernel source changed since."""
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+        blk = txt.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(blk)
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != source_digest(HESS_SRC):
+        return None
+    return rec
+
+
+def traffic_probe():
+    """Workload of the traffic profile: a 1 GiB device copy (the counters'
+    calibration), then one C2 Hessian and one fused pass.  Run under
+    rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE)."""
+    import torch
+    import paper_1404_3177_amd as mnl
+    import synth
+    x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    x.fill_(1.0)
+    torch.cuda.synchronize()
+    y = x.clone()   # reads 1 GiB, writes 1 GiB
+    torch.cuda.synchronize()
+    del x, y
+    pr = synth.make_config("c2")
+    ctx = mnl.Context(0)
+    dp = mnl.Problem.from_numpy(pr, device="cuda:0")
+    th = torch.from_numpy(0.5 * pr.theta_true).cuda()
+    ctx.hessian(dp, th, prec="fp64")
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "done", "hessian_source": source_digest(HESS_SRC)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,11 +311,17 @@ def main():
                     help="requests of the serving stream (0: skip serving)")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only run the workload of the counter profile")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the "
               "fit is not sharded across GPUs in this build", file=sys.stderr)
         sys.exit(2)
+
+    if args.traffic_probe:
+        traffic_probe()
+        return
 
     import numpy as np
     import torch
@@ -356,6 +409,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": ks["tflops"] / ks["peak"],
             "traffic": None,
+            "traffic_source": None,
             "kernel": f"k_hess_tiles<{ {'fp64': 0, 'fp32': 1, 'bf16': 2}[args.prec] }>",
             "kernel_ms": ks["hess_ms"],
             "launches": ks["n_hess"],
@@ -380,6 +434,12 @@ def main():
         "serving": serve,
         "cpu_baseline": cpu,
     }
+    if args.prec == "fp64" and args.config == "c2":
+        rec = recorded_traffic()
+        if rec is not None:
+            res["roofline"]["traffic"] = rec["hbm_bytes_per_launch"]
+            res["roofline"]["traffic_source"] = os.path.relpath(
+                TRAFFIC_PROFILE, ROOT)
     print(json.dumps(res), flush=True)
 
 
