@@ -58,7 +58,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed on {failed}")
     tmp = LIB + ".tmp"
     cmd = [cc, "-shared", "-fPIC", "-pthread", "--offload-arch=gfx950", *objs,
-           "-o", tmp]
+           "-lrocblas", "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)

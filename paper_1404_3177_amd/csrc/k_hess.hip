@@ -24,9 +24,15 @@
 // Tiles of both GEMM kinds run in one launch on MFMA (FP64, FP32 or BF16
 // operands), split over observations; the split partials are summed in a
 // fixed order, so the result is reproducible.
+//  * for large beta-beta products (many pairs x many feature pairs) the two
+//    operands are materialised instead: X o X once per fit and Omega in
+//    chunks of observations, and the product is a plain library GEMM
+//    (rocBLAS, atomics off, chunks accumulated in a fixed order).
 #include <algorithm>
 #include <map>
 #include <tuple>
+
+#include <rocblas/rocblas.h>
 
 #include "mnl_common.h"
 
@@ -588,6 +594,43 @@ __global__ __launch_bounds__(kThreads) void k_hess_alt(
   }
 }
 
+// Materialised beta-beta operands.  Omega rows follow the plan's pair rows
+// (0 entries are padding): om[j][r] = w_i P_in (delta_nm - P_im) for the
+// observations i = i0 + j of one chunk, in the precision the tile kernels
+// use for it (FP64 from P, else FP32 from P32), stored in the operand type.
+template <typename OT, typename CT>
+__global__ void k_form_omega(int K, const double *P, const float *P32,
+                             const double *w, const int32_t *pair_nm,
+                             int64_t nrow, int64_t i0, int nc, OT *om) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= nrow) return;
+  const int32_t pm = pair_nm[r];
+  const int n = pm & 0xffff, m = pm >> 16;
+  const CT dl = n == m ? CT(1) : CT(0);
+  for (int j = blockIdx.y; j < nc; j += gridDim.y) {
+    const int64_t i = i0 + j;
+    CT v = CT(0);
+    if (pm != 0) {
+      const CT pn = P32 ? CT(P32[i * K + n]) : CT(P[i * K + n]);
+      const CT pmv = P32 ? CT(P32[i * K + m]) : CT(P[i * K + m]);
+      const CT wi = w ? CT(w[i]) : CT(1);
+      v = wi * pn * (dl - pmv);
+    }
+    om[int64_t(j) * nrow + r] = OT(v);
+  }
+}
+
+// xx[i][q] = x_ia x_ib for feature pair q = (a, b): iteration-invariant
+template <typename OT, typename CT>
+__global__ void k_form_xx(const double *X, int p, const uint32_t *combo,
+                          int64_t ncombo, int64_t N, OT *xx) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= ncombo) return;
+  const int fa = combo[q] & 0xffff, fb = combo[q] >> 16;
+  for (int64_t i = blockIdx.y; i < N; i += gridDim.y)
+    xx[i * ncombo + q] = OT(CT(X[i * p + fa] * X[i * p + fb]));
+}
+
 // sum the observation splits of the per-alternative sums in a fixed order
 __global__ void k_alt_reduce(const double *alt, int S, int64_t n,
                              double *red) {
@@ -716,6 +759,8 @@ struct Plan {
   int kc_bb = 4, kc_xg = 4, pstride_bb = 1, bb_full = 0;
   int nbuf_bb = 1, nbuf_xg = 1;
   int tn = 1;                    // 16-column MFMA tiles per workgroup tile
+  bool bb_gemm = false;          // beta-beta by materialised operands + GEMM
+  int64_t gemm_nc = 0;           // observations per Omega chunk
   // alt kernel
   int alt_nb = 1, alt_S = 1, alt_nrt = 1, alt_ngrp = 1;
   int64_t alt_chunk = 0;
@@ -875,12 +920,29 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
   pl->xg_M = nrt_xg * kRows;
   pl->xg_N = std::max<int64_t>(nct_xg * cw_xg, 16);
 
+  // large beta-beta products go to a library GEMM on materialised
+  // operands (where it runs faster than the generated-operand tiles:
+  // always for BF16, for FP32 / FP64 with many feature pairs)
+  {
+    const double bbsz = double(nrow_bb) * double(ncombo);
+    pl->bb_gemm = nrow_bb > 0 &&
+                  ((prec == 2 && bbsz >= 1e6) ||
+                   (prec != 2 && ncombo >= 512 && bbsz >= 2e6));
+    if (pl->bb_gemm) {
+      const size_t osz = prec == 2 ? 2 : (prec == 1 ? 4 : 8);
+      int64_t nc = int64_t((size_t(1) << 30) / (size_t(nrow_bb) * osz));
+      nc = std::max<int64_t>(256, nc / 256 * 256);
+      pl->gemm_nc = std::min<int64_t>(nc, d.N);
+    }
+  }
+
   // output tiles, then observation splits
   struct OutTile { int type, row0, col0, tn; };
   std::vector<OutTile> out_tiles;
-  for (int64_t rt = 0; rt < nrt_bb; ++rt)
-    for (int64_t ct = 0; ct < nct_bb; ++ct)
-      out_tiles.push_back({T_BB, int(rt * kRows), int(ct * cw_bb), tn_bb});
+  if (!pl->bb_gemm)
+    for (int64_t rt = 0; rt < nrt_bb; ++rt)
+      for (int64_t ct = 0; ct < nct_bb; ++ct)
+        out_tiles.push_back({T_BB, int(rt * kRows), int(ct * cw_bb), tn_bb});
   for (int64_t rt = 0; rt < nrt_xg; ++rt)
     for (int64_t ct = 0; ct < nct_xg; ++ct) {
       const int64_t r0 = rt * kRows, c0 = ct * cw_xg;
@@ -1115,7 +1177,12 @@ struct PartLayout {
 PartLayout part_layout(const Plan &pl) {
   const Dims &d = pl.d;
   const size_t asz = pl.prec == 0 ? 8 : 4;
-  const size_t bytes_bb = size_t(pl.S) * pl.bb_M * pl.bb_N * asz;
+  const size_t osz = pl.prec == 2 ? 2 : asz;
+  // GEMM mode: the product [nrow][ncombo] then one Omega chunk
+  const size_t bytes_bb =
+      pl.bb_gemm ? ((size_t(pl.nrow_bb) * pl.ncombo * asz + 255) & ~size_t(255)) +
+                       size_t(pl.gemm_nc) * pl.nrow_bb * osz
+                 : size_t(pl.S) * pl.bb_M * pl.bb_N * asz;
   const size_t bytes_xg = size_t(pl.S) * pl.xg_M * pl.xg_N * asz;
   const int nl = d.p + d.a + d.g, nr = d.a + d.g;
   PartLayout L;
@@ -1176,11 +1243,14 @@ hipError_t launch_assemble(const Plan &pl, const HessArgs &h, void *pbb,
                            void *pxg, const double *alt, hipStream_t s) {
   const Dims &d = pl.d;
   if (pl.nrow_bb > 0) {
+    // tile partials [S][bb_M][bb_N], or the GEMM product [nrow][ncombo]
+    const int Sb = pl.bb_gemm ? 1 : pl.S;
+    const int64_t Mp = pl.bb_gemm ? pl.nrow_bb : pl.bb_M;
+    const int64_t Np = pl.bb_gemm ? pl.ncombo : pl.bb_N;
     const int64_t n = pl.nrow_bb * pl.ncombo;
     hipLaunchKernelGGL(k_assemble_bb<AccT>, dim3((unsigned)((n + 255) / 256)),
-                       dim3(256), 0, s, d, (const AccT *)pbb, pl.S, pl.bb_M,
-                       pl.bb_N, pl.pair_nm, pl.bb_combo, pl.nrow_bb,
-                       pl.ncombo, h.H);
+                       dim3(256), 0, s, d, (const AccT *)pbb, Sb, Mp, Np,
+                       pl.pair_nm, pl.bb_combo, pl.nrow_bb, pl.ncombo, h.H);
   }
   if (pl.nrow_xg > 0) {
     const int64_t n = pl.nrow_xg * pl.ncol_xg;
@@ -1197,6 +1267,72 @@ hipError_t launch_assemble(const Plan &pl, const HessArgs &h, void *pbb,
 }
 
 }  // namespace
+
+// The beta-beta product by materialised operands: X o X (once per call
+// epoch of the context, reused by every Hessian of a fit), Omega chunk by
+// chunk, C = sum over chunks of (X o X)^T Omega on rocBLAS (column-major:
+// C^T [ncombo x nrow] = XX_chunk [ncombo x nc] * Omega_chunk^T).
+template <typename OT, typename CT>
+int bb_gemm_run(Ctx *c, const Plan &pl, const HessArgs &h, void *cbuf,
+                void *omega, hipStream_t s) {
+  const Dims &d = pl.d;
+  const int64_t nrow = pl.nrow_bb, ncombo = pl.ncombo;
+  void *xxv;
+  MNL_TRY(ws_get(c, S_XX, size_t(d.N) * ncombo * sizeof(OT), &xxv));
+  OT *xx = static_cast<OT *>(xxv);
+  if (!(c->xx_X == h.X && c->xx_N == d.N && c->xx_p == d.p &&
+        c->xx_prec == h.prec && c->xx_epoch == c->call_epoch &&
+        c->xx_buf == xxv)) {
+    dim3 grid((unsigned)((ncombo + 255) / 256),
+              (unsigned)std::min<int64_t>(d.N, 4096));
+    hipLaunchKernelGGL((k_form_xx<OT, CT>), grid, dim3(256), 0, s, h.X, d.p,
+                       pl.bb_combo, ncombo, d.N, xx);
+    MNL_HIP(c, hipGetLastError());
+    c->xx_X = h.X;
+    c->xx_N = d.N;
+    c->xx_p = d.p;
+    c->xx_prec = h.prec;
+    c->xx_epoch = c->call_epoch;
+    c->xx_buf = xxv;
+  }
+  if (!c->blas) {
+    rocblas_handle hb;
+    if (rocblas_create_handle(&hb) != rocblas_status_success)
+      return set_error(c, MNL_ERR_HIP, "rocblas_create_handle failed");
+    // no atomics: every GEMM result is bitwise reproducible
+    (void)rocblas_set_atomics_mode(hb, rocblas_atomics_not_allowed);
+    c->blas = hb;
+  }
+  rocblas_handle hb = static_cast<rocblas_handle>(c->blas);
+  if (rocblas_set_stream(hb, s) != rocblas_status_success)
+    return set_error(c, MNL_ERR_HIP, "rocblas_set_stream failed");
+  const rocblas_datatype ab =
+      h.prec == 2 ? rocblas_datatype_bf16_r
+                  : (h.prec == 1 ? rocblas_datatype_f32_r
+                                 : rocblas_datatype_f64_r);
+  const rocblas_datatype ct =
+      h.prec == 0 ? rocblas_datatype_f64_r : rocblas_datatype_f32_r;
+  const CT one = CT(1), zero = CT(0);
+  OT *om = static_cast<OT *>(omega);
+  for (int64_t i0 = 0; i0 < d.N; i0 += pl.gemm_nc) {
+    const int nc = int(std::min<int64_t>(pl.gemm_nc, d.N - i0));
+    dim3 grid((unsigned)((nrow + 255) / 256), (unsigned)std::min(nc, 1024));
+    hipLaunchKernelGGL((k_form_omega<OT, CT>), grid, dim3(256), 0, s, d.K,
+                       h.prec == 0 ? h.P : nullptr,
+                       h.prec == 0 ? nullptr : h.P32, h.w, pl.pair_nm, nrow,
+                       i0, nc, om);
+    MNL_HIP(c, hipGetLastError());
+    const rocblas_status st = rocblas_gemm_ex(
+        hb, rocblas_operation_none, rocblas_operation_transpose,
+        rocblas_int(ncombo), rocblas_int(nrow), rocblas_int(nc), &one,
+        xx + i0 * ncombo, ab, rocblas_int(ncombo), om, ab, rocblas_int(nrow),
+        i0 == 0 ? &zero : &one, cbuf, ct, rocblas_int(ncombo), cbuf, ct,
+        rocblas_int(ncombo), ct, rocblas_gemm_algo_standard, 0, 0);
+    if (st != rocblas_status_success)
+      return set_error(c, MNL_ERR_HIP, "rocblas_gemm_ex failed (%d)", int(st));
+  }
+  return MNL_OK;
+}
 
 int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   Plan *pl;
@@ -1217,6 +1353,21 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
                        dim3(256), 0, s, alt_part, pl->alt_S, int64_t(n_alt),
                        alt);
     MNL_HIP(c, hipGetLastError());
+  }
+  // the timed span: the beta-beta GEMM (if any) and the tiles
+  const bool timed = c->ev_ready && (pl->ntiles > 0 || pl->bb_gemm);
+  if (timed) MNL_HIP(c, hipEventRecord(c->ev_h0, s));
+  if (pl->bb_gemm) {
+    // product first, then the Omega chunk buffer (see part_layout)
+    const size_t asz = h.prec == 0 ? 8 : 4;
+    const size_t cbytes =
+        (size_t(pl->nrow_bb) * pl->ncombo * asz + 255) & ~size_t(255);
+    if (h.prec == 0)
+      MNL_TRY((bb_gemm_run<double, double>(c, *pl, h, pbb, wb + cbytes, s)));
+    else if (h.prec == 1)
+      MNL_TRY((bb_gemm_run<float, float>(c, *pl, h, pbb, wb + cbytes, s)));
+    else
+      MNL_TRY((bb_gemm_run<__bf16, float>(c, *pl, h, pbb, wb + cbytes, s)));
   }
   HessDev hd;
   hd.d = d;
@@ -1246,9 +1397,6 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   hd.nbuf_xg = pl->nbuf_xg;
   hd.pstride_bb = pl->pstride_bb;
   hd.bb_full = pl->bb_full;
-  if (c->ev_ready && pl->ntiles > 0) {
-    MNL_HIP(c, hipEventRecord(c->ev_h0, s));
-  }
   if (h.prec == 0) {
     MNL_HIP(c, launch_tiles<0>(*pl, hd, s));
   } else if (h.prec == 1) {
@@ -1256,7 +1404,7 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   } else {
     MNL_HIP(c, launch_tiles<2>(*pl, hd, s));
   }
-  if (c->ev_ready && pl->ntiles > 0) {
+  if (timed) {
     MNL_HIP(c, hipEventRecord(c->ev_h1, s));
     c->hess_pending = true;
   }
@@ -1281,7 +1429,16 @@ int hessian_footprint(Ctx *c, const Dims &d, int prec, size_t *part_bytes,
   MNL_TRY(plan_host(c, d, prec, &pl));
   *part_bytes = part_layout(pl).total;
   *table_bytes = pl.dev_bytes;
+  if (pl.bb_gemm)  // X o X of the materialised product (workspace slot S_XX)
+    *table_bytes += size_t(d.N) * pl.ncombo * (prec == 2 ? 2 : (prec == 1 ? 4 : 8));
   return MNL_OK;
+}
+
+void blas_release(Ctx *c) {
+  if (c->blas) {
+    (void)rocblas_destroy_handle(static_cast<rocblas_handle>(c->blas));
+    c->blas = nullptr;
+  }
 }
 
 }  // namespace mnl

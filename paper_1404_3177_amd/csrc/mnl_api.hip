@@ -339,6 +339,7 @@ int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
   MNL_TRY(check_opts(c, &o));
   MNL_HIP(c, hipSetDevice(c->device));
   const double t_start = now_ms();
+  ++c->call_epoch;  // data-derived caches are valid within one call only
   std::memset(info, 0, sizeof *info);
   MNL_TRY(ensure_events(c));
   c->hess_pending = c->pass_pending = false;
@@ -507,6 +508,7 @@ void mnl_destroy(mnl_ctx *ctx) {
   for (auto &b : ctx->c.bufs)
     if (b.ptr) (void)hipFree(b.ptr);
   hessian_cache_free(&ctx->c);
+  blas_release(&ctx->c);
   if (ctx->c.ev_ready) {
     (void)hipEventDestroy(ctx->c.ev_h0);
     (void)hipEventDestroy(ctx->c.ev_h1);
@@ -568,6 +570,7 @@ int mnl_hessian(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
     return set_error(c, MNL_ERR_ARG, "bad precision");
   MNL_HIP(c, hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
+  ++c->call_epoch;
   void *lg;
   MNL_TRY(ws_get(c, S_LG, size_t(d.np + 1) * 8, &lg));
   MNL_TRY(run_pass(c, d, prob, theta, (double *)lg, S_P, S_P32, S_YBAR,

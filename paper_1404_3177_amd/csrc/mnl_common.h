@@ -143,6 +143,8 @@ struct HessArgs {
 };
 int hessian_run(Ctx *c, const HessArgs &a, hipStream_t s);
 void hessian_cache_free(Ctx *c);
+// Destroy the context's library GEMM handle.
+void blas_release(Ctx *c);
 // Device bytes hessian_run takes for a shape: split partials (workspace
 // slot S_HPART) and tile tables.
 int hessian_footprint(Ctx *c, const Dims &d, int prec, size_t *part_bytes,
@@ -175,6 +177,15 @@ struct Ctx {
   hipMemPool_t pool = nullptr;
   hipStream_t ostream = nullptr;
   int ncu = 0;   // compute units of `device` (0: not queried yet)
+  // library GEMM handle (rocBLAS), created on first use
+  void *blas = nullptr;
+  // X o X of the materialised beta-beta product, valid within one call
+  // epoch (one top-level API call: a fit reuses it across its Hessians)
+  uint64_t call_epoch = 0, xx_epoch = ~uint64_t(0);
+  const double *xx_X = nullptr;
+  const void *xx_buf = nullptr;
+  int64_t xx_N = 0;
+  int xx_p = 0, xx_prec = -1;
 };
 
 // Raise a kernel's dynamic-LDS limit on the current device to at least
@@ -215,6 +226,7 @@ enum Slot {
   S_HTAB,          // Hessian tile tables
   S_CHOL,          // Cholesky scratch
   S_THETA0,        // zero start
+  S_XX,            // X o X operand of the materialised beta-beta product
   S_NSLOTS
 };
 

@@ -286,6 +286,7 @@ void mnl_server_destroy(mnl_server *sv) {
     if (sl->stream) {
       (void)hipStreamSynchronize(sl->stream);
       ctx_release(&sl->ctx);
+      blas_release(&sl->ctx);
       (void)hipStreamSynchronize(sl->stream);
       if (sl->ctx.ev_ready) {
         (void)hipEventDestroy(sl->ctx.ev_h0);

@@ -20,6 +20,7 @@ SHAPES = [  # N, K, p, g, a, weights
     (1500, 13, 12, 2, 2, "uniform"),
     (600, 66, 1, 1, 1, None),
     (300, 129, 3, 1, 1, "uniform"),   # many alternatives: blocked pair rows
+    (600, 100, 32, 1, 1, "uniform"),  # many pairs: beta-beta by library GEMM
 ]
 
 
