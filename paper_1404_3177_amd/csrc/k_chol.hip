@@ -15,7 +15,16 @@
 // panel suffices and no two workgroups write the same entry.  A failure flag
 // in device memory makes every later launch return at once.  In A, the
 // diagonal holds D and the strict lower triangle the multipliers of L.
+//
+// Large systems factor by outer panels of NBO columns: the 32-wide steps
+// update only the columns of their outer panel (all rows below), then one
+// library symmetric rank-NBO update (rocBLAS syrkx, atomics off) applies
+// L21 D L21^T to the trailing lower triangle, and a small kernel applies it
+// to the g row.  Each trailing entry is then read and written once per
+// outer panel instead of once per 32-wide step.
 #include <cmath>
+
+#include <rocblas/rocblas.h>
 
 #include "mnl_common.h"
 
@@ -27,6 +36,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int NBF = 32;   // factorisation panel width
 constexpr int NBS = 64;   // backward-solve panel width
 constexpr int TILE = 64;  // trailing-update tile
+constexpr int NBO = 256;  // outer panel width of the blocked factorisation
+constexpr int64_t kOuterMin = 2048;  // smallest n factored by outer panels
 
 // Round-off floor of the pivots, n * eps * max_k A_kk with A = -H, and g^T
 // into row n of the matrix buffer.
@@ -68,8 +79,11 @@ __device__ inline double recip(double d) {
 
 // One step of the blocked right-looking LDL^T factorisation, panel j0
 // (width jb <= NBF), in a single launch.  Workgroup b owns the lower 64x64
-// tile (ti, tj) of the trailing rows [j1, nrows) x columns [j1, n),
-// j1 = j0 + jb.  Every wave factors the panel's diagonal block itself
+// tile (ti, tj) of the trailing rows [j1, nrows) x columns [j1, cend),
+// j1 = j0 + jb; tiles are enumerated by rows (the whole lower triangle, when
+// tcols covers every tile column) or by the tcols tile columns (an outer
+// panel: cend ends it, and at least one tile column exists so that every
+// panel row is factored).  Every wave factors the panel's diagonal block itself
 // (lanes 0..31 hold its rows) while lanes 32..63 carry 32 panel rows of tile
 // row ti (waves 0, 1) or tile column tj (waves 2, 3) through the same column
 // steps, so the diagonal factor and the panel's triangular solve are one
@@ -82,7 +96,8 @@ __device__ inline double recip(double d) {
 // g itself).  Pivots are checked against the round-off floor.
 __global__ __launch_bounds__(256) void k_chol_step(
     double *A, int64_t n, int64_t nrows, int64_t j0, const double *prev,
-    int64_t j0p, double *cur, const double *floor_p, int32_t *info, int neg) {
+    int64_t j0p, double *cur, const double *floor_p, int32_t *info, int neg,
+    int64_t cend, int64_t tcols) {
   __shared__ double Pr[TILE][NBF + 1];
   __shared__ double Pc[TILE][NBF + 1];
   __shared__ double colb[4][128];
@@ -96,10 +111,23 @@ __global__ __launch_bounds__(256) void k_chol_step(
   const int jb = (int)min<int64_t>(NBF, n - j0);
   const int64_t j1 = j0 + jb;
   const int64_t b = blockIdx.x;
-  int64_t ti = (int64_t)((sqrt(8.0 * double(b) + 1.0) - 1.0) * 0.5);
-  while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
-  while (ti * (ti + 1) / 2 > b) --ti;
-  const int64_t tj = b - ti * (ti + 1) / 2;
+  const int64_t T = (nrows - j1 + TILE - 1) / TILE;
+  int64_t ti, tj;
+  if (tcols >= T) {
+    ti = (int64_t)((sqrt(8.0 * double(b) + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+    while (ti * (ti + 1) / 2 > b) --ti;
+    tj = b - ti * (ti + 1) / 2;
+  } else {
+    // column tj holds tiles ti = tj .. T-1 (tcols <= NBO / TILE columns)
+    int64_t rem = b;
+    tj = 0;
+    while (rem >= T - tj) {
+      rem -= T - tj;
+      ++tj;
+    }
+    ti = tj + rem;
+  }
   const int64_t R0 = j1 + ti * TILE, C0 = j1 + tj * TILE;
   const bool same = ti == tj;
 
@@ -134,7 +162,7 @@ __global__ __launch_bounds__(256) void k_chol_step(
     }
   }
   // the tile this workgroup updates, loaded while the chain runs
-  const bool upd = C0 < n;
+  const bool upd = C0 < cend;
   double tv[4][4];
 #pragma unroll
   for (int t = 0; t < 4; ++t)
@@ -142,7 +170,7 @@ __global__ __launch_bounds__(256) void k_chol_step(
     for (int r = 0; r < 4; ++r) {
       const int64_t rr = R0 + 16 * wv + (lane >> 4) + 4 * r;
       const int64_t cc = C0 + 16 * t + (lane & 15);
-      tv[t][r] = (upd && rr < nrows && cc < n && cc <= rr) ? A[rr * n + cc] : 0.0;
+      tv[t][r] = (upd && rr < nrows && cc < cend && cc <= rr) ? A[rr * n + cc] : 0.0;
     }
 #pragma unroll
   for (int k = 0; k < NBF; ++k) {
@@ -221,7 +249,7 @@ __global__ __launch_bounds__(256) void k_chol_step(
         const int64_t rr = R0 + 16 * wv + (lane >> 4) + 4 * r;
         const int64_t cc = C0 + 16 * t + (lane & 15);
         const double sr = (neg && rr < n) ? -1.0 : 1.0;
-        if (rr < nrows && cc < n && cc <= rr)
+        if (rr < nrows && cc < cend && cc <= rr)
           A[rr * n + cc] = sr * tv[t][r] - acc[t][r];
       }
     }
@@ -250,7 +278,7 @@ __global__ __launch_bounds__(256) void k_chol_step(
   }
 }
 
-// the last panel's factor into A, and y (row n) into z
+// the last panel's factor into A, and y (row n) into z (if given)
 __global__ __launch_bounds__(256) void k_chol_copy(double *A, int64_t n,
                                                    int64_t nrows, int64_t j0p,
                                                    const double *prev,
@@ -265,9 +293,49 @@ __global__ __launch_bounds__(256) void k_chol_copy(double *A, int64_t n,
     if (j0p + k < n && (r - j0p >= NBF || k <= r - j0p))
       A[r * n + j0p + k] = prev[r * NBF + k];
   }
+  if (!z) return;
   for (int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x; c < n;
        c += int64_t(gridDim.x) * 256)
     z[c] = c >= j0p ? prev[n * NBF + (c - j0p)] : A[n * n + c];
+}
+
+// Operands of an outer panel's trailing update, columns [J0, J0 + NBO):
+// W[i][k] = L[J1 + i][J0 + k] D_k for the trailing rows i < n - J1 (the
+// library update then forms L21 W^T), and the g row's own update
+// A[n][j] -= sum_k L[j][J0 + k] D_k y_k, one wave per column j, the 256
+// products summed in a fixed order.  Blocks [0, nbw) form W, the rest the
+// g row.
+__global__ __launch_bounds__(256) void k_outer_prep(double *A, int64_t n,
+                                                    int64_t J0, double *W,
+                                                    int64_t nbw,
+                                                    const int32_t *info) {
+  __shared__ double dy[NBO];
+  if (info[0]) return;
+  const int64_t J1 = J0 + NBO, m = n - J1;
+  const int tid = threadIdx.x;
+  if (int64_t(blockIdx.x) < nbw) {
+    const int64_t e = int64_t(blockIdx.x) * 256 + tid;
+    if (e < m * NBO) {
+      const int64_t i = e / NBO;
+      const int k = int(e - i * NBO);
+      W[e] = A[(J1 + i) * n + J0 + k] * A[(J0 + k) * (n + 1)];
+    }
+    return;
+  }
+  // D_k y_k for the wave products
+  for (int k = tid; k < NBO; k += 256)
+    dy[k] = A[(J0 + k) * (n + 1)] * A[n * n + J0 + k];
+  __syncthreads();
+  const int lane = tid & 63;
+  const int64_t j = J1 + (int64_t(blockIdx.x) - nbw) * 4 + (tid >> 6);
+  if (j >= n) return;
+  const double *Lj = A + j * n + J0;
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < NBO / 64; ++q) v = fma(Lj[q * 64 + lane], dy[q * 64 + lane], v);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) A[n * n + j] -= v;
 }
 
 __device__ inline double readlane_f64(double v, int l) {
@@ -331,30 +399,76 @@ __global__ __launch_bounds__(256) void k_chol_bwd(const double *A, int64_t n,
 
 }  // namespace
 
+size_t chol_workspace_bytes(int64_t n) {
+  const int64_t nrows = n + 1;
+  const int64_t w = n >= kOuterMin ? (n - NBO) * NBO : 0;
+  return size_t(n + 8 + 2 * nrows * NBF + w) * 8;
+}
+
 int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
                    double *delta, int32_t *info, hipStream_t s) {
   void *scr;
   const int64_t nrows = n + 1;
+  const bool outer = n >= kOuterMin;
   // two panel buffers of nrows x NBF (each a multiple of 256 bytes, so
-  // both stay 16-byte aligned), z, floor
-  MNL_TRY(ws_get(c, S_CHOL, size_t(n + 8 + 2 * nrows * NBF) * 8, &scr));
+  // both stay 16-byte aligned), z, floor, then W of the outer panels
+  MNL_TRY(ws_get(c, S_CHOL, chol_workspace_bytes(n), &scr));
   double *pbuf[2] = {static_cast<double *>(scr),
                      static_cast<double *>(scr) + nrows * NBF};
   double *z = pbuf[1] + nrows * NBF;
   double *floor_p = z + n;
+  double *W = floor_p + 8;
+  rocblas_handle hb = nullptr;
+  if (outer) {
+    void *hv;
+    MNL_TRY(blas_get(c, s, &hv));
+    hb = static_cast<rocblas_handle>(hv);
+  }
   hipLaunchKernelGGL(k_floor, dim3(1), dim3(256), 0, s, A, n, g, floor_p,
                      info);
   int step = 0;
   int64_t j0p = -1;
-  for (int64_t j0 = 0; j0 < n; j0 += NBF, ++step) {
-    const int64_t jb = std::min<int64_t>(NBF, n - j0);
-    const int64_t rest = nrows - j0 - jb;   // >= 1: the g row
-    const int64_t T = (rest + TILE - 1) / TILE;
-    const double *prev = j0p >= 0 ? pbuf[(step - 1) & 1] : nullptr;
-    hipLaunchKernelGGL(k_chol_step, dim3((unsigned)(T * (T + 1) / 2)),
-                       dim3(256), 0, s, A, n, nrows, j0, prev, j0p,
-                       pbuf[step & 1], floor_p, info, j0 == 0 ? 1 : 0);
-    j0p = j0;
+  const int64_t wo = outer ? NBO : n;
+  for (int64_t J0 = 0; J0 < n; J0 += wo) {
+    const int64_t J1 = std::min<int64_t>(n, J0 + wo);
+    const bool last_outer = J1 == n;
+    for (int64_t j0 = J0; j0 < J1; j0 += NBF, ++step) {
+      const int64_t jb = std::min<int64_t>(NBF, n - j0);
+      const int64_t rest = nrows - j0 - jb;   // >= 1: the g row
+      const int64_t T = (rest + TILE - 1) / TILE;
+      // inside an outer panel only its own columns are updated
+      const int64_t tc =
+          last_outer ? T
+                     : std::max<int64_t>(1, (J1 - j0 - jb + TILE - 1) / TILE);
+      const int64_t nblk = tc >= T ? T * (T + 1) / 2 : tc * T - tc * (tc - 1) / 2;
+      const double *prev = j0p >= 0 ? pbuf[(step - 1) & 1] : nullptr;
+      hipLaunchKernelGGL(k_chol_step, dim3((unsigned)nblk), dim3(256), 0, s, A,
+                         n, nrows, j0, prev, j0p, pbuf[step & 1], floor_p,
+                         info, j0 == 0 ? 1 : 0, last_outer ? n : J1, tc);
+      j0p = j0;
+    }
+    if (last_outer) break;
+    // close the outer panel: its last step's factor into A, the operands of
+    // the trailing update, then A22 -= L21 D L21^T (the first panel's
+    // trailing block still holds H: beta = -1 forms A = -H on the way)
+    {
+      const int64_t cnt = (nrows - j0p) * NBF;
+      const unsigned gr = (unsigned)std::min<int64_t>(1024, (cnt + 255) / 256);
+      hipLaunchKernelGGL(k_chol_copy, dim3(gr), dim3(256), 0, s, A, n, nrows,
+                         j0p, pbuf[(step - 1) & 1], (double *)nullptr, info);
+      j0p = -1;
+    }
+    const int64_t m = n - J1;
+    const int64_t nbw = (m * NBO + 255) / 256, nbg = (m + 3) / 4;
+    hipLaunchKernelGGL(k_outer_prep, dim3((unsigned)(nbw + nbg)), dim3(256), 0,
+                       s, A, n, J0, W, nbw, info);
+    const double alpha = -1.0, beta = J0 == 0 ? -1.0 : 1.0;
+    const rocblas_status st = rocblas_dsyrkx(
+        hb, rocblas_fill_upper, rocblas_operation_transpose, rocblas_int(m),
+        rocblas_int(NBO), &alpha, A + J1 * n + J0, rocblas_int(n), W,
+        rocblas_int(NBO), &beta, A + J1 * n + J1, rocblas_int(n));
+    if (st != rocblas_status_success)
+      return set_error(c, MNL_ERR_HIP, "rocblas_dsyrkx failed (%d)", int(st));
   }
   {
     const int64_t cnt = std::max<int64_t>((nrows - j0p) * NBF, n);

@@ -1295,17 +1295,9 @@ int bb_gemm_run(Ctx *c, const Plan &pl, const HessArgs &h, void *cbuf,
     c->xx_epoch = c->call_epoch;
     c->xx_buf = xxv;
   }
-  if (!c->blas) {
-    rocblas_handle hb;
-    if (rocblas_create_handle(&hb) != rocblas_status_success)
-      return set_error(c, MNL_ERR_HIP, "rocblas_create_handle failed");
-    // no atomics: every GEMM result is bitwise reproducible
-    (void)rocblas_set_atomics_mode(hb, rocblas_atomics_not_allowed);
-    c->blas = hb;
-  }
-  rocblas_handle hb = static_cast<rocblas_handle>(c->blas);
-  if (rocblas_set_stream(hb, s) != rocblas_status_success)
-    return set_error(c, MNL_ERR_HIP, "rocblas_set_stream failed");
+  void *hv;
+  MNL_TRY(blas_get(c, s, &hv));
+  rocblas_handle hb = static_cast<rocblas_handle>(hv);
   const rocblas_datatype ab =
       h.prec == 2 ? rocblas_datatype_bf16_r
                   : (h.prec == 1 ? rocblas_datatype_f32_r
@@ -1434,11 +1426,5 @@ int hessian_footprint(Ctx *c, const Dims &d, int prec, size_t *part_bytes,
   return MNL_OK;
 }
 
-void blas_release(Ctx *c) {
-  if (c->blas) {
-    (void)rocblas_destroy_handle(static_cast<rocblas_handle>(c->blas));
-    c->blas = nullptr;
-  }
-}
 
 }  // namespace mnl

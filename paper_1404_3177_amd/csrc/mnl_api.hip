@@ -8,6 +8,8 @@
 #include <mutex>
 #include <utility>
 
+#include <rocblas/rocblas.h>
+
 #include "mnl_common.h"
 
 struct mnl_ctx {
@@ -76,6 +78,29 @@ void ctx_release(Ctx *c) {
   }
   c->total_bytes = 0;
   hessian_cache_free(c);
+}
+
+int blas_get(Ctx *c, hipStream_t s, void **handle) {
+  if (!c->blas) {
+    rocblas_handle hb;
+    if (rocblas_create_handle(&hb) != rocblas_status_success)
+      return set_error(c, MNL_ERR_HIP, "rocblas_create_handle failed");
+    // no atomics: every library product is bitwise reproducible
+    (void)rocblas_set_atomics_mode(hb, rocblas_atomics_not_allowed);
+    c->blas = hb;
+  }
+  rocblas_handle hb = static_cast<rocblas_handle>(c->blas);
+  if (rocblas_set_stream(hb, s) != rocblas_status_success)
+    return set_error(c, MNL_ERR_HIP, "rocblas_set_stream failed");
+  *handle = c->blas;
+  return MNL_OK;
+}
+
+void blas_release(Ctx *c) {
+  if (c->blas) {
+    (void)rocblas_destroy_handle(static_cast<rocblas_handle>(c->blas));
+    c->blas = nullptr;
+  }
 }
 
 hipError_t raise_lds_limit(const void *kernel, int bytes) {
@@ -429,7 +454,7 @@ int fit_workspace_footprint(Ctx *c, const Dims &d, int prec, size_t *bytes) {
   if (d.g) t += 2 * al(N * size_t(d.g) * 8);            // S_YBAR pair
   t += al(((np + 1) * np + 64) * 8);                    // S_H
   t += 2 * al(np * 8) + al(256);                        // delta, trial, scalars
-  t += al((np + 8 + 2 * (np + 1) * 32) * 8);            // Cholesky scratch
+  t += al(chol_workspace_bytes(int64_t(np)));           // Cholesky scratch
   // Hessian partials and tables; a mixed fit may redo the Hessian in FP64
   size_t part = 0, tab = 0;
   MNL_TRY(hessian_footprint(c, d, prec, &part, &tab));

@@ -143,7 +143,10 @@ struct HessArgs {
 };
 int hessian_run(Ctx *c, const HessArgs &a, hipStream_t s);
 void hessian_cache_free(Ctx *c);
-// Destroy the context's library GEMM handle.
+// The context's library BLAS handle (rocBLAS, atomics off), bound to
+// stream s; created on first use.
+int blas_get(Ctx *c, hipStream_t s, void **handle);
+// Destroy the context's library BLAS handle.
 void blas_release(Ctx *c);
 // Device bytes hessian_run takes for a shape: split partials (workspace
 // slot S_HPART) and tile tables.
@@ -156,6 +159,8 @@ int hessian_footprint(Ctx *c, const Dims &d, int prec, size_t *part_bytes,
 // info[0] receives 0 or (1 + index of the failed pivot).
 int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
                    double *delta, int32_t *info, hipStream_t s);
+// Scratch bytes chol_solve_run takes (workspace slot S_CHOL).
+size_t chol_workspace_bytes(int64_t n);
 
 // Context ---------------------------------------------------------------------
 struct Ctx {

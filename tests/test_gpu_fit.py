@@ -85,6 +85,27 @@ def test_newton_steps_follow_oracle_trajectory(ctx):
     assert info["stop_reason"] == R.STOP_GTOL and info["iters"] == 0
 
 
+@pytest.mark.parametrize("shape", [(3000, 43, 50, 1, 1, "uniform"),
+                                   (3000, 49, 48, 0, 0, None)])
+def test_newton_step_large_system_matches_oracle(ctx, shape):
+    # n_p >= 2048 (2,144 ragged, 2,304 a whole number of outer panels): the
+    # factorisation runs by outer panels with library trailing updates
+    N, K, p, g, a, wk = shape
+    pr = synth.make_problem(N, K, p, g, a, seed=77 + K, weights=wk)
+    assert pr.n_params >= 2048
+    th0 = np.zeros(pr.n_params)
+    grad = R.gradient(th0, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
+    H = R.hessian(th0, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
+    d_ref = R.newton_direction(H, grad)
+    dp = device_problem(pr)
+    th = theta_tensor(th0)
+    info = ctx.newton_step(dp, th, gtol=GTOL, ftol=0.0)
+    assert info["stop_reason"] == 0, info
+    step_ref = 0.5 ** (info["ls_iters"] - 1) * d_ref
+    step = th.cpu().numpy() - th0
+    assert np.linalg.norm(step - step_ref) <= 1e-9 * np.linalg.norm(step_ref)
+
+
 def test_fit_is_deterministic(ctx):
     import torch
     pr = synth.make_problem(20000, 12, 6, 2, 1, seed=9, weights="uniform")
