@@ -18,10 +18,12 @@
 //
 // Large systems factor by outer panels of NBO columns: the 32-wide steps
 // update only the columns of their outer panel (all rows below), then one
-// library symmetric rank-NBO update (rocBLAS syrkx, atomics off) applies
-// L21 D L21^T to the trailing lower triangle, and a small kernel applies it
-// to the g row.  Each trailing entry is then read and written once per
-// outer panel instead of once per 32-wide step.
+// library GEMM (rocBLAS, atomics off) applies L21 (D L21^T) to the trailing
+// square (the upper triangle it also writes is never read: twice the flops
+// of a symmetric update, yet faster than the library's triangular forms),
+// and a small kernel applies the update to the g row.  Each trailing entry
+// is then read and written once per outer panel instead of once per 32-wide
+// step.
 #include <cmath>
 
 #include <rocblas/rocblas.h>
@@ -449,8 +451,9 @@ int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
     }
     if (last_outer) break;
     // close the outer panel: its last step's factor into A, the operands of
-    // the trailing update, then A22 -= L21 D L21^T (the first panel's
-    // trailing block still holds H: beta = -1 forms A = -H on the way)
+    // the trailing update, then A22 -= L21 D L21^T (column-major view of the
+    // row-major buffer; the first panel's trailing block still holds H:
+    // beta = -1 forms A = -H on the way)
     {
       const int64_t cnt = (nrows - j0p) * NBF;
       const unsigned gr = (unsigned)std::min<int64_t>(1024, (cnt + 255) / 256);
@@ -463,12 +466,13 @@ int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
     hipLaunchKernelGGL(k_outer_prep, dim3((unsigned)(nbw + nbg)), dim3(256), 0,
                        s, A, n, J0, W, nbw, info);
     const double alpha = -1.0, beta = J0 == 0 ? -1.0 : 1.0;
-    const rocblas_status st = rocblas_dsyrkx(
-        hb, rocblas_fill_upper, rocblas_operation_transpose, rocblas_int(m),
-        rocblas_int(NBO), &alpha, A + J1 * n + J0, rocblas_int(n), W,
-        rocblas_int(NBO), &beta, A + J1 * n + J1, rocblas_int(n));
+    const rocblas_status st = rocblas_dgemm(
+        hb, rocblas_operation_transpose, rocblas_operation_none, rocblas_int(m),
+        rocblas_int(m), rocblas_int(NBO), &alpha, A + J1 * n + J0,
+        rocblas_int(n), W, rocblas_int(NBO), &beta, A + J1 * n + J1,
+        rocblas_int(n));
     if (st != rocblas_status_success)
-      return set_error(c, MNL_ERR_HIP, "rocblas_dsyrkx failed (%d)", int(st));
+      return set_error(c, MNL_ERR_HIP, "rocblas_dgemm failed (%d)", int(st));
   }
   {
     const int64_t cnt = std::max<int64_t>((nrows - j0p) * NBF, n);

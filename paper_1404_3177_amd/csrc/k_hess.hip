@@ -503,9 +503,10 @@ __global__ __launch_bounds__(kThreads) void k_hess_alt(
   const int64_t i_end = min(d.N, i_begin + obs_chunk);
   // two LDS buffers, each: Xs [TB][p], Zs [TB][nb][a], Ys [TB][nb][g],
   // Yb [TB][g] (Ybar), Ps [TB][nb] (P), Ws [TB] (weights, 0 past the end)
+  // and one zero slot, the source of every padding operand entry
   const int oZ = kAltTB * p, oY = oZ + kAltTB * nb * a,
             oB = oY + kAltTB * nb * g, oP = oB + kAltTB * g,
-            oW = oP + kAltTB * nb, bsz = oW + kAltTB;
+            oW = oP + kAltTB * nb, o0 = oW + kAltTB, bsz = o0 + 1;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   // stale values are multiplied by a zero weight, so start from zeros
   // (never NaN) and load only whole rows of real observations
@@ -514,19 +515,32 @@ __global__ __launch_bounds__(kThreads) void k_hess_alt(
   auto stage = [&](int b, int64_t i0) {
     double *B = sm + b * bsz;
     const int nobs = (int)min<int64_t>(kAltTB, i_end - i0);
-    for (int j = wv; j < kAltTB; j += kThreads / kWave) {
-      const int64_t ii = i0 + j;
-      if (j < nobs) {
-        wave_copy_lds(X + ii * p, B + j * p, 2 * p, lane);
-        wave_copy_lds(Z + (ii * K + n0) * a, B + oZ + j * nb * a,
-                      2 * nbe * a, lane);
-        wave_copy_lds(Y + (ii * K + n0) * g, B + oY + j * nb * g,
-                      2 * nbe * g, lane);
-        wave_copy_lds(Ybar + ii * g, B + oB + j * g, 2 * g, lane);
-        wave_copy_lds(P + ii * K + n0, B + oP + j * nb, 2 * nbe, lane);
+    // the tile's X rows, Ybar rows and weights are contiguous in memory:
+    // one copy each, its 64-dword pieces spread over the waves
+    auto wg_copy = [&](const double *src, double *dst, int ndw) {
+      const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src);
+      char *d8 = reinterpret_cast<char *>(dst);
+      for (int c = 64 * wv; c < ndw; c += kThreads) {
+        if (c + lane < ndw)
+          __builtin_amdgcn_global_load_lds(s32 + c + lane,
+                                           (lds_void_t *)(d8 + 4 * c), 4, 0, 0);
       }
-      if (lane == 0) B[oW + j] = j < nobs ? (w ? w[ii] : 1.0) : 0.0;
+    };
+    wg_copy(X + i0 * p, B, 2 * nobs * p);
+    wg_copy(Ybar + i0 * g, B + oB, 2 * nobs * g);
+    if (w) wg_copy(w + i0, B + oW, 2 * nobs);
+    // per observation, the slices of the workgroup's alternatives
+    for (int j = wv; j < nobs; j += kThreads / kWave) {
+      const int64_t ii = i0 + j;
+      wave_copy_lds(Z + (ii * K + n0) * a, B + oZ + j * nb * a, 2 * nbe * a,
+                    lane);
+      wave_copy_lds(Y + (ii * K + n0) * g, B + oY + j * nb * g, 2 * nbe * g,
+                    lane);
+      wave_copy_lds(P + ii * K + n0, B + oP + j * nb, 2 * nbe, lane);
     }
+    // unit weights without w, zero weights past the last observation
+    if (wv == 0 && lane < kAltTB && (!w || lane >= nobs))
+      B[oW + lane] = lane < nobs ? 1.0 : 0.0;
   };
   d4 acc[NQ][NRT];
 #pragma unroll
@@ -537,40 +551,74 @@ __global__ __launch_bounds__(kThreads) void k_hess_alt(
   const int ntile = (int)((i_end - i_begin + kAltTB - 1) / kAltTB);
   if (ntile > 0) stage(0, i_begin);
   __syncthreads();
-  const int rl = lane & 15;
+  // Operand roles of this lane, fixed for the kernel, as LDS offsets
+  // base + ob * (observation stride) + q * (alternative stride) so that the
+  // loop has no branch: entries that are padding read the zero slot.
+  // B column r = rl: z_qr or y_q,r-a, minus ybar_r-a for the latter.
+  const int rl = lane & 15, obq = lane >> 4;
+  const int wvu = __builtin_amdgcn_readfirstlane(wv);
+  int bB = o0, bSo = 0, bSq = 0, bY = o0, bYo = 0;
+  if (rl < a) {
+    bB = oZ + rl; bSo = nb * a; bSq = a;
+  } else if (rl < nr) {
+    bB = oY + rl - a; bSo = nb * g; bSq = g; bY = oB + rl - a; bYo = g;
+  }
+  // A rows l = 16 rt + rl: x_l (l < p) in every tile, z / y - ybar only in
+  // the rows p .. nl-1, which (NRT = ceil(nl / 16), nr <= 16) lie in the
+  // last two tiles: slot 0 is tile NRT-2, slot 1 tile NRT-1
+  int aB[2], aSo[2], aSq[2], aY[2], aYo[2];
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2) {
+    const int l = 16 * (NRT - 2 + s2) + rl;
+    aB[s2] = o0; aSo[s2] = 0; aSq[s2] = 0; aY[s2] = o0; aYo[s2] = 0;
+    if (l >= p && l < p + a) {
+      aB[s2] = oZ + l - p; aSo[s2] = nb * a; aSq[s2] = a;
+    } else if (l >= p + a && l < nl) {
+      aB[s2] = oY + l - p - a; aSo[s2] = nb * g; aSq[s2] = g;
+      aY[s2] = oB + l - p - a; aYo[s2] = g;
+    }
+  }
+  // slot 0 holds such rows only when they reach into tile NRT-2
+  const bool two = NRT >= 2 && p < 16 * (NRT - 1);
   for (int t = 0; t < ntile; ++t) {
     const int cur = t & 1;
     // the next tile streams into the other buffer while this one is used
     if (t + 1 < ntile) stage(cur ^ 1, i_begin + int64_t(t + 1) * kAltTB);
     const double *B = sm + cur * bsz;
-    const double *Xs = B, *Zs = B + oZ, *Ys = B + oY, *Yb = B + oB,
-                 *Ps = B + oP, *Ws = B + oW;
+    const double *Ps = B + oP, *Ws = B + oW;
 #pragma unroll 1
     for (int ks = 0; ks < kAltTB / 4; ++ks) {
-      const int ob = 4 * ks + (lane >> 4);
+      const int ob = 4 * ks + obq;
       const double wo = Ws[ob];
+      // observation-only parts, shared by the workgroup's alternatives
+      double xv[NRT];
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt) {
+        const int l = 16 * rt + rl;
+        xv[rt] = B[l < p ? ob * p + l : o0];
+      }
+      const double ybB = B[bY + ob * bYo];
+      const double ybA0 = two ? B[aY[0] + ob * aYo[0]] : 0.0;
+      const double ybA1 = B[aY[1] + ob * aYo[1]];
+      // every wave runs all NQ alternative slots: past the workgroup's last
+      // alternative the staged P is zero, so those products add nothing
+      // (and are not written out)
 #pragma unroll
       for (int jq = 0; jq < NQ; ++jq) {
-        const int q = wv + 4 * jq;
-        if (q < nbe) {
-          const double u = wo * Ps[ob * nb + q];
-          const double *zq = Zs + (ob * nb + q) * a;
-          const double *yq = Ys + (ob * nb + q) * g;
-          const double *ybq = Yb + ob * g;
-          // R operand: column r = rl
-          double bv = 0.0;
-          if (rl < a) bv = zq[rl];
-          else if (rl < nr) bv = yq[rl - a] - ybq[rl - a];
+        const int q = wvu + 4 * jq;   // wave-uniform
+        // the weight scales the R operand, so the x rows of L (the same for
+        // every alternative) feed the MFMAs unscaled
+        const double u = wo * Ps[ob * nb + q];
+        const double bv = (B[bB + ob * bSo + q * bSq] - ybB) * u;
+        const double z0 =
+            two ? B[aB[0] + ob * aSo[0] + q * aSq[0]] - ybA0 : 0.0;
+        const double z1 = B[aB[1] + ob * aSo[1] + q * aSq[1]] - ybA1;
 #pragma unroll
-          for (int rt = 0; rt < NRT; ++rt) {
-            const int l = 16 * rt + rl;
-            double lv = 0.0;
-            if (l < p) lv = Xs[ob * p + l];
-            else if (l < p + a) lv = zq[l - p];
-            else if (l < nl) lv = yq[l - p - a] - ybq[l - p - a];
-            acc[jq][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                u * lv, bv, acc[jq][rt], 0, 0, 0);
-          }
+        for (int rt = 0; rt < NRT; ++rt) {
+          const double lv =
+              rt == NRT - 1 ? xv[rt] + z1 : (rt == NRT - 2 ? xv[rt] + z0 : xv[rt]);
+          acc[jq][rt] =
+              __builtin_amdgcn_mfma_f64_16x16x4f64(lv, bv, acc[jq][rt], 0, 0, 0);
         }
       }
     }
@@ -1063,23 +1111,26 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
     int nrt = (nl + 15) / 16;
     if (nrt > 8)
       return set_error(c, MNL_ERR_UNSUPPORTED, "more than 128 features");
-    if (nrt == 5) nrt = 6;
-    if (nrt == 7) nrt = 8;
     const int nq = nrt == 1 ? 8 : (nrt == 2 ? 4 : (nrt <= 4 ? 2 : 1));
     const int nb = 4 * nq;
     pl->alt_nrt = nrt;
     pl->alt_nb = nb;
     const int ngrp = (K + nb - 1) / nb;
     pl->alt_ngrp = ngrp;
-    int Sa = std::max(1, 1024 / ngrp);
+    // one round of resident workgroups (at most 3 per CU: register and
+    // LDS limits), split evenly over the alternative groups
+    pl->alt_lds = 2 * (size_t(kAltTB) *
+                           (p + size_t(nb) * a + size_t(nb) * g + g + nb + 1) +
+                       1) * 8;
+    const int wpc = int(std::max<size_t>(
+        1, std::min<size_t>(3, (160 * 1024) / pl->alt_lds)));
+    int Sa = std::max(1, wpc * device_cus(c) / ngrp);
     Sa = int(std::min<int64_t>(Sa, std::max<int64_t>(1, d.N / 64)));
     int64_t ch = (d.N + Sa - 1) / Sa;
     ch = (ch + kAltTB - 1) / kAltTB * kAltTB;
     Sa = int((d.N + ch - 1) / ch);
     pl->alt_S = Sa;
     pl->alt_chunk = ch;
-    pl->alt_lds = 2 * size_t(kAltTB) *
-                  (p + size_t(nb) * a + size_t(nb) * g + g + nb + 1) * 8;
     if (pl->alt_lds > 150 * 1024)
       return set_error(c, MNL_ERR_UNSUPPORTED, "per-alternative tile too big");
   }
@@ -1233,7 +1284,9 @@ hipError_t launch_alt(const Plan &pl, const HessArgs &h, double *part,
     case 2: return launch_alt_nrt<2>(pl, h, part, s);
     case 3: return launch_alt_nrt<3>(pl, h, part, s);
     case 4: return launch_alt_nrt<4>(pl, h, part, s);
+    case 5: return launch_alt_nrt<5>(pl, h, part, s);
     case 6: return launch_alt_nrt<6>(pl, h, part, s);
+    case 7: return launch_alt_nrt<7>(pl, h, part, s);
     default: return launch_alt_nrt<8>(pl, h, part, s);
   }
 }
