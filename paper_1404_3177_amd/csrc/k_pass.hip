@@ -75,15 +75,22 @@ __device__ inline double wave_max(double v) {
 }
 
 struct Lay {  // LDS layout, offsets in doubles
-  int Kp, p16;
-  int xs, us, ws, gz, gam, alf, red, ch;
+  int Kp, p16, cap;
+  int xs, us, ws, gz, gam, alf, red, ch, ysc, lg;
   int total;
 };
+
+// register slots for the z and y values of one alternative
+__host__ __device__ inline int pass_cap(const Dims &d) {
+  const int mx = d.a > d.g ? d.a : d.g;
+  return mx <= 4 ? 4 : (mx <= 8 ? 8 : 16);
+}
 
 __host__ __device__ inline Lay make_lay(const Dims &d) {
   Lay L;
   L.Kp = (d.K + 15) & ~15;
   L.p16 = (d.p + 15) & ~15;
+  L.cap = pass_cap(d);
   int o = 0;
   L.xs = o;  o += L.p16 * kXS;                // X^T tile [p16][kXS]
   L.us = o;  o += kTB * L.Kp;                 // U, then e, then R [kTB][Kp]
@@ -93,22 +100,27 @@ __host__ __device__ inline Lay make_lay(const Dims &d) {
   L.alf = o; o += d.g;                        // alpha
   L.red = o; o += kWaves * (1 + d.g);         // loglik, alpha grad per wave
   L.ch = o;  o += kTB / 2;                    // choices, two per double
+  L.ysc = o; o += d.g > 0 ? kWaves * L.cap * kWave : 0;  // Ybar transpose
+  L.lg = o;  o += 2 * kTB;                    // max and sum per observation
   L.total = o;
   return L;
 }
 
 // NTW: beta-gradient MFMA tiles per wave; CAP: register slots for the z
-// and y values of one alternative (>= a and >= g)
-template <int NTW, int CAP>
+// and y values of one alternative (>= a and >= g); ZR: a > 0 (without Z
+// no register is spent on z, gamma or the gamma gradient)
+template <int NTW, int CAP, bool ZR>
 __global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
                                                    int64_t stride) {
+  constexpr int CZ = ZR ? CAP : 1;
   extern __shared__ double sm[];
   const Dims d = A.d;
   const Lay L = make_lay(d);
   const int K = d.K, p = d.p, g = d.g, a = d.a, Kp = L.Kp, p16 = L.p16;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   double *xs = sm + L.xs, *us = sm + L.us, *ws = sm + L.ws, *gz = sm + L.gz,
-         *gam = sm + L.gam, *alf = sm + L.alf, *red = sm + L.red;
+         *gam = sm + L.gam, *alf = sm + L.alf, *red = sm + L.red,
+         *lgm = sm + L.lg, *lgs = sm + L.lg + kTB;
   int32_t *chs = reinterpret_cast<int32_t *>(sm + L.ch);
   const double *th = A.theta;
   const int64_t offg = d.off_gamma(), offa = d.off_alpha();
@@ -127,6 +139,14 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
                       // on lane 0 the log-normalisers
   const int p4 = (p + 3) / 4;
   __syncthreads();
+  // lane k < 64 keeps gamma_k and its gamma-gradient sums in registers
+  // (alternatives past 64 use the per-wave LDS sums)
+  double gamr[CZ], gzr[CZ];
+#pragma unroll
+  for (int c = 0; c < CZ; ++c) {
+    gamr[c] = (ZR && c < a && lane < K) ? gam[lane * a + c] : 0.0;
+    gzr[c] = 0.0;
+  }
 
   const int64_t ntiles = (d.N + kTB - 1) / kTB;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -178,23 +198,25 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
       const double *yr = A.Y + gi * K * g;
       const double *zr = A.Z + gi * Ka;
       double *ui = us + i * Kp;
-      double zv[CAP], yv[CAP];
+      double zv[CZ], yv[CAP];
       const bool own = lane < K;
 #pragma unroll
-      for (int c = 0; c < CAP; ++c) {
-        zv[c] = (c < a && own) ? zr[lane * a + c] : 0.0;
+      for (int c = 0; c < CZ; ++c)
+        zv[c] = (ZR && c < a && own) ? zr[lane * a + c] : 0.0;
+#pragma unroll
+      for (int c = 0; c < CAP; ++c)
         yv[c] = (c < g && own) ? yr[lane * g + c] : 0.0;
-      }
       double m = -INFINITY;
       {
         double u = -INFINITY;
         if (own) {
           u = ui[lane];
 #pragma unroll
-          for (int c = 0; c < CAP; ++c) {
-            if (c < a) u = fma(zv[c], gam[lane * a + c], u);
+          for (int c = 0; c < CZ; ++c)
+            if (ZR && c < a) u = fma(zv[c], gamr[c], u);
+#pragma unroll
+          for (int c = 0; c < CAP; ++c)
             if (c < g) u = fma(yv[c], alf[c], u);
-          }
           ui[lane] = u;
         }
         m = u;
@@ -222,7 +244,12 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
         }
       }
       s = wave_sum(s);
-      if (lane == 0) lsum -= wi * (m + log(s));
+      // the log-normaliser is taken after the tile's observations, one
+      // observation per lane
+      if (lane == 0) {
+        lgm[i] = m;
+        lgs[i] = s;
+      }
       const double inv = 1.0 / s;
       if (g > 0) {
         // Ybar_c = sum_k P_k y_kc, all c reduced together
@@ -239,19 +266,31 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
               if (c < g) part[c] = fma(P, yr[k * g + c], part[c]);
           }
         }
+        // all g sums at once: the 64 x CAP partial values go through this
+        // wave's LDS block transposed, lane (c, j) adds CAP of them in order
+        // and each group of 64 / CAP lanes combines its results by DPP
+        // (every lane of a group ends with the same bits)
+        double *scr = sm + L.ysc + wv * (CAP * kWave);
 #pragma unroll
-        for (int c = 0; c < CAP; ++c) {
-          if (c < g) {
-            const double yb = wave_sum(part[c]);
-            // y at the choice, from its lane or from memory
-            const double ych = ci < kWave ? readlane_f64(yv[c], ci)
-                                          : yr[ci * g + c];
-            if (lane == 0) {
-              if (A.Ybar) A.Ybar[gi * g + c] = yb;
-              // alpha gradient: w_i (y_{i,c_i} - ybar_i)   (Eq. 9, centred)
-              red[wv * (1 + g) + 1 + c] += wi * (ych - yb);
-            }
-          }
+        for (int c = 0; c < CAP; ++c)
+          if (c < g) scr[c * kWave + lane] = part[c];
+        __builtin_amdgcn_wave_barrier();
+        constexpr int LPC = kWave / CAP;
+        const int cl = lane / LPC, jl = lane % LPC;
+        double yb = 0.0;
+        if (cl < g) {
+#pragma unroll
+          for (int q = 0; q < CAP; ++q) yb += scr[cl * kWave + jl * CAP + q];
+        }
+        yb += dpp_f64<0xB1>(yb);
+        if constexpr (LPC >= 4) yb += dpp_f64<0x4E>(yb);
+        if constexpr (LPC >= 8) yb += dpp_f64<0x141>(yb);
+        if constexpr (LPC >= 16) yb += dpp_f64<0x140>(yb);
+        __builtin_amdgcn_wave_barrier();
+        if (jl == 0 && cl < g) {
+          if (A.Ybar) A.Ybar[gi * g + cl] = yb;
+          // alpha gradient: w_i (y_{i,c_i} - ybar_i)   (Eq. 9, centred)
+          red[wv * (1 + g) + 1 + cl] += wi * (yr[ci * g + cl] - yb);
         }
       }
       const int64_t row = gi * K;
@@ -263,16 +302,23 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
           if (A.P32) A.P32[row + k] = (float)P;
           const double R = wi * ((k == ci ? 1.0 : 0.0) - P);
           ui[k] = R;
-          double *gzk = gz + wv * Ka + k * a;
           if (k0 == 0) {
 #pragma unroll
-            for (int c = 0; c < CAP; ++c)
-              if (c < a) gzk[c] = fma(R, zv[c], gzk[c]);
+            for (int c = 0; c < CZ; ++c)
+              if (ZR && c < a) gzr[c] = fma(R, zv[c], gzr[c]);
           } else {
+            double *gzk = gz + wv * Ka + k * a;
             for (int c = 0; c < a; ++c) gzk[c] = fma(R, zr[k * a + c], gzk[c]);
           }
         }
       }
+    }
+    // log-normalisers of this wave's observations of the tile, lane q
+    // taking observation wv + 4 q
+    {
+      const int iq = wv + kWaves * lane;
+      if (lane < kTB / kWaves && iq < nobs)
+        lsum -= ws[iq] * (lgm[iq] + log(lgs[iq]));
     }
     __syncthreads();
 
@@ -294,6 +340,13 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
   }
 
   // ---- this workgroup's partial row --------------------------------------------
+  // the register gamma-gradient sums join the per-wave LDS sums
+  if (ZR && lane < K) {
+#pragma unroll
+    for (int c = 0; c < CZ; ++c)
+      if (c < a) gz[wv * Ka + lane * a + c] = gzr[c];
+  }
+  __syncthreads();
   double *out = A.partial + int64_t(blockIdx.x) * stride;
   lsum = wave_sum(lsum);
   if (lane == 0) red[wv * (1 + g)] = lsum;
@@ -367,7 +420,7 @@ int pass_plan(const Dims &d, PassPlan *plan) {
   if (ntw > 32) return MNL_ERR_UNSUPPORTED;
   const int mx = d.a > d.g ? d.a : d.g;
   if (mx > 16) return MNL_ERR_UNSUPPORTED;
-  plan->cap = mx <= 4 ? 4 : (mx <= 8 ? 8 : 16);
+  plan->cap = L.cap;
   if (size_t(L.total) * 8 > 160 * 1024) return MNL_ERR_UNSUPPORTED;
   plan->ntw = ntw;
   plan->tb = kTB;
@@ -382,12 +435,18 @@ hipError_t launch_pass(const PassPlan &plan, const PassArgs &a,
                        hipStream_t s) {
   dim3 grid(plan.grid), block(kThreads);
   const size_t lds = plan.lds_bytes;
-#define MNL_PASS_LAUNCH(J, C)                                                 \
+#define MNL_PASS_LAUNCH2(J, C, Z)                                             \
   do {                                                                        \
     hipError_t e_ = raise_lds_limit(                                          \
-        reinterpret_cast<const void *>(&k_pass<J, C>), (int)lds);             \
+        reinterpret_cast<const void *>(&k_pass<J, C, Z>), (int)lds);          \
     if (e_ != hipSuccess) return e_;                                          \
-    hipLaunchKernelGGL((k_pass<J, C>), grid, block, lds, s, a, plan.stride);  \
+    hipLaunchKernelGGL((k_pass<J, C, Z>), grid, block, lds, s, a,             \
+                       plan.stride);                                          \
+  } while (0)
+#define MNL_PASS_LAUNCH(J, C)                                                 \
+  do {                                                                        \
+    if (a.d.a > 0) MNL_PASS_LAUNCH2(J, C, true);                              \
+    else MNL_PASS_LAUNCH2(J, C, false);                                       \
   } while (0)
 #define MNL_PASS_CAP(J)                                                       \
   do {                                                                        \
@@ -405,6 +464,7 @@ hipError_t launch_pass(const PassPlan &plan, const PassArgs &a,
   }
 #undef MNL_PASS_CAP
 #undef MNL_PASS_LAUNCH
+#undef MNL_PASS_LAUNCH2
   return hipGetLastError();
 }
 
