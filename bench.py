@@ -352,7 +352,7 @@ def main():
 
     variants = {}
     if not args.no_variants and args.prec == "fp64":
-        for vp in ("fp32",):
+        for vp in ("fp32", "bf16"):
             log(f"variant: {vp} Hessian")
             th_v, inf_v, lat_v, tot_v = time_fits(ctx, dp, max(3, args.steps // 2),
                                                   1, vp)
