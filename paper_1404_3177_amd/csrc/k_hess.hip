@@ -645,38 +645,95 @@ __global__ __launch_bounds__(kThreads) void k_hess_alt(
 // Materialised beta-beta operands.  Omega rows follow the plan's pair rows
 // (0 entries are padding): om[j][r] = w_i P_in (delta_nm - P_im) for the
 // observations i = i0 + j of one chunk, in the precision the tile kernels
-// use for it (FP64 from P, else FP32 from P32), stored in the operand type.
+// use for it (FP64 from P, else FP32 from P32), stored in the operand type
+// with row stride ld (a multiple of 8).  A workgroup stages the P rows and
+// weights of `ob` observations in LDS; each thread owns 8 consecutive pair
+// rows and writes them as one vector per observation.
 template <typename OT, typename CT>
-__global__ void k_form_omega(int K, const double *P, const float *P32,
-                             const double *w, const int32_t *pair_nm,
-                             int64_t nrow, int64_t i0, int nc, OT *om) {
-  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= nrow) return;
-  const int32_t pm = pair_nm[r];
-  const int n = pm & 0xffff, m = pm >> 16;
-  const CT dl = n == m ? CT(1) : CT(0);
-  for (int j = blockIdx.y; j < nc; j += gridDim.y) {
-    const int64_t i = i0 + j;
-    CT v = CT(0);
-    if (pm != 0) {
-      const CT pn = P32 ? CT(P32[i * K + n]) : CT(P[i * K + n]);
-      const CT pmv = P32 ? CT(P32[i * K + m]) : CT(P[i * K + m]);
-      const CT wi = w ? CT(w[i]) : CT(1);
-      v = wi * pn * (dl - pmv);
+__global__ __launch_bounds__(256) void k_form_omega(
+    int K, const double *P, const float *P32, const double *w,
+    const int32_t *pair_nm, int64_t nrow, int64_t ld, int64_t i0, int nc,
+    int ob, OT *om) {
+  typedef OT ov8 __attribute__((ext_vector_type(8)));
+  extern __shared__ double smo[];
+  CT *Ps = reinterpret_cast<CT *>(smo);   // [ob][K]
+  CT *Ws = Ps + ob * K;                    // [ob]
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t(blockIdx.x) * 256 + tid) * 8;
+  const bool mine = r0 < ld;
+  int nn[8], mm[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int32_t pm = (mine && r0 + q < nrow) ? pair_nm[r0 + q] : 0;
+    nn[q] = pm & 0xffff;
+    mm[q] = pm >> 16;   // 0 with nn: a padding row
+  }
+  const int nblk = (nc + ob - 1) / ob;
+  for (int bj = blockIdx.y; bj < nblk; bj += gridDim.y) {
+    const int j0 = bj * ob;
+    const int nj = min(ob, nc - j0);
+    const int64_t ib = i0 + j0;
+    __syncthreads();   // the previous block's rows are no longer read
+    for (int e = tid; e < nj * K; e += 256)
+      Ps[e] = P32 ? CT(P32[ib * K + e]) : CT(P[ib * K + e]);
+    for (int e = tid; e < nj; e += 256) Ws[e] = w ? CT(w[ib + e]) : CT(1);
+    __syncthreads();
+    if (!mine) continue;
+    for (int jj = 0; jj < nj; ++jj) {
+      const CT wj = Ws[jj];
+      const CT *Pj = Ps + jj * K;
+      ov8 v;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const bool ok = nn[q] != 0;   // every valid pair row has n >= 1
+        const CT pn = Pj[nn[q]], pmv = Pj[mm[q]];
+        v[q] = ok ? OT(wj * pn * ((nn[q] == mm[q] ? CT(1) : CT(0)) - pmv))
+                  : OT(0);
+      }
+      *reinterpret_cast<ov8 *>(om + int64_t(j0 + jj) * ld + r0) = v;
     }
-    om[int64_t(j) * nrow + r] = OT(v);
   }
 }
 
-// xx[i][q] = x_ia x_ib for feature pair q = (a, b): iteration-invariant
+// xx[i][q] = x_ia x_ib for feature pair q = (a, b), row stride ld (a
+// multiple of 8): iteration-invariant.  A workgroup stages the X rows of
+// `ob` observations at a time; each thread owns 8 consecutive pairs.
 template <typename OT, typename CT>
-__global__ void k_form_xx(const double *X, int p, const uint32_t *combo,
-                          int64_t ncombo, int64_t N, OT *xx) {
-  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= ncombo) return;
-  const int fa = combo[q] & 0xffff, fb = combo[q] >> 16;
-  for (int64_t i = blockIdx.y; i < N; i += gridDim.y)
-    xx[i * ncombo + q] = OT(CT(X[i * p + fa] * X[i * p + fb]));
+__global__ __launch_bounds__(256) void k_form_xx(const double *X, int p,
+                                                 const uint32_t *combo,
+                                                 int64_t ncombo, int64_t ld,
+                                                 int64_t N, int ob, OT *xx) {
+  typedef OT ov8 __attribute__((ext_vector_type(8)));
+  extern __shared__ double smx[];   // [ob][p]
+  const int tid = threadIdx.x;
+  const int64_t q0 = (int64_t(blockIdx.x) * 256 + tid) * 8;
+  const bool mine = q0 < ld;
+  int fa[8], fb[8];
+  bool ok[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    ok[q] = mine && q0 + q < ncombo;
+    const uint32_t cq = ok[q] ? combo[q0 + q] : 0u;
+    fa[q] = int(cq & 0xffff);
+    fb[q] = int(cq >> 16);
+  }
+  const int64_t nblk = (N + ob - 1) / ob;
+  for (int64_t bj = blockIdx.y; bj < nblk; bj += gridDim.y) {
+    const int64_t ib = bj * ob;
+    const int nj = int(min<int64_t>(ob, N - ib));
+    __syncthreads();
+    for (int e = tid; e < nj * p; e += 256) smx[e] = X[ib * p + e];
+    __syncthreads();
+    if (!mine) continue;
+    for (int jj = 0; jj < nj; ++jj) {
+      const double *xr = smx + jj * p;
+      ov8 v;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        v[q] = ok[q] ? OT(CT(xr[fa[q]] * xr[fb[q]])) : OT(0);
+      *reinterpret_cast<ov8 *>(xx + (ib + jj) * ld + q0) = v;
+    }
+  }
 }
 
 // sum the observation splits of the per-alternative sums in a fixed order
@@ -1225,6 +1282,10 @@ int build_plan(Ctx *c, const Dims &d, int prec, Plan **out) {
 struct PartLayout {
   size_t o_xg, o_alt, o_red, total, n_alt;
 };
+// leading dimension of a materialised GEMM operand: a multiple of 8
+// elements, so that 8-element vector stores stay aligned
+int64_t gemm_ld(int64_t n) { return (n + 7) / 8 * 8; }
+
 PartLayout part_layout(const Plan &pl) {
   const Dims &d = pl.d;
   const size_t asz = pl.prec == 0 ? 8 : 4;
@@ -1232,7 +1293,7 @@ PartLayout part_layout(const Plan &pl) {
   // GEMM mode: the product [nrow][ncombo] then one Omega chunk
   const size_t bytes_bb =
       pl.bb_gemm ? ((size_t(pl.nrow_bb) * pl.ncombo * asz + 255) & ~size_t(255)) +
-                       size_t(pl.gemm_nc) * pl.nrow_bb * osz
+                       size_t(pl.gemm_nc) * gemm_ld(pl.nrow_bb) * osz
                  : size_t(pl.S) * pl.bb_M * pl.bb_N * asz;
   const size_t bytes_xg = size_t(pl.S) * pl.xg_M * pl.xg_N * asz;
   const int nl = d.p + d.a + d.g, nr = d.a + d.g;
@@ -1330,16 +1391,19 @@ int bb_gemm_run(Ctx *c, const Plan &pl, const HessArgs &h, void *cbuf,
                 void *omega, hipStream_t s) {
   const Dims &d = pl.d;
   const int64_t nrow = pl.nrow_bb, ncombo = pl.ncombo;
+  const int64_t ldx = gemm_ld(ncombo), ldo = gemm_ld(nrow);
   void *xxv;
-  MNL_TRY(ws_get(c, S_XX, size_t(d.N) * ncombo * sizeof(OT), &xxv));
+  MNL_TRY(ws_get(c, S_XX, size_t(d.N) * ldx * sizeof(OT), &xxv));
   OT *xx = static_cast<OT *>(xxv);
   if (!(c->xx_X == h.X && c->xx_N == d.N && c->xx_p == d.p &&
         c->xx_prec == h.prec && c->xx_epoch == c->call_epoch &&
         c->xx_buf == xxv)) {
-    dim3 grid((unsigned)((ncombo + 255) / 256),
-              (unsigned)std::min<int64_t>(d.N, 4096));
-    hipLaunchKernelGGL((k_form_xx<OT, CT>), grid, dim3(256), 0, s, h.X, d.p,
-                       pl.bb_combo, ncombo, d.N, xx);
+    const int obx = 32;
+    dim3 grid((unsigned)((ldx / 8 + 255) / 256),
+              (unsigned)std::min<int64_t>((d.N + obx - 1) / obx, 8192));
+    hipLaunchKernelGGL((k_form_xx<OT, CT>), grid, dim3(256),
+                       size_t(obx) * d.p * 8, s, h.X, d.p, pl.bb_combo,
+                       ncombo, ldx, d.N, obx, xx);
     MNL_HIP(c, hipGetLastError());
     c->xx_X = h.X;
     c->xx_N = d.N;
@@ -1359,18 +1423,23 @@ int bb_gemm_run(Ctx *c, const Plan &pl, const HessArgs &h, void *cbuf,
       h.prec == 0 ? rocblas_datatype_f64_r : rocblas_datatype_f32_r;
   const CT one = CT(1), zero = CT(0);
   OT *om = static_cast<OT *>(omega);
+  // observations per Omega workgroup: their P rows in at most 64 KB of LDS
+  const int obo = int(std::max<int64_t>(
+      1, std::min<int64_t>(32, (64 * 1024) / (int64_t(d.K) * sizeof(CT) + 8))));
+  const size_t lds_o = size_t(obo) * (d.K + 1) * sizeof(CT);
   for (int64_t i0 = 0; i0 < d.N; i0 += pl.gemm_nc) {
     const int nc = int(std::min<int64_t>(pl.gemm_nc, d.N - i0));
-    dim3 grid((unsigned)((nrow + 255) / 256), (unsigned)std::min(nc, 1024));
-    hipLaunchKernelGGL((k_form_omega<OT, CT>), grid, dim3(256), 0, s, d.K,
+    dim3 grid((unsigned)((ldo / 8 + 255) / 256),
+              (unsigned)std::min<int64_t>((nc + obo - 1) / obo, 8192));
+    hipLaunchKernelGGL((k_form_omega<OT, CT>), grid, dim3(256), lds_o, s, d.K,
                        h.prec == 0 ? h.P : nullptr,
                        h.prec == 0 ? nullptr : h.P32, h.w, pl.pair_nm, nrow,
-                       i0, nc, om);
+                       ldo, i0, nc, obo, om);
     MNL_HIP(c, hipGetLastError());
     const rocblas_status st = rocblas_gemm_ex(
         hb, rocblas_operation_none, rocblas_operation_transpose,
         rocblas_int(ncombo), rocblas_int(nrow), rocblas_int(nc), &one,
-        xx + i0 * ncombo, ab, rocblas_int(ncombo), om, ab, rocblas_int(nrow),
+        xx + i0 * ldx, ab, rocblas_int(ldx), om, ab, rocblas_int(ldo),
         i0 == 0 ? &zero : &one, cbuf, ct, rocblas_int(ncombo), cbuf, ct,
         rocblas_int(ncombo), ct, rocblas_gemm_algo_standard, 0, 0);
     if (st != rocblas_status_success)
@@ -1475,7 +1544,8 @@ int hessian_footprint(Ctx *c, const Dims &d, int prec, size_t *part_bytes,
   *part_bytes = part_layout(pl).total;
   *table_bytes = pl.dev_bytes;
   if (pl.bb_gemm)  // X o X of the materialised product (workspace slot S_XX)
-    *table_bytes += size_t(d.N) * pl.ncombo * (prec == 2 ? 2 : (prec == 1 ? 4 : 8));
+    *table_bytes += size_t(d.N) * gemm_ld(pl.ncombo) *
+                    (prec == 2 ? 2 : (prec == 1 ? 4 : 8));
   return MNL_OK;
 }
 
