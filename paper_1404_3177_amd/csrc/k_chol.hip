@@ -348,55 +348,53 @@ __device__ inline double readlane_f64(double v, int l) {
 }
 
 // backward substitution L^T delta = y, panel j0 (jb <= NBS rows): every
-// workgroup solves the panel's unit-triangular system in one wave (delta_c
-// broadcast by readlane), then subtracts L[panel][c]^T delta_panel from its
-// 64-column chunk of z (four row groups, summed in a fixed order)
+// workgroup solves the panel's unit-triangular system in one wave (lane t
+// holds column t of the panel's L in registers, delta_c is broadcast by
+// readlane), then subtracts L[panel][c]^T delta_panel from its 64-column
+// chunk of z (four row groups, summed in a fixed order).  Every load is
+// issued at the start, so the chain and the update wait on one round trip.
 __global__ __launch_bounds__(256) void k_chol_bwd(const double *A, int64_t n,
                                                   int64_t j0, double *z,
                                                   double *delta,
                                                   const int32_t *info) {
-  __shared__ double L[NBS][NBS + 1];
   __shared__ double dp[NBS];
   __shared__ double part[4][64];
   if (info[0]) return;
   const int jb = (int)min<int64_t>(NBS, n - j0);
-  const int tid = threadIdx.x;
-  for (int e = tid; e < jb * jb; e += 256) {
-    const int i = e / jb, j = e - (e / jb) * jb;
-    L[i][j] = (j < i) ? A[(j0 + i) * n + j0 + j] : 0.0;
+  const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+  // this thread's share of the update: column c, rows grp, grp + 4, ...
+  const int64_t c = int64_t(blockIdx.x) * 64 + lane;
+  double av[NBS / 4];
+#pragma unroll
+  for (int u = 0; u < NBS / 4; ++u) {
+    const int r = grp + 4 * u;
+    av[u] = (c < j0 && r < jb) ? A[(j0 + r) * n + c] : 0.0;
   }
-  __syncthreads();
-  if (tid < 64) {
+  if (grp == 0) {
+    double lcol[NBS];
+#pragma unroll
+    for (int cc = 0; cc < NBS; ++cc)
+      lcol[cc] = (cc < jb && lane < cc) ? A[(j0 + cc) * n + j0 + lane] : 0.0;
     // rows past jb are identity rows, so the chain always has NBS steps
-    // (unrolled: the L loads do not wait on the chain)
-    double zt = tid < jb ? z[j0 + tid] : 0.0;
+    double zt = lane < jb ? z[j0 + lane] : 0.0;
     double dl = 0.0;
 #pragma unroll
-    for (int c = NBS - 1; c >= 0; --c) {
-      const double lc = (c < jb && tid < c) ? L[c][tid] : 0.0;
-      const double dc = readlane_f64(zt, c);
-      dl = tid == c ? dc : dl;
-      zt = fma(-lc, dc, zt);
+    for (int cc = NBS - 1; cc >= 0; --cc) {
+      const double dc = readlane_f64(zt, cc);
+      dl = lane == cc ? dc : dl;
+      zt = fma(-lcol[cc], dc, zt);
     }
-    dp[tid] = dl;
+    dp[lane] = dl;
   }
   __syncthreads();
   if (blockIdx.x == 0 && tid < jb) delta[j0 + tid] = dp[tid];
-  const int64_t c = int64_t(blockIdx.x) * 64 + (tid & 63);
-  const int grp = tid >> 6;
-  double s = 0.0;
-  if (c < j0) {
-    const double *colp = A + j0 * n + c;
-    double s2[2] = {0.0, 0.0};
-#pragma unroll 8
-    for (int r = grp; r < jb; r += 4)
-      s2[(r >> 2) & 1] = fma(colp[int64_t(r) * n], dp[r], s2[(r >> 2) & 1]);
-    s = s2[0] + s2[1];
-  }
-  part[grp][tid & 63] = s;
+  double s2[2] = {0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < NBS / 4; ++u) s2[u & 1] = fma(av[u], dp[grp + 4 * u], s2[u & 1]);
+  part[grp][lane] = s2[0] + s2[1];
   __syncthreads();
   if (grp == 0 && c < j0)
-    z[c] -= (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
+    z[c] -= (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 }  // namespace
