@@ -1064,7 +1064,7 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
     // a partial tile to write and reduce)
     const int64_t slots = int64_t(device_cus(c)) * std::max(1, 16 * 64 / NT);
     const int64_t max_s =
-        std::max<int64_t>(1, std::min<int64_t>(64, d.N / 1024));
+        std::max<int64_t>(1, std::min<int64_t>(64, d.N / 128));
     double best = -1.0;
     for (int sc = 1; sc <= max_s; ++sc) {
       const int64_t wg = int64_t(sc) * nout;
