@@ -501,6 +501,29 @@ __global__ __launch_bounds__(256) void k_sumsq(const double *x, int64_t n,
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
+// The scalars one Newton-step decision needs, in one buffer for one copy
+// to the host: out[0] the factorisation status (0 without one), out[1]
+// l = lg[0], out[2] |g|^2 over lg[1..n] (summed as k_sumsq does).
+__global__ __launch_bounds__(256) void k_scalars(const double *lg, int64_t n,
+                                                 const int32_t *status,
+                                                 double *out) {
+  __shared__ double red[256];
+  const double *x = lg + 1;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s = fma(x[i], x[i], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = status ? double(status[0]) : 0.0;
+    out[1] = lg[0];
+    out[2] = red[0];
+  }
+}
+
 __global__ void k_validate(Dims d, const double *X, const double *Y,
                            const double *Z, const double *w,
                            const int32_t *choice, int32_t *flags) {
@@ -530,6 +553,12 @@ hipError_t launch_axpy(const double *x, const double *d, double t, double *out,
 hipError_t launch_sumsq(const double *x, int64_t n, double *out,
                         hipStream_t s) {
   hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(256), 0, s, x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scalars(const double *lg, int64_t n, const int32_t *status,
+                          double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_scalars, dim3(1), dim3(256), 0, s, lg, n, status, out);
   return hipGetLastError();
 }
 

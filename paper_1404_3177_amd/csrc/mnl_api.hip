@@ -96,6 +96,16 @@ int blas_get(Ctx *c, hipStream_t s, void **handle) {
   return MNL_OK;
 }
 
+void events_release(Ctx *c) {
+  if (!c->ev_ready) return;
+  (void)hipEventDestroy(c->ev_h0);
+  (void)hipEventDestroy(c->ev_h1);
+  (void)hipEventDestroy(c->ev_p0);
+  (void)hipEventDestroy(c->ev_p1);
+  for (auto &e : c->ev_q) (void)hipEventDestroy(e);
+  c->ev_ready = false;
+}
+
 void blas_release(Ctx *c) {
   if (c->blas) {
     (void)rocblas_destroy_handle(static_cast<rocblas_handle>(c->blas));
@@ -218,14 +228,26 @@ int ensure_events(Ctx *c) {
   MNL_HIP(c, hipEventCreate(&c->ev_h1));
   MNL_HIP(c, hipEventCreate(&c->ev_p0));
   MNL_HIP(c, hipEventCreate(&c->ev_p1));
+  for (auto &e : c->ev_q) MNL_HIP(c, hipEventCreate(&e));
   c->ev_ready = true;
   return MNL_OK;
+}
+
+// milliseconds between two recorded (and completed) events, 0 on error
+double event_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.0;
+  }
+  return double(ms);
 }
 
 struct StepState {
   double *lg;        // [0] l, [1..] g at theta
   double *lg_trial;
   int cur;           // which P/Ybar slots hold theta's values (0 or 1)
+  double g2 = 0.0;   // |g|^2 at theta after an accepted step
 };
 
 // Hessian at the current theta (its P/Ybar in slot set `cur`) into S_H.
@@ -282,7 +304,6 @@ int validate_data(Ctx *c, const Dims &d, const mnl_problem *pr,
 int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
                 const mnl_fit_opts &o, StepState &st, double l_old,
                 mnl_fit_info *info, int *reason, hipStream_t s) {
-  const bool mixed = o.prec != MNL_PREC_FP64;
   void *Hv, *dv, *tv, *sv;
   // n_p + 1 rows: the factorisation carries g as an extra row; 64 doubles
   // of padding let its kernels load whole panel rows unconditionally
@@ -292,22 +313,41 @@ int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
   MNL_TRY(ws_get(c, S_SCAL, 256, &sv));
   double *H = (double *)Hv, *delta = (double *)dv, *th_t = (double *)tv;
   int32_t *cinfo = (int32_t *)sv + 32;
+  double *sc = (double *)sv + 24;   // status, l and |g|^2 of a trial
+  const int nxt = st.cur ^ 1;
+  const bool want32 = o.prec != MNL_PREC_FP64;
+  // one trial of the line search at step t: theta + t delta, its pass and
+  // the decision scalars (with the factorisation status when asked)
+  auto trial_at = [&](double t, const int32_t *status) -> int {
+    MNL_HIP(c, launch_axpy(theta, delta, t, th_t, d.np, s));
+    MNL_TRY(run_pass(c, d, pr, th_t, st.lg_trial, nxt ? S_P_TRIAL : S_P,
+                     nxt ? S_P32_TRIAL : S_P32, nxt ? S_YBAR_TRIAL : S_YBAR,
+                     want32, s));
+    MNL_HIP(c, launch_scalars(st.lg_trial, d.np, status, sc, s));
+    return MNL_OK;
+  };
 
-  // Hessian and Newton direction (Eq. 6): delta = (-H)^{-1} g
-  double t0 = now_ms();
+  // Hessian and Newton direction (Eq. 6): delta = (-H)^{-1} g; the full
+  // step's trial runs behind the factorisation, so one copy to the host
+  // brings the factorisation status and the trial's l and |g|^2
   int prec = o.prec;
   int32_t fail = 0;
+  double sh[3] = {0.0, 0.0, 0.0};
   for (int attempt = 0; attempt < 2; ++attempt) {
+    MNL_HIP(c, hipEventRecord(c->ev_q[0], s));
     MNL_TRY(form_hessian(c, d, pr, st.cur, prec, H, s));
-    MNL_HIP(c, hipStreamSynchronize(s));
-    collect_timing(c, info);
-    double t1 = now_ms();
-    info->t_hessian += t1 - t0;
+    MNL_HIP(c, hipEventRecord(c->ev_q[1], s));
     // the factorisation works on A = -H in place
     MNL_TRY(chol_solve_run(c, H, d.np, st.lg + 1, delta, cinfo, s));
-    MNL_TRY(copy_d2h(c, &fail, cinfo, 4, s));
-    t0 = now_ms();
-    info->t_chol += t0 - t1;
+    MNL_HIP(c, hipEventRecord(c->ev_q[2], s));
+    MNL_TRY(trial_at(1.0, cinfo));
+    MNL_HIP(c, hipEventRecord(c->ev_q[3], s));
+    MNL_TRY(copy_d2h(c, sh, sc, sizeof sh, s));
+    collect_timing(c, info);
+    info->t_hessian += event_ms(c->ev_q[0], c->ev_q[1]);
+    info->t_chol += event_ms(c->ev_q[1], c->ev_q[2]);
+    fail = int32_t(sh[0]);
+    if (fail == 0) info->t_ls += event_ms(c->ev_q[2], c->ev_q[3]);
     if (fail == 0 || prec == MNL_PREC_FP64) break;
     // a rounded Hessian that is not positive definite: redo it in FP64
     prec = MNL_PREC_FP64;
@@ -317,23 +357,21 @@ int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
     *reason = MNL_STOP_NOT_PD;
     return MNL_OK;
   }
-  (void)mixed;
 
-  // halving line search (Sec. 3.1)
+  // halving line search (Sec. 3.1); the full step is already evaluated
   const double tau =
       o.ls_tol_ulps * std::numeric_limits<double>::epsilon() * std::fabs(l_old);
   double t = 1.0;
-  const int nxt = st.cur ^ 1;
-  const bool want32 = o.prec != MNL_PREC_FP64;
-  double tl0 = now_ms();
   for (int trial = 1; trial <= o.ls_max + 1; ++trial) {
-    MNL_HIP(c, launch_axpy(theta, delta, t, th_t, d.np, s));
-    MNL_TRY(run_pass(c, d, pr, th_t, st.lg_trial, nxt ? S_P_TRIAL : S_P,
-                     nxt ? S_P32_TRIAL : S_P32, nxt ? S_YBAR_TRIAL : S_YBAR,
-                     want32, s));
-    double l_new;
-    MNL_TRY(copy_d2h(c, &l_new, st.lg_trial, 8, s));
-    collect_timing(c, info);
+    if (trial > 1) {
+      MNL_HIP(c, hipEventRecord(c->ev_q[2], s));
+      MNL_TRY(trial_at(t, nullptr));
+      MNL_HIP(c, hipEventRecord(c->ev_q[3], s));
+      MNL_TRY(copy_d2h(c, sh, sc, sizeof sh, s));
+      collect_timing(c, info);
+      info->t_ls += event_ms(c->ev_q[2], c->ev_q[3]);
+    }
+    const double l_new = sh[1];
     info->ls_iters += 1;
     if (std::isfinite(l_new) && l_new >= l_old - tau) {
       info->ls_backtracks += trial - 1;
@@ -341,16 +379,15 @@ int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
                                 hipMemcpyDeviceToDevice, s));
       std::swap(st.lg, st.lg_trial);
       st.cur = nxt;
+      st.g2 = sh[2];
       info->loglik_diff = l_new - l_old;
       info->loglik = l_new;
-      info->t_ls += now_ms() - tl0;
       *reason = MNL_STOP_NONE;
       return MNL_OK;
     }
     t *= 0.5;
   }
   info->ls_backtracks += o.ls_max;
-  info->t_ls += now_ms() - tl0;
   *reason = MNL_STOP_LS_FAIL;
   return MNL_OK;
 }
@@ -382,12 +419,12 @@ int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
                    o.prec != MNL_PREC_FP64, s));
   double l = 0.0, gnorm = 0.0;
   {
-    MNL_HIP(c, launch_sumsq(st.lg + 1, d.np, gn2, s));
-    double h[1];
-    MNL_TRY(copy_d2h(c, &l, st.lg, 8, s));
-    MNL_TRY(copy_d2h(c, h, gn2, 8, s));
+    MNL_HIP(c, launch_scalars(st.lg, d.np, nullptr, gn2, s));
+    double h[3];
+    MNL_TRY(copy_d2h(c, h, gn2, sizeof h, s));
     collect_timing(c, info);
-    gnorm = std::sqrt(h[0]);
+    l = h[1];
+    gnorm = std::sqrt(h[2]);
   }
   info->t_loglik_grad = now_ms() - t0;
   info->loglik_diff = std::numeric_limits<double>::quiet_NaN();
@@ -416,10 +453,7 @@ int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
     }
     info->iters += 1;
     l = info->loglik;
-    MNL_HIP(c, launch_sumsq(st.lg + 1, d.np, gn2, s));
-    double h[1];
-    MNL_TRY(copy_d2h(c, h, gn2, 8, s));
-    gnorm = std::sqrt(h[0]);
+    gnorm = std::sqrt(st.g2);   // from the accepted trial's scalars
     if (one_step) {
       info->grad_norm = step_gnorm;
       info->loglik = l;
@@ -534,12 +568,7 @@ void mnl_destroy(mnl_ctx *ctx) {
     if (b.ptr) (void)hipFree(b.ptr);
   hessian_cache_free(&ctx->c);
   blas_release(&ctx->c);
-  if (ctx->c.ev_ready) {
-    (void)hipEventDestroy(ctx->c.ev_h0);
-    (void)hipEventDestroy(ctx->c.ev_h1);
-    (void)hipEventDestroy(ctx->c.ev_p0);
-    (void)hipEventDestroy(ctx->c.ev_p1);
-  }
+  events_release(&ctx->c);
   delete ctx;
 }
 

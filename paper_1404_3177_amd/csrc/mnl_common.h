@@ -122,6 +122,9 @@ hipError_t launch_pass_reduce(const PassPlan &plan, const double *partial,
 hipError_t launch_axpy(const double *x, const double *d, double t, double *out,
                        int64_t n, hipStream_t s);
 // out[0] = sum(x^2) in a fixed order (single workgroup)
+// out[0..2] = status[0] (0 if status is NULL), lg[0], sum of lg[1..n]^2
+hipError_t launch_scalars(const double *lg, int64_t n, const int32_t *status,
+                          double *out, hipStream_t s);
 hipError_t launch_sumsq(const double *x, int64_t n, double *out,
                         hipStream_t s);
 // Flags [0]: choice out of range count, [1]: non-finite data count.
@@ -148,6 +151,8 @@ void hessian_cache_free(Ctx *c);
 int blas_get(Ctx *c, hipStream_t s, void **handle);
 // Destroy the context's library BLAS handle.
 void blas_release(Ctx *c);
+// Destroy the context's timing events.
+void events_release(Ctx *c);
 // Device bytes hessian_run takes for a shape: split partials (workspace
 // slot S_HPART) and tile tables.
 int hessian_footprint(Ctx *c, const Dims &d, int prec, size_t *part_bytes,
@@ -172,6 +177,7 @@ struct Ctx {
   // kernel on the caller's stream (read after the driver's next sync)
   hipEvent_t ev_h0 = nullptr, ev_h1 = nullptr, ev_p0 = nullptr,
              ev_p1 = nullptr;
+  hipEvent_t ev_q[4] = {nullptr, nullptr, nullptr, nullptr};  // phases
   bool ev_ready = false;
   bool hess_pending = false, pass_pending = false;
   // host-side caches of Hessian tile tables (keyed by shape)

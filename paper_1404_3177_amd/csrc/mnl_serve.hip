@@ -288,12 +288,7 @@ void mnl_server_destroy(mnl_server *sv) {
       ctx_release(&sl->ctx);
       blas_release(&sl->ctx);
       (void)hipStreamSynchronize(sl->stream);
-      if (sl->ctx.ev_ready) {
-        (void)hipEventDestroy(sl->ctx.ev_h0);
-        (void)hipEventDestroy(sl->ctx.ev_h1);
-        (void)hipEventDestroy(sl->ctx.ev_p0);
-        (void)hipEventDestroy(sl->ctx.ev_p1);
-      }
+      events_release(&sl->ctx);
       (void)hipStreamDestroy(sl->stream);
     }
     delete sl;
