@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_floor(double *Hm, int64_t n,
   red[threadIdx.x] = bad ? INFINITY : m;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h)
+    if (int(threadIdx.x) < h)
       red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
     __syncthreads();
   }

@@ -495,7 +495,7 @@ __global__ __launch_bounds__(256) void k_sumsq(const double *x, int64_t n,
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    if (int(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = red[0];
@@ -514,7 +514,7 @@ __global__ __launch_bounds__(256) void k_scalars(const double *lg, int64_t n,
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    if (int(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
