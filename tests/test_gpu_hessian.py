@@ -21,6 +21,12 @@ SHAPES = [  # N, K, p, g, a, weights
     (600, 66, 1, 1, 1, None),
     (300, 129, 3, 1, 1, "uniform"),   # many alternatives: blocked pair rows
     (600, 100, 32, 1, 1, "uniform"),  # many pairs: beta-beta by library GEMM
+    # 128-column tiles with one, two and several observation rounds per
+    # tile and ragged last rounds
+    (3001, 9, 21, 1, 3, "uniform"),
+    (4000, 25, 4, 1, 5, None),
+    (20, 9, 21, 1, 3, None),
+    (45, 9, 21, 0, 2, "int"),
 ]
 
 
