@@ -31,6 +31,10 @@ Readings taken where the paper is silent (all also used by the GPU path):
   * the Newton system is solved by Cholesky of -H; a failed factorisation, or
     a pivot d_j <= n_p * eps * max_k(-H_kk), is reported as "Hessian not
     negative definite".
+  * the summary's standard errors are the square roots of the diagonal of
+    the inverse observed information (-H)^{-1} at the given theta, its
+    p-values two-sided normal tails of z = theta / se; predict returns the
+    probabilities of Eqs. 3-4 on data without choices.
 """
 from __future__ import annotations
 
@@ -365,3 +369,35 @@ def fit(X, Y, Z, choice, w=None, theta0=None, opts: Optional[FitOptions] = None,
 def fit_problem(prob, theta0=None, opts=None, record=False) -> FitResult:
     return fit(prob.X, prob.Y, prob.Z, prob.choice, prob.w, theta0, opts,
                record)
+
+
+# ---- fitted-model methods: predict and summary (Sec. 2.3) --------------------
+
+def predict(theta, X, Y, Z):
+    """Choice probabilities of the fitted model on (new) data: Eqs. 3-4 at
+    the utilities of Eq. 2.  No choices are needed."""
+    return probabilities(normalized_utility(theta, X, Y, Z))
+
+
+def covariance(theta, X, Y, Z, w=None):
+    """Asymptotic covariance of the maximum-likelihood estimate: the inverse
+    of the observed information -H, with H of Eq. 10 at theta.  Raises
+    NotNegativeDefinite when -H has no Cholesky factor."""
+    A = -hessian(theta, X, Y, Z, None, w)
+    try:
+        np.linalg.cholesky(A)
+    except np.linalg.LinAlgError as exc:
+        raise NotNegativeDefinite(str(exc)) from exc
+    return np.linalg.inv(A)
+
+
+def summary(theta, X, Y, Z, w=None):
+    """Coefficient table of the summary method (Sec. 2.3): standard errors
+    sqrt(diag((-H)^{-1})), Wald statistics z = theta / se and two-sided
+    normal p-values erfc(|z| / sqrt 2)."""
+    import math
+    theta = np.asarray(theta, dtype=np.float64)
+    se = np.sqrt(np.diag(covariance(theta, X, Y, Z, w)))
+    z = theta / se
+    pval = np.array([math.erfc(abs(v) / math.sqrt(2.0)) for v in z])
+    return se, z, pval

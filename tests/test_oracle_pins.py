@@ -487,3 +487,112 @@ def test_line_search_rule_at_optimum():
     _, _, trials, ok = R.line_search(th, d, l_hat, pr.X, pr.Y, pr.Z,
                                      pr.choice, None, R.FitOptions(ls_max=3))
     assert not ok and trials == 4
+
+
+# ---------------------------------------------------------------------------
+# fitted-model methods (Sec. 2.3): predict and the summary's standard errors
+
+def test_intercept_only_standard_errors_closed_form():
+    # inverse information of the log-odds xi_k = log(n_k / n_0):
+    # var = 1/n_k + 1/n_0 on the diagonal, cov = 1/n_0 off it
+    K = 5
+    pr = synth.make_problem(600, K, 1, 0, 0, seed=8, weights="uniform",
+                            coef_sd=0.7)
+    res = R.fit_problem(pr, opts=R.FitOptions(gtol=1e-10, ftol=0.0))
+    n = np.array([pr.w[pr.choice == k].sum() for k in range(K)])
+    C = R.covariance(res.theta, pr.X, pr.Y, pr.Z, pr.w)
+    ref = np.full((K - 1, K - 1), 1.0 / n[0]) + np.diag(1.0 / n[1:])
+    np.testing.assert_allclose(C, ref, rtol=1e-9, atol=0)
+    se, z, pval = R.summary(res.theta, pr.X, pr.Y, pr.Z, pr.w)
+    np.testing.assert_allclose(se, np.sqrt(1.0 / n[1:] + 1.0 / n[0]),
+                               rtol=1e-9)
+    np.testing.assert_allclose(z, res.theta / se, rtol=1e-15)
+
+
+def test_binary_logit_standard_errors_equal_irls():
+    # K = 2: the textbook logistic-regression covariance (X^T W X)^{-1}
+    pr = synth.make_problem(400, 2, 4, 0, 0, seed=6, weights="uniform")
+    b = irls_binary(pr.X, (pr.choice == 1).astype(float), pr.w)
+    s = 1.0 / (1.0 + np.exp(-(pr.X @ b)))
+    info = pr.X.T @ ((pr.w * s * (1 - s))[:, None] * pr.X)
+    se_ref = np.sqrt(np.diag(np.linalg.inv(info)))
+    se, _, _ = R.summary(b, pr.X, pr.Y, pr.Z, pr.w)
+    np.testing.assert_allclose(se, se_ref, rtol=1e-12)
+
+
+def test_saturated_groups_standard_errors():
+    # one-hot groups, K = 2: se of a group's log-odds is sqrt(1/c1 + 1/c0)
+    rng = np.random.default_rng(9)
+    G, N = 3, 900
+    grp = rng.integers(0, G, N)
+    X = np.zeros((N, G))
+    X[np.arange(N), grp] = 1.0
+    choice = (rng.random(N) < 0.25 + 0.15 * grp).astype(np.int32)
+    Y = np.zeros((N, 2, 0))
+    res = R.fit(X, Y, Y, choice, None, opts=R.FitOptions(gtol=1e-11, ftol=0))
+    se, _, _ = R.summary(res.theta, X, Y, Y)
+    for j in range(G):
+        c1 = np.sum((grp == j) & (choice == 1))
+        c0 = np.sum((grp == j) & (choice == 0))
+        assert se[j] == pytest.approx(math.sqrt(1 / c1 + 1 / c0), rel=1e-9)
+
+
+def test_standard_errors_weight_scaling_and_replication():
+    pr = tiny(12, N=40, K=4, p=2, g=1, a=1, weights="int")
+    th = pr.theta_true
+    se, _, _ = R.summary(th, pr.X, pr.Y, pr.Z, pr.w)
+    se3, _, _ = R.summary(th, pr.X, pr.Y, pr.Z, 3.0 * pr.w)
+    np.testing.assert_allclose(se3, se / math.sqrt(3.0), rtol=1e-12)
+    idx = np.repeat(np.arange(pr.N), pr.w.astype(int))
+    se_rep, _, _ = R.summary(th, pr.X[idx], pr.Y[idx], pr.Z[idx])
+    np.testing.assert_allclose(se_rep, se, rtol=1e-12)
+
+
+def test_p_values_normal_tail():
+    pr = tiny(13, N=200, K=3, p=2, g=1, a=1)
+    se, z, pval = R.summary(pr.theta_true, pr.X, pr.Y, pr.Z, pr.w)
+    import scipy.stats
+    np.testing.assert_allclose(pval, 2.0 * scipy.stats.norm.sf(np.abs(z)),
+                               rtol=1e-12)
+
+
+def test_covariance_rejects_singular_model():
+    # a duplicated column: -H is singular
+    pr = tiny(14, N=60, K=3, p=2, g=0, a=0)
+    X = np.concatenate([pr.X, pr.X[:, 1:2]], axis=1)
+    th = np.zeros(R.num_params(3, 3, 0, 0))
+    with pytest.raises(R.NotNegativeDefinite):
+        R.covariance(th, X, pr.Y, pr.Z, pr.w)
+
+
+def test_predict_binary_is_sigmoid():
+    pr = synth.make_problem(50, 2, 3, 0, 0, seed=15)
+    P = R.predict(pr.theta_true, pr.X, pr.Y, pr.Z)
+    s = 1.0 / (1.0 + np.exp(-(pr.X @ pr.theta_true)))
+    np.testing.assert_allclose(P[:, 1], s, rtol=1e-14)
+    np.testing.assert_allclose(P[:, 0], 1.0 - s, rtol=1e-13, atol=1e-16)
+
+
+def test_predict_at_zero_and_at_intercept_only_optimum():
+    pr = tiny(16, N=30, K=6)
+    P = R.predict(np.zeros(pr.n_params), pr.X, pr.Y, pr.Z)
+    np.testing.assert_allclose(P, 1.0 / 6.0, rtol=1e-15)
+    K = 4
+    pr = synth.make_problem(500, K, 1, 0, 0, seed=17, coef_sd=0.6)
+    res = R.fit_problem(pr, opts=R.FitOptions(gtol=1e-10, ftol=0.0))
+    n = np.bincount(pr.choice, minlength=K).astype(float)
+    P = R.predict(res.theta, pr.X, pr.Y, pr.Z)
+    np.testing.assert_allclose(P, np.tile(n / n.sum(), (pr.N, 1)), rtol=1e-10)
+
+
+def test_predict_utility_by_hand():
+    # Eq. 2 written out for one observation of a model with every chunk
+    pr = tiny(18, N=5, K=3, p=2, g=2, a=1)
+    beta, gamma, alpha = R.split_theta(pr.theta_true, 3, 2, 2, 1)
+    i = 3
+    u = np.array([(pr.X[i] @ beta[k - 1] if k else 0.0)
+                  + pr.Z[i, k] @ gamma[k] + pr.Y[i, k] @ alpha
+                  for k in range(3)])
+    e = np.exp(u - u.max())
+    np.testing.assert_allclose(R.predict(pr.theta_true, pr.X, pr.Y, pr.Z)[i],
+                               e / e.sum(), rtol=1e-14)
