@@ -67,6 +67,60 @@ def pass_bytes(pr):
     return float(b)
 
 
+def predict_bytes(pr):
+    """Algorithmic HBM bytes of one prediction: read X, Y, Z, write P."""
+    N, K, p, g, a = pr.N, pr.K, pr.p, pr.g, pr.a
+    return float(N * (p + K * g + K * a) * 8 + N * K * 8)
+
+
+def fitted_methods(ctx, pr, dp, theta, reps=5):
+    """Time predict (one fused pass without choices) and the summary's
+    standard errors (FP64 Hessian + factorisation with identity rows) at
+    the fitted theta; compare the standard errors with the oracle's
+    recorded table when one exists for this workload."""
+    import numpy as np
+    import torch
+
+    import paper_1404_3177_amd as mnl
+    X, Y, Z, _, w = dp._refs
+    dq = mnl.Problem(X, Y, Z, None, w)
+    ctx.predict(dq, theta)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(
+        enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.predict(dq, theta)
+    e1.record()
+    torch.cuda.synchronize()
+    pms = e0.elapsed_time(e1) / reps
+    se = ctx.summary(dq, theta)[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        se = ctx.summary(dq, theta)[0]
+    torch.cuda.synchronize()
+    sms = (time.perf_counter() - t0) / reps * 1e3
+    out = {"predict": {"ms": pms, "bytes": predict_bytes(pr),
+                       "achieved_gbps": predict_bytes(pr) / pms * 1e-6,
+                       "peak_gbps": HBM_GBPS,
+                       "frac": predict_bytes(pr) / pms * 1e-6 / HBM_GBPS},
+           "summary": {"ms": sms, "n_params": pr.n_params,
+                       "se_rel_err_vs_oracle": None}}
+    gold = os.path.join(ROOT, "tests", "golden",
+                        f"summary_{pr.name}.npz")
+    if os.path.exists(gold):
+        ref = np.load(gold)
+        th_ref = ref["theta"]
+        if np.array_equal(theta.cpu().numpy(), th_ref) or \
+                np.linalg.norm(theta.cpu().numpy() - th_ref) <= \
+                1e-8 * np.linalg.norm(th_ref):
+            sr = ctx.summary(dq, torch.from_numpy(th_ref).cuda())[0]
+            out["summary"]["se_rel_err_vs_oracle"] = float(
+                np.max(np.abs(sr.cpu().numpy() - ref["se"]) / ref["se"]))
+    return out
+
+
 def time_fits(ctx, dp, steps, warmup, prec):
     import torch
     for _ in range(warmup):
@@ -372,6 +426,11 @@ def main():
                     np.linalg.norm(gold["theta"]))
             variants[f"{vp}_hessian"] = ent
 
+    methods = None
+    if not args.no_variants:
+        log("fitted-model methods: predict and summary")
+        methods = fitted_methods(ctx, pr, dp, theta)
+
     serve = None
     if args.serve_requests > 0:
         serve = serving(args.serve_requests, args.serve_slots, args.serve_load)
@@ -431,6 +490,7 @@ def main():
                 "phase_ms": {k: info[k] for k in ("t_loglik_grad", "t_hessian",
                                                    "t_chol", "t_ls")}},
         "variants": variants,
+        "fitted_methods": methods,
         "serving": serve,
         "cpu_baseline": cpu,
     }

@@ -212,6 +212,32 @@ int mnl_fit(mnl_ctx *ctx, const mnl_problem *prob, const double *theta0,
             const mnl_fit_opts *opts, double *theta_out, mnl_fit_info *info,
             void *stream);
 
+/* ---- Fitted-model methods (Sec. 2.3: summary and predict) ----------------- */
+
+/* Choice probabilities on (new) data at theta: Eqs. 3-4 at the utilities of
+ * Eq. 2, one fused pass.  prob->choice and prob->w are not read (either may
+ * be NULL).
+ *   theta   [n_p] device, input.
+ *   P       [N][K] device, output; alternative 0 in column 0.
+ * Asynchronous on `stream`. */
+int mnl_predict(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
+                double *P, void *stream);
+
+/* The summary's coefficient table at theta (normally the fitted one): the
+ * asymptotic standard errors se = sqrt(diag((-H)^{-1})), H the FP64 Hessian
+ * of Eq. 10 at theta, the Wald statistics z = theta / se and their two-sided
+ * normal p-values erfc(|z| / sqrt 2).  One FP64 Hessian and one LDL^T
+ * factorisation of -H with n_p identity rows appended (the workspace holds
+ * (2 n_p + 1) x n_p doubles).  prob->choice is not read (may be NULL).
+ *   theta   [n_p] device, input.
+ *   se      [n_p] device, output.
+ *   zval    [n_p] device, output, may be NULL.
+ *   pval    [n_p] device, output, may be NULL.
+ * MNL_ERR_NOT_PD (outputs unspecified) when -H has a pivot at or below
+ * n_p * eps * max_k(-H_kk).  Synchronises `stream`. */
+int mnl_stderr(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
+               double *se, double *zval, double *pval, void *stream);
+
 /* ---- Serving: continuous batching of independent fits -------------------
  *
  * A server runs many fits at once on one device.  Requests arrive with

@@ -379,11 +379,12 @@ def predict(theta, X, Y, Z):
     return probabilities(normalized_utility(theta, X, Y, Z))
 
 
-def covariance(theta, X, Y, Z, w=None):
+def covariance(theta, X, Y, Z, w=None, H=None):
     """Asymptotic covariance of the maximum-likelihood estimate: the inverse
-    of the observed information -H, with H of Eq. 10 at theta.  Raises
-    NotNegativeDefinite when -H has no Cholesky factor."""
-    A = -hessian(theta, X, Y, Z, None, w)
+    of the observed information -H, with H of Eq. 10 at theta (computed
+    unless given).  Raises NotNegativeDefinite when -H has no Cholesky
+    factor."""
+    A = -(hessian(theta, X, Y, Z, None, w) if H is None else H)
     try:
         np.linalg.cholesky(A)
     except np.linalg.LinAlgError as exc:
@@ -391,13 +392,13 @@ def covariance(theta, X, Y, Z, w=None):
     return np.linalg.inv(A)
 
 
-def summary(theta, X, Y, Z, w=None):
+def summary(theta, X, Y, Z, w=None, H=None):
     """Coefficient table of the summary method (Sec. 2.3): standard errors
     sqrt(diag((-H)^{-1})), Wald statistics z = theta / se and two-sided
     normal p-values erfc(|z| / sqrt 2)."""
     import math
     theta = np.asarray(theta, dtype=np.float64)
-    se = np.sqrt(np.diag(covariance(theta, X, Y, Z, w)))
+    se = np.sqrt(np.diag(covariance(theta, X, Y, Z, w, H)))
     z = theta / se
     pval = np.array([math.erfc(abs(v) / math.sqrt(2.0)) for v in z])
     return se, z, pval

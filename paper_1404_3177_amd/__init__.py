@@ -46,8 +46,9 @@ def _stream_handle(stream=None) -> Optional[int]:
 
 class Problem:
     """Device-resident problem.  Tensors must be contiguous: X float64
-    [N, p], Y float64 [N, K, g], Z float64 [N, K, a], choice int32 [N],
-    w float64 [N] or None."""
+    [N, p], Y float64 [N, K, g], Z float64 [N, K, a], choice int32 [N]
+    (None for data that are only predicted or summarised), w float64 [N] or
+    None."""
 
     def __init__(self, X, Y, Z, choice, w=None):
         import torch
@@ -57,12 +58,13 @@ class Problem:
         for t, name in ((X, "X"), (Y, "Y"), (Z, "Z")):
             if t.dtype != torch.float64 or not t.is_contiguous():
                 raise ValueError(f"{name} must be contiguous float64")
-        if choice.dtype != torch.int32 or not choice.is_contiguous():
+        if choice is not None and (choice.dtype != torch.int32 or
+                                   not choice.is_contiguous()):
             raise ValueError("choice must be contiguous int32")
         if w is not None and (w.dtype != torch.float64 or not w.is_contiguous()):
             raise ValueError("w must be contiguous float64")
         if Y.shape[0] != N or Z.shape[0] != N or Z.shape[1] != K or \
-                choice.shape[0] != N:
+                (choice is not None and choice.shape[0] != N):
             raise ValueError("inconsistent shapes")
         self.N, self.K, self.p, self.g, self.a = N, K, p, g, a
         self.device = X.device
@@ -70,7 +72,8 @@ class Problem:
         self.c = MnlProblem(
             N=N, K=K, p=p, g=g, a=a,
             X=X.data_ptr() if p else None, Y=Y.data_ptr() if g else None,
-            Z=Z.data_ptr() if a else None, choice=choice.data_ptr(),
+            Z=Z.data_ptr() if a else None,
+            choice=choice.data_ptr() if choice is not None else None,
             w=w.data_ptr() if w is not None else None)
 
     @property
@@ -180,6 +183,31 @@ class Context:
             ctypes.byref(o), theta.data_ptr(), ctypes.byref(info),
             _stream_handle(stream)))
         return theta, info.as_dict()
+
+
+    def predict(self, prob: Problem, theta, stream=None):
+        """Choice probabilities [N, K] (device tensor) on prob's data; its
+        choices and weights are not read."""
+        import torch
+        P = torch.empty(prob.N, prob.K, dtype=torch.float64,
+                        device=prob.device)
+        self._check(self.lib.mnl_predict(
+            self.h, ctypes.byref(prob.c), theta.data_ptr(), P.data_ptr(),
+            _stream_handle(stream)))
+        return P
+
+    def summary(self, prob: Problem, theta, stream=None):
+        """(se, z, p) device tensors: standard errors sqrt(diag((-H)^-1)),
+        Wald statistics theta / se and two-sided normal p-values."""
+        import torch
+        n = prob.n_params
+        out = [torch.empty(n, dtype=torch.float64, device=prob.device)
+               for _ in range(3)]
+        self._check(self.lib.mnl_stderr(
+            self.h, ctypes.byref(prob.c), theta.data_ptr(),
+            out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(),
+            _stream_handle(stream)))
+        return tuple(out)
 
 
 def fit_footprint(N: int, K: int, p: int, g: int, a: int, prec="fp64",

@@ -28,7 +28,7 @@ EXPORTS = [
     "mnl_version", "mnl_strerror", "mnl_default_opts", "mnl_num_params",
     "mnl_create", "mnl_destroy", "mnl_workspace_bytes", "mnl_last_error",
     "mnl_loglik_grad", "mnl_hessian", "mnl_newton_step", "mnl_fit",
-    "mnl_fit_footprint", "mnl_server_now_ms", "mnl_server_create",
+    "mnl_predict", "mnl_stderr", "mnl_fit_footprint", "mnl_server_now_ms", "mnl_server_create",
     "mnl_server_destroy", "mnl_server_submit", "mnl_server_wait",
     "mnl_server_get_stats",
 ]
@@ -134,6 +134,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                     ctypes.POINTER(MnlFitInfo), P]
     lib.mnl_fit.argtypes = [P, prob, P, ctypes.POINTER(MnlFitOpts), P,
                             ctypes.POINTER(MnlFitInfo), P]
+    lib.mnl_predict.argtypes = [P, prob, P, P, P]
+    lib.mnl_stderr.argtypes = [P, prob, P, P, P, P, P]
     lib.mnl_fit_footprint.argtypes = [prob, I32]
     lib.mnl_fit_footprint.restype = I64
     lib.mnl_server_now_ms.argtypes = []
@@ -149,7 +151,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                     ctypes.c_double, ctypes.POINTER(I32)]
     lib.mnl_server_get_stats.argtypes = [P, ctypes.POINTER(MnlServerStats)]
     for name in ("mnl_create", "mnl_loglik_grad", "mnl_hessian",
-                 "mnl_newton_step", "mnl_fit", "mnl_server_create",
+                 "mnl_newton_step", "mnl_fit", "mnl_predict", "mnl_stderr",
+                 "mnl_server_create",
                  "mnl_server_submit", "mnl_server_wait",
                  "mnl_server_get_stats"):
         getattr(lib, name).restype = ctypes.c_int

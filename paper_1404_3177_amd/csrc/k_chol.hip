@@ -24,6 +24,12 @@
 // and a small kernel applies the update to the g row.  Each trailing entry
 // is then read and written once per outer panel instead of once per 32-wide
 // step.
+//
+// The same factorisation gives the summary's standard errors: with n more
+// rows holding the identity below the g row, the augmented factor leaves
+// R L^{-T} D^{-1} = L^{-T} D^{-1} =: X in them (the rows are eliminated like
+// the g row), and diag((-H)^{-1}) = diag(L^{-T} D^{-1} L^{-1}) is
+// sum_k X_ik^2 D_k.
 #include <cmath>
 
 #include <rocblas/rocblas.h>
@@ -54,7 +60,7 @@ __global__ __launch_bounds__(256) void k_floor(double *Hm, int64_t n,
     const double v = -Hm[i * n + i];
     if (!isfinite(v)) bad = true;
     m = fmax(m, v);
-    Hm[n * n + i] = g[i];
+    Hm[n * n + i] = g ? g[i] : 0.0;
   }
   red[threadIdx.x] = bad ? INFINITY : m;
   __syncthreads();
@@ -340,6 +346,47 @@ __global__ __launch_bounds__(256) void k_outer_prep(double *A, int64_t n,
   if (lane == 0) A[n * n + j] -= v;
 }
 
+// Rows n + 1 .. 2n of the matrix buffer := the identity (row n + 1 + i
+// holds e_i^T).
+__global__ __launch_bounds__(256) void k_eye_rows(double *A, int64_t n) {
+  const int64_t cnt = n * n;
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < cnt;
+       e += int64_t(gridDim.x) * 256) {
+    const int64_t i = e / n, j = e - i * n;
+    A[(n + 1) * n + e] = i == j ? 1.0 : 0.0;
+  }
+}
+
+// Standard errors from the augmented factor: one wave per coefficient i,
+// v_i = sum_{k >= i} X_ik^2 D_k over row n + 1 + i (X_ik = 0 for k < i),
+// lane-strided partial sums combined by a fixed butterfly.  se = sqrt(v),
+// z = theta / se, p = erfc(|z| / sqrt 2) (z and p optional).
+__global__ __launch_bounds__(256) void k_inv_diag(const double *A, int64_t n,
+                                                  const double *theta,
+                                                  double *se, double *zv,
+                                                  double *pv,
+                                                  const int32_t *info) {
+  if (info[0]) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const double *xr = A + (n + 1 + i) * n;
+  double v = 0.0;
+  for (int64_t k = i + lane; k < n; k += 64) {
+    const double x = xr[k];
+    v = fma(x * x, A[k * (n + 1)], v);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) {
+    const double s = sqrt(v);
+    se[i] = s;
+    const double z = theta[i] / s;
+    if (zv) zv[i] = z;
+    if (pv) pv[i] = erfc(fabs(z) * 0.70710678118654752440);
+  }
+}
+
 __device__ inline double readlane_f64(double v, int l) {
   const uint64_t u = __builtin_bit_cast(uint64_t, v);
   const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l);
@@ -399,20 +446,23 @@ __global__ __launch_bounds__(256) void k_chol_bwd(const double *A, int64_t n,
 
 }  // namespace
 
-size_t chol_workspace_bytes(int64_t n) {
-  const int64_t nrows = n + 1;
+size_t chol_workspace_bytes(int64_t n, int64_t extra) {
+  const int64_t nrows = n + 1 + extra;
   const int64_t w = n >= kOuterMin ? (n - NBO) * NBO : 0;
   return size_t(n + 8 + 2 * nrows * NBF + w) * 8;
 }
 
 int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
-                   double *delta, int32_t *info, hipStream_t s) {
+                   double *delta, int32_t *info, hipStream_t s,
+                   int64_t extra) {
   void *scr;
-  const int64_t nrows = n + 1;
+  if (extra != 0 && extra != n)
+    return set_error(c, MNL_ERR_ARG, "identity rows must number n");
+  const int64_t nrows = n + 1 + extra;
   const bool outer = n >= kOuterMin;
   // two panel buffers of nrows x NBF (each a multiple of 256 bytes, so
   // both stay 16-byte aligned), z, floor, then W of the outer panels
-  MNL_TRY(ws_get(c, S_CHOL, chol_workspace_bytes(n), &scr));
+  MNL_TRY(ws_get(c, S_CHOL, chol_workspace_bytes(n, extra), &scr));
   double *pbuf[2] = {static_cast<double *>(scr),
                      static_cast<double *>(scr) + nrows * NBF};
   double *z = pbuf[1] + nrows * NBF;
@@ -426,6 +476,10 @@ int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
   }
   hipLaunchKernelGGL(k_floor, dim3(1), dim3(256), 0, s, A, n, g, floor_p,
                      info);
+  if (extra) {
+    const unsigned gr = (unsigned)std::min<int64_t>(4096, (n * n + 255) / 256);
+    hipLaunchKernelGGL(k_eye_rows, dim3(gr), dim3(256), 0, s, A, n);
+  }
   int step = 0;
   int64_t j0p = -1;
   const int64_t wo = outer ? NBO : n;
@@ -471,12 +525,29 @@ int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
         rocblas_int(n));
     if (st != rocblas_status_success)
       return set_error(c, MNL_ERR_HIP, "rocblas_dgemm failed (%d)", int(st));
+    if (extra) {
+      // identity rows: X[:, J1:n] -= X[:, J0:J1] (L21 D)^T, the same update
+      // as the g row's (these rows are never negated, so beta = 1)
+      const double one = 1.0;
+      double *Xr = A + (n + 1) * n;
+      const rocblas_status sx = rocblas_dgemm(
+          hb, rocblas_operation_transpose, rocblas_operation_none,
+          rocblas_int(m), rocblas_int(extra), rocblas_int(NBO), &alpha, W,
+          rocblas_int(NBO), Xr + J0, rocblas_int(n), &one, Xr + J1,
+          rocblas_int(n));
+      if (sx != rocblas_status_success)
+        return set_error(c, MNL_ERR_HIP, "rocblas_dgemm failed (%d)", int(sx));
+    }
   }
   {
     const int64_t cnt = std::max<int64_t>((nrows - j0p) * NBF, n);
     const unsigned gr = (unsigned)std::min<int64_t>(1024, (cnt + 255) / 256);
     hipLaunchKernelGGL(k_chol_copy, dim3(gr), dim3(256), 0, s, A, n, nrows,
-                       j0p, pbuf[(step - 1) & 1], z, info);
+                       j0p, pbuf[(step - 1) & 1], delta ? z : nullptr, info);
+  }
+  if (!delta) {
+    MNL_HIP(c, hipGetLastError());
+    return MNL_OK;
   }
   const int64_t last = ((n - 1) / NBS) * NBS;
   for (int64_t j0 = last; j0 >= 0; j0 -= NBS) {
@@ -486,6 +557,15 @@ int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
   }
   MNL_HIP(c, hipGetLastError());
   return MNL_OK;
+}
+
+hipError_t launch_inv_diag(const double *A, int64_t n, const double *theta,
+                           double *se, double *z, double *pval,
+                           const int32_t *info, hipStream_t s) {
+  const unsigned gr = (unsigned)((n + 3) / 4);
+  hipLaunchKernelGGL(k_inv_diag, dim3(gr), dim3(256), 0, s, A, n, theta, se,
+                     z, pval, info);
+  return hipGetLastError();
 }
 
 }  // namespace mnl

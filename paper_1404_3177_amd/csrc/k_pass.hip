@@ -166,7 +166,8 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
         ws[tid] = tid < nobs ? (A.w ? A.w[i0 + tid] : 1.0) : 0.0;
         // an out-of-range choice (rejected when validation is on) is
         // clamped so that no access leaves the tile
-        int c = tid < nobs ? A.choice[i0 + tid] : 0;
+        // (no choices: predictions only, alternative 0 stands in)
+        int c = (tid < nobs && A.choice) ? A.choice[i0 + tid] : 0;
         chs[tid] = c < 0 ? 0 : (c >= K ? K - 1 : c);
       }
     }

@@ -128,7 +128,7 @@ hipError_t raise_lds_limit(const void *kernel, int bytes) {
   return e;
 }
 
-int check_problem(Ctx *c, const mnl_problem *pr, Dims *d) {
+int check_problem(Ctx *c, const mnl_problem *pr, Dims *d, bool need_choice) {
   if (!pr) return set_error(c, MNL_ERR_ARG, "problem is NULL");
   if (pr->N < 1) return set_error(c, MNL_ERR_ARG, "N must be >= 1");
   if (pr->K < 2) return set_error(c, MNL_ERR_ARG, "K must be >= 2");
@@ -137,7 +137,8 @@ int check_problem(Ctx *c, const mnl_problem *pr, Dims *d) {
   if (pr->p > 0 && !pr->X) return set_error(c, MNL_ERR_ARG, "X is NULL");
   if (pr->g > 0 && !pr->Y) return set_error(c, MNL_ERR_ARG, "Y is NULL");
   if (pr->a > 0 && !pr->Z) return set_error(c, MNL_ERR_ARG, "Z is NULL");
-  if (!pr->choice) return set_error(c, MNL_ERR_ARG, "choice is NULL");
+  if (need_choice && !pr->choice)
+    return set_error(c, MNL_ERR_ARG, "choice is NULL");
   d->N = pr->N;
   d->K = pr->K;
   d->p = pr->p;
@@ -630,6 +631,70 @@ int mnl_hessian(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
   MNL_TRY(run_pass(c, d, prob, theta, (double *)lg, S_P, S_P32, S_YBAR,
                    prec != MNL_PREC_FP64, s));
   return form_hessian(c, d, prob, 0, prec, H, s);
+}
+
+int mnl_predict(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
+                double *P, void *stream) {
+  if (!ctx) return MNL_ERR_ARG;
+  Ctx *c = &ctx->c;
+  Dims d;
+  MNL_TRY(check_problem(c, prob, &d, false));
+  if (!theta || !P) return set_error(c, MNL_ERR_ARG, "NULL argument");
+  MNL_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  PassPlan plan;
+  int rc = pass_plan(d, &plan);
+  if (rc != MNL_OK) return set_error(c, rc, "shape beyond pass limits");
+  // the fused pass with no choices: P is its output, the partial rows of
+  // l and g are left unreduced
+  void *partial;
+  MNL_TRY(ws_get(c, S_PARTIAL, size_t(plan.grid) * plan.stride * 8, &partial));
+  PassArgs A;
+  A.d = d;
+  A.X = prob->X;
+  A.Y = prob->Y;
+  A.Z = prob->Z;
+  A.w = nullptr;
+  A.choice = nullptr;
+  A.theta = theta;
+  A.P = P;
+  A.P32 = nullptr;
+  A.Ybar = nullptr;
+  A.partial = (double *)partial;
+  MNL_HIP(c, launch_pass(plan, A, s));
+  return MNL_OK;
+}
+
+int mnl_stderr(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
+               double *se, double *zval, double *pval, void *stream) {
+  if (!ctx) return MNL_ERR_ARG;
+  Ctx *c = &ctx->c;
+  Dims d;
+  MNL_TRY(check_problem(c, prob, &d, false));
+  if (!theta || !se) return set_error(c, MNL_ERR_ARG, "NULL argument");
+  MNL_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  ++c->call_epoch;
+  void *lg, *Hv, *sv;
+  MNL_TRY(ws_get(c, S_LG, size_t(d.np + 1) * 8, &lg));
+  // 2 n_p + 1 rows: H, the (zero) g row and n_p identity rows, plus the
+  // factorisation's padding
+  MNL_TRY(ws_get(c, S_H, (size_t(2 * d.np + 1) * d.np + 64) * 8, &Hv));
+  MNL_TRY(ws_get(c, S_SCAL, 256, &sv));
+  int32_t *cinfo = (int32_t *)sv + 32;
+  double *H = (double *)Hv;
+  MNL_TRY(run_pass(c, d, prob, theta, (double *)lg, S_P, S_P32, S_YBAR, false,
+                   s));
+  MNL_TRY(form_hessian(c, d, prob, 0, MNL_PREC_FP64, H, s));
+  MNL_TRY(chol_solve_run(c, H, d.np, nullptr, nullptr, cinfo, s, d.np));
+  MNL_HIP(c, launch_inv_diag(H, d.np, theta, se, zval, pval, cinfo, s));
+  int32_t fail = 0;
+  MNL_TRY(copy_d2h(c, &fail, cinfo, sizeof fail, s));
+  c->hess_pending = c->pass_pending = false;
+  if (fail)
+    return set_error(c, MNL_ERR_NOT_PD,
+                     "-H not positive definite (pivot %d)", int(fail) - 1);
+  return MNL_OK;
 }
 
 int mnl_newton_step(mnl_ctx *ctx, const mnl_problem *prob, double *theta,

@@ -160,12 +160,21 @@ int hessian_footprint(Ctx *c, const Dims &d, int prec, size_t *part_bytes,
 
 // ---- Cholesky and solves ------------------------------------------------------
 // Factor A = -H in place (lower triangle holds L) and solve L L^T delta = g;
-// A has n + 1 rows of n (row n is scratch for g).
+// A has n + 1 + extra rows of n plus 64 doubles of padding (row n is
+// scratch for g, NULL g reads as zeros; NULL delta skips the solve).
+// extra = n appends identity rows that end up holding L^{-T} D^{-1}.
 // info[0] receives 0 or (1 + index of the failed pivot).
 int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
-                   double *delta, int32_t *info, hipStream_t s);
+                   double *delta, int32_t *info, hipStream_t s,
+                   int64_t extra = 0);
 // Scratch bytes chol_solve_run takes (workspace slot S_CHOL).
-size_t chol_workspace_bytes(int64_t n);
+size_t chol_workspace_bytes(int64_t n, int64_t extra = 0);
+// se_i = sqrt(diag((-H)^{-1})_i) from a factor with identity rows; z and
+// pval (optional) the Wald statistic theta_i / se_i and its two-sided
+// normal p-value.  Nothing is written when info[0] != 0.
+hipError_t launch_inv_diag(const double *A, int64_t n, const double *theta,
+                           double *se, double *z, double *pval,
+                           const int32_t *info, hipStream_t s);
 
 // Context ---------------------------------------------------------------------
 struct Ctx {
@@ -205,7 +214,10 @@ struct Ctx {
 hipError_t raise_lds_limit(const void *kernel, int bytes);
 
 // Validate a problem description and fill its dimensions.
-int check_problem(Ctx *c, const mnl_problem *pr, Dims *d);
+// (choices may be NULL when need_choice is false: the pass then reads
+// alternative 0 for every observation and its l and g are meaningless)
+int check_problem(Ctx *c, const mnl_problem *pr, Dims *d,
+                  bool need_choice = true);
 int check_opts(Ctx *c, const mnl_fit_opts *o);
 // Newton-Raphson loop on device data (theta in/out on the device).
 int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
