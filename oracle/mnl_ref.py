@@ -35,9 +35,15 @@ Readings taken where the paper is silent (all also used by the GPU path):
     the inverse observed information (-H)^{-1} at the given theta, its
     p-values two-sided normal tails of z = theta / se; predict returns the
     probabilities of Eqs. 3-4 on data without choices.
+  * the inexact Newton method (the paper's stated next step) takes its
+    direction from truncated conjugate gradients on (-H) d = g from d = 0,
+    with relative residual eta = min(1/2, sqrt(||g||)), at most cg_maxiter
+    Hessian-vector products, and d = g when the first search direction
+    shows non-positive curvature; line search and stop rules are Newton's.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 from typing import List, Optional
 
@@ -275,6 +281,11 @@ class FitOptions:
     gtol: float = 1e-6
     ls_max: int = 30
     ls_tol_ulps: float = 64.0
+    # "newton": the direction solves the Newton system exactly (Eq. 6);
+    # "newton-cg": truncated conjugate gradients on Hessian-vector products
+    # (the inexact Newton method of Sec. 6), at most cg_maxiter products
+    method: str = "newton"
+    cg_maxiter: int = 250
 
 
 @dataclass
@@ -289,6 +300,7 @@ class FitResult:
     stop_reason: int
     loglik_diff: float
     history: List[dict] = field(default_factory=list)
+    cg_iters: int = 0          # Hessian-vector products (newton-cg)
 
 
 def line_search(theta, delta, l_old, X, Y, Z, choice, w, opts: FitOptions):
@@ -321,7 +333,7 @@ def fit(X, Y, Z, choice, w=None, theta0=None, opts: Optional[FitOptions] = None,
     theta = np.zeros(n_p) if theta0 is None else np.array(theta0, dtype=np.float64)
     l = loglik(theta, X, Y, Z, choice, w)
     gr = gradient(theta, X, Y, Z, choice, w)
-    iters = ls_iters = backtracks = 0
+    iters = ls_iters = backtracks = cg_iters = 0
     dl = float("nan")
     hist = []
     reason = None
@@ -337,11 +349,16 @@ def fit(X, Y, Z, choice, w=None, theta0=None, opts: Optional[FitOptions] = None,
             reason = STOP_MAXITER
             break
         H = hessian(theta, X, Y, Z, choice, w)
-        try:
-            delta = newton_direction(H, gr)
-        except NotNegativeDefinite:
-            reason = STOP_NOT_PD
-            break
+        if opts.method == "newton-cg":
+            delta, ncg = cg_direction(lambda v: H @ v, gr,
+                                      forcing_term(gnorm), opts.cg_maxiter)
+            cg_iters += ncg
+        else:
+            try:
+                delta = newton_direction(H, gr)
+            except NotNegativeDefinite:
+                reason = STOP_NOT_PD
+                break
         th_new, l_new, trials, ok = line_search(theta, delta, l, X, Y, Z,
                                                 choice, w, opts)
         ls_iters += trials
@@ -363,12 +380,55 @@ def fit(X, Y, Z, choice, w=None, theta0=None, opts: Optional[FitOptions] = None,
     return FitResult(theta=theta, loglik=l, grad=gr,
                      grad_norm=float(np.linalg.norm(gr)), iters=iters,
                      ls_iters=ls_iters, ls_backtracks=backtracks,
-                     stop_reason=reason, loglik_diff=dl, history=hist)
+                     stop_reason=reason, loglik_diff=dl, history=hist,
+                     cg_iters=cg_iters)
 
 
 def fit_problem(prob, theta0=None, opts=None, record=False) -> FitResult:
     return fit(prob.X, prob.Y, prob.Z, prob.choice, prob.w, theta0, opts,
                record)
+
+
+# ---- inexact (truncated) Newton (Sec. 6) -------------------------------------
+
+def hessian_vector(theta, X, Y, Z, v, w=None):
+    """H(theta) v with H of Eq. 10: the product an inexact Newton method
+    takes instead of forming and factoring H."""
+    return hessian(theta, X, Y, Z, None, w) @ np.asarray(v, dtype=np.float64)
+
+
+def forcing_term(gnorm):
+    """Relative residual at which the inner solve stops:
+    eta = min(1/2, sqrt(||g||)), the choice that keeps truncated Newton
+    superlinearly convergent near the optimum."""
+    return min(0.5, math.sqrt(gnorm))
+
+
+def cg_direction(hv, grad, eta, maxcg):
+    """Truncated conjugate gradients for (-H) d = g from d = 0, where hv(v)
+    returns H v.  Stops when ||r|| <= eta ||g||, after maxcg products, or
+    when a search direction p has p^T (-H) p <= 0 (then d = g if no step
+    was taken yet).  Returns (d, number of Hessian-vector products)."""
+    grad = np.asarray(grad, dtype=np.float64)
+    d = np.zeros_like(grad)
+    r = grad.copy()
+    p = r.copy()
+    rr = float(r @ r)
+    gn = math.sqrt(rr)
+    for j in range(maxcg):
+        if math.sqrt(rr) <= eta * gn:
+            return d, j
+        Ap = -hv(p)
+        pAp = float(p @ Ap)
+        if not pAp > 0.0:
+            return (grad.copy() if j == 0 else d), j + 1
+        alpha = rr / pAp
+        d = d + alpha * p
+        r = r - alpha * Ap
+        rr_new = float(r @ r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return d, maxcg
 
 
 # ---- fitted-model methods: predict and summary (Sec. 2.3) --------------------

@@ -596,3 +596,97 @@ def test_predict_utility_by_hand():
     e = np.exp(u - u.max())
     np.testing.assert_allclose(R.predict(pr.theta_true, pr.X, pr.Y, pr.Z)[i],
                                e / e.sum(), rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# inexact Newton (Sec. 6): Hessian-vector products and truncated CG
+
+@pytest.mark.parametrize("shape", SHAPES[:4])
+def test_hessian_vector_central_differences(shape):
+    N, K, p, g, a = shape
+    pr = tiny(50 + K, N=N, K=K, p=p, g=g, a=a)
+    th = pr.theta_true
+    v = np.random.default_rng(3).normal(size=pr.n_params)
+    hv = R.hessian_vector(th, pr.X, pr.Y, pr.Z, v, pr.w)
+    h = 1e-5
+    gp = R.gradient(th + h * v, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
+    gm = R.gradient(th - h * v, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
+    fd = (gp - gm) / (2 * h)
+    assert np.abs(hv - fd).max() <= 1e-7 * np.abs(hv).max()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_hessian_vector_per_observation_form(shape):
+    # -sum_i w_i J_i^T (P_i o u_i - P_i (P_i . u_i)), u_i = J_i v: no H formed
+    N, K, p, g, a = shape
+    pr = tiny(60 + K, N=N, K=K, p=p, g=g, a=a)
+    th = pr.theta_true
+    v = np.random.default_rng(4).normal(size=pr.n_params)
+    J = unnormalized_jacobians(pr.X, pr.Y, pr.Z)
+    U = J @ th
+    P = np.exp(U - scipy.special.logsumexp(U, axis=1)[:, None])
+    u = J @ v
+    s = P * (u - (P * u).sum(axis=1, keepdims=True))
+    ref = -np.einsum("i,ikq,ik->q", pr.w, J, s)
+    hv = R.hessian_vector(th, pr.X, pr.Y, pr.Z, v, pr.w)
+    np.testing.assert_allclose(hv, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_cg_distinct_eigenvalues_and_exact_solve():
+    # CG on an SPD system ends in as many steps as distinct eigenvalues
+    rng = np.random.default_rng(5)
+    Q, _ = np.linalg.qr(rng.normal(size=(12, 12)))
+    lam = np.array([1.0] * 5 + [3.0] * 4 + [10.0] * 3)
+    A = Q @ np.diag(lam) @ Q.T
+    b = rng.normal(size=12)
+    d, it = R.cg_direction(lambda v: -A @ v, b, 1e-12, 50)
+    assert it == 3
+    np.testing.assert_allclose(d, np.linalg.solve(A, b), rtol=1e-10)
+    # a loose tolerance stops early with the residual below it
+    d2, it2 = R.cg_direction(lambda v: -A @ v, b, 0.5, 50)
+    assert it2 < 3 and np.linalg.norm(b - A @ d2) <= 0.5 * np.linalg.norm(b)
+    # the iteration cap
+    _, it3 = R.cg_direction(lambda v: -A @ v, b, 1e-12, 2)
+    assert it3 == 2
+
+
+def test_cg_non_positive_curvature_returns_gradient():
+    A = np.diag([-1.0, 2.0])
+    b = np.array([1.0, 0.0])
+    d, it = R.cg_direction(lambda v: -A @ v, b, 1e-12, 10)
+    assert it == 1 and np.array_equal(d, b)
+
+
+def test_cg_matches_newton_direction_at_full_depth():
+    pr = tiny(70, N=60, K=4, p=3, g=1, a=1)
+    th = pr.theta_true
+    H = R.hessian(th, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
+    gr = R.gradient(th, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
+    d, it = R.cg_direction(lambda v: H @ v, gr, 1e-13, 4 * pr.n_params)
+    np.testing.assert_allclose(d, R.newton_direction(H, gr), rtol=1e-9,
+                               atol=1e-11)
+
+
+def test_forcing_term():
+    assert R.forcing_term(1e4) == 0.5
+    assert R.forcing_term(1e-6) == pytest.approx(1e-3, rel=1e-15)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_newton_cg_fit_reaches_newton_optimum(seed):
+    pr = synth.make_problem(800, 5, 3, 1, 1, seed=80 + seed, weights="uniform")
+    o_nr = R.FitOptions(gtol=1e-9, ftol=0.0)
+    o_cg = R.FitOptions(gtol=1e-9, ftol=0.0, method="newton-cg")
+    nr = R.fit_problem(pr, opts=o_nr)
+    cg = R.fit_problem(pr, opts=o_cg)
+    assert nr.stop_reason == cg.stop_reason == R.STOP_GTOL
+    assert np.linalg.norm(cg.theta - nr.theta) <= 1e-9 * np.linalg.norm(nr.theta)
+    assert cg.cg_iters >= cg.iters >= nr.iters
+
+
+def test_newton_cg_binary_equals_irls():
+    pr = synth.make_problem(300, 2, 4, 0, 0, seed=7, weights="uniform")
+    res = R.fit_problem(pr, opts=R.FitOptions(gtol=1e-11, ftol=0.0,
+                                              method="newton-cg"))
+    b = irls_binary(pr.X, (pr.choice == 1).astype(float), pr.w)
+    np.testing.assert_allclose(res.theta, b, rtol=0, atol=1e-9)
