@@ -121,16 +121,17 @@ def fitted_methods(ctx, pr, dp, theta, reps=5):
     return out
 
 
-def time_fits(ctx, dp, steps, warmup, prec):
+def time_fits(ctx, dp, steps, warmup, prec, method="newton"):
     import torch
     for _ in range(warmup):
-        ctx.fit(dp, gtol=GTOL, ftol=0.0, prec=prec)
+        ctx.fit(dp, gtol=GTOL, ftol=0.0, prec=prec, method=method)
     torch.cuda.synchronize()
     lat, infos = [], []
     t0 = time.perf_counter()
     for _ in range(steps):
         t = time.perf_counter()
-        theta, info = ctx.fit(dp, gtol=GTOL, ftol=0.0, prec=prec)
+        theta, info = ctx.fit(dp, gtol=GTOL, ftol=0.0, prec=prec,
+                              method=method)
         lat.append(time.perf_counter() - t)
         infos.append(info)
     torch.cuda.synchronize()
@@ -425,6 +426,21 @@ def main():
                     np.linalg.norm(th_v.cpu().numpy() - gold["theta"]) /
                     np.linalg.norm(gold["theta"]))
             variants[f"{vp}_hessian"] = ent
+        log("variant: inexact Newton (Newton-CG, Hessian-vector passes)")
+        th_c, inf_c, lat_c, tot_c = time_fits(ctx, dp, max(3, args.steps // 2),
+                                              1, "fp64", "newton-cg")
+        ic = inf_c[-1]
+        ent = {"fits_per_s": len(lat_c) / tot_c,
+               "ms_per_fit": tot_c / len(lat_c) * 1e3,
+               "iters": ic["iters"], "hessvec_products": ic["cg_iters"],
+               "ms_in_products": ic["t_hessian"],
+               "ms_per_product": ic["t_hessian"] / max(ic["cg_iters"], 1),
+               "grad_norm": ic["grad_norm"], "stop_reason": ic["stop_reason"]}
+        if os.path.exists(gold_path):
+            ent["coef_rel_err_vs_oracle"] = float(
+                np.linalg.norm(th_c.cpu().numpy() - gold["theta"]) /
+                np.linalg.norm(gold["theta"]))
+        variants["newton_cg"] = ent
 
     methods = None
     if not args.no_variants:

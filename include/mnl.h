@@ -99,9 +99,22 @@ typedef struct {
     const double *w;           /* [N] frequency weights >= 0, NULL = ones  */
 } mnl_problem;
 
+/* Newton direction.  NEWTON solves H delta = -g exactly by factoring H
+ * (Eq. 6).  NEWTON_CG is the inexact (truncated) Newton method the paper
+ * names as its next step (Sec. 6): conjugate gradients on (-H) d = g from
+ * d = 0 with FP64 Hessian-vector products (H is never formed), stopped at
+ * relative residual min(1/2, sqrt(||g||_2)), after cg_maxiter products, or
+ * at a direction of non-positive curvature (d = g if that is the first);
+ * the line search and stop rules are Newton's.  prec does not apply. */
+typedef enum {
+    MNL_METHOD_NEWTON = 0,
+    MNL_METHOD_NEWTON_CG = 1
+} mnl_method;
+
 /* Fit options; defaults (mnl_default_opts) are mnlogit's maxiter = 50,
- * ftol = 1e-6, gtol = 1e-6 (Sec. 2.3), FP64 Hessian, 30 halvings, and a
- * line-search acceptance slack of 64 ulps of |l|. */
+ * ftol = 1e-6, gtol = 1e-6 (Sec. 2.3), FP64 Hessian, 30 halvings, a
+ * line-search acceptance slack of 64 ulps of |l|, no validation, and the
+ * exact Newton direction (cg_maxiter 250 when NEWTON_CG is chosen). */
 typedef struct {
     int32_t maxiter;           /* >= 0                                     */
     double ftol;               /* stop when |dl| < ftol (0 disables)       */
@@ -111,6 +124,9 @@ typedef struct {
     double ls_tol_ulps;        /* accept l_t >= l - ls_tol_ulps*eps*|l|    */
     int32_t validate;          /* nonzero: check choices and finiteness of
                                   the data before fitting                  */
+    int32_t method;            /* mnl_method of the Newton direction       */
+    int32_t cg_maxiter;        /* NEWTON_CG: Hessian-vector products per
+                                  iteration at most, >= 1                  */
 } mnl_fit_opts;
 
 /* Report of a fit or of one Newton step (mnlogit's est.stat). Times in ms:
@@ -138,7 +154,7 @@ typedef struct {
     double t_hess_kernel;      /* GPU time in the Hessian MFMA kernel      */
     double t_pass_kernel;      /* GPU time in the fused pass kernel        */
     int32_t n_pass;            /* fused passes run                         */
-    int32_t reserved;
+    int32_t cg_iters;          /* NEWTON_CG: Hessian-vector products       */
 } mnl_fit_info;
 
 /* Library version string ("major.minor"). */
@@ -211,6 +227,16 @@ int mnl_newton_step(mnl_ctx *ctx, const mnl_problem *prob, double *theta,
 int mnl_fit(mnl_ctx *ctx, const mnl_problem *prob, const double *theta0,
             const mnl_fit_opts *opts, double *theta_out, mnl_fit_info *info,
             void *stream);
+
+/* Hessian-vector product H(theta) v (Eq. 10's H, never formed): one fused
+ * pass for P at theta, then one pass of v through -sum_i w_i J_i^T
+ * (diag P_i - P_i P_i^T) J_i, J_i = dU_i/dtheta.  prob->choice is not read
+ * (may be NULL).
+ *   theta, v  [n_p] device, input.
+ *   Hv        [n_p] device, output (Hessian sign).
+ * Asynchronous on `stream`. */
+int mnl_hessvec(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
+                const double *v, double *Hv, void *stream);
 
 /* ---- Fitted-model methods (Sec. 2.3: summary and predict) ----------------- */
 

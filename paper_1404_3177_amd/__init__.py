@@ -19,8 +19,9 @@ import ctypes
 from typing import Optional
 
 from . import _lib
-from ._lib import (MnlError, MnlFitInfo, MnlFitOpts, MnlProblem,  # noqa
-                   MnlServerOpts, MnlServerResult, MnlServerStats, PREC,
+from ._lib import (METHOD, MnlError, MnlFitInfo, MnlFitOpts,  # noqa
+                   MnlProblem, MnlServerOpts, MnlServerResult,
+                   MnlServerStats, PREC,
                    STOP_FTOL, STOP_GTOL, STOP_LS_FAIL, STOP_MAXITER,
                    STOP_NONE, STOP_NONFINITE, STOP_NOT_PD)
 
@@ -131,6 +132,8 @@ class Context:
         for k, v in kw.items():
             if k == "prec" and isinstance(v, str):
                 v = PREC[v]
+            if k == "method" and isinstance(v, str):
+                v = METHOD[v]
             if not hasattr(o, k):
                 raise TypeError(f"unknown option {k}")
             setattr(o, k, v)
@@ -184,6 +187,16 @@ class Context:
             _stream_handle(stream)))
         return theta, info.as_dict()
 
+
+    def hessvec(self, prob: Problem, theta, v, stream=None):
+        """H(theta) v (device tensor, Hessian sign) without forming H."""
+        import torch
+        Hv = torch.empty(prob.n_params, dtype=torch.float64,
+                         device=prob.device)
+        self._check(self.lib.mnl_hessvec(
+            self.h, ctypes.byref(prob.c), theta.data_ptr(), v.data_ptr(),
+            Hv.data_ptr(), _stream_handle(stream)))
+        return Hv
 
     def predict(self, prob: Problem, theta, stream=None):
         """Choice probabilities [N, K] (device tensor) on prob's data; its

@@ -23,12 +23,13 @@ ERRORS = {
 STOP_NONE, STOP_GTOL, STOP_FTOL, STOP_MAXITER = 0, 1, 2, 3
 STOP_LS_FAIL, STOP_NOT_PD, STOP_NONFINITE = 4, 5, 6
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+METHOD = {"newton": 0, "newton-cg": 1}
 
 EXPORTS = [
     "mnl_version", "mnl_strerror", "mnl_default_opts", "mnl_num_params",
     "mnl_create", "mnl_destroy", "mnl_workspace_bytes", "mnl_last_error",
     "mnl_loglik_grad", "mnl_hessian", "mnl_newton_step", "mnl_fit",
-    "mnl_predict", "mnl_stderr", "mnl_fit_footprint", "mnl_server_now_ms", "mnl_server_create",
+    "mnl_hessvec", "mnl_predict", "mnl_stderr", "mnl_fit_footprint", "mnl_server_now_ms", "mnl_server_create",
     "mnl_server_destroy", "mnl_server_submit", "mnl_server_wait",
     "mnl_server_get_stats",
 ]
@@ -48,7 +49,8 @@ class MnlFitOpts(ctypes.Structure):
         ("maxiter", ctypes.c_int32), ("ftol", ctypes.c_double),
         ("gtol", ctypes.c_double), ("prec", ctypes.c_int32),
         ("ls_max", ctypes.c_int32), ("ls_tol_ulps", ctypes.c_double),
-        ("validate", ctypes.c_int32),
+        ("validate", ctypes.c_int32), ("method", ctypes.c_int32),
+        ("cg_maxiter", ctypes.c_int32),
     ]
 
 
@@ -62,11 +64,11 @@ class MnlFitInfo(ctypes.Structure):
         ("t_loglik_grad", ctypes.c_double), ("t_hessian", ctypes.c_double),
         ("t_chol", ctypes.c_double), ("t_ls", ctypes.c_double),
         ("t_hess_kernel", ctypes.c_double), ("t_pass_kernel", ctypes.c_double),
-        ("n_pass", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("n_pass", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class MnlServerOpts(ctypes.Structure):
@@ -134,6 +136,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                     ctypes.POINTER(MnlFitInfo), P]
     lib.mnl_fit.argtypes = [P, prob, P, ctypes.POINTER(MnlFitOpts), P,
                             ctypes.POINTER(MnlFitInfo), P]
+    lib.mnl_hessvec.argtypes = [P, prob, P, P, P, P]
     lib.mnl_predict.argtypes = [P, prob, P, P, P]
     lib.mnl_stderr.argtypes = [P, prob, P, P, P, P, P]
     lib.mnl_fit_footprint.argtypes = [prob, I32]
@@ -151,7 +154,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                     ctypes.c_double, ctypes.POINTER(I32)]
     lib.mnl_server_get_stats.argtypes = [P, ctypes.POINTER(MnlServerStats)]
     for name in ("mnl_create", "mnl_loglik_grad", "mnl_hessian",
-                 "mnl_newton_step", "mnl_fit", "mnl_predict", "mnl_stderr",
+                 "mnl_newton_step", "mnl_fit", "mnl_hessvec", "mnl_predict",
+                 "mnl_stderr",
                  "mnl_server_create",
                  "mnl_server_submit", "mnl_server_wait",
                  "mnl_server_get_stats"):

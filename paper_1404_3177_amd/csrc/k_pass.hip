@@ -24,6 +24,13 @@
 //      across all of the workgroup's tiles.
 // At the end each workgroup writes one partial row, reduced in a fixed
 // order by k_pass_reduce.
+//
+// Hessian-vector mode (HV): with v in theta's place, step 2 and the Y/Z
+// terms give u_i = J_i v, the utilities of v.  With the probabilities P at
+// the current theta read from HBM, s_ik = P_ik (u_ik - sum_k' P_ik' u_ik')
+// is (diag P_i - P_i P_i^T) u_i, and R_ik = -w_i s_ik takes the residual's
+// place, so the gradient sums give H v = -sum_i w_i J_i^T (diag P_i -
+// P_i P_i^T) J_i v, the Hessian of Eq. 10 applied to v, without forming H.
 #include "mnl_common.h"
 
 namespace mnl {
@@ -109,7 +116,7 @@ __host__ __device__ inline Lay make_lay(const Dims &d) {
 // NTW: beta-gradient MFMA tiles per wave; CAP: register slots for the z
 // and y values of one alternative (>= a and >= g); ZR: a > 0 (without Z
 // no register is spent on z, gamma or the gamma gradient)
-template <int NTW, int CAP, bool ZR>
+template <int NTW, int CAP, bool ZR, bool HV>
 __global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
                                                    int64_t stride) {
   constexpr int CZ = ZR ? CAP : 1;
@@ -232,6 +239,65 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
           m = fmax(m, u);
         }
       }
+      if constexpr (HV) {
+        const double *pin = A.Pin + gi * K;
+        double pu = 0.0;
+        for (int k0 = 0; k0 < K; k0 += kWave) {
+          const int k = k0 + lane;
+          if (k < K) pu = fma(pin[k], ui[k], pu);
+        }
+        const double ub = wave_sum(pu);
+        for (int k0 = 0; k0 < K; k0 += kWave) {
+          const int k = k0 + lane;
+          if (k < K) {
+            const double R = -wi * (pin[k] * (ui[k] - ub));
+            ui[k] = R;
+            if (k0 == 0) {
+#pragma unroll
+              for (int c = 0; c < CZ; ++c)
+                if (ZR && c < a) gzr[c] = fma(R, zv[c], gzr[c]);
+            } else {
+              double *gzk = gz + wv * Ka + k * a;
+              for (int c = 0; c < a; ++c) gzk[c] = fma(R, zr[k * a + c], gzk[c]);
+            }
+          }
+        }
+        if (g > 0) {
+          // alpha part: sum_k R_ik y_ikc, all c reduced together as for Ybar
+          double part[CAP];
+          const double R0 = own ? ui[lane] : 0.0;
+#pragma unroll
+          for (int c = 0; c < CAP; ++c) part[c] = (c < g) ? R0 * yv[c] : 0.0;
+          for (int k0 = kWave; k0 < K; k0 += kWave) {
+            const int k = k0 + lane;
+            if (k < K) {
+              const double R = ui[k];
+#pragma unroll
+              for (int c = 0; c < CAP; ++c)
+                if (c < g) part[c] = fma(R, yr[k * g + c], part[c]);
+            }
+          }
+          double *scr = sm + L.ysc + wv * (CAP * kWave);
+#pragma unroll
+          for (int c = 0; c < CAP; ++c)
+            if (c < g) scr[c * kWave + lane] = part[c];
+          __builtin_amdgcn_wave_barrier();
+          constexpr int LPC = kWave / CAP;
+          const int cl = lane / LPC, jl = lane % LPC;
+          double yb = 0.0;
+          if (cl < g) {
+#pragma unroll
+            for (int q = 0; q < CAP; ++q) yb += scr[cl * kWave + jl * CAP + q];
+          }
+          yb += dpp_f64<0xB1>(yb);
+          if constexpr (LPC >= 4) yb += dpp_f64<0x4E>(yb);
+          if constexpr (LPC >= 8) yb += dpp_f64<0x141>(yb);
+          if constexpr (LPC >= 16) yb += dpp_f64<0x140>(yb);
+          __builtin_amdgcn_wave_barrier();
+          if (jl == 0 && cl < g) red[wv * (1 + g) + 1 + cl] += yb;
+        }
+        continue;
+      }
       m = wave_max(m);
       double s = 0.0;
       for (int k0 = 0; k0 < K; k0 += kWave) {
@@ -318,7 +384,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
     // taking observation wv + 4 q
     {
       const int iq = wv + kWaves * lane;
-      if (lane < kTB / kWaves && iq < nobs)
+      if (!HV && lane < kTB / kWaves && iq < nobs)
         lsum -= ws[iq] * (lgm[iq] + log(lgs[iq]));
     }
     __syncthreads();
@@ -436,13 +502,18 @@ hipError_t launch_pass(const PassPlan &plan, const PassArgs &a,
                        hipStream_t s) {
   dim3 grid(plan.grid), block(kThreads);
   const size_t lds = plan.lds_bytes;
-#define MNL_PASS_LAUNCH2(J, C, Z)                                             \
+#define MNL_PASS_LAUNCH3(J, C, Z, H)                                          \
   do {                                                                        \
     hipError_t e_ = raise_lds_limit(                                          \
-        reinterpret_cast<const void *>(&k_pass<J, C, Z>), (int)lds);          \
+        reinterpret_cast<const void *>(&k_pass<J, C, Z, H>), (int)lds);       \
     if (e_ != hipSuccess) return e_;                                          \
-    hipLaunchKernelGGL((k_pass<J, C, Z>), grid, block, lds, s, a,             \
+    hipLaunchKernelGGL((k_pass<J, C, Z, H>), grid, block, lds, s, a,          \
                        plan.stride);                                          \
+  } while (0)
+#define MNL_PASS_LAUNCH2(J, C, Z)                                             \
+  do {                                                                        \
+    if (a.Pin) MNL_PASS_LAUNCH3(J, C, Z, true);                               \
+    else MNL_PASS_LAUNCH3(J, C, Z, false);                                    \
   } while (0)
 #define MNL_PASS_LAUNCH(J, C)                                                 \
   do {                                                                        \
@@ -466,6 +537,7 @@ hipError_t launch_pass(const PassPlan &plan, const PassArgs &a,
 #undef MNL_PASS_CAP
 #undef MNL_PASS_LAUNCH
 #undef MNL_PASS_LAUNCH2
+#undef MNL_PASS_LAUNCH3
   return hipGetLastError();
 }
 
@@ -569,6 +641,92 @@ hipError_t launch_validate(const Dims &d, const double *X, const double *Y,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_validate, dim3((unsigned)((d.N + 255) / 256)),
                      dim3(256), 0, s, d, X, Y, Z, w, choice, flags);
+  return hipGetLastError();
+}
+
+// ---- truncated conjugate gradients (inexact Newton) ----------------------------
+
+namespace {
+// sum over threads of one workgroup of 1024, in a fixed tree order; every
+// thread returns the total
+__device__ inline double block_sum_1024(double v, double *red) {
+  const int t = threadIdx.x;
+  __syncthreads();   // red may still be read from a previous sum
+  red[t] = v;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// d = 0, r = p = g, scal[0] = g.g
+__global__ __launch_bounds__(1024) void k_cg_init(const double *g, double *d,
+                                                  double *r, double *p,
+                                                  int64_t n, double *scal) {
+  __shared__ double red[1024];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double gi = g[i];
+    d[i] = 0.0;
+    r[i] = gi;
+    p[i] = gi;
+    s = fma(gi, gi, s);
+  }
+  s = block_sum_1024(s, red);
+  if (threadIdx.x == 0) {
+    scal[0] = s;
+    scal[1] = 0.0;
+  }
+}
+
+// One conjugate-gradient step on (-H) d = g given Hp = H p:
+// pAp = p.(-H p); if pAp > 0: alpha = rr / pAp, d += alpha p,
+// r -= alpha (-H p), rr' = r.r, p = r + (rr' / rr) p.  scal[0] holds rr
+// (updated), scal[1] receives pAp (d, r, p untouched when pAp <= 0).
+__global__ __launch_bounds__(1024) void k_cg_update(const double *Hp,
+                                                    double *d, double *r,
+                                                    double *p, int64_t n,
+                                                    double *scal) {
+  __shared__ double red[1024];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) s = fma(p[i], -Hp[i], s);
+  const double pAp = block_sum_1024(s, red);
+  const double rr = scal[0];
+  if (!(pAp > 0.0)) {
+    if (threadIdx.x == 0) scal[1] = pAp;
+    return;   // uniform: every thread holds the same pAp
+  }
+  const double alpha = rr / pAp;
+  s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    d[i] = fma(alpha, p[i], d[i]);
+    const double ri = fma(alpha, Hp[i], r[i]);
+    r[i] = ri;
+    s = fma(ri, ri, s);
+  }
+  const double rr_new = block_sum_1024(s, red);
+  const double beta = rr_new / rr;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) p[i] = fma(beta, p[i], r[i]);
+  if (threadIdx.x == 0) {
+    scal[0] = rr_new;
+    scal[1] = pAp;
+  }
+}
+}  // namespace
+
+hipError_t launch_cg_init(const double *g, double *d, double *r, double *p,
+                          int64_t n, double *scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(1024), 0, s, g, d, r, p, n,
+                     scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(const double *Hp, double *d, double *r, double *p,
+                            int64_t n, double *scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update, dim3(1), dim3(1024), 0, s, Hp, d, r, p, n,
+                     scal);
   return hipGetLastError();
 }
 

@@ -155,7 +155,9 @@ int check_problem(Ctx *c, const mnl_problem *pr, Dims *d, bool need_choice) {
 int check_opts(Ctx *c, const mnl_fit_opts *o) {
   if (o->maxiter < 0 || o->ls_max < 0 || o->ls_max > 1000 ||
       !(o->gtol >= 0) || !(o->ftol >= 0) || !(o->ls_tol_ulps >= 0) ||
-      o->prec < MNL_PREC_FP64 || o->prec > MNL_PREC_BF16)
+      o->prec < MNL_PREC_FP64 || o->prec > MNL_PREC_BF16 ||
+      o->method < MNL_METHOD_NEWTON || o->method > MNL_METHOD_NEWTON_CG ||
+      o->cg_maxiter < 1)
     return set_error(c, MNL_ERR_ARG, "invalid fit options");
   return MNL_OK;
 }
@@ -299,12 +301,69 @@ int validate_data(Ctx *c, const Dims &d, const mnl_problem *pr,
   return MNL_OK;
 }
 
+// Inexact Newton direction (Sec. 6): truncated CG on (-H) d = g from d = 0
+// with Hessian-vector passes at the P of slot set `cur`; stops when
+// ||r|| <= eta ||g||, eta = min(1/2, sqrt(||g||)), after cg_maxiter
+// products, or at p^T (-H) p <= 0 (d = g when that happens first).  One
+// host round trip per product carries r.r and p^T (-H) p.
+int cg_direction(Ctx *c, const Dims &d, const mnl_problem *pr,
+                 const StepState &st, const mnl_fit_opts &o, double gnorm,
+                 double *delta, int *ncg, hipStream_t s) {
+  PassPlan plan;
+  int rc = pass_plan(d, &plan);
+  if (rc != MNL_OK)
+    return set_error(c, rc, "shape beyond the fused-pass limits");
+  void *cv, *partial, *Pv;
+  const int64_t n = d.np;
+  MNL_TRY(ws_get(c, S_CG, size_t(3 * n + 8) * 8, &cv));
+  MNL_TRY(ws_get(c, S_PARTIAL, size_t(plan.grid) * plan.stride * 8, &partial));
+  MNL_TRY(ws_get(c, st.cur ? S_P_TRIAL : S_P, size_t(d.N) * d.K * 8, &Pv));
+  double *r = (double *)cv, *p = r + n, *Hp = p + n, *scal = Hp + n;
+  const double *g = st.lg + 1;
+  MNL_HIP(c, launch_cg_init(g, delta, r, p, n, scal, s));
+  const double eta = std::min(0.5, std::sqrt(gnorm));
+  PassArgs A;
+  A.d = d;
+  A.X = pr->X;
+  A.Y = pr->Y;
+  A.Z = pr->Z;
+  A.w = pr->w;
+  A.choice = nullptr;
+  A.theta = p;
+  A.P = nullptr;
+  A.P32 = nullptr;
+  A.Ybar = nullptr;
+  A.partial = (double *)partial;
+  A.Pin = (const double *)Pv;
+  double rr = gnorm * gnorm;
+  int j = 0;
+  for (; j < o.cg_maxiter; ++j) {
+    if (j > 0 && std::sqrt(rr) <= eta * gnorm) break;
+    MNL_HIP(c, launch_pass(plan, A, s));
+    MNL_HIP(c, launch_pass_reduce(plan, (double *)partial, scal + 2, Hp, n, s));
+    MNL_HIP(c, launch_cg_update(Hp, delta, r, p, n, scal, s));
+    double h[2];
+    MNL_TRY(copy_d2h(c, h, scal, sizeof h, s));
+    rr = h[0];
+    if (!(h[1] > 0.0)) {
+      if (j == 0)
+        MNL_HIP(c, hipMemcpyAsync(delta, g, size_t(n) * 8,
+                                  hipMemcpyDeviceToDevice, s));
+      ++j;
+      break;
+    }
+  }
+  *ncg = j;
+  return MNL_OK;
+}
+
 // Core of one Newton iteration, given l and g at theta (in lg, P/Ybar in
 // slot set `cur`).  On an accepted step theta is updated in place and lg,
 // cur describe the new point.  Returns MNL_OK with *reason set.
 int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
                 const mnl_fit_opts &o, StepState &st, double l_old,
-                mnl_fit_info *info, int *reason, hipStream_t s) {
+                double gnorm, mnl_fit_info *info, int *reason,
+                hipStream_t s) {
   void *Hv, *dv, *tv, *sv;
   // n_p + 1 rows: the factorisation carries g as an extra row; 64 doubles
   // of padding let its kernels load whole panel rows unconditionally
@@ -334,7 +393,22 @@ int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
   int prec = o.prec;
   int32_t fail = 0;
   double sh[3] = {0.0, 0.0, 0.0};
-  for (int attempt = 0; attempt < 2; ++attempt) {
+  if (o.method == MNL_METHOD_NEWTON_CG) {
+    // inexact Newton: the inner solve's time is reported as t_hessian
+    int ncg = 0;
+    MNL_HIP(c, hipEventRecord(c->ev_q[0], s));
+    MNL_TRY(cg_direction(c, d, pr, st, o, gnorm, delta, &ncg, s));
+    info->cg_iters += ncg;
+    MNL_HIP(c, hipEventRecord(c->ev_q[2], s));
+    MNL_TRY(trial_at(1.0, nullptr));
+    MNL_HIP(c, hipEventRecord(c->ev_q[3], s));
+    MNL_TRY(copy_d2h(c, sh, sc, sizeof sh, s));
+    collect_timing(c, info);
+    info->t_hessian += event_ms(c->ev_q[0], c->ev_q[2]);
+    info->t_ls += event_ms(c->ev_q[2], c->ev_q[3]);
+  }
+  for (int attempt = 0; o.method == MNL_METHOD_NEWTON && attempt < 2;
+       ++attempt) {
     MNL_HIP(c, hipEventRecord(c->ev_q[0], s));
     MNL_TRY(form_hessian(c, d, pr, st.cur, prec, H, s));
     MNL_HIP(c, hipEventRecord(c->ev_q[1], s));
@@ -446,7 +520,8 @@ int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
     if (one_step && info->iters >= 1) break;
     int r = MNL_STOP_NONE;
     const double step_gnorm = gnorm;
-    MNL_TRY(newton_core(c, d, prob, theta, o, st, l, info, &r, s));
+    MNL_TRY(newton_core(c, d, prob, theta, o, st, l, step_gnorm, info, &r,
+                        s));
     if (r != MNL_STOP_NONE) {
       reason = r;
       if (one_step) info->grad_norm = step_gnorm;
@@ -490,6 +565,7 @@ int fit_workspace_footprint(Ctx *c, const Dims &d, int prec, size_t *bytes) {
   t += al(((np + 1) * np + 64) * 8);                    // S_H
   t += 2 * al(np * 8) + al(256);                        // delta, trial, scalars
   t += al(chol_workspace_bytes(int64_t(np)));           // Cholesky scratch
+  t += al((3 * np + 8) * 8);                            // inexact Newton
   // Hessian partials and tables; a mixed fit may redo the Hessian in FP64
   size_t part = 0, tab = 0;
   MNL_TRY(hessian_footprint(c, d, prec, &part, &tab));
@@ -537,6 +613,8 @@ void mnl_default_opts(mnl_fit_opts *o) {
   o->ls_max = 30;
   o->ls_tol_ulps = 64.0;
   o->validate = 0;
+  o->method = MNL_METHOD_NEWTON;
+  o->cg_maxiter = 250;
 }
 
 int64_t mnl_num_params(int32_t K, int32_t p, int32_t g, int32_t a) {
@@ -631,6 +709,47 @@ int mnl_hessian(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
   MNL_TRY(run_pass(c, d, prob, theta, (double *)lg, S_P, S_P32, S_YBAR,
                    prec != MNL_PREC_FP64, s));
   return form_hessian(c, d, prob, 0, prec, H, s);
+}
+
+int mnl_hessvec(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
+                const double *v, double *Hv, void *stream) {
+  if (!ctx) return MNL_ERR_ARG;
+  Ctx *c = &ctx->c;
+  Dims d;
+  MNL_TRY(check_problem(c, prob, &d, false));
+  if (!theta || !v || !Hv) return set_error(c, MNL_ERR_ARG, "NULL argument");
+  MNL_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  ++c->call_epoch;
+  PassPlan plan;
+  int rc = pass_plan(d, &plan);
+  if (rc != MNL_OK) return set_error(c, rc, "shape beyond pass limits");
+  void *lg, *Pv, *partial;
+  MNL_TRY(ws_get(c, S_LG, size_t(d.np + 1) * 8, &lg));
+  // P at theta (slot S_P), then the pass of v with P read back
+  MNL_TRY(run_pass(c, d, prob, theta, (double *)lg, S_P, S_P32, S_YBAR, false,
+                   s));
+  MNL_TRY(ws_get(c, S_P, size_t(d.N) * d.K * 8, &Pv));
+  MNL_TRY(ws_get(c, S_PARTIAL, size_t(plan.grid) * plan.stride * 8, &partial));
+  PassArgs A;
+  A.d = d;
+  A.X = prob->X;
+  A.Y = prob->Y;
+  A.Z = prob->Z;
+  A.w = prob->w;
+  A.choice = nullptr;
+  A.theta = v;
+  A.P = nullptr;
+  A.P32 = nullptr;
+  A.Ybar = nullptr;
+  A.partial = (double *)partial;
+  A.Pin = (const double *)Pv;
+  MNL_HIP(c, launch_pass(plan, A, s));
+  // l of this pass is meaningless: it goes to the scratch l slot
+  MNL_HIP(c, launch_pass_reduce(plan, (double *)partial, (double *)lg, Hv,
+                                d.np, s));
+  c->pass_pending = false;
+  return MNL_OK;
 }
 
 int mnl_predict(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,

@@ -108,6 +108,9 @@ struct PassArgs {
   float *P32;        // [N][K] f32 or null
   double *Ybar;      // [N][g] or null
   double *partial;   // [grid][stride]
+  // Hessian-vector mode when set: P [N][K] at the current theta, theta
+  // then holds v and the gradient rows sum to H v (l, P, Ybar not formed)
+  const double *Pin = nullptr;
 };
 
 hipError_t launch_pass(const PassPlan &plan, const PassArgs &a,
@@ -127,6 +130,13 @@ hipError_t launch_scalars(const double *lg, int64_t n, const int32_t *status,
                           double *out, hipStream_t s);
 hipError_t launch_sumsq(const double *x, int64_t n, double *out,
                         hipStream_t s);
+// Truncated CG on (-H) d = g (single workgroup each): init sets d = 0,
+// r = p = g, scal[0] = g.g; update takes Hp = H p and does one step,
+// scal[0] = r.r after it, scal[1] = p.(-H p) (no step when <= 0).
+hipError_t launch_cg_init(const double *g, double *d, double *r, double *p,
+                          int64_t n, double *scal, hipStream_t s);
+hipError_t launch_cg_update(const double *Hp, double *d, double *r, double *p,
+                            int64_t n, double *scal, hipStream_t s);
 // Flags [0]: choice out of range count, [1]: non-finite data count.
 hipError_t launch_validate(const Dims &d, const double *X, const double *Y,
                            const double *Z, const double *w,
@@ -250,6 +260,7 @@ enum Slot {
   S_CHOL,          // Cholesky scratch
   S_THETA0,        // zero start
   S_XX,            // X o X operand of the materialised beta-beta product
+  S_CG,            // inexact Newton: r, p, H p [np] each, scalars
   S_NSLOTS
 };
 
