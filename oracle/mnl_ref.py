@@ -40,6 +40,11 @@ Readings taken where the paper is silent (all also used by the GPU path):
     with relative residual eta = min(1/2, sqrt(||g||)), at most cg_maxiter
     Hessian-vector products, and d = g when the first search direction
     shows non-positive curvature; line search and stop rules are Newton's.
+  * the collinearity check follows App. B's necessary conditions with a
+    column-order QR at tolerance linDepTol (default 1e-6): X and every Z_k
+    must have full column rank, the differenced generic data stacked over
+    alternatives too; a dependent Z variable is dropped for every
+    alternative (coefficient chunks have one length).
 """
 from __future__ import annotations
 
@@ -462,3 +467,46 @@ def summary(theta, X, Y, Z, w=None, H=None):
     z = theta / se
     pval = np.array([math.erfc(abs(v) / math.sqrt(2.0)) for v in z])
     return se, z, pval
+
+
+# ---- collinearity check (Sec. 2.3 linDepTol, App. B) -------------------------
+
+def independent_columns(M, tol=1e-6):
+    """Columns of M [rows, n] kept by a column-order QR with tolerance tol
+    (R's qr as mnlogit calls it with linDepTol): column j is dropped when
+    the norm of its part orthogonal to the kept columns before it is below
+    tol times its own norm (a zero column is always dropped).  Gram-Schmidt
+    with a second orthogonalisation pass.  Returns a boolean mask [n]."""
+    M = np.asarray(M, dtype=np.float64)
+    keep = np.zeros(M.shape[1], dtype=bool)
+    Q = []
+    for j in range(M.shape[1]):
+        col = M[:, j]
+        nrm = float(np.linalg.norm(col))
+        r = col.copy()
+        for _ in range(2):
+            for q in Q:
+                r = r - (q @ r) * q
+        res = float(np.linalg.norm(r))
+        if nrm > 0.0 and res >= tol * nrm:
+            keep[j] = True
+            Q.append(r / res)
+    return keep
+
+
+def collinearity_mask(X, Y, Z, tol=1e-6):
+    """Variables kept so that App. B's necessary conditions for a
+    non-singular Hessian hold: X and every Z_k of full column rank, and the
+    differenced generic data Ytil_k (k >= 1) stacked over alternatives of
+    full column rank.  A Z variable is dropped if it is dependent in any
+    alternative (its coefficients gamma_kc go for every k).  Returns boolean
+    masks (keep_x [p], keep_y [g], keep_z [a])."""
+    N, K = Y.shape[0], Y.shape[1]
+    g, a = Y.shape[2], Z.shape[2]
+    keep_x = independent_columns(X, tol)
+    keep_z = np.ones(a, dtype=bool)
+    for k in range(K):
+        keep_z &= independent_columns(Z[:, k, :], tol)
+    Yt = differenced_generic(Y)[:, 1:, :].reshape(N * (K - 1), g)
+    keep_y = independent_columns(Yt, tol)
+    return keep_x, keep_y, keep_z

@@ -690,3 +690,55 @@ def test_newton_cg_binary_equals_irls():
                                               method="newton-cg"))
     b = irls_binary(pr.X, (pr.choice == 1).astype(float), pr.w)
     np.testing.assert_allclose(res.theta, b, rtol=0, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# collinearity check (linDepTol, App. B)
+
+def test_independent_columns_exact_dependencies():
+    rng = np.random.default_rng(21)
+    M = rng.normal(size=(200, 6))
+    assert R.independent_columns(M).all()
+    M[:, 3] = 2.0 * M[:, 0] - M[:, 1]       # in the span of earlier columns
+    M[:, 5] = 0.0                           # zero column
+    np.testing.assert_array_equal(R.independent_columns(M),
+                                  [1, 1, 1, 0, 1, 0])
+    # a column spanned by later columns is kept; the first column that
+    # closes the dependent set goes
+    M2 = rng.normal(size=(100, 3))
+    M2 = np.column_stack([M2[:, 0] + M2[:, 1], M2])
+    np.testing.assert_array_equal(R.independent_columns(M2), [1, 1, 0, 1])
+
+
+def test_independent_columns_rank_and_tolerance():
+    rng = np.random.default_rng(22)
+    B = rng.normal(size=(300, 4))
+    M = np.column_stack([B, B @ rng.normal(size=(4, 3))])
+    keep = R.independent_columns(M)
+    assert keep.sum() == np.linalg.matrix_rank(M) == 4
+    # a perturbation far above tol keeps the column, far below drops it
+    for eps, kept in ((1e-3, True), (1e-9, False)):
+        C = np.column_stack([B, B[:, 0] + eps * rng.normal(size=300)])
+        assert R.independent_columns(C, 1e-6)[4] == kept
+
+
+def test_collinearity_mask_app_b_generic_constant():
+    # generic data equal over alternatives: Ytil = 0, every alpha dropped,
+    # and the fit on the remaining data converges where it was singular
+    pr = synth.make_problem(500, 4, 2, 2, 1, seed=18)
+    pr.Y = np.ascontiguousarray(np.repeat(pr.Y[:, :1, :], 4, axis=1))
+    kx, ky, kz = R.collinearity_mask(pr.X, pr.Y, pr.Z)
+    assert kx.all() and kz.all() and not ky.any()
+    bad = R.fit_problem(pr, opts=R.FitOptions(gtol=1e-8, ftol=0))
+    assert bad.stop_reason == R.STOP_NOT_PD
+    ok = R.fit(pr.X[:, kx], pr.Y[:, :, ky], pr.Z[:, :, kz], pr.choice, pr.w,
+               opts=R.FitOptions(gtol=1e-8, ftol=0))
+    assert ok.stop_reason == R.STOP_GTOL
+
+
+def test_collinearity_mask_z_dependent_in_one_alternative():
+    pr = synth.make_problem(300, 3, 2, 0, 3, seed=23)
+    pr.Z[:, 1, 2] = pr.Z[:, 1, 0] - 3.0 * pr.Z[:, 1, 1]
+    kx, ky, kz = R.collinearity_mask(pr.X, pr.Y, pr.Z)
+    np.testing.assert_array_equal(kz, [1, 1, 0])
+    assert kx.all() and ky.size == 0
