@@ -74,10 +74,11 @@ def predict_bytes(pr):
 
 
 def fitted_methods(ctx, pr, dp, theta, reps=5):
-    """Time predict (one fused pass without choices) and the summary's
-    standard errors (FP64 Hessian + factorisation with identity rows) at
-    the fitted theta; compare the standard errors with the oracle's
-    recorded table when one exists for this workload."""
+    """Time the collinearity check (Gram products and ordered
+    elimination), predict (one fused pass without choices) and the
+    summary's standard errors (FP64 Hessian + factorisation with identity
+    rows) at the fitted theta; compare the standard errors with the
+    oracle's recorded table when one exists for this workload."""
     import numpy as np
     import torch
 
@@ -101,7 +102,15 @@ def fitted_methods(ctx, pr, dp, theta, reps=5):
         se = ctx.summary(dq, theta)[0]
     torch.cuda.synchronize()
     sms = (time.perf_counter() - t0) / reps * 1e3
-    out = {"predict": {"ms": pms, "bytes": predict_bytes(pr),
+    ctx.collinear(dq)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        keep = ctx.collinear(dq)
+    cms = (time.perf_counter() - t0) / reps * 1e3
+    out = {"collinear": {"ms": cms, "kept": [int(k.sum()) for k in keep],
+                         "of": [pr.p, pr.g, pr.a]},
+           "predict": {"ms": pms, "bytes": predict_bytes(pr),
                        "achieved_gbps": predict_bytes(pr) / pms * 1e-6,
                        "peak_gbps": HBM_GBPS,
                        "frac": predict_bytes(pr) / pms * 1e-6 / HBM_GBPS},

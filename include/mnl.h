@@ -238,6 +238,43 @@ int mnl_fit(mnl_ctx *ctx, const mnl_problem *prob, const double *theta0,
 int mnl_hessvec(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
                 const double *v, double *Hv, void *stream);
 
+/* ---- Collinearity check (Sec. 2.3 linDepTol, App. B) ---------------------- */
+
+/* Variables to keep so that App. B's necessary conditions for a
+ * non-singular Hessian hold: X and every Z_k = Z[:, k, :] of full column
+ * rank, and the differenced generic data Y_k - Y_0 (k >= 1) stacked over
+ * alternatives of full column rank.  Within each matrix the columns are
+ * taken in order and column j is dropped when its part orthogonal to the
+ * kept columns before it has norm below tol times its own norm (mnlogit's
+ * qr with tol = linDepTol, default 1e-6); a zero column is dropped.  A Z
+ * variable dependent in any alternative is dropped for all.  Computed on
+ * Gram matrices (library GEMMs over the observations, then an ordered
+ * elimination on the device), which agrees with QR while the kept columns'
+ * condition number squared times eps stays well below tol^2.
+ * prob->choice is not read (may be NULL).
+ *   tol      in [0, 1).
+ *   keep_x   [p] host int32, output: 1 keep, 0 drop (NULL iff p == 0).
+ *   keep_y   [g] host int32, output (NULL iff g == 0).
+ *   keep_z   [a] host int32, output (NULL iff a == 0).
+ * At most 1024 columns per kind (MNL_ERR_UNSUPPORTED).  The workspace
+ * takes N (K-1) g doubles for the differenced data.  Synchronises
+ * `stream`. */
+int mnl_collinear(mnl_ctx *ctx, const mnl_problem *prob, double tol,
+                  int32_t *keep_x, int32_t *keep_y, int32_t *keep_z,
+                  void *stream);
+
+/* Copies of the data with only the kept columns (flags as mnl_collinear
+ * returns them, host int32):
+ *   X_out  [N][p'] device, Y_out [N][K][g'], Z_out [N][K][a'], p', g', a'
+ *          the kept counts; an output may be NULL when its count is 0.
+ * The reduced problem fits theta' of n_p' = (K-1) p' + K a' + g'
+ * coefficients, those of the dropped variables being absent.
+ * Asynchronous on `stream` (the selection indices are copied first). */
+int mnl_select_columns(mnl_ctx *ctx, const mnl_problem *prob,
+                       const int32_t *keep_x, const int32_t *keep_y,
+                       const int32_t *keep_z, double *X_out, double *Y_out,
+                       double *Z_out, void *stream);
+
 /* ---- Fitted-model methods (Sec. 2.3: summary and predict) ----------------- */
 
 /* Choice probabilities on (new) data at theta: Eqs. 3-4 at the utilities of

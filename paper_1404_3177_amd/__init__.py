@@ -188,6 +188,39 @@ class Context:
         return theta, info.as_dict()
 
 
+    def collinear(self, prob: Problem, tol: float = 1e-6, stream=None):
+        """Keep masks (numpy bool) of the X, Y and Z variables."""
+        import numpy as np
+        ks = [np.zeros(n, dtype=np.int32) for n in (prob.p, prob.g, prob.a)]
+        self._check(self.lib.mnl_collinear(
+            self.h, ctypes.byref(prob.c), float(tol),
+            *[k.ctypes.data if k.size else None for k in ks],
+            _stream_handle(stream)))
+        return tuple(k.astype(bool) for k in ks)
+
+    def select_columns(self, prob: Problem, keep_x, keep_y, keep_z,
+                       stream=None) -> "Problem":
+        """A new device Problem holding only the kept columns (same
+        choices and weights)."""
+        import numpy as np
+        import torch
+        ks = [np.ascontiguousarray(k, dtype=np.int32)
+              for k in (keep_x, keep_y, keep_z)]
+        px, py, pz = (int(k.sum()) for k in ks)
+        dev = prob.device
+        N, K = prob.N, prob.K
+        Xo = torch.empty(N, px, dtype=torch.float64, device=dev)
+        Yo = torch.empty(N, K, py, dtype=torch.float64, device=dev)
+        Zo = torch.empty(N, K, pz, dtype=torch.float64, device=dev)
+        self._check(self.lib.mnl_select_columns(
+            self.h, ctypes.byref(prob.c),
+            *[k.ctypes.data if k.size else None for k in ks],
+            Xo.data_ptr() if px else None, Yo.data_ptr() if py else None,
+            Zo.data_ptr() if pz else None, _stream_handle(stream)))
+        # the host masks are read before the call returns
+        _, _, _, choice, w = prob._refs
+        return Problem(Xo, Yo, Zo, choice, w)
+
     def hessvec(self, prob: Problem, theta, v, stream=None):
         """H(theta) v (device tensor, Hessian sign) without forming H."""
         import torch

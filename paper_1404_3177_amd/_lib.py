@@ -29,7 +29,8 @@ EXPORTS = [
     "mnl_version", "mnl_strerror", "mnl_default_opts", "mnl_num_params",
     "mnl_create", "mnl_destroy", "mnl_workspace_bytes", "mnl_last_error",
     "mnl_loglik_grad", "mnl_hessian", "mnl_newton_step", "mnl_fit",
-    "mnl_hessvec", "mnl_predict", "mnl_stderr", "mnl_fit_footprint", "mnl_server_now_ms", "mnl_server_create",
+    "mnl_hessvec", "mnl_collinear", "mnl_select_columns", "mnl_predict",
+    "mnl_stderr", "mnl_fit_footprint", "mnl_server_now_ms", "mnl_server_create",
     "mnl_server_destroy", "mnl_server_submit", "mnl_server_wait",
     "mnl_server_get_stats",
 ]
@@ -137,6 +138,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mnl_fit.argtypes = [P, prob, P, ctypes.POINTER(MnlFitOpts), P,
                             ctypes.POINTER(MnlFitInfo), P]
     lib.mnl_hessvec.argtypes = [P, prob, P, P, P, P]
+    lib.mnl_collinear.argtypes = [P, prob, ctypes.c_double, P, P, P, P]
+    lib.mnl_select_columns.argtypes = [P, prob, P, P, P, P, P, P, P]
     lib.mnl_predict.argtypes = [P, prob, P, P, P]
     lib.mnl_stderr.argtypes = [P, prob, P, P, P, P, P]
     lib.mnl_fit_footprint.argtypes = [prob, I32]
@@ -155,6 +158,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mnl_server_get_stats.argtypes = [P, ctypes.POINTER(MnlServerStats)]
     for name in ("mnl_create", "mnl_loglik_grad", "mnl_hessian",
                  "mnl_newton_step", "mnl_fit", "mnl_hessvec", "mnl_predict",
+                 "mnl_collinear", "mnl_select_columns",
                  "mnl_stderr",
                  "mnl_server_create",
                  "mnl_server_submit", "mnl_server_wait",

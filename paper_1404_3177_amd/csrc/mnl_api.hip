@@ -752,6 +752,38 @@ int mnl_hessvec(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
   return MNL_OK;
 }
 
+int mnl_collinear(mnl_ctx *ctx, const mnl_problem *prob, double tol,
+                  int32_t *keep_x, int32_t *keep_y, int32_t *keep_z,
+                  void *stream) {
+  if (!ctx) return MNL_ERR_ARG;
+  Ctx *c = &ctx->c;
+  Dims d;
+  MNL_TRY(check_problem(c, prob, &d, false));
+  if (!(tol >= 0.0) || !(tol < 1.0))
+    return set_error(c, MNL_ERR_ARG, "tol must lie in [0, 1)");
+  if ((d.p && !keep_x) || (d.g && !keep_y) || (d.a && !keep_z))
+    return set_error(c, MNL_ERR_ARG, "NULL keep array");
+  MNL_HIP(c, hipSetDevice(c->device));
+  ++c->call_epoch;
+  return collinear_run(c, d, prob, tol, keep_x, keep_y, keep_z,
+                       (hipStream_t)stream);
+}
+
+int mnl_select_columns(mnl_ctx *ctx, const mnl_problem *prob,
+                       const int32_t *keep_x, const int32_t *keep_y,
+                       const int32_t *keep_z, double *X_out, double *Y_out,
+                       double *Z_out, void *stream) {
+  if (!ctx) return MNL_ERR_ARG;
+  Ctx *c = &ctx->c;
+  Dims d;
+  MNL_TRY(check_problem(c, prob, &d, false));
+  if ((d.p && !keep_x) || (d.g && !keep_y) || (d.a && !keep_z))
+    return set_error(c, MNL_ERR_ARG, "NULL keep array");
+  MNL_HIP(c, hipSetDevice(c->device));
+  return select_columns_run(c, d, prob, keep_x, keep_y, keep_z, X_out, Y_out,
+                            Z_out, (hipStream_t)stream);
+}
+
 int mnl_predict(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
                 double *P, void *stream) {
   if (!ctx) return MNL_ERR_ARG;

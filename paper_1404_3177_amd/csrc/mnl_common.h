@@ -186,6 +186,20 @@ hipError_t launch_inv_diag(const double *A, int64_t n, const double *theta,
                            double *se, double *z, double *pval,
                            const int32_t *info, hipStream_t s);
 
+// ---- collinearity check -------------------------------------------------------
+// Keep flags (host int32, 1 = keep) of the X, Y and Z variables: column-order
+// selection at tolerance tol on X, each Z_k (a Z variable must pass for every
+// k) and the differenced generic data stacked over alternatives.
+// Synchronises s.
+int collinear_run(Ctx *c, const Dims &d, const mnl_problem *pr, double tol,
+                  int32_t *keep_x, int32_t *keep_y, int32_t *keep_z,
+                  hipStream_t s);
+// Copies of X, Y, Z with only the kept columns (device outputs).
+int select_columns_run(Ctx *c, const Dims &d, const mnl_problem *pr,
+                       const int32_t *keep_x, const int32_t *keep_y,
+                       const int32_t *keep_z, double *X_out, double *Y_out,
+                       double *Z_out, hipStream_t s);
+
 // Context ---------------------------------------------------------------------
 struct Ctx {
   int device = 0;
@@ -261,6 +275,7 @@ enum Slot {
   S_THETA0,        // zero start
   S_XX,            // X o X operand of the materialised beta-beta product
   S_CG,            // inexact Newton: r, p, H p [np] each, scalars
+  S_COLLIN,        // collinearity check: Gram matrices, masks, indices
   S_NSLOTS
 };
 
