@@ -45,6 +45,9 @@ Readings taken where the paper is silent (all also used by the GPU path):
     must have full column rank, the differenced generic data stacked over
     alternatives too; a dependent Z variable is dropped for every
     alternative (coefficient chunks have one length).
+  * hypothesis tests are the textbook likelihood-ratio, Wald, Rao score and
+    Hausman-McFadden statistics with chi-square p-values; the score test is
+    taken at the restricted estimate embedded in the full model.
 """
 from __future__ import annotations
 
@@ -510,3 +513,44 @@ def collinearity_mask(X, Y, Z, tol=1e-6):
     Yt = differenced_generic(Y)[:, 1:, :].reshape(N * (K - 1), g)
     keep_y = independent_columns(Yt, tol)
     return keep_x, keep_y, keep_z
+
+
+# ---- hypothesis tests (Sec. 2.3: lrtest, waldtest, scoretest, hmftest) -------
+
+def chi2_sf(x, df):
+    """Upper tail of the chi-square distribution with df degrees of
+    freedom (scipy)."""
+    import scipy.stats
+    return float(scipy.stats.chi2.sf(x, df))
+
+
+def lr_test(l_full, l_restricted, df):
+    """Likelihood-ratio statistic 2 (l_full - l_restricted), df and its
+    chi-square p-value."""
+    stat = 2.0 * (l_full - l_restricted)
+    return stat, df, chi2_sf(stat, df)
+
+
+def wald_test(theta, V, idx):
+    """Wald statistic of theta_S = 0 for the coefficients idx:
+    theta_S^T (V_SS)^{-1} theta_S with V the estimate's covariance."""
+    idx = np.asarray(idx)
+    t = np.asarray(theta, dtype=np.float64)[idx]
+    stat = float(t @ np.linalg.solve(V[np.ix_(idx, idx)], t))
+    return stat, idx.size, chi2_sf(stat, idx.size)
+
+
+def score_test(grad, H, df):
+    """Rao score statistic g^T (-H)^{-1} g of the full model at the
+    restricted estimate (restricted coefficients at zero)."""
+    stat = float(grad @ np.linalg.solve(-H, grad))
+    return stat, df, chi2_sf(stat, df)
+
+
+def hm_test(theta_sub, V_sub, theta_full, V_full):
+    """Hausman-McFadden statistic for IIA on the coefficients common to a
+    fit on a subset of alternatives and the full fit:
+    d^T (V_sub - V_full)^{-1} d, d = theta_sub - theta_full."""
+    d = np.asarray(theta_sub) - np.asarray(theta_full)
+    stat = float(d @ np.linalg.solve(V_sub - V_full, d))
+    return stat, d.size, chi2_sf(stat, d.size)

@@ -742,3 +742,72 @@ def test_collinearity_mask_z_dependent_in_one_alternative():
     kx, ky, kz = R.collinearity_mask(pr.X, pr.Y, pr.Z)
     np.testing.assert_array_equal(kz, [1, 1, 0])
     assert kx.all() and ky.size == 0
+
+
+# ---------------------------------------------------------------------------
+# hypothesis tests (Sec. 2.3)
+
+def _two_by_two(seed):
+    rng = np.random.default_rng(seed)
+    N = 1200
+    x = (rng.random(N) < 0.4).astype(float)
+    y = (rng.random(N) < 0.25 + 0.15 * x).astype(np.int32)
+    X1 = np.column_stack([np.ones(N), x])
+    E = np.zeros((N, 2, 0))
+    return X1, E, y, x
+
+
+def test_score_and_lr_tests_in_a_two_by_two_table():
+    # binary logit with one binary covariate against the intercept-only
+    # model: the score statistic is Pearson's chi-square of the 2 x 2 table
+    # and the likelihood ratio is the G statistic 2 sum O log(O / E)
+    X1, E, y, x = _two_by_two(41)
+    opts = R.FitOptions(gtol=1e-11, ftol=0.0)
+    full = R.fit(X1, E, E, y, None, opts=opts)
+    rest = R.fit(X1[:, :1], E, E, y, None, opts=opts)
+    th0 = np.array([rest.theta[0], 0.0])
+    g = R.gradient(th0, X1, E, E, y)
+    H = R.hessian(th0, X1, E, E, y)
+    O = np.array([[np.sum((x == a) & (y == b)) for b in (0, 1)]
+                  for a in (0, 1)], dtype=float)
+    Ex = O.sum(1, keepdims=True) * O.sum(0, keepdims=True) / O.sum()
+    pearson = float(((O - Ex) ** 2 / Ex).sum())
+    gstat = float(2.0 * (O * np.log(O / Ex)).sum())
+    s, df, p = R.score_test(g, H, 1)
+    assert s == pytest.approx(pearson, rel=1e-9) and df == 1
+    lr, _, plr = R.lr_test(full.loglik, rest.loglik, 1)
+    assert lr == pytest.approx(gstat, rel=1e-9)
+    assert p == pytest.approx(math.erfc(math.sqrt(s / 2.0)), rel=1e-12)
+
+
+def test_wald_single_coefficient_is_z_squared():
+    pr = tiny(42, N=400, K=3, p=2, g=1, a=1)
+    res = R.fit_problem(pr, opts=R.FitOptions(gtol=1e-10, ftol=0.0))
+    V = R.covariance(res.theta, pr.X, pr.Y, pr.Z, pr.w)
+    se, z, pv = R.summary(res.theta, pr.X, pr.Y, pr.Z, pr.w)
+    for j in (0, 3, pr.n_params - 1):
+        w, df, p = R.wald_test(res.theta, V, [j])
+        assert w == pytest.approx(z[j] ** 2, rel=1e-12) and df == 1
+        assert p == pytest.approx(pv[j], rel=1e-9)
+
+
+def test_score_test_vanishes_at_the_optimum_and_chi2_closed_form():
+    pr = tiny(43, N=300, K=3, p=2, g=1, a=0)
+    res = R.fit_problem(pr, opts=R.FitOptions(gtol=1e-12, ftol=0.0))
+    H = R.hessian(res.theta, pr.X, pr.Y, pr.Z, None, pr.w)
+    s, _, p = R.score_test(res.grad, H, 2)
+    assert s < 1e-20 and p == pytest.approx(1.0)
+    for x in (0.1, 1.0, 7.5):
+        assert R.chi2_sf(x, 2) == pytest.approx(math.exp(-x / 2), rel=1e-14)
+
+
+def test_hm_test_identical_fits_and_definition():
+    pr = tiny(44, N=400, K=4, p=2, g=0, a=0)
+    res = R.fit_problem(pr, opts=R.FitOptions(gtol=1e-10, ftol=0.0))
+    V = R.covariance(res.theta, pr.X, pr.Y, pr.Z, pr.w)
+    d = np.array([0.1, -0.2])
+    Vd = np.array([[0.02, 0.005], [0.005, 0.03]])
+    s, df, _ = R.hm_test(res.theta[:2] + d, V[:2, :2] + Vd, res.theta[:2],
+                         V[:2, :2])
+    assert s == pytest.approx(float(d @ np.linalg.inv(Vd) @ d), rel=1e-12)
+    assert df == 2
