@@ -301,6 +301,46 @@ int mnl_predict(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
 int mnl_stderr(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
                double *se, double *zval, double *pval, void *stream);
 
+/* ---- Hypothesis tests (Sec. 2.3: lrtest, waldtest, scoretest, hmftest) ---
+ * The statistics are quadratic forms in the estimate's covariance or the
+ * Hessian; these three calls supply them (the likelihood ratio needs only
+ * the two fits' log-likelihoods). */
+
+/* Covariance of the estimate, (-H)^{-1} at theta (FP64 Hessian of Eq. 10),
+ * restricted to the coefficients idx:
+ *   idx   [nidx] host int32, coefficient indices in Eq. 8 order; NULL with
+ *         nidx == 0 means all n_p coefficients in order.
+ *   V     [s][s] device, output, s = nidx (or n_p); V[a][b] =
+ *         ((-H)^{-1})[idx[a]][idx[b]], exactly symmetric.
+ * One FP64 Hessian and one factorisation with identity rows (as
+ * mnl_stderr).  MNL_ERR_NOT_PD when -H fails the pivot test; MNL_ERR_ARG
+ * for an index outside [0, n_p).  prob->choice is not read.  Synchronises
+ * `stream`. */
+int mnl_covariance(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
+                   const int32_t *idx, int32_t nidx, double *V,
+                   void *stream);
+
+/* Quadratic form d^T M^{-1} d with M = A - B and d = x - x0 (B and x0
+ * optional) for a symmetric positive definite M, through M's L D L^T
+ * factor (d rides along as an extra row: sum_k y_k^2 D_k with
+ * y = D^{-1} L^{-1} d).  With hessian_sign != 0, M is negative definite
+ * (a Hessian as mnl_hessian returns it) and the form is d^T (-M)^{-1} d:
+ * the score statistic for M = H, d = g.  The Wald statistic is
+ * theta_S^T V_SS^{-1} theta_S; the Hausman-McFadden statistic takes
+ * A = V_subset, B = V_full, x = theta_subset, x0 = theta_full.
+ *   A, B   [n][n] device, inputs (not modified; lower triangles read).
+ *   x, x0  [n] device, inputs.
+ *   out    host, output.
+ * MNL_ERR_NOT_PD when a pivot is at or below n eps max_k M_kk.
+ * Synchronises `stream`. */
+int mnl_quadform(mnl_ctx *ctx, const double *A, const double *B,
+                 const double *x, const double *x0, int64_t n,
+                 int32_t hessian_sign, double *out, void *stream);
+
+/* Upper tail P(chi^2_df > x) of the chi-square distribution (host):
+ * the p-value of the test statistics above.  NaN for df <= 0. */
+double mnl_chi2_sf(double x, double df);
+
 /* ---- Serving: continuous batching of independent fits -------------------
  *
  * A server runs many fits at once on one device.  Requests arrive with

@@ -26,11 +26,16 @@ from ._lib import (METHOD, MnlError, MnlFitInfo, MnlFitOpts,  # noqa
                    STOP_NONE, STOP_NONFINITE, STOP_NOT_PD)
 
 __all__ = ["Context", "Problem", "HostProblem", "Server", "num_params",
-           "default_opts", "fit_footprint", "MnlError"]
+           "default_opts", "fit_footprint", "chi2_sf", "MnlError"]
 
 
 def num_params(K: int, p: int, g: int, a: int) -> int:
     return int(_lib.load().mnl_num_params(K, p, g, a))
+
+
+def chi2_sf(x: float, df: float) -> float:
+    """Upper tail of the chi-square distribution (the library's)."""
+    return float(_lib.load().mnl_chi2_sf(float(x), float(df)))
 
 
 def default_opts() -> dict:
@@ -220,6 +225,34 @@ class Context:
         # the host masks are read before the call returns
         _, _, _, choice, w = prob._refs
         return Problem(Xo, Yo, Zo, choice, w)
+
+    def covariance(self, prob: Problem, theta, idx=None, stream=None):
+        """(-H)^{-1} at theta restricted to the coefficients idx (all if
+        None): a device tensor [s, s]."""
+        import numpy as np
+        import torch
+        n = prob.n_params
+        sel = None if idx is None else np.ascontiguousarray(idx, np.int32)
+        s = n if sel is None else sel.size
+        V = torch.empty(s, s, dtype=torch.float64, device=prob.device)
+        self._check(self.lib.mnl_covariance(
+            self.h, ctypes.byref(prob.c), theta.data_ptr(),
+            sel.ctypes.data if sel is not None else None,
+            0 if sel is None else s, V.data_ptr(), _stream_handle(stream)))
+        return V
+
+    def quadform(self, A, x, B=None, x0=None, hessian_sign: bool = False,
+                 stream=None) -> float:
+        """d^T (A - B)^{-1} d with d = x - x0 (B, x0 optional) for a
+        symmetric positive definite A - B on the device (d^T (B - A)^{-1} d
+        when hessian_sign)."""
+        out = ctypes.c_double()
+        ts = [None if t is None else t.contiguous() for t in (A, B, x, x0)]
+        self._check(self.lib.mnl_quadform(
+            self.h, *[t.data_ptr() if t is not None else None for t in ts],
+            int(x.numel()), 1 if hessian_sign else 0, ctypes.byref(out),
+            _stream_handle(stream)))
+        return out.value
 
     def hessvec(self, prob: Problem, theta, v, stream=None):
         """H(theta) v (device tensor, Hessian sign) without forming H."""

@@ -30,7 +30,8 @@ EXPORTS = [
     "mnl_create", "mnl_destroy", "mnl_workspace_bytes", "mnl_last_error",
     "mnl_loglik_grad", "mnl_hessian", "mnl_newton_step", "mnl_fit",
     "mnl_hessvec", "mnl_collinear", "mnl_select_columns", "mnl_predict",
-    "mnl_stderr", "mnl_fit_footprint", "mnl_server_now_ms", "mnl_server_create",
+    "mnl_stderr", "mnl_covariance", "mnl_quadform", "mnl_chi2_sf",
+    "mnl_fit_footprint", "mnl_server_now_ms", "mnl_server_create",
     "mnl_server_destroy", "mnl_server_submit", "mnl_server_wait",
     "mnl_server_get_stats",
 ]
@@ -139,6 +140,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                             ctypes.POINTER(MnlFitInfo), P]
     lib.mnl_hessvec.argtypes = [P, prob, P, P, P, P]
     lib.mnl_collinear.argtypes = [P, prob, ctypes.c_double, P, P, P, P]
+    lib.mnl_covariance.argtypes = [P, prob, P, P, I32, P, P]
+    lib.mnl_quadform.argtypes = [P, P, P, P, P, I64, I32,
+                                 ctypes.POINTER(ctypes.c_double), P]
+    lib.mnl_chi2_sf.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.mnl_chi2_sf.restype = ctypes.c_double
     lib.mnl_select_columns.argtypes = [P, prob, P, P, P, P, P, P, P]
     lib.mnl_predict.argtypes = [P, prob, P, P, P]
     lib.mnl_stderr.argtypes = [P, prob, P, P, P, P, P]
@@ -158,7 +164,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mnl_server_get_stats.argtypes = [P, ctypes.POINTER(MnlServerStats)]
     for name in ("mnl_create", "mnl_loglik_grad", "mnl_hessian",
                  "mnl_newton_step", "mnl_fit", "mnl_hessvec", "mnl_predict",
-                 "mnl_collinear", "mnl_select_columns",
+                 "mnl_collinear", "mnl_select_columns", "mnl_covariance",
+                 "mnl_quadform",
                  "mnl_stderr",
                  "mnl_server_create",
                  "mnl_server_submit", "mnl_server_wait",

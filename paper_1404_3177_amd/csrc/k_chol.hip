@@ -387,6 +387,71 @@ __global__ __launch_bounds__(256) void k_inv_diag(const double *A, int64_t n,
   }
 }
 
+// Covariance entries from the augmented factor: V[a][b] =
+// sum_k X[ia][k] X[ib][k] D_k over k >= max(ia, ib) (X = L^{-T} D^{-1}
+// upper triangular), one wave per entry; the products commute, so
+// V[a][b] and V[b][a] are bitwise equal.
+__global__ __launch_bounds__(256) void k_cov_sub(const double *A, int64_t n,
+                                                 const int32_t *idx, int s,
+                                                 double *V,
+                                                 const int32_t *info) {
+  if (info[0]) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t e = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (e >= int64_t(s) * s) return;
+  const int a = int(e / s), b = int(e - int64_t(a) * s);
+  const int64_t ia = idx[a], ib = idx[b];
+  const double *xa = A + (n + 1 + ia) * n, *xb = A + (n + 1 + ib) * n;
+  double v = 0.0;
+  for (int64_t k = (ia > ib ? ia : ib) + lane; k < n; k += 64)
+    v = fma(xa[k] * xb[k], A[k * (n + 1)], v);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) V[e] = v;
+}
+
+// out = sgn (A - B) for n x n matrices (B optional), then the vector
+// x - x0 (x0 optional) into out[n^2 ..] (the g row of the buffer)
+__global__ __launch_bounds__(256) void k_signed_copy(const double *A,
+                                                     const double *B,
+                                                     const double *x,
+                                                     const double *x0,
+                                                     double sgn, int64_t n,
+                                                     double *out) {
+  const int64_t cnt = n * n;
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < cnt + n;
+       e += int64_t(gridDim.x) * 256) {
+    if (e < cnt) {
+      out[e] = sgn * (B ? A[e] - B[e] : A[e]);
+    } else {
+      const int64_t j = e - cnt;
+      out[e] = x0 ? x[j] - x0[j] : x[j];
+    }
+  }
+}
+
+// x^T A^{-1} x = sum_k D_k y_k^2 with y = D^{-1} L^{-1} x the factor's g
+// row; one workgroup, fixed-order tree
+__global__ __launch_bounds__(256) void k_quad(const double *A, int64_t n,
+                                              double *out,
+                                              const int32_t *info) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  double v = 0.0;
+  if (!info[0])
+    for (int64_t k = t; k < n; k += 256) {
+      const double y = A[n * n + k];
+      v = fma(y * y, A[k * (n + 1)], v);
+    }
+  red[t] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) out[0] = red[0];
+}
+
 __device__ inline double readlane_f64(double v, int l) {
   const uint64_t u = __builtin_bit_cast(uint64_t, v);
   const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l);
@@ -557,6 +622,31 @@ int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
   }
   MNL_HIP(c, hipGetLastError());
   return MNL_OK;
+}
+
+hipError_t launch_cov_sub(const double *A, int64_t n, const int32_t *idx,
+                          int s, double *V, const int32_t *info,
+                          hipStream_t st) {
+  const int64_t waves = int64_t(s) * s;
+  hipLaunchKernelGGL(k_cov_sub, dim3((unsigned)((waves + 3) / 4)), dim3(256),
+                     0, st, A, n, idx, s, V, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_signed_copy(const double *A, const double *B,
+                              const double *x, const double *x0, double sgn,
+                              int64_t n, double *out, hipStream_t s) {
+  const unsigned gr = (unsigned)std::max<int64_t>(
+      1, std::min<int64_t>(4096, (n * n + n + 255) / 256));
+  hipLaunchKernelGGL(k_signed_copy, dim3(gr), dim3(256), 0, s, A, B, x, x0,
+                     sgn, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_quad(const double *A, int64_t n, double *out,
+                       const int32_t *info, hipStream_t s) {
+  hipLaunchKernelGGL(k_quad, dim3(1), dim3(256), 0, s, A, n, out, info);
+  return hipGetLastError();
 }
 
 hipError_t launch_inv_diag(const double *A, int64_t n, const double *theta,

@@ -584,6 +584,74 @@ int fit_workspace_footprint(Ctx *c, const Dims &d, int prec, size_t *bytes) {
 
 }  // namespace mnl
 
+namespace mnl {
+
+// Upper tail of the chi-square distribution, Q(df/2, x/2) with Q the
+// regularised upper incomplete gamma function: the power series of the
+// lower function for x < a + 1, else Legendre's continued fraction for the
+// upper one evaluated by the modified Lentz method (Abramowitz & Stegun
+// 6.5.29 and 6.5.31).
+double chi2_upper_tail(double x, double df) {
+  if (!(df > 0.0) || std::isnan(x)) return std::numeric_limits<double>::quiet_NaN();
+  if (x <= 0.0) return 1.0;
+  const double a = 0.5 * df, z = 0.5 * x;
+  const double lpre = a * std::log(z) - z - std::lgamma(a);
+  const double eps = 1e-16;
+  if (z < a + 1.0) {
+    // P(a, z) = z^a e^{-z} / Gamma(a + 1) sum_n z^n / ((a+1)...(a+n))
+    double term = 1.0 / a, sum = term;
+    for (int n = 1; n < 100000; ++n) {
+      term *= z / (a + n);
+      sum += term;
+      if (std::fabs(term) < std::fabs(sum) * eps) break;
+    }
+    return 1.0 - std::exp(lpre) * sum;
+  }
+  // Q(a, z) = z^a e^{-z} / Gamma(a) * 1 / (z + 1 - a - 1 (1 - a) /
+  //           (z + 3 - a - 2 (2 - a) / (z + 5 - a - ...)))
+  const double tiny = 1e-300;
+  double b = z + 1.0 - a, cc = 1.0 / tiny, dd = 1.0 / b, h = dd;
+  for (int n = 1; n < 100000; ++n) {
+    const double an = -n * (n - a);
+    b += 2.0;
+    dd = an * dd + b;
+    if (std::fabs(dd) < tiny) dd = tiny;
+    cc = b + an / cc;
+    if (std::fabs(cc) < tiny) cc = tiny;
+    dd = 1.0 / dd;
+    const double del = dd * cc;
+    h *= del;
+    if (std::fabs(del - 1.0) < eps) break;
+  }
+  return std::exp(lpre) * h;
+}
+
+namespace {
+// FP64 Hessian at theta factored as -H = L D L^T with n_p identity rows
+// appended (they end as L^{-T} D^{-1}); *H_out is the matrix buffer,
+// *cinfo_out the device status.
+int factor_with_identity(Ctx *c, const Dims &d, const mnl_problem *prob,
+                         const double *theta, double **H_out,
+                         int32_t **cinfo_out, hipStream_t s) {
+  void *lg, *Hv, *sv;
+  MNL_TRY(ws_get(c, S_LG, size_t(d.np + 1) * 8, &lg));
+  // 2 n_p + 1 rows: H, the (zero) g row and n_p identity rows, plus the
+  // factorisation's padding
+  MNL_TRY(ws_get(c, S_H, (size_t(2 * d.np + 1) * d.np + 64) * 8, &Hv));
+  MNL_TRY(ws_get(c, S_SCAL, 256, &sv));
+  int32_t *cinfo = (int32_t *)sv + 32;
+  double *H = (double *)Hv;
+  MNL_TRY(run_pass(c, d, prob, theta, (double *)lg, S_P, S_P32, S_YBAR, false,
+                   s));
+  MNL_TRY(form_hessian(c, d, prob, 0, MNL_PREC_FP64, H, s));
+  MNL_TRY(chol_solve_run(c, H, d.np, nullptr, nullptr, cinfo, s, d.np));
+  *H_out = H;
+  *cinfo_out = cinfo;
+  return MNL_OK;
+}
+}  // namespace
+}  // namespace mnl
+
 using namespace mnl;
 
 extern "C" {
@@ -816,6 +884,84 @@ int mnl_predict(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
   return MNL_OK;
 }
 
+
+int mnl_covariance(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
+                   const int32_t *idx, int32_t nidx, double *V,
+                   void *stream) {
+  if (!ctx) return MNL_ERR_ARG;
+  Ctx *c = &ctx->c;
+  Dims d;
+  MNL_TRY(check_problem(c, prob, &d, false));
+  if (!theta || !V || (nidx > 0 && !idx) || nidx < 0)
+    return set_error(c, MNL_ERR_ARG, "NULL argument or negative count");
+  const int32_t s_n = nidx ? nidx : int32_t(d.np);
+  std::vector<int32_t> sel(s_n);
+  for (int32_t j = 0; j < s_n; ++j) {
+    sel[j] = nidx ? idx[j] : j;
+    if (sel[j] < 0 || sel[j] >= d.np)
+      return set_error(c, MNL_ERR_ARG, "coefficient index out of range");
+  }
+  MNL_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  ++c->call_epoch;
+  double *H;
+  int32_t *cinfo;
+  MNL_TRY(factor_with_identity(c, d, prob, theta, &H, &cinfo, s));
+  void *iv;
+  MNL_TRY(ws_get(c, S_COLLIN, size_t(s_n) * 4 + 8, &iv));
+  MNL_HIP(c, hipMemcpyAsync(iv, sel.data(), size_t(s_n) * 4,
+                            hipMemcpyHostToDevice, s));
+  MNL_HIP(c, launch_cov_sub(H, d.np, (const int32_t *)iv, s_n, V, cinfo, s));
+  int32_t fail = 0;
+  MNL_TRY(copy_d2h(c, &fail, cinfo, sizeof fail, s));
+  c->hess_pending = c->pass_pending = false;
+  if (fail)
+    return set_error(c, MNL_ERR_NOT_PD,
+                     "-H not positive definite (pivot %d)", int(fail) - 1);
+  return MNL_OK;
+}
+
+int mnl_quadform(mnl_ctx *ctx, const double *A, const double *B,
+                 const double *x, const double *x0, int64_t n,
+                 int32_t hessian_sign, double *out, void *stream) {
+  if (!ctx) return MNL_ERR_ARG;
+  Ctx *c = &ctx->c;
+  if (!A || !x || !out || n < 1)
+    return set_error(c, MNL_ERR_ARG, "NULL argument or empty matrix");
+  MNL_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  void *bv, *sv;
+  // matrix rows, then d = x - x0 as the g row, plus padding
+  MNL_TRY(ws_get(c, S_H, (size_t(n + 1) * n + 64) * 8, &bv));
+  MNL_TRY(ws_get(c, S_SCAL, 256, &sv));
+  int32_t *cinfo = (int32_t *)sv + 32;
+  double *qd = (double *)sv + 8;
+  double *Bf = (double *)bv;
+  // the factorisation takes a Hessian-signed matrix and factors its
+  // negation: a positive definite A goes in negated
+  MNL_HIP(c, launch_signed_copy(A, B, x, x0, hessian_sign ? 1.0 : -1.0, n,
+                                Bf, s));
+  // d = x - x0 is already in the g row (its copy into that row is then
+  // element by element onto itself)
+  MNL_TRY(chol_solve_run(c, Bf, n, Bf + n * n, nullptr, cinfo, s));
+  MNL_HIP(c, launch_quad(Bf, n, qd, cinfo, s));
+  struct {
+    double q;
+    int32_t fail;
+  } h;
+  MNL_HIP(c, hipMemcpyAsync(&h.q, qd, 8, hipMemcpyDeviceToHost, s));
+  MNL_HIP(c, hipMemcpyAsync(&h.fail, cinfo, 4, hipMemcpyDeviceToHost, s));
+  MNL_HIP(c, hipStreamSynchronize(s));
+  if (h.fail)
+    return set_error(c, MNL_ERR_NOT_PD,
+                     "matrix not positive definite (pivot %d)",
+                     int(h.fail) - 1);
+  *out = h.q;
+  return MNL_OK;
+}
+
+double mnl_chi2_sf(double x, double df) { return chi2_upper_tail(x, df); }
+
 int mnl_stderr(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
                double *se, double *zval, double *pval, void *stream) {
   if (!ctx) return MNL_ERR_ARG;
@@ -826,18 +972,9 @@ int mnl_stderr(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
   MNL_HIP(c, hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
   ++c->call_epoch;
-  void *lg, *Hv, *sv;
-  MNL_TRY(ws_get(c, S_LG, size_t(d.np + 1) * 8, &lg));
-  // 2 n_p + 1 rows: H, the (zero) g row and n_p identity rows, plus the
-  // factorisation's padding
-  MNL_TRY(ws_get(c, S_H, (size_t(2 * d.np + 1) * d.np + 64) * 8, &Hv));
-  MNL_TRY(ws_get(c, S_SCAL, 256, &sv));
-  int32_t *cinfo = (int32_t *)sv + 32;
-  double *H = (double *)Hv;
-  MNL_TRY(run_pass(c, d, prob, theta, (double *)lg, S_P, S_P32, S_YBAR, false,
-                   s));
-  MNL_TRY(form_hessian(c, d, prob, 0, MNL_PREC_FP64, H, s));
-  MNL_TRY(chol_solve_run(c, H, d.np, nullptr, nullptr, cinfo, s, d.np));
+  double *H;
+  int32_t *cinfo;
+  MNL_TRY(factor_with_identity(c, d, prob, theta, &H, &cinfo, s));
   MNL_HIP(c, launch_inv_diag(H, d.np, theta, se, zval, pval, cinfo, s));
   int32_t fail = 0;
   MNL_TRY(copy_d2h(c, &fail, cinfo, sizeof fail, s));

@@ -185,6 +185,20 @@ size_t chol_workspace_bytes(int64_t n, int64_t extra = 0);
 hipError_t launch_inv_diag(const double *A, int64_t n, const double *theta,
                            double *se, double *z, double *pval,
                            const int32_t *info, hipStream_t s);
+// V[a][b] = ((-H)^{-1})[idx[a]][idx[b]] (device idx [s], V [s][s]) from a
+// factor with identity rows.
+hipError_t launch_cov_sub(const double *A, int64_t n, const int32_t *idx,
+                          int s, double *V, const int32_t *info,
+                          hipStream_t st);
+// out[0..n^2) = sgn (A - B) (B may be NULL), out[n^2 .. n^2 + n) = x - x0
+// (x0 may be NULL): the matrix and g rows of a factorisation buffer.
+hipError_t launch_signed_copy(const double *A, const double *B,
+                              const double *x, const double *x0, double sgn,
+                              int64_t n, double *out, hipStream_t s);
+// out[0] = sum_k D_k y_k^2 over the factor's g row: x^T A^{-1} x when x
+// was the g row of A's factorisation (0 when info[0] != 0).
+hipError_t launch_quad(const double *A, int64_t n, double *out,
+                       const int32_t *info, hipStream_t s);
 
 // ---- collinearity check -------------------------------------------------------
 // Keep flags (host int32, 1 = keep) of the X, Y and Z variables: column-order
