@@ -108,7 +108,23 @@ def fitted_methods(ctx, pr, dp, theta, reps=5):
     for _ in range(reps):
         keep = ctx.collinear(dq)
     cms = (time.perf_counter() - t0) / reps * 1e3
-    out = {"collinear": {"ms": cms, "kept": [int(k.sum()) for k in keep],
+    # Wald test of one alternative's beta chunk (covariance block and a
+    # quadratic form) and the score test of alpha at theta
+    from paper_1404_3177_amd import hypothesis as hyp
+    idx = list(range(pr.p))
+    hyp.waldtest(ctx, dq, theta, idx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        wald = hyp.waldtest(ctx, dq, theta, idx)
+    wms = (time.perf_counter() - t0) / reps * 1e3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        score = hyp.scoretest(ctx, dp, theta, pr.g)
+    scms = (time.perf_counter() - t0) / reps * 1e3
+    out = {"wald_test": {"ms": wms, "df": wald[1], "stat": wald[0]},
+           "score_test": {"ms": scms, "df": score[1], "stat": score[0]},
+           "collinear": {"ms": cms, "kept": [int(k.sum()) for k in keep],
                          "of": [pr.p, pr.g, pr.a]},
            "predict": {"ms": pms, "bytes": predict_bytes(pr),
                        "achieved_gbps": predict_bytes(pr) / pms * 1e-6,

@@ -8,11 +8,13 @@
 // complement: after equilibrating G to unit diagonal, eliminating the kept
 // columns in order leaves the squared residual ratio of column j on the
 // diagonal, so column j goes when that pivot is below tol^2 (or when the
-// column is zero).  The Gram matrices are library GEMMs over the
-// observations (X^T X, the K blocks Z_k^T Z_k as one strided batch, and
-// Ytil^T Ytil over the N (K - 1) stacked rows of Ytil_k = Y_k - Y_0, which
-// a small kernel forms first); one workgroup per Gram matrix then runs the
-// ordered elimination.  The Gram route squares the condition number: it
+// column is zero).  The Gram matrices (X^T X, the K blocks Z_k^T Z_k, and
+// Ytil^T Ytil over the N (K - 1) stacked rows of Ytil_k = Y_k - Y_0) come
+// from one pass over the observations (k_gram: tiles of observations staged
+// in LDS, each thread owning up to 16 Gram entries, Ytil formed on the fly;
+// per-workgroup partials summed in a fixed order).  Shapes beyond its
+// limits take library GEMMs instead (Ytil then formed in the workspace).
+// One workgroup per Gram matrix then runs the ordered elimination.  The Gram route squares the condition number: it
 // agrees with the QR criterion while kappa(kept columns)^2 eps << tol^2.
 #include <algorithm>
 #include <vector>
@@ -36,6 +38,89 @@ __global__ __launch_bounds__(256) void k_ydiff(const double *Y, int64_t N,
     const int k = 1 + int(r / g), c = int(r % g);
     Yt[e] = Y[(i * K + k) * g + c] - Y[i * K * g + c];
   }
+}
+
+// One Gram entry: the LDS offsets (within an observation's staged row
+// [x | y | z]) of its two columns, its kind (0: product, 2: differenced
+// generic data summed over alternatives 1..K-1) and its two destinations
+// in the column-major Gram storage.
+struct GramEnt {
+  int32_t oj, ol, kind, dst, dst2, pad;
+};
+constexpr int kGramEPT = 16;   // entries per thread at most
+
+// Partial Gram entries of workgroup b over its observation range.
+__global__ __launch_bounds__(256) void k_gram(const double *X,
+                                              const double *Y,
+                                              const double *Z, int64_t N,
+                                              int p, int K, int g, int a,
+                                              const GramEnt *ent, int E,
+                                              int T, double *partial) {
+  extern __shared__ double sm[];
+  const int t = threadIdx.x;
+  const int rowlen = p + K * g + K * a;
+  const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = int64_t(blockIdx.x) * chunk;
+  const int64_t i1 = i0 + chunk < N ? i0 + chunk : N;
+  double acc[kGramEPT];
+  GramEnt me[kGramEPT];
+#pragma unroll
+  for (int q = 0; q < kGramEPT; ++q) {
+    acc[q] = 0.0;
+    const int e = t + 256 * q;
+    me[q] = e < E ? ent[e] : GramEnt{0, 0, -1, 0, 0, 0};
+  }
+  for (int64_t ib = i0; ib < i1; ib += T) {
+    const int nt = int(i1 - ib < T ? i1 - ib : T);
+    for (int x = t; x < nt * p; x += 256)
+      sm[(x / p) * rowlen + x % p] = X[ib * p + x];
+    const int kg = K * g, ka = K * a;
+    for (int x = t; x < nt * kg; x += 256)
+      sm[(x / kg) * rowlen + p + x % kg] = Y[ib * kg + x];
+    for (int x = t; x < nt * ka; x += 256)
+      sm[(x / ka) * rowlen + p + kg + x % ka] = Z[ib * ka + x];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kGramEPT; ++q) {
+      const GramEnt m = me[q];
+      if (m.kind < 0) continue;
+      double s = acc[q];
+      if (m.kind == 0) {
+        for (int o = 0; o < nt; ++o) {
+          const double *r = sm + o * rowlen;
+          s = fma(r[m.oj], r[m.ol], s);
+        }
+      } else {
+        for (int o = 0; o < nt; ++o) {
+          const double *r = sm + o * rowlen;
+          const double yj = r[m.oj], yl = r[m.ol];
+          for (int k = 1; k < K; ++k)
+            s = fma(r[m.oj + k * g] - yj, r[m.ol + k * g] - yl, s);
+        }
+      }
+      acc[q] = s;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < kGramEPT; ++q) {
+    const int e = t + 256 * q;
+    if (e < E) partial[int64_t(blockIdx.x) * E + e] = acc[q];
+  }
+}
+
+// Gram entries: the G partials of each entry summed in order, written to
+// both of its places
+__global__ __launch_bounds__(256) void k_gram_reduce(const double *partial,
+                                                     int G, int E,
+                                                     const GramEnt *ent,
+                                                     double *out) {
+  const int e = int(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= E) return;
+  double s = 0.0;
+  for (int b = 0; b < G; ++b) s += partial[int64_t(b) * E + e];
+  out[ent[e].dst] = s;
+  out[ent[e].dst2] = s;
 }
 
 // Ordered elimination on each Gram matrix (block b: matrix b of size n,
@@ -120,6 +205,50 @@ int collinear_run(Ctx *c, const Dims &d, const mnl_problem *pr, double tol,
   double *Gx = (double *)gv, *Gz = Gx + size_t(p) * p,
          *Gy = Gz + size_t(K) * a * a;
   int32_t *kd = (int32_t *)(Gy + size_t(g) * g);
+  // one pass of k_gram when the entries and a staged row fit
+  const int64_t rowlen = int64_t(p) + int64_t(K) * (g + a);
+  const int64_t E = int64_t(p) * (p + 1) / 2 + int64_t(K) * a * (a + 1) / 2 +
+                    int64_t(g) * (g + 1) / 2;
+  if (E <= 256 * kGramEPT && rowlen <= 8192) {
+    std::vector<GramEnt> ent;
+    ent.reserve(size_t(E));
+    for (int l = 0; l < p; ++l)
+      for (int j = 0; j <= l; ++j)
+        ent.push_back({j, l, 0, j + l * p, l + j * p, 0});
+    const int zo = p + K * g;
+    for (int k = 0; k < K; ++k)
+      for (int l = 0; l < a; ++l)
+        for (int j = 0; j <= l; ++j) {
+          const int base = p * p + k * a * a;
+          ent.push_back({zo + k * a + j, zo + k * a + l, 0, base + j + l * a,
+                         base + l + j * a, 0});
+        }
+    for (int l = 0; l < g; ++l)
+      for (int j = 0; j <= l; ++j) {
+        const int base = p * p + K * a * a;
+        ent.push_back({p + j, p + l, 2, base + j + l * g, base + l + j * g,
+                       0});
+      }
+    const int T = int(std::max<int64_t>(1, std::min<int64_t>(16, 8192 / rowlen)));
+    const int G = int(std::max<int64_t>(
+        1, std::min<int64_t>(512, (N + 4 * T - 1) / (4 * T))));
+    void *ev, *pv;
+    MNL_TRY(ws_get(c, S_CG, size_t(E) * sizeof(GramEnt) + 8, &ev));
+    MNL_TRY(ws_get(c, S_PARTIAL, size_t(G) * size_t(E) * 8, &pv));
+    MNL_HIP(c, hipMemcpyAsync(ev, ent.data(), ent.size() * sizeof(GramEnt),
+                              hipMemcpyHostToDevice, s));
+    const int lds = int(T * rowlen * 8);
+    MNL_HIP(c, raise_lds_limit(reinterpret_cast<const void *>(&k_gram), lds));
+    hipLaunchKernelGGL(k_gram, dim3(G), dim3(256), lds, s, pr->X, pr->Y, pr->Z,
+                       N, p, K, g, a, (const GramEnt *)ev, int(E), T,
+                       (double *)pv);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(unsigned((E + 255) / 256)),
+                       dim3(256), 0, s, (const double *)pv, G, int(E),
+                       (const GramEnt *)ev, Gx);
+    MNL_HIP(c, hipGetLastError());
+    // the host table must outlive its copy
+    MNL_HIP(c, hipStreamSynchronize(s));
+  } else {
   void *hv;
   MNL_TRY(blas_get(c, s, &hv));
   rocblas_handle hb = static_cast<rocblas_handle>(hv);
@@ -152,6 +281,7 @@ int collinear_run(Ctx *c, const Dims &d, const mnl_problem *pr, double tol,
   if (st != rocblas_status_success)
     return set_error(c, MNL_ERR_HIP, "rocblas Gram product failed (%d)",
                      int(st));
+  }
   const double tol2 = tol * tol;
   int32_t *kx = kd, *kz = kx + p, *ky = kz + size_t(K) * a;
   if (p > 0)
