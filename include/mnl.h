@@ -103,7 +103,9 @@ typedef struct {
  * (Eq. 6).  NEWTON_CG is the inexact (truncated) Newton method the paper
  * names as its next step (Sec. 6): conjugate gradients on (-H) d = g from
  * d = 0 with FP64 Hessian-vector products (H is never formed), stopped at
- * relative residual min(1/2, sqrt(||g||_2)), after cg_maxiter products, or
+ * relative residual min(1/2, sqrt(||g||_2 / ||g_0||_2)), g_0 the gradient
+ * where the call started (so a single newton_step uses 1/2), after
+ * cg_maxiter products, or
  * at a direction of non-positive curvature (d = g if that is the first);
  * the line search and stop rules are Newton's.  prec does not apply. */
 typedef enum {

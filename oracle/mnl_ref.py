@@ -37,7 +37,8 @@ Readings taken where the paper is silent (all also used by the GPU path):
     probabilities of Eqs. 3-4 on data without choices.
   * the inexact Newton method (the paper's stated next step) takes its
     direction from truncated conjugate gradients on (-H) d = g from d = 0,
-    with relative residual eta = min(1/2, sqrt(||g||)), at most cg_maxiter
+    with relative residual eta = min(1/2, sqrt(||g|| / ||g_0||)) (g_0 the
+    gradient where the fit started), at most cg_maxiter
     Hessian-vector products, and d = g when the first search direction
     shows non-positive curvature; line search and stop rules are Newton's.
   * the collinearity check follows App. B's necessary conditions with a
@@ -342,6 +343,7 @@ def fit(X, Y, Z, choice, w=None, theta0=None, opts: Optional[FitOptions] = None,
     l = loglik(theta, X, Y, Z, choice, w)
     gr = gradient(theta, X, Y, Z, choice, w)
     iters = ls_iters = backtracks = cg_iters = 0
+    gnorm0 = None
     dl = float("nan")
     hist = []
     reason = None
@@ -358,8 +360,11 @@ def fit(X, Y, Z, choice, w=None, theta0=None, opts: Optional[FitOptions] = None,
             break
         H = hessian(theta, X, Y, Z, choice, w)
         if opts.method == "newton-cg":
+            if gnorm0 is None:
+                gnorm0 = gnorm
             delta, ncg = cg_direction(lambda v: H @ v, gr,
-                                      forcing_term(gnorm), opts.cg_maxiter)
+                                      forcing_term(gnorm, gnorm0),
+                                      opts.cg_maxiter)
             cg_iters += ncg
         else:
             try:
@@ -405,11 +410,13 @@ def hessian_vector(theta, X, Y, Z, v, w=None):
     return hessian(theta, X, Y, Z, None, w) @ np.asarray(v, dtype=np.float64)
 
 
-def forcing_term(gnorm):
+def forcing_term(gnorm, gnorm0):
     """Relative residual at which the inner solve stops:
-    eta = min(1/2, sqrt(||g||)), the choice that keeps truncated Newton
-    superlinearly convergent near the optimum."""
-    return min(0.5, math.sqrt(gnorm))
+    eta = min(1/2, sqrt(||g|| / ||g_0||)), g_0 the gradient where the fit
+    started: the choice min(1/2, sqrt(||g||)) that keeps truncated Newton
+    superlinearly convergent near the optimum, made independent of the
+    scale of the summed log-likelihood."""
+    return min(0.5, math.sqrt(gnorm / gnorm0))
 
 
 def cg_direction(hv, grad, eta, maxcg):

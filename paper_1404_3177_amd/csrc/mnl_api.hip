@@ -303,12 +303,13 @@ int validate_data(Ctx *c, const Dims &d, const mnl_problem *pr,
 
 // Inexact Newton direction (Sec. 6): truncated CG on (-H) d = g from d = 0
 // with Hessian-vector passes at the P of slot set `cur`; stops when
-// ||r|| <= eta ||g||, eta = min(1/2, sqrt(||g||)), after cg_maxiter
+// ||r|| <= eta ||g||, eta = min(1/2, sqrt(||g|| / ||g_0||)) with g_0 the
+// gradient where the call started, after cg_maxiter
 // products, or at p^T (-H) p <= 0 (d = g when that happens first).  One
 // host round trip per product carries r.r and p^T (-H) p.
 int cg_direction(Ctx *c, const Dims &d, const mnl_problem *pr,
                  const StepState &st, const mnl_fit_opts &o, double gnorm,
-                 double *delta, int *ncg, hipStream_t s) {
+                 double gnorm0, double *delta, int *ncg, hipStream_t s) {
   PassPlan plan;
   int rc = pass_plan(d, &plan);
   if (rc != MNL_OK)
@@ -321,7 +322,7 @@ int cg_direction(Ctx *c, const Dims &d, const mnl_problem *pr,
   double *r = (double *)cv, *p = r + n, *Hp = p + n, *scal = Hp + n;
   const double *g = st.lg + 1;
   MNL_HIP(c, launch_cg_init(g, delta, r, p, n, scal, s));
-  const double eta = std::min(0.5, std::sqrt(gnorm));
+  const double eta = std::min(0.5, std::sqrt(gnorm / gnorm0));
   PassArgs A;
   A.d = d;
   A.X = pr->X;
@@ -362,7 +363,7 @@ int cg_direction(Ctx *c, const Dims &d, const mnl_problem *pr,
 // cur describe the new point.  Returns MNL_OK with *reason set.
 int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
                 const mnl_fit_opts &o, StepState &st, double l_old,
-                double gnorm, mnl_fit_info *info, int *reason,
+                double gnorm, double gnorm0, mnl_fit_info *info, int *reason,
                 hipStream_t s) {
   void *Hv, *dv, *tv, *sv;
   // n_p + 1 rows: the factorisation carries g as an extra row; 64 doubles
@@ -397,7 +398,7 @@ int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
     // inexact Newton: the inner solve's time is reported as t_hessian
     int ncg = 0;
     MNL_HIP(c, hipEventRecord(c->ev_q[0], s));
-    MNL_TRY(cg_direction(c, d, pr, st, o, gnorm, delta, &ncg, s));
+    MNL_TRY(cg_direction(c, d, pr, st, o, gnorm, gnorm0, delta, &ncg, s));
     info->cg_iters += ncg;
     MNL_HIP(c, hipEventRecord(c->ev_q[2], s));
     MNL_TRY(trial_at(1.0, nullptr));
@@ -502,6 +503,7 @@ int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
     gnorm = std::sqrt(h[2]);
   }
   info->t_loglik_grad = now_ms() - t0;
+  const double gnorm0 = gnorm;   // scale of the inexact Newton forcing term
   info->loglik_diff = std::numeric_limits<double>::quiet_NaN();
   int reason = MNL_STOP_NONE;
   for (;;) {
@@ -520,8 +522,8 @@ int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
     if (one_step && info->iters >= 1) break;
     int r = MNL_STOP_NONE;
     const double step_gnorm = gnorm;
-    MNL_TRY(newton_core(c, d, prob, theta, o, st, l, step_gnorm, info, &r,
-                        s));
+    MNL_TRY(newton_core(c, d, prob, theta, o, st, l, step_gnorm, gnorm0, info,
+                        &r, s));
     if (r != MNL_STOP_NONE) {
       reason = r;
       if (one_step) info->grad_norm = step_gnorm;

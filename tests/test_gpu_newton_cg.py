@@ -52,8 +52,9 @@ def test_newton_cg_step_matches_oracle_direction(ctx):
     th0 = np.zeros(pr.n_params)
     gr = R.gradient(th0, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
     H = R.hessian(th0, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
-    d_ref, n_ref = R.cg_direction(lambda v: H @ v, gr,
-                                  R.forcing_term(np.linalg.norm(gr)), 250)
+    gn = np.linalg.norm(gr)
+    d_ref, n_ref = R.cg_direction(lambda v: H @ v, gr, R.forcing_term(gn, gn),
+                                  250)
     th = theta_tensor(th0)
     info = ctx.newton_step(device_problem(pr), th, gtol=GTOL, ftol=0.0,
                            method="newton-cg")

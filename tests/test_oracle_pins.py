@@ -668,8 +668,11 @@ def test_cg_matches_newton_direction_at_full_depth():
 
 
 def test_forcing_term():
-    assert R.forcing_term(1e4) == 0.5
-    assert R.forcing_term(1e-6) == pytest.approx(1e-3, rel=1e-15)
+    assert R.forcing_term(1e4, 1e4) == 0.5
+    assert R.forcing_term(1e-2, 1e4) == pytest.approx(1e-3, rel=1e-15)
+    # independent of the log-likelihood's scale
+    assert R.forcing_term(3e-3, 7.0) == pytest.approx(R.forcing_term(3e-2, 70.0),
+                                                      rel=1e-15)
 
 
 @pytest.mark.parametrize("seed", [1, 2])
