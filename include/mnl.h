@@ -365,6 +365,14 @@ typedef struct {
     int32_t slots;             /* fits in flight at once, 1..256            */
     size_t hbm_budget;         /* bytes admitted fits may hold; 0 = 80 % of
                                   the device memory free at creation       */
+    int32_t host_only;         /* nonzero: scheduler test mode with no
+                                  device: admission, slots and accounting
+                                  as usual, but an admitted request only
+                                  waits host_fit_ms and returns theta = 0
+                                  (stop_reason MNL_STOP_NONE, no
+                                  iterations); hbm_budget must be > 0      */
+    int32_t reserved;
+    double host_fit_ms;        /* host_only: time each "fit" takes          */
 } mnl_server_opts;
 
 /* One finished request (mnl_server_wait).  Times in ms on the server clock

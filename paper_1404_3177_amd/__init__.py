@@ -347,9 +347,12 @@ class Server:
     fit report and the arrival / admission / completion times (ms on the
     server clock, now_ms())."""
 
-    def __init__(self, slots: int = 8, hbm_budget: int = 0, device: int = 0):
+    def __init__(self, slots: int = 8, hbm_budget: int = 0, device: int = 0,
+                 host_only: bool = False, host_fit_ms: float = 0.0):
         self.lib = _lib.load()
-        o = MnlServerOpts(device=device, slots=slots, hbm_budget=hbm_budget)
+        o = MnlServerOpts(device=device, slots=slots, hbm_budget=hbm_budget,
+                          host_only=1 if host_only else 0,
+                          host_fit_ms=float(host_fit_ms))
         h = ctypes.c_void_p()
         rc = self.lib.mnl_server_create(ctypes.byref(h), ctypes.byref(o))
         if rc != 0:

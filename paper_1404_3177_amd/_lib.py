@@ -75,7 +75,9 @@ class MnlFitInfo(ctypes.Structure):
 
 class MnlServerOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32),
-                ("hbm_budget", ctypes.c_size_t)]
+                ("hbm_budget", ctypes.c_size_t),
+                ("host_only", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("host_fit_ms", ctypes.c_double)]
 
 
 class MnlServerResult(ctypes.Structure):

@@ -10,7 +10,11 @@
 // request that arrives while others run starts as soon as a slot and memory
 // are free.  The arithmetic of a fit depends only on its own shape and data
 // (fixed reduction partitions), never on the slot or on the other fits.
+// A host-only mode runs the same scheduler with no device (admitted
+// requests wait a given time instead of fitting), so admission, slot and
+// budget accounting can be tested anywhere.
 #include <algorithm>
+#include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -61,6 +65,8 @@ struct Request {
 struct mnl_server {
   int device = 0;
   size_t budget = 0;
+  bool host_only = false;
+  double host_fit_ms = 0.0;
   hipMemPool_t pool = nullptr;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -140,9 +146,19 @@ void run_request(mnl_server *sv, mnl_server::Slot *sl, const Request &r,
   res->status = rc;
 }
 
+// host-only mode: the request "runs" for host_fit_ms and returns theta = 0
+void run_request_host(mnl_server *sv, const Request &r,
+                      mnl_server_result *res) {
+  res->status = MNL_OK;
+  std::this_thread::sleep_for(
+      std::chrono::duration<double, std::milli>(sv->host_fit_ms));
+  std::memset(r.theta_out, 0, size_t(r.d.np) * 8);
+  res->info.stop_reason = MNL_STOP_NONE;
+}
+
 void slot_main(mnl_server *sv, int i) {
   mnl_server::Slot *sl = sv->slots[i];
-  (void)hipSetDevice(sv->device);
+  if (!sv->host_only) (void)hipSetDevice(sv->device);
   for (;;) {
     Request r;
     {
@@ -167,7 +183,8 @@ void slot_main(mnl_server *sv, int i) {
     res.t_arrival = r.t_arrival;
     res.t_admit = now_ms();
     res.footprint = r.footprint;
-    run_request(sv, sl, r, &res);
+    if (sv->host_only) run_request_host(sv, r, &res);
+    else run_request(sv, sl, r, &res);
     res.t_done = now_ms();
     {
       std::lock_guard<std::mutex> lk(sv->mu);
@@ -216,6 +233,19 @@ int mnl_server_create(mnl_server **out, const mnl_server_opts *o) {
   if (!out || !o) return MNL_ERR_ARG;
   *out = nullptr;
   if (o->slots < 1 || o->slots > 256) return MNL_ERR_ARG;
+  if (o->host_only) {
+    if (o->hbm_budget == 0 || !(o->host_fit_ms >= 0.0)) return MNL_ERR_ARG;
+    mnl_server *sv = new mnl_server;
+    sv->host_only = true;
+    sv->host_fit_ms = o->host_fit_ms;
+    sv->budget = o->hbm_budget;
+    for (int i = 0; i < o->slots; ++i)
+      sv->slots.push_back(new mnl_server::Slot);
+    for (int i = 0; i < o->slots; ++i)
+      sv->slots[i]->th = std::thread(slot_main, sv, i);
+    *out = sv;
+    return MNL_OK;
+  }
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess) {
     (void)hipGetLastError();
@@ -281,6 +311,11 @@ void mnl_server_destroy(mnl_server *sv) {
   sv->cv_work.notify_all();
   for (auto *sl : sv->slots)
     if (sl->th.joinable()) sl->th.join();
+  if (sv->host_only) {
+    for (auto *sl : sv->slots) delete sl;
+    delete sv;
+    return;
+  }
   (void)hipSetDevice(sv->device);
   for (auto *sl : sv->slots) {
     if (sl->stream) {
