@@ -161,6 +161,7 @@ void slot_main(mnl_server *sv, int i) {
   if (!sv->host_only) (void)hipSetDevice(sv->device);
   for (;;) {
     Request r;
+    double t_admit = 0.0;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
       sv->cv_work.wait(lk, [&] {
@@ -175,13 +176,15 @@ void slot_main(mnl_server *sv, int i) {
       sv->peak_in_use = std::max(sv->peak_in_use, sv->in_use);
       sv->running += 1;
       sv->max_running = std::max(sv->max_running, sv->running);
+      // taken under the lock: admission times follow the queue order
+      t_admit = now_ms();
     }
     mnl_server_result res;
     std::memset(&res, 0, sizeof res);
     res.id = r.id;
     res.slot = i;
     res.t_arrival = r.t_arrival;
-    res.t_admit = now_ms();
+    res.t_admit = t_admit;
     res.footprint = r.footprint;
     if (sv->host_only) run_request_host(sv, r, &res);
     else run_request(sv, sl, r, &res);
