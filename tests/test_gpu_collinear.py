@@ -89,3 +89,28 @@ def test_config_data_full_rank(ctx):
     pr = synth.make_config("c2")
     kx, ky, kz = ctx.collinear(device_problem(pr))
     assert kx.all() and ky.all() and kz.all()
+
+
+@pytest.mark.parametrize("case", ["many_alternatives", "library_route"])
+def test_masks_match_oracle_other_routes(ctx, case):
+    rng = np.random.default_rng(36)
+    if case == "many_alternatives":
+        # 129 alternatives: long staged rows in the one-pass Gram kernel
+        pr = synth.make_problem(1500, 129, 3, 2, 2, seed=37)
+        pr.Z[:, 100, 1] = 2.0 * pr.Z[:, 100, 0]
+        pr.Y[:, :, 1] = pr.Y[:, :, 0] + 0.5      # Ytil_1 = Ytil_0
+    else:
+        # 5,050 X^T X entries: the library GEMM route (Ytil formed first)
+        pr = synth.make_problem(3000, 4, 100, 2, 1, seed=38)
+        pr.X[:, 70] = pr.X[:, 3] - pr.X[:, 50]
+        pr.X[:, 99] = 0.0
+        pr.Y[:, :, 1] = 3.0 * pr.Y[:, :, 0] + rng.normal(size=(3000, 1))
+    ref = R.collinearity_mask(pr.X, pr.Y, pr.Z)
+    got = ctx.collinear(device_problem(pr))
+    for r, g_ in zip(ref, got):
+        np.testing.assert_array_equal(g_, r, err_msg=case)
+    if case == "many_alternatives":
+        np.testing.assert_array_equal(got[1], [1, 0])
+        np.testing.assert_array_equal(got[2], [1, 0])
+    else:
+        assert got[0].sum() == 98 and not got[0][70] and not got[0][99]
