@@ -150,8 +150,10 @@ typedef struct {
     double loglik_diff;        /* l change of the last step                */
     double t_total;            /* wall time of the call                    */
     double t_loglik_grad;      /* first pass (l, g, P) before stepping     */
-    double t_hessian;          /* Hessian formation                        */
-    double t_chol;             /* Cholesky factorisation + solves          */
+    double t_hessian;          /* Hessian formation (NEWTON_CG: the inner
+                                  conjugate-gradient solve)                */
+    double t_chol;             /* Cholesky factorisation + solves (0 for
+                                  NEWTON_CG)                               */
     double t_ls;               /* line-search passes                       */
     double t_hess_kernel;      /* GPU time in the Hessian MFMA kernel      */
     double t_pass_kernel;      /* GPU time in the fused pass kernel        */
