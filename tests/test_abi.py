@@ -79,6 +79,25 @@ def test_null_context_is_rejected(lib):
     assert lib.mnl_fit(None, None, None, None, None, None, None) == -1
     assert lib.mnl_workspace_bytes(None) == 0
     lib.mnl_destroy(None)
+    # the calls that widen the fit: methods, preprocessing, tests
+    assert lib.mnl_hessian(None, None, None, 0, None, None) == -1
+    assert lib.mnl_newton_step(None, None, None, None, None, None) == -1
+    assert lib.mnl_hessvec(None, None, None, None, None, None) == -1
+    assert lib.mnl_predict(None, None, None, None, None) == -1
+    assert lib.mnl_stderr(None, None, None, None, None, None, None) == -1
+    assert lib.mnl_covariance(None, None, None, None, 0, None, None) == -1
+    assert lib.mnl_quadform(None, None, None, None, None, 1, 0, None,
+                            None) == -1
+    assert lib.mnl_collinear(None, None, 1e-6, None, None, None, None) == -1
+    assert lib.mnl_select_columns(None, None, None, None, None, None, None,
+                                  None, None) == -1
+
+
+def test_default_method_is_exact_newton(lib):
+    from paper_1404_3177_amd import _lib
+    o = _lib.MnlFitOpts()
+    lib.mnl_default_opts(ctypes.byref(o))
+    assert o.method == 0 and o.cg_maxiter == 250 and o.validate == 0
 
 
 def test_struct_layouts_match_header():
