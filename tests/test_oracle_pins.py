@@ -814,3 +814,50 @@ def test_hm_test_identical_fits_and_definition():
                          V[:2, :2])
     assert s == pytest.approx(float(d @ np.linalg.inv(Vd) @ d), rel=1e-12)
     assert df == 2
+
+
+def test_wald_test_two_by_two_is_woolf():
+    # the log odds ratio of a 2 x 2 table has variance 1/a + 1/b + 1/c + 1/d
+    # at the optimum (Woolf), so its Wald statistic is in closed form
+    X1, E, y, x = _two_by_two(45)
+    full = R.fit(X1, E, E, y, None, opts=R.FitOptions(gtol=1e-12, ftol=0.0))
+    O = np.array([[np.sum((x == a) & (y == b)) for b in (0, 1)]
+                  for a in (0, 1)], dtype=float)
+    lor = math.log(O[1, 1] * O[0, 0] / (O[1, 0] * O[0, 1]))
+    V = R.covariance(full.theta, X1, E, E)
+    w, df, _ = R.wald_test(full.theta, V, [1])
+    assert full.theta[1] == pytest.approx(lor, rel=1e-10)
+    assert w == pytest.approx(lor ** 2 / (1.0 / O).sum(), rel=1e-9)
+
+
+def _hm_pipeline(X, Y, Z, choice, alts):
+    """Full fit, fit on the alternatives `alts` (base first), and the HM
+    statistic over their common coefficients."""
+    K, p, g, a = Y.shape[1], X.shape[1], Y.shape[2], Z.shape[2]
+    o = R.FitOptions(gtol=1e-11, ftol=0.0)
+    full = R.fit(X, Y, Z, choice, None, opts=o)
+    m = np.isin(choice, alts)
+    lut = -np.ones(K, int)
+    lut[alts] = np.arange(len(alts))
+    Xs, Ys, Zs = X[m], Y[m][:, alts], Z[m][:, alts]
+    sub = R.fit(Xs, Ys, Zs, lut[choice[m]].astype(np.int32), None, opts=o)
+    idx = [(j - 1) * p + c for j in alts[1:] for c in range(p)]
+    idx += [(K - 1) * p + j * a + c for j in alts for c in range(a)]
+    idx += [(K - 1) * p + K * a + c for c in range(g)]
+    Vf = R.covariance(full.theta, X, Y, Z)[np.ix_(idx, idx)]
+    Vs = R.covariance(sub.theta, Xs, Ys, Zs)
+    return R.hm_test(sub.theta, Vs, full.theta[idx], Vf)
+
+
+def test_hm_test_invariant_to_rescaling_a_variable():
+    # rescaling a column of X rescales its coefficients and their
+    # covariances; the HM statistic of the refits does not change
+    pr = synth.make_problem(3000, 4, 3, 1, 0, seed=73)
+    alts = [0, 1, 3]
+    s1, df, _ = _hm_pipeline(pr.X, pr.Y, pr.Z, pr.choice, alts)
+    X2 = pr.X.copy()
+    X2[:, 2] *= 8.0
+    Y2 = pr.Y * 0.25
+    s2, _, _ = _hm_pipeline(X2, Y2, pr.Z, pr.choice, alts)
+    assert df == 2 * 3 + 1
+    assert s2 == pytest.approx(s1, rel=1e-7)
