@@ -170,3 +170,25 @@ def test_hmftest_indefinite_difference_reported(ctx):
     with pytest.raises(mnl.MnlError) as ei:
         hyp.hmftest(ctx, dp, theta, [0, 1, 3], gtol=1e-10, ftol=0.0)
     assert ei.value.code == -3
+
+
+def test_wald_test_two_by_two_is_woolf(ctx):
+    # log odds ratio of a 2 x 2 table: (log OR)^2 / (1/a + 1/b + 1/c + 1/d)
+    import torch
+    import paper_1404_3177_amd as mnl
+    from paper_1404_3177_amd import hypothesis as hyp
+    rng = np.random.default_rng(45)
+    N = 1200
+    x = (rng.random(N) < 0.4).astype(float)
+    y = (rng.random(N) < 0.25 + 0.15 * x).astype(np.int32)
+    X1 = np.column_stack([np.ones(N), x])
+    E = torch.zeros(N, 2, 0, dtype=torch.float64).cuda()
+    prob = mnl.Problem(torch.from_numpy(X1).cuda(), E, E,
+                       torch.from_numpy(y).cuda())
+    theta, info = ctx.fit(prob, gtol=1e-12, ftol=0.0)
+    O = np.array([[np.sum((x == a) & (y == b)) for b in (0, 1)]
+                  for a in (0, 1)], dtype=float)
+    lor = np.log(O[1, 1] * O[0, 0] / (O[1, 0] * O[0, 1]))
+    w, df, _ = hyp.waldtest(ctx, prob, theta, [1])
+    assert float(theta.cpu()[1]) == pytest.approx(lor, rel=1e-10)
+    assert w == pytest.approx(lor ** 2 / (1.0 / O).sum(), rel=1e-9)
