@@ -107,7 +107,9 @@ __host__ __device__ inline Lay make_lay(const Dims &d) {
   L.alf = o; o += d.g;                        // alpha
   L.red = o; o += kWaves * (1 + d.g);         // loglik, alpha grad per wave
   L.ch = o;  o += kTB / 2;                    // choices, two per double
-  L.ysc = o; o += d.g > 0 ? kWaves * L.cap * kWave : 0;  // Ybar transpose
+  // Ybar transpose: per wave CAP rows of 64 values, one padding slot after
+  // every CAP values, so the transposed reads hit distinct banks
+  L.ysc = o; o += d.g > 0 ? kWaves * L.cap * (kWave + kWave / L.cap) : 0;
   L.lg = o;  o += 2 * kTB;                    // max and sum per observation
   L.total = o;
   return L;
@@ -277,17 +279,19 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
                 if (c < g) part[c] = fma(R, yr[k * g + c], part[c]);
             }
           }
-          double *scr = sm + L.ysc + wv * (CAP * kWave);
+          constexpr int RS = kWave + kWave / CAP;   // padded row
+          double *scr = sm + L.ysc + wv * (CAP * RS);
 #pragma unroll
           for (int c = 0; c < CAP; ++c)
-            if (c < g) scr[c * kWave + lane] = part[c];
+            if (c < g) scr[c * RS + lane + lane / CAP] = part[c];
           __builtin_amdgcn_wave_barrier();
           constexpr int LPC = kWave / CAP;
           const int cl = lane / LPC, jl = lane % LPC;
           double yb = 0.0;
           if (cl < g) {
 #pragma unroll
-            for (int q = 0; q < CAP; ++q) yb += scr[cl * kWave + jl * CAP + q];
+            for (int q = 0; q < CAP; ++q)
+              yb += scr[cl * RS + jl * (CAP + 1) + q];
           }
           yb += dpp_f64<0xB1>(yb);
           if constexpr (LPC >= 4) yb += dpp_f64<0x4E>(yb);
@@ -337,17 +341,19 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
         // wave's LDS block transposed, lane (c, j) adds CAP of them in order
         // and each group of 64 / CAP lanes combines its results by DPP
         // (every lane of a group ends with the same bits)
-        double *scr = sm + L.ysc + wv * (CAP * kWave);
+        constexpr int RS = kWave + kWave / CAP;   // padded row
+        double *scr = sm + L.ysc + wv * (CAP * RS);
 #pragma unroll
         for (int c = 0; c < CAP; ++c)
-          if (c < g) scr[c * kWave + lane] = part[c];
+          if (c < g) scr[c * RS + lane + lane / CAP] = part[c];
         __builtin_amdgcn_wave_barrier();
         constexpr int LPC = kWave / CAP;
         const int cl = lane / LPC, jl = lane % LPC;
         double yb = 0.0;
         if (cl < g) {
 #pragma unroll
-          for (int q = 0; q < CAP; ++q) yb += scr[cl * kWave + jl * CAP + q];
+          for (int q = 0; q < CAP; ++q)
+            yb += scr[cl * RS + jl * (CAP + 1) + q];
         }
         yb += dpp_f64<0xB1>(yb);
         if constexpr (LPC >= 4) yb += dpp_f64<0x4E>(yb);
