@@ -252,17 +252,18 @@ int mnl_hessvec(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
  * kept columns before it has norm below tol times its own norm (mnlogit's
  * qr with tol = linDepTol, default 1e-6); a zero column is dropped.  A Z
  * variable dependent in any alternative is dropped for all.  Computed on
- * Gram matrices (library GEMMs over the observations, then an ordered
- * elimination on the device), which agrees with QR while the kept columns'
+ * Gram matrices (one pass over the observations; library GEMMs beyond 4096
+ * Gram entries or 8192 doubles per observation), then an ordered
+ * elimination on the device, which agrees with QR while the kept columns'
  * condition number squared times eps stays well below tol^2.
  * prob->choice is not read (may be NULL).
  *   tol      in [0, 1).
  *   keep_x   [p] host int32, output: 1 keep, 0 drop (NULL iff p == 0).
  *   keep_y   [g] host int32, output (NULL iff g == 0).
  *   keep_z   [a] host int32, output (NULL iff a == 0).
- * At most 1024 columns per kind (MNL_ERR_UNSUPPORTED).  The workspace
- * takes N (K-1) g doubles for the differenced data.  Synchronises
- * `stream`. */
+ * At most 1024 columns per kind (MNL_ERR_UNSUPPORTED).  On the library
+ * route the workspace also takes N (K-1) g doubles for the differenced
+ * data.  Synchronises `stream`. */
 int mnl_collinear(mnl_ctx *ctx, const mnl_problem *prob, double tol,
                   int32_t *keep_x, int32_t *keep_y, int32_t *keep_z,
                   void *stream);
