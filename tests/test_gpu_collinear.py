@@ -29,10 +29,14 @@ def _dependent_problem(seed):
     return pr
 
 
-@pytest.mark.parametrize("case", ["random", "dependent", "zero", "app_b"])
+@pytest.mark.parametrize("case", ["random", "dependent", "zero", "app_b",
+                                  "wide"])
 def test_masks_match_oracle(ctx, case):
     if case == "random":
         pr = synth.make_problem(3000, 7, 5, 2, 2, seed=31)
+    elif case == "wide":
+        # fewer observations than columns: X keeps at most N columns
+        pr = synth.make_problem(12, 3, 20, 1, 1, seed=39)
     elif case == "dependent":
         pr = _dependent_problem(32)
     elif case == "zero":
