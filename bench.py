@@ -396,7 +396,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the "
-              "fit is not sharded across GPUs in this build", file=sys.stderr)
+              "fit is not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
 
     if args.traffic_probe:
