@@ -28,6 +28,7 @@ SE_SHAPES = [  # N, K, p, g, a, weights
     (2000, 19, 3, 1, 0, "uniform"),
     (5000, 13, 12, 2, 2, "int"),
     (3000, 33, 2, 0, 2, None),
+    (4000, 70, 2, 1, 1, "uniform"),   # more than 64 alternatives
     (3000, 43, 50, 1, 1, "uniform"),
 ]
 
