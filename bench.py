@@ -122,7 +122,25 @@ def fitted_methods(ctx, pr, dp, theta, reps=5):
     for _ in range(reps):
         score = hyp.scoretest(ctx, dp, theta, pr.g)
     scms = (time.perf_counter() - t0) / reps * 1e3
-    out = {"wald_test": {"ms": wms, "df": wald[1], "stat": wald[0]},
+    # Hessian-vector product H(theta) v: the pass at theta, then the pass
+    # of v in Hessian-vector mode (reads X, Y, Z, w and P)
+    v = torch.ones(pr.n_params, dtype=torch.float64, device=theta.device)
+    ctx.hessvec(dq, theta, v)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        ctx.hessvec(dq, theta, v)
+    e1.record()
+    torch.cuda.synchronize()
+    hms = e0.elapsed_time(e1) / reps
+    N, K = pr.N, pr.K
+    hv_bytes = float(N * (pr.p + K * pr.g + K * pr.a) * 8 + N * K * 8 +
+                     (8 * N if pr.w is not None else 0))
+    hbytes = pass_bytes(pr) + hv_bytes
+    out = {"hessvec": {"ms": hms, "bytes": hbytes,
+                       "achieved_gbps": hbytes / hms * 1e-6,
+                       "frac": hbytes / hms * 1e-6 / HBM_GBPS},
+           "wald_test": {"ms": wms, "df": wald[1], "stat": wald[0]},
            "score_test": {"ms": scms, "df": score[1], "stat": score[0]},
            "collinear": {"ms": cms, "kept": [int(k.sum()) for k in keep],
                          "of": [pr.p, pr.g, pr.a]},
