@@ -129,6 +129,15 @@ typedef struct {
     int32_t method;            /* mnl_method of the Newton direction       */
     int32_t cg_maxiter;        /* NEWTON_CG: Hessian-vector products per
                                   iteration at most, >= 1                  */
+    int32_t graph;             /* nonzero: from the second iteration on,
+                                  each Newton step (Hessian, factorisation,
+                                  full-step trial) is captured once per
+                                  parity of the alternating buffers into a
+                                  HIP graph and replayed.  Needs a
+                                  non-default stream; NEWTON_CG, shapes on
+                                  library GEMMs (large beta-beta products,
+                                  n_p >= 2048) and the default stream run
+                                  eagerly.  Results are bitwise the same.  */
 } mnl_fit_opts;
 
 /* Report of a fit or of one Newton step (mnlogit's est.stat). Times in ms:
@@ -159,6 +168,10 @@ typedef struct {
     double t_pass_kernel;      /* GPU time in the fused pass kernel        */
     int32_t n_pass;            /* fused passes run                         */
     int32_t cg_iters;          /* NEWTON_CG: Hessian-vector products       */
+    int32_t graph_steps;       /* Newton steps run as graph replays (their
+                                  kernels are not in t_hess_kernel, n_hess,
+                                  t_pass_kernel, n_pass)                   */
+    int32_t reserved;
 } mnl_fit_info;
 
 /* Library version string ("major.minor"). */

@@ -52,7 +52,7 @@ class MnlFitOpts(ctypes.Structure):
         ("gtol", ctypes.c_double), ("prec", ctypes.c_int32),
         ("ls_max", ctypes.c_int32), ("ls_tol_ulps", ctypes.c_double),
         ("validate", ctypes.c_int32), ("method", ctypes.c_int32),
-        ("cg_maxiter", ctypes.c_int32),
+        ("cg_maxiter", ctypes.c_int32), ("graph", ctypes.c_int32),
     ]
 
 
@@ -67,10 +67,12 @@ class MnlFitInfo(ctypes.Structure):
         ("t_chol", ctypes.c_double), ("t_ls", ctypes.c_double),
         ("t_hess_kernel", ctypes.c_double), ("t_pass_kernel", ctypes.c_double),
         ("n_pass", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
+        ("graph_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_
+                if f != "reserved"}
 
 
 class MnlServerOpts(ctypes.Structure):

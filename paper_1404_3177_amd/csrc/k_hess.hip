@@ -1448,6 +1448,13 @@ int bb_gemm_run(Ctx *c, const Plan &pl, const HessArgs &h, void *cbuf,
   return MNL_OK;
 }
 
+int hessian_uses_library(Ctx *c, const Dims &d, int prec, bool *uses) {
+  Plan *pl;
+  MNL_TRY(build_plan(c, d, prec, &pl));
+  *uses = pl->bb_gemm;
+  return MNL_OK;
+}
+
 int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   Plan *pl;
   MNL_TRY(build_plan(c, h.d, h.prec, &pl));

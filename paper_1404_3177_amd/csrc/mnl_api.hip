@@ -96,7 +96,19 @@ int blas_get(Ctx *c, hipStream_t s, void **handle) {
   return MNL_OK;
 }
 
+void graphs_release(Ctx *c) {
+  for (auto &g : c->step_exec) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+}
+
 void events_release(Ctx *c) {
+  graphs_release(c);
+  if (c->pinned) {
+    (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+  }
   if (!c->ev_ready) return;
   (void)hipEventDestroy(c->ev_h0);
   (void)hipEventDestroy(c->ev_h1);
@@ -363,8 +375,8 @@ int cg_direction(Ctx *c, const Dims &d, const mnl_problem *pr,
 // cur describe the new point.  Returns MNL_OK with *reason set.
 int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
                 const mnl_fit_opts &o, StepState &st, double l_old,
-                double gnorm, double gnorm0, mnl_fit_info *info, int *reason,
-                hipStream_t s) {
+                double gnorm, double gnorm0, bool use_graph,
+                mnl_fit_info *info, int *reason, hipStream_t s) {
   void *Hv, *dv, *tv, *sv;
   // n_p + 1 rows: the factorisation carries g as an extra row; 64 doubles
   // of padding let its kernels load whole panel rows unconditionally
@@ -394,7 +406,51 @@ int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
   int prec = o.prec;
   int32_t fail = 0;
   double sh[3] = {0.0, 0.0, 0.0};
-  if (o.method == MNL_METHOD_NEWTON_CG) {
+  bool done = false;
+  if (use_graph) {
+    // the step of this parity: captured on first use (every buffer it
+    // touches exists by now), then replayed; eager on any capture error
+    hipGraphExec_t &ex = c->step_exec[st.cur];
+    if (!ex) {
+      const bool ev = c->ev_ready;
+      c->ev_ready = false;   // no timing events inside the graph
+      hipGraph_t gr = nullptr;
+      int rc = MNL_OK;
+      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) ==
+          hipSuccess) {
+        rc = form_hessian(c, d, pr, st.cur, prec, H, s);
+        if (rc == MNL_OK) rc = chol_solve_run(c, H, d.np, st.lg + 1, delta,
+                                              cinfo, s);
+        if (rc == MNL_OK) rc = trial_at(1.0, cinfo);
+        if (rc == MNL_OK &&
+            hipMemcpyAsync(c->pinned, sc, 3 * sizeof(double),
+                           hipMemcpyDeviceToHost, s) != hipSuccess)
+          rc = MNL_ERR_HIP;
+        const hipError_t ee = hipStreamEndCapture(s, &gr);
+        if (ee != hipSuccess) rc = MNL_ERR_HIP;
+        if (rc == MNL_OK &&
+            hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) != hipSuccess)
+          ex = nullptr;
+        if (gr) (void)hipGraphDestroy(gr);
+      }
+      (void)hipGetLastError();
+      c->ev_ready = ev;
+      if (!ex) use_graph = false;
+    }
+    if (ex) {
+      MNL_HIP(c, hipGraphLaunch(ex, s));
+      MNL_HIP(c, hipStreamSynchronize(s));
+      info->graph_steps += 1;
+      std::memcpy(sh, c->pinned, sizeof sh);
+      fail = int32_t(sh[0]);
+      done = fail == 0 || prec == MNL_PREC_FP64;
+      if (!done) {
+        prec = MNL_PREC_FP64;   // the FP64 retry runs eagerly
+        info->hess_fallbacks += 1;
+      }
+    }
+  }
+  if (!done && o.method == MNL_METHOD_NEWTON_CG) {
     // inexact Newton: the inner solve's time is reported as t_hessian
     int ncg = 0;
     MNL_HIP(c, hipEventRecord(c->ev_q[0], s));
@@ -408,7 +464,7 @@ int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
     info->t_hessian += event_ms(c->ev_q[0], c->ev_q[2]);
     info->t_ls += event_ms(c->ev_q[2], c->ev_q[3]);
   }
-  for (int attempt = 0; o.method == MNL_METHOD_NEWTON && attempt < 2;
+  for (int attempt = 0; !done && o.method == MNL_METHOD_NEWTON && attempt < 2;
        ++attempt) {
     MNL_HIP(c, hipEventRecord(c->ev_q[0], s));
     MNL_TRY(form_hessian(c, d, pr, st.cur, prec, H, s));
@@ -504,6 +560,24 @@ int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
   }
   info->t_loglik_grad = now_ms() - t0;
   const double gnorm0 = gnorm;   // scale of the inexact Newton forcing term
+  // captured steps: only on a non-default stream, for exact Newton steps
+  // whose Hessian and factorisation make no library calls
+  bool graph_ok = o.graph != 0 && s != nullptr &&
+                  o.method == MNL_METHOD_NEWTON && d.np < 2048 && !one_step;
+  if (graph_ok) {
+    bool lib = false;
+    MNL_TRY(hessian_uses_library(c, d, o.prec, &lib));
+    graph_ok = !lib;
+  }
+  if (graph_ok && !c->pinned) {
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->pinned), 256) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      c->pinned = nullptr;
+      graph_ok = false;
+    }
+  }
+  graphs_release(c);   // graphs hold the previous fit's pointers
   info->loglik_diff = std::numeric_limits<double>::quiet_NaN();
   int reason = MNL_STOP_NONE;
   for (;;) {
@@ -522,8 +596,14 @@ int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
     if (one_step && info->iters >= 1) break;
     int r = MNL_STOP_NONE;
     const double step_gnorm = gnorm;
-    MNL_TRY(newton_core(c, d, prob, theta, o, st, l, step_gnorm, gnorm0, info,
-                        &r, s));
+    // graph replay from the second iteration (the first allocates)
+    const bool g_now = graph_ok && info->iters >= 1;
+    const int rcn = newton_core(c, d, prob, theta, o, st, l, step_gnorm,
+                                gnorm0, g_now, info, &r, s);
+    if (rcn != MNL_OK) {
+      graphs_release(c);
+      return rcn;
+    }
     if (r != MNL_STOP_NONE) {
       reason = r;
       if (one_step) info->grad_norm = step_gnorm;
@@ -549,6 +629,7 @@ int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
   if (!one_step || reason == MNL_STOP_GTOL || reason == MNL_STOP_NONFINITE)
     info->grad_norm = gnorm;
   info->t_total = now_ms() - t_start;
+  graphs_release(c);
   return MNL_OK;
 }
 
@@ -685,6 +766,7 @@ void mnl_default_opts(mnl_fit_opts *o) {
   o->validate = 0;
   o->method = MNL_METHOD_NEWTON;
   o->cg_maxiter = 250;
+  o->graph = 0;
 }
 
 int64_t mnl_num_params(int32_t K, int32_t p, int32_t g, int32_t a) {

@@ -155,6 +155,9 @@ struct HessArgs {
   int prec;
 };
 int hessian_run(Ctx *c, const HessArgs &a, hipStream_t s);
+// Whether the Hessian of this shape and precision calls a library GEMM
+// (such steps are not captured into graphs).
+int hessian_uses_library(Ctx *c, const Dims &d, int prec, bool *uses);
 void hessian_cache_free(Ctx *c);
 // The context's library BLAS handle (rocBLAS, atomics off), bound to
 // stream s; created on first use.
@@ -226,6 +229,11 @@ struct Ctx {
              ev_p1 = nullptr;
   hipEvent_t ev_q[4] = {nullptr, nullptr, nullptr, nullptr};  // phases
   bool ev_ready = false;
+  // captured Newton steps of the current fit, one per parity of the
+  // alternating P / gradient buffers, and the page-locked host scalars
+  // their last copy writes
+  hipGraphExec_t step_exec[2] = {nullptr, nullptr};
+  double *pinned = nullptr;
   bool hess_pending = false, pass_pending = false;
   // host-side caches of Hessian tile tables (keyed by shape)
   void *hess_cache = nullptr;

@@ -1,0 +1,79 @@
+"""Newton steps captured into HIP graphs (opts.graph): the same fits,
+bitwise, as the eager path, on a non-default stream."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mnl_ref as R
+from tests.gpu_util import device_problem, theta_tensor
+
+pytestmark = pytest.mark.gpu
+GTOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1404_3177_amd as mnl
+    return mnl.Context(0)
+
+
+@pytest.fixture(scope="module")
+def stream():
+    import torch
+    return torch.cuda.Stream()
+
+
+@pytest.mark.parametrize("shape,prec", [
+    ((2000, 10, 6, 1, 0, None), "fp64"),
+    ((20000, 12, 6, 2, 1, "uniform"), "fp64"),
+    ((5000, 13, 12, 2, 2, "int"), "bf16"),
+    ((100000, 50, 21, 5, 5, None), "fp32"),
+])
+def test_graph_fit_equals_eager_fit(ctx, stream, shape, prec):
+    import torch
+    N, K, p, g, a, wk = shape
+    pr = synth.make_problem(N, K, p, g, a, seed=900 + K, weights=wk)
+    dp = device_problem(pr)
+    t_e, i_e = ctx.fit(dp, gtol=GTOL, ftol=0.0, prec=prec, stream=stream)
+    # two graph fits in a row: the graphs of one fit never serve the next
+    for _ in range(2):
+        t_g, i_g = ctx.fit(dp, gtol=GTOL, ftol=0.0, prec=prec, graph=1,
+                           stream=stream)
+        stream.synchronize()
+        assert torch.equal(t_g, t_e)
+        assert (i_g["iters"], i_g["ls_iters"], i_g["stop_reason"]) == \
+            (i_e["iters"], i_e["ls_iters"], i_e["stop_reason"])
+        # every step after the first was a replay
+        assert i_g["graph_steps"] == i_g["iters"] - 1 and \
+            i_e["graph_steps"] == 0
+
+
+def test_graph_fit_with_backtracking_matches_oracle(ctx, stream):
+    # a far start: line-search halvings run eagerly between replays
+    pr = synth.make_problem(3000, 5, 3, 1, 1, seed=43, coef_sd=1.0)
+    th0 = np.full(pr.n_params, 2.0)
+    ref = R.fit_problem(pr, theta0=th0, opts=R.FitOptions(gtol=GTOL, ftol=0))
+    theta, info = ctx.fit(device_problem(pr), theta0=theta_tensor(th0),
+                          gtol=GTOL, ftol=0.0, graph=1, stream=stream)
+    stream.synchronize()
+    assert ref.ls_iters > ref.iters   # backtracking happened
+    assert info["iters"] == ref.iters and info["ls_iters"] == ref.ls_iters
+    th = theta.cpu().numpy()
+    assert np.linalg.norm(th - ref.theta) <= 1e-8 * np.linalg.norm(ref.theta)
+
+
+def test_graph_option_falls_back_where_it_cannot_capture(ctx, stream):
+    import torch
+    # the default stream, and a shape on the outer-panel factorisation
+    pr = synth.make_problem(1500, 6, 4, 1, 1, seed=44)
+    dp = device_problem(pr)
+    t_e, _ = ctx.fit(dp, gtol=GTOL, ftol=0.0)
+    t_g, i_g = ctx.fit(dp, gtol=GTOL, ftol=0.0, graph=1)
+    assert torch.equal(t_e, t_g) and i_g["graph_steps"] == 0
+    pr = synth.make_problem(3000, 43, 50, 1, 1, seed=120, weights="uniform")
+    dp = device_problem(pr)
+    t_e, i_e = ctx.fit(dp, gtol=GTOL, ftol=0.0, maxiter=2, stream=stream)
+    t_g, i_g = ctx.fit(dp, gtol=GTOL, ftol=0.0, maxiter=2, graph=1,
+                       stream=stream)
+    stream.synchronize()
+    assert torch.equal(t_e, t_g) and i_g["graph_steps"] == 0
