@@ -136,8 +136,9 @@ typedef struct {
                                   HIP graph and replayed.  Needs a
                                   non-default stream; NEWTON_CG, shapes on
                                   library GEMMs (large beta-beta products,
-                                  n_p >= 2048) and the default stream run
-                                  eagerly.  Results are bitwise the same.  */
+                                  n_p >= 2048), the default stream and
+                                  mnl_newton_step run eagerly.  Results are
+                                  bitwise the same.                        */
 } mnl_fit_opts;
 
 /* Report of a fit or of one Newton step (mnlogit's est.stat). Times in ms:
