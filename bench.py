@@ -255,7 +255,7 @@ STOP_NAMES = {0: "none", 1: "gtol", 2: "ftol", 3: "maxiter", 4: "ls_fail",
               5: "not_pd", 6: "nonfinite"}
 
 
-def serve_run(hps, slots, prec, arrivals_s=None):
+def serve_run(hps, slots, prec, arrivals_s=None, graph=0):
     """Run host problems through a fresh continuous-batching server.  With
     arrivals_s (seconds from the start) requests are submitted at those
     times (open loop); without, all at once (closed loop, the saturated
@@ -279,7 +279,8 @@ def serve_run(hps, slots, prec, arrivals_s=None):
             if dt <= 0:
                 break
             time.sleep(min(dt, 2.0) * 1e-3)
-        srv.submit(h, gtol=GTOL, ftol=0.0, prec=prec, t_arrival=t_arr)
+        srv.submit(h, gtol=GTOL, ftol=0.0, prec=prec, t_arrival=t_arr,
+                   graph=graph)
     th.join()
     st = srv.stats()
     srv.close()

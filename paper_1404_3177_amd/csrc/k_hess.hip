@@ -1213,6 +1213,8 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
 // the memory from its pool and uploads on its stream; otherwise the upload
 // is synchronous.
 int plan_upload(Ctx *c, Plan *pl) {
+  if (c->capturing)
+    return set_error(c, MNL_ERR_HIP, "Hessian tables inside a capture");
   hipError_t e;
   if (c->pool)
     e = hipMallocFromPoolAsync(&pl->dev, pl->dev_bytes, c->pool, c->ostream);

@@ -30,11 +30,19 @@ int set_error(Ctx *c, int code, const char *fmt, ...) {
   return code;
 }
 
+void graphs_release(Ctx *c);
+
 int ws_get(Ctx *c, int slot, size_t bytes, void **ptr) {
   if (bytes == 0) bytes = 256;
   bytes = (bytes + 255) & ~size_t(255);
   Buf &b = c->bufs[slot];
   if (b.bytes < bytes) {
+    if (c->capturing)
+      return set_error(c, MNL_ERR_HIP, "workspace growth inside a capture");
+    // captured steps hold the workspace's addresses: a buffer that moves
+    // (a mixed-precision fit's FP64 retry grows the Hessian partials, for
+    // one) makes them stale, so they are dropped and captured again
+    graphs_release(c);
     if (b.ptr) {
       if (c->pool) {
         // stream-ordered: later work on ostream cannot see the old buffer
@@ -418,6 +426,7 @@ int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
       int rc = MNL_OK;
       if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) ==
           hipSuccess) {
+        c->capturing = true;
         rc = form_hessian(c, d, pr, st.cur, prec, H, s);
         if (rc == MNL_OK) rc = chol_solve_run(c, H, d.np, st.lg + 1, delta,
                                               cinfo, s);
@@ -427,6 +436,7 @@ int newton_core(Ctx *c, const Dims &d, const mnl_problem *pr, double *theta,
                            hipMemcpyDeviceToHost, s) != hipSuccess)
           rc = MNL_ERR_HIP;
         const hipError_t ee = hipStreamEndCapture(s, &gr);
+        c->capturing = false;
         if (ee != hipSuccess) rc = MNL_ERR_HIP;
         if (rc == MNL_OK &&
             hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) != hipSuccess)

@@ -234,6 +234,9 @@ struct Ctx {
   // their last copy writes
   hipGraphExec_t step_exec[2] = {nullptr, nullptr};
   double *pinned = nullptr;
+  // a step is being captured: nothing may allocate (an allocation would be
+  // recorded into the graph instead of happening)
+  bool capturing = false;
   bool hess_pending = false, pass_pending = false;
   // host-side caches of Hessian tile tables (keyed by shape)
   void *hess_cache = nullptr;

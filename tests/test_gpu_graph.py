@@ -77,3 +77,54 @@ def test_graph_option_falls_back_where_it_cannot_capture(ctx, stream):
                        stream=stream)
     stream.synchronize()
     assert torch.equal(t_e, t_g) and i_g["graph_steps"] == 0
+
+
+def test_graph_fit_with_fp64_retries_equals_eager_fit(ctx, stream):
+    # near-separable data: as the probabilities saturate the BF16 Hessian
+    # stops being positive definite and the step is redone in FP64 between
+    # replays; the retry's larger partials move the workspace, so the
+    # captured steps are dropped and captured again
+    import torch
+    pr = synth.make_problem(20000, 100, 11, 0, 0, seed=5, coef_sd=3.0,
+                            weights="int")
+    dp = device_problem(pr)
+    t_e, i_e = ctx.fit(dp, gtol=GTOL, ftol=0.0, prec="bf16", maxiter=12,
+                       stream=stream)
+    t_g, i_g = ctx.fit(dp, gtol=GTOL, ftol=0.0, prec="bf16", maxiter=12,
+                       graph=1, stream=stream)
+    stream.synchronize()
+    print("fallbacks", i_e["hess_fallbacks"], "graph steps", i_g["graph_steps"],
+          "iters", i_e["iters"], flush=True)
+    assert i_e["hess_fallbacks"] > 0 and i_g["graph_steps"] > 0
+    assert torch.equal(t_g, t_e)
+    for k in ("iters", "ls_iters", "stop_reason", "hess_fallbacks", "loglik"):
+        assert i_g[k] == i_e[k], k
+
+
+def test_served_graph_fits_equal_eager_served_fits():
+    import paper_1404_3177_amd as mnl
+    probs = [synth.make_problem(20000, 100, 11, 0, 0, seed=5, coef_sd=3.0,
+                                weights="int"),
+             synth.make_problem(1500, 6, 4, 1, 0, seed=45),
+             synth.make_problem(4000, 12, 5, 2, 1, seed=46, weights="uniform")]
+    hps = [mnl.HostProblem.from_numpy(pr) for pr in probs]
+    out = []
+    for graph in (0, 1):
+        srv = mnl.Server(slots=2)
+        try:
+            ids = [srv.submit(h, gtol=GTOL, ftol=0.0, prec="bf16", maxiter=12,
+                              graph=graph) for h in hps]
+            res = {}
+            while len(res) < len(ids):
+                for r in srv.wait(timeout_ms=60_000):
+                    res[r["id"]] = r
+            out.append([res[i] for i in ids])
+        finally:
+            srv.close()
+    for r0, r1 in zip(*out):
+        assert r0["status"] == 0 and r1["status"] == 0
+        assert np.array_equal(r0["theta"], r1["theta"])
+        for k in ("iters", "ls_iters", "stop_reason", "hess_fallbacks"):
+            assert r0["info"][k] == r1["info"][k], k
+    assert out[1][0]["info"]["hess_fallbacks"] > 0
+    assert out[1][0]["info"]["graph_steps"] > 0
