@@ -137,7 +137,10 @@ typedef struct {
                                   non-default stream; NEWTON_CG, shapes on
                                   library GEMMs (large beta-beta products,
                                   n_p >= 2048), the default stream and
-                                  mnl_newton_step run eagerly.  Results are
+                                  mnl_newton_step run eagerly.  Growth of
+                                  the workspace (the first FP64 retry of a
+                                  mixed Hessian) drops the captured steps,
+                                  which are captured again.  Results are
                                   bitwise the same.                        */
 } mnl_fit_opts;
 
