@@ -128,3 +128,24 @@ def test_served_graph_fits_equal_eager_served_fits():
             assert r0["info"][k] == r1["info"][k], k
     assert out[1][0]["info"]["hess_fallbacks"] > 0
     assert out[1][0]["info"]["graph_steps"] > 0
+
+
+def test_graph_option_is_ignored_by_newton_cg_and_single_steps(ctx, stream):
+    import torch
+    pr = synth.make_problem(3000, 8, 5, 1, 1, seed=47, weights="uniform")
+    dp = device_problem(pr)
+    t_e, i_e = ctx.fit(dp, gtol=GTOL, ftol=0.0, method="newton-cg",
+                       stream=stream)
+    t_g, i_g = ctx.fit(dp, gtol=GTOL, ftol=0.0, method="newton-cg", graph=1,
+                       stream=stream)
+    stream.synchronize()
+    assert torch.equal(t_e, t_g) and i_g["graph_steps"] == 0
+    assert i_g["cg_iters"] == i_e["cg_iters"] > 0
+    th_e = theta_tensor(np.zeros(pr.n_params))
+    th_g = theta_tensor(np.zeros(pr.n_params))
+    for _ in range(3):
+        s_e = ctx.newton_step(dp, th_e, stream=stream)
+        s_g = ctx.newton_step(dp, th_g, stream=stream, graph=1)
+        stream.synchronize()
+        assert torch.equal(th_e, th_g) and s_g["graph_steps"] == 0
+        assert s_e["loglik"] == s_g["loglik"]
