@@ -117,10 +117,13 @@ __host__ __device__ inline Lay make_lay(const Dims &d) {
 
 // NTW: beta-gradient MFMA tiles per wave; CAP: register slots for the z
 // and y values of one alternative (>= a and >= g); ZR: a > 0 (without Z
-// no register is spent on z, gamma or the gamma gradient)
+// no register is spent on z, gamma or the gamma gradient).  With NTW <= 2
+// and CAP <= 8 the kernel is held to 168 VGPRs for three waves per SIMD:
+// more loads in flight per CU outweigh the few registers spilled.
 template <int NTW, int CAP, bool ZR, bool HV>
-__global__ __launch_bounds__(kThreads) void k_pass(PassArgs A,
-                                                   int64_t stride) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(NTW <= 2 && CAP <= 8 ? 3 : 1))) void
+k_pass(PassArgs A, int64_t stride) {
   constexpr int CZ = ZR ? CAP : 1;
   extern __shared__ double sm[];
   const Dims d = A.d;
@@ -499,7 +502,14 @@ int pass_plan(const Dims &d, PassPlan *plan) {
   plan->tb = kTB;
   plan->lds_bytes = size_t(L.total) * 8;
   const int64_t ntiles = (d.N + kTB - 1) / kTB;
-  plan->grid = (int)(ntiles < 1024 ? ntiles : 1024);
+  // kernels with at most two beta tiles per wave and eight value slots are
+  // built for three waves per SIMD (three workgroups per CU, LDS allowing):
+  // one round of 3 x 256 workgroups; the others hold two waves per SIMD and
+  // take two rounds of 2 x 256 (the count depends on the shape alone)
+  const int gmax =
+      (ntw <= 2 && L.cap <= 8 && 3 * plan->lds_bytes <= 160 * 1024) ? 768
+                                                                     : 1024;
+  plan->grid = (int)(ntiles < gmax ? ntiles : gmax);
   plan->stride = 1 + d.np;
   return MNL_OK;
 }
