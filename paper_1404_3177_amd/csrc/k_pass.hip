@@ -504,11 +504,12 @@ int pass_plan(const Dims &d, PassPlan *plan) {
   const int64_t ntiles = (d.N + kTB - 1) / kTB;
   // kernels with at most two beta tiles per wave and eight value slots are
   // built for three waves per SIMD (three workgroups per CU, LDS allowing):
-  // one round of 3 x 256 workgroups; the others hold two waves per SIMD and
-  // take two rounds of 2 x 256 (the count depends on the shape alone)
+  // one round of 3 x 256 workgroups; the others hold two waves per SIMD (one
+  // round of 2 x 256) or one (two rounds).  The count depends on the shape
+  // alone, so the sums are deterministic.
   const int gmax =
       (ntw <= 2 && L.cap <= 8 && 3 * plan->lds_bytes <= 160 * 1024) ? 768
-                                                                     : 1024;
+                                                                     : 512;
   plan->grid = (int)(ntiles < gmax ? ntiles : gmax);
   plan->stride = 1 + d.np;
   return MNL_OK;
