@@ -9,14 +9,14 @@
  *
  * Data kinds (this ABI's letters; the paper swaps Y and Z):
  *   X [N][p]     individual-specific data, alternative-specific coefficients
- *                beta_k (paper: X_i . beta_k).  An intercept is a column of
- *                ones supplied by the caller (Sec. 3.1: "another individual
- *                specific variable" whose data is unity).
+ *                beta_k (paper: X_i . beta_k).  An intercept is an X column
+ *                of ones supplied by the caller, with alternative-specific
+ *                coefficients like any other column of X (Sec. 3.1).
  *   Y [N][K][g]  alternative-varying data, generic coefficients alpha
  *                (paper: Z_ik . alpha).
  *   Z [N][K][a]  alternative-varying data, alternative-specific coefficients
  *                gamma_k (paper: Y_ik . gamma_k).
- * Alternative 0 is the base: beta_0 = 0 (Sec. 2.1 normalisation).  theta has
+ * Alternative 0 is the base: beta_0 = 0 (Sec. 2.2 normalisation).  theta has
  * n_p = (K-1) p + K a + g entries in the Eq. 8 order
  *   theta = (beta_1 .. beta_{K-1}, gamma_0 .. gamma_{K-1}, alpha),
  * each chunk contiguous, features in column order within a chunk.
@@ -64,7 +64,7 @@ enum {
 };
 
 /* Stop reasons reported in mnl_fit_info.stop_reason.  The first three are
- * mnlogit's gtol / ftol / maxiter rules (Sec. 2.3 and its est.stat report). */
+ * mnlogit's gtol / ftol / maxiter rules (Sec. 2.4 and its est.stat report). */
 enum {
     MNL_STOP_NONE = 0,         /* a step was taken, no rule met (newton_step) */
     MNL_STOP_GTOL = 1,         /* ||g||_2 <= gtol                          */
@@ -101,7 +101,7 @@ typedef struct {
 
 /* Newton direction.  NEWTON solves H delta = -g exactly by factoring H
  * (Eq. 6).  NEWTON_CG is the inexact (truncated) Newton method the paper
- * names as its next step (Sec. 6): conjugate gradients on (-H) d = g from
+ * names as its next step (Sec. 5): conjugate gradients on (-H) d = g from
  * d = 0 with FP64 Hessian-vector products (H is never formed), stopped at
  * relative residual min(1/2, sqrt(||g||_2 / ||g_0||_2)), g_0 the gradient
  * where the call started (so a single newton_step uses 1/2), after
@@ -114,7 +114,7 @@ typedef enum {
 } mnl_method;
 
 /* Fit options; defaults (mnl_default_opts) are mnlogit's maxiter = 50,
- * ftol = 1e-6, gtol = 1e-6 (Sec. 2.3), FP64 Hessian, 30 halvings, a
+ * ftol = 1e-6, gtol = 1e-6 (Sec. 2.4), FP64 Hessian, 30 halvings, a
  * line-search acceptance slack of 64 ulps of |l|, no validation, and the
  * exact Newton direction (cg_maxiter 250 when NEWTON_CG is chosen). */
 typedef struct {
@@ -259,7 +259,7 @@ int mnl_fit(mnl_ctx *ctx, const mnl_problem *prob, const double *theta0,
 int mnl_hessvec(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
                 const double *v, double *Hv, void *stream);
 
-/* ---- Collinearity check (Sec. 2.3 linDepTol, App. B) ---------------------- */
+/* ---- Collinearity check (Sec. 2.4 linDepTol, App. B) ---------------------- */
 
 /* Variables to keep so that App. B's necessary conditions for a
  * non-singular Hessian hold: X and every Z_k = Z[:, k, :] of full column
@@ -297,7 +297,7 @@ int mnl_select_columns(mnl_ctx *ctx, const mnl_problem *prob,
                        const int32_t *keep_z, double *X_out, double *Y_out,
                        double *Z_out, void *stream);
 
-/* ---- Fitted-model methods (Sec. 2.3: summary and predict) ----------------- */
+/* ---- Fitted-model methods (Sec. 2.4: summary and predict) ----------------- */
 
 /* Choice probabilities on (new) data at theta: Eqs. 3-4 at the utilities of
  * Eq. 2, one fused pass.  prob->choice and prob->w are not read (either may
@@ -323,7 +323,7 @@ int mnl_predict(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
 int mnl_stderr(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
                double *se, double *zval, double *pval, void *stream);
 
-/* ---- Hypothesis tests (Sec. 2.3: lrtest, waldtest, scoretest, hmftest) ---
+/* ---- Hypothesis tests (Sec. 2.4: lrtest, waldtest, scoretest, hmftest) ---
  * The statistics are quadratic forms in the estimate's covariance or the
  * Hessian; these three calls supply them (the likelihood ratio needs only
  * the two fits' log-likelihoods). */
@@ -362,6 +362,13 @@ int mnl_quadform(mnl_ctx *ctx, const double *A, const double *B,
 /* Upper tail P(chi^2_df > x) of the chi-square distribution (host):
  * the p-value of the test statistics above.  NaN for df <= 0. */
 double mnl_chi2_sf(double x, double df);
+
+/* Likelihood-ratio statistic of nested fits (host): *stat =
+ * 2 (loglik_full - loglik_restricted) and, when pval is not NULL, its
+ * chi-square tail with df degrees of freedom (the number of restrictions).
+ * MNL_ERR_ARG for df <= 0 or a NULL stat. */
+int mnl_lrtest(double loglik_full, double loglik_restricted, int32_t df,
+               double *stat, double *pval);
 
 /* ---- Serving: continuous batching of independent fits -------------------
  *

@@ -70,7 +70,7 @@ STOP_NONFINITE = 6
 
 def num_params(K: int, p: int, g: int, a: int) -> int:
     """Number of coefficients: K-1 identified beta chunks (beta_0 = 0 after
-    normalisation, Sec. 2.1), K gamma chunks and one alpha chunk (Eq. 8)."""
+    normalisation, Sec. 2.2), K gamma chunks and one alpha chunk (Eq. 8)."""
     return (K - 1) * p + K * a + g
 
 
@@ -86,7 +86,7 @@ def split_theta(theta, K, p, g, a):
 
 
 def differenced_generic(Y):
-    """Generic-coefficient data relative to the base alternative (Sec. 2.1,
+    """Generic-coefficient data relative to the base alternative (Sec. 2.2,
     after Eq. 2): Ytil_k = Y_k - Y_0, so Ytil_0 = 0."""
     return Y - Y[:, :1, :]
 
@@ -285,14 +285,14 @@ def newton_direction(H, grad):
 
 @dataclass
 class FitOptions:
-    maxiter: int = 50          # mnlogit() defaults (Sec. 2.3)
+    maxiter: int = 50          # mnlogit() defaults (Sec. 2.4)
     ftol: float = 1e-6
     gtol: float = 1e-6
     ls_max: int = 30
     ls_tol_ulps: float = 64.0
     # "newton": the direction solves the Newton system exactly (Eq. 6);
     # "newton-cg": truncated conjugate gradients on Hessian-vector products
-    # (the inexact Newton method of Sec. 6), at most cg_maxiter products
+    # (the inexact Newton method of Sec. 5), at most cg_maxiter products
     method: str = "newton"
     cg_maxiter: int = 250
 
@@ -402,7 +402,7 @@ def fit_problem(prob, theta0=None, opts=None, record=False) -> FitResult:
                record)
 
 
-# ---- inexact (truncated) Newton (Sec. 6) -------------------------------------
+# ---- inexact (truncated) Newton (Sec. 5) -------------------------------------
 
 def hessian_vector(theta, X, Y, Z, v, w=None):
     """H(theta) v with H of Eq. 10: the product an inexact Newton method
@@ -446,7 +446,7 @@ def cg_direction(hv, grad, eta, maxcg):
     return d, maxcg
 
 
-# ---- fitted-model methods: predict and summary (Sec. 2.3) --------------------
+# ---- fitted-model methods: predict and summary (Sec. 2.4) --------------------
 
 def predict(theta, X, Y, Z):
     """Choice probabilities of the fitted model on (new) data: Eqs. 3-4 at
@@ -468,7 +468,7 @@ def covariance(theta, X, Y, Z, w=None, H=None):
 
 
 def summary(theta, X, Y, Z, w=None, H=None):
-    """Coefficient table of the summary method (Sec. 2.3): standard errors
+    """Coefficient table of the summary method (Sec. 2.4): standard errors
     sqrt(diag((-H)^{-1})), Wald statistics z = theta / se and two-sided
     normal p-values erfc(|z| / sqrt 2)."""
     import math
@@ -479,7 +479,7 @@ def summary(theta, X, Y, Z, w=None, H=None):
     return se, z, pval
 
 
-# ---- collinearity check (Sec. 2.3 linDepTol, App. B) -------------------------
+# ---- collinearity check (Sec. 2.4 linDepTol, App. B) -------------------------
 
 def independent_columns(M, tol=1e-6):
     """Columns of M [rows, n] kept by a column-order QR with tolerance tol
@@ -522,7 +522,7 @@ def collinearity_mask(X, Y, Z, tol=1e-6):
     return keep_x, keep_y, keep_z
 
 
-# ---- hypothesis tests (Sec. 2.3: lrtest, waldtest, scoretest, hmftest) -------
+# ---- hypothesis tests (Sec. 2.4: lrtest, waldtest, scoretest, hmftest) -------
 
 def chi2_sf(x, df):
     """Upper tail of the chi-square distribution with df degrees of

@@ -26,7 +26,7 @@ from ._lib import (METHOD, MnlError, MnlFitInfo, MnlFitOpts,  # noqa
                    STOP_NONE, STOP_NONFINITE, STOP_NOT_PD)
 
 __all__ = ["Context", "Problem", "HostProblem", "Server", "num_params",
-           "default_opts", "fit_footprint", "chi2_sf", "MnlError"]
+           "default_opts", "fit_footprint", "chi2_sf", "lr_stat", "MnlError"]
 
 
 def num_params(K: int, p: int, g: int, a: int) -> int:
@@ -36,6 +36,17 @@ def num_params(K: int, p: int, g: int, a: int) -> int:
 def chi2_sf(x: float, df: float) -> float:
     """Upper tail of the chi-square distribution (the library's)."""
     return float(_lib.load().mnl_chi2_sf(float(x), float(df)))
+
+
+def lr_stat(loglik_full: float, loglik_restricted: float, df: int):
+    """Likelihood-ratio statistic of nested fits and its chi-square
+    p-value, (stat, p), from the library (mnl_lrtest)."""
+    stat, p = ctypes.c_double(), ctypes.c_double()
+    rc = _lib.load().mnl_lrtest(float(loglik_full), float(loglik_restricted),
+                                int(df), ctypes.byref(stat), ctypes.byref(p))
+    if rc != 0:
+        raise MnlError(rc, "mnl_lrtest failed")
+    return stat.value, p.value
 
 
 def default_opts() -> dict:

@@ -31,6 +31,7 @@ EXPORTS = [
     "mnl_loglik_grad", "mnl_hessian", "mnl_newton_step", "mnl_fit",
     "mnl_hessvec", "mnl_collinear", "mnl_select_columns", "mnl_predict",
     "mnl_stderr", "mnl_covariance", "mnl_quadform", "mnl_chi2_sf",
+    "mnl_lrtest",
     "mnl_fit_footprint", "mnl_server_now_ms", "mnl_server_create",
     "mnl_server_destroy", "mnl_server_submit", "mnl_server_wait",
     "mnl_server_get_stats",
@@ -149,6 +150,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.c_double), P]
     lib.mnl_chi2_sf.argtypes = [ctypes.c_double, ctypes.c_double]
     lib.mnl_chi2_sf.restype = ctypes.c_double
+    lib.mnl_lrtest.argtypes = [ctypes.c_double, ctypes.c_double,
+                               ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_double)]
+    lib.mnl_lrtest.restype = ctypes.c_int
     lib.mnl_select_columns.argtypes = [P, prob, P, P, P, P, P, P, P]
     lib.mnl_predict.argtypes = [P, prob, P, P, P]
     lib.mnl_stderr.argtypes = [P, prob, P, P, P, P, P]

@@ -1,4 +1,4 @@
-// Collinearity check of the data (Sec. 2.3 linDepTol, App. B): the
+// Collinearity check of the data (Sec. 2.4 linDepTol, App. B): the
 // variables to keep so that X, every Z_k and the differenced generic data
 // stacked over alternatives have full column rank.
 //

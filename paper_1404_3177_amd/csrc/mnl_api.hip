@@ -321,7 +321,7 @@ int validate_data(Ctx *c, const Dims &d, const mnl_problem *pr,
   return MNL_OK;
 }
 
-// Inexact Newton direction (Sec. 6): truncated CG on (-H) d = g from d = 0
+// Inexact Newton direction (Sec. 5): truncated CG on (-H) d = g from d = 0
 // with Hessian-vector passes at the P of slot set `cur`; stops when
 // ||r|| <= eta ||g||, eta = min(1/2, sqrt(||g|| / ||g_0||)) with g_0 the
 // gradient where the call started, after cg_maxiter
@@ -1055,6 +1055,14 @@ int mnl_quadform(mnl_ctx *ctx, const double *A, const double *B,
 }
 
 double mnl_chi2_sf(double x, double df) { return chi2_upper_tail(x, df); }
+
+int mnl_lrtest(double loglik_full, double loglik_restricted, int32_t df,
+               double *stat, double *pval) {
+  if (!stat || df <= 0) return MNL_ERR_ARG;
+  *stat = 2.0 * (loglik_full - loglik_restricted);
+  if (pval) *pval = chi2_upper_tail(*stat, double(df));
+  return MNL_OK;
+}
 
 int mnl_stderr(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
                double *se, double *zval, double *pval, void *stream) {

@@ -1,20 +1,20 @@
-"""Hypothesis tests of fitted models (Sec. 2.3: lrtest, waldtest,
+"""Hypothesis tests of fitted models (Sec. 2.4: lrtest, waldtest,
 scoretest, hmftest).
 
-Each statistic is a likelihood difference or a quadratic form that the
-library evaluates on the device (mnl_covariance, mnl_quadform); p-values
-come from the library's chi-square tail (mnl_chi2_sf).  This module only
-selects coefficients and data subsets.
+Each statistic is a likelihood difference (mnl_lrtest) or a quadratic form
+that the library evaluates on the device (mnl_covariance, mnl_quadform);
+p-values come from the library's chi-square tail (mnl_chi2_sf).  This
+module only selects coefficients and data subsets.
 """
 from __future__ import annotations
 
-from . import Context, Problem, chi2_sf
+from . import Context, Problem, chi2_sf, lr_stat
 
 
 def lrtest(loglik_full: float, loglik_restricted: float, df: int):
     """Likelihood-ratio test: (2 (l_full - l_restricted), df, p)."""
-    stat = 2.0 * (loglik_full - loglik_restricted)
-    return stat, df, chi2_sf(stat, df)
+    stat, p = lr_stat(loglik_full, loglik_restricted, df)
+    return stat, df, p
 
 
 def waldtest(ctx: Context, prob: Problem, theta, idx):

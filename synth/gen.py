@@ -13,11 +13,11 @@ with this project's names:
 
 The coefficient vector is laid out as in Eq. 8:
   theta = (beta_1 .. beta_{K-1}, gamma_0 .. gamma_{K-1}, alpha),
-with beta_0 fixed at zero (alternative 0 is the base, Sec. 2.1).
+with beta_0 fixed at zero (alternative 0 is the base, Sec. 2.2).
 
 Choices are drawn by simulating the random-utility model itself: each
 individual takes the alternative of largest U_ik + e_ik with e_ik i.i.d.
-standard Gumbel (Sec. 2.1, the utility-maximisation principle).  That yields
+standard Gumbel (Sec. 2.2, the utility-maximisation principle).  That yields
 exactly the logit choice law without evaluating any probability here.
 
 Draw order for one problem (one numpy PCG64 stream): X, Y, Z, theta_true,

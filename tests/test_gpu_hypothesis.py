@@ -134,7 +134,9 @@ def test_score_test_two_by_two_is_pearson(ctx):
 
 
 def _oracle_hm(pr, alts):
-    from paper_1404_3177_amd.hypothesis import common_coefficients
+    # the coefficients the subset model shares with the full one, in the
+    # subset model's Eq. 8 order: beta of its non-base alternatives, gamma
+    # of all its alternatives, then alpha
     o = R.FitOptions(gtol=1e-10, ftol=0.0)
     full = R.fit_problem(pr, opts=o)
     m = np.isin(pr.choice, alts)
@@ -142,7 +144,10 @@ def _oracle_hm(pr, alts):
     lut[alts] = np.arange(len(alts))
     Xs, Ys, Zs = pr.X[m], pr.Y[m][:, alts], pr.Z[m][:, alts]
     sub = R.fit(Xs, Ys, Zs, lut[pr.choice[m]].astype(np.int32), None, opts=o)
-    idx = common_coefficients(pr.K, pr.p, pr.g, pr.a, alts)
+    idx = [(j - 1) * pr.p + c for j in alts[1:] for c in range(pr.p)]
+    idx += [(pr.K - 1) * pr.p + j * pr.a + c for j in alts
+            for c in range(pr.a)]
+    idx += [(pr.K - 1) * pr.p + pr.K * pr.a + c for c in range(pr.g)]
     Vf = R.covariance(full.theta, pr.X, pr.Y, pr.Z)[np.ix_(idx, idx)]
     Vs = R.covariance(sub.theta, Xs, Ys, Zs)
     return R.hm_test(sub.theta, Vs, full.theta[idx], Vf)

@@ -33,6 +33,17 @@ def test_chi2_sf_closed_forms_and_edges(mnl):
     assert math.isnan(mnl.chi2_sf(1.0, 0.0))
 
 
+def test_lrtest_in_the_library(mnl):
+    # the statistic 2 (l_full - l_restricted) and its chi-square tail come
+    # from mnl_lrtest; df <= 0 is an argument error
+    from paper_1404_3177_amd import hypothesis as hyp
+    s, df, p = hyp.lrtest(-1000.25, -1003.5, 2)
+    assert s == 6.5 and df == 2
+    assert p == pytest.approx(math.exp(-3.25), rel=1e-13)
+    with pytest.raises(mnl.MnlError):
+        mnl.lr_stat(-1.0, -2.0, 0)
+
+
 def test_common_coefficients_layout():
     from paper_1404_3177_amd.hypothesis import common_coefficients
     # K = 4, p = 2, g = 1, a = 1: beta_1..3 at 0..5, gamma_0..3 at 6..9,

@@ -173,7 +173,7 @@ def test_intercept_only_closed_form():
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_binary_logit_equals_irls(seed):
-    # K = 2 is binary logistic regression (Sec. 2.1)
+    # K = 2 is binary logistic regression (Sec. 2.2)
     pr = synth.make_problem(300, 2, 4, 0, 0, seed=seed, weights="uniform")
     res = R.fit_problem(pr, opts=R.FitOptions(gtol=1e-11, ftol=0.0))
     b = irls_binary(pr.X, (pr.choice == 1).astype(float), pr.w)
@@ -490,7 +490,7 @@ def test_line_search_rule_at_optimum():
 
 
 # ---------------------------------------------------------------------------
-# fitted-model methods (Sec. 2.3): predict and the summary's standard errors
+# fitted-model methods (Sec. 2.4): predict and the summary's standard errors
 
 def test_intercept_only_standard_errors_closed_form():
     # inverse information of the log-odds xi_k = log(n_k / n_0):
@@ -599,7 +599,7 @@ def test_predict_utility_by_hand():
 
 
 # ---------------------------------------------------------------------------
-# inexact Newton (Sec. 6): Hessian-vector products and truncated CG
+# inexact Newton (Sec. 5): Hessian-vector products and truncated CG
 
 @pytest.mark.parametrize("shape", SHAPES[:4])
 def test_hessian_vector_central_differences(shape):
@@ -748,7 +748,7 @@ def test_collinearity_mask_z_dependent_in_one_alternative():
 
 
 # ---------------------------------------------------------------------------
-# hypothesis tests (Sec. 2.3)
+# hypothesis tests (Sec. 2.4)
 
 def _two_by_two(seed):
     rng = np.random.default_rng(seed)
@@ -861,3 +861,59 @@ def test_hm_test_invariant_to_rescaling_a_variable():
     s2, _, _ = _hm_pipeline(X2, Y2, pr.Z, pr.choice, alts)
     assert df == 2 * 3 + 1
     assert s2 == pytest.approx(s1, rel=1e-7)
+
+
+
+def _hm_parts(X, choice, alts, K):
+    """Full and subset fits of an X-only model: the subset estimate, the
+    matching full-model coefficients and both covariances."""
+    N = X.shape[0]
+    E = np.zeros((N, K, 0))
+    o = R.FitOptions(gtol=1e-11, ftol=0.0)
+    full = R.fit(X, E, E, choice, None, opts=o)
+    m = np.isin(choice, alts)
+    lut = -np.ones(K, int)
+    lut[alts] = np.arange(len(alts))
+    Xs = X[m]
+    Es = np.zeros((Xs.shape[0], len(alts), 0))
+    sub = R.fit(Xs, Es, Es, lut[choice[m]].astype(np.int32), None, opts=o)
+    p = X.shape[1]
+    idx = [(j - 1) * p + c for j in alts[1:] for c in range(p)]
+    Vf = R.covariance(full.theta, X, E, E)[np.ix_(idx, idx)]
+    Vs = R.covariance(sub.theta, Xs, Es, Es)
+    return sub.theta, full.theta[idx], Vs, Vf
+
+
+def test_hm_test_chi_square_law_under_iia():
+    # Choices drawn from a logit with fixed coefficients satisfy IIA.  Then
+    # d = theta_sub - theta_full is asymptotically normal with covariance
+    # V_sub - V_full (the full fit is efficient, the subset fit only
+    # consistent), so d^T (V_sub - V_full)^{-1} d is chi-square with df =
+    # the number of common coefficients (Hausman and McFadden 1984).  With
+    # the covariances averaged over the replications (the per-sample
+    # difference is nearly singular at these sizes) the statistic's mean
+    # must lie within 3 standard errors of df.  A swapped difference gives
+    # -df, a sum a mean far below df.
+    B = np.array([[0.0, 0.0], [0.8, -0.5], [-0.4, 0.9]])
+    reps, N = 200, 3000
+    TS, TF, VS, VF = [], [], [], []
+    for r in range(reps):
+        rng = np.random.default_rng(7000 + r)
+        X = rng.normal(size=(N, 2))
+        U = X @ B.T + rng.gumbel(size=(N, 3))
+        ts, tf, Vs, Vf = _hm_parts(X, U.argmax(1).astype(np.int32), [0, 1], 3)
+        TS.append(ts); TF.append(tf); VS.append(Vs); VF.append(Vf)
+    TS, TF = np.array(TS), np.array(TF)
+    Vs, Vf = np.mean(VS, axis=0), np.mean(VF, axis=0)
+    # the covariance of d across replications is V_sub - V_full
+    C = np.cov((TS - TF).T)
+    np.testing.assert_allclose(np.diag(C), np.diag(Vs - Vf), rtol=0.3)
+    stats = np.array([R.hm_test(TS[r], Vs, TF[r], Vf)[0] for r in range(reps)])
+    df = R.hm_test(TS[0], Vs, TF[0], Vf)[1]
+    assert df == 2
+    se = math.sqrt(2.0 * df / reps)
+    assert abs(stats.mean() - df) <= 3.0 * se, (stats.mean(), se)
+    assert np.all(stats >= 0.0)
+    # tail probabilities roughly uniform: about 10 % fall below 0.1
+    pv = np.array([R.chi2_sf(x, df) for x in stats])
+    assert 0.05 <= np.mean(pv < 0.1) <= 0.17
