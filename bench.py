@@ -2,21 +2,26 @@
 """Newton-Raphson multinomial-logit fits per second on one MI355X.
 
 One step = one whole fit (fused pass, block Hessian, Cholesky solve, halving
-line search, repeated until ||g||_2 <= 1e-8) of the 100,000-individual,
-50-alternative workload (21 individual-specific columns incl. intercept,
-5 generic and 5 alternative-specific alternative-varying variables), data
-already resident in HBM, started from theta = 0.
+line search, repeated until ||g||_2 <= 1e-8) of the largest single-GPU
+workload: 400,000 individuals, 100 alternatives, 51 individual-specific
+columns (incl. intercept, equicorrelated features) and 5 generic
+alternative-varying variables (5,054 coefficients), data already resident
+in HBM, started from theta = 0, FP64 throughout.
 
     python bench.py [--steps K] [--warmup W] [--prec fp64|fp32|bf16]
+                    [--config c3]
 
-Prints one JSON line.  Besides the fit rate it reports the Hessian MFMA
-kernel's rate against the MFMA peak of its dtype (HIP events around every
-launch, on the stream it runs on), the fused pass kernel's HBM rate, the
-p50/p99 fit latency, the FP32-Hessian variant and the FP64 CPU oracle timed
-on the host cores over a bounded sample, and the continuous-batching
-server on a stream of uneven fits: saturated fits/s (mixed-precision and
-FP64 Hessians), p50/p99 latency under Poisson arrivals, and a batch of 1024
-small fits.
+Prints one JSON line.  Besides the fit rate it reports the beta-beta
+Hessian MFMA kernel's rate against the MFMA peak of its dtype (HIP events
+around every launch, on the stream it runs on), the fused pass kernel's HBM
+rate, the p50/p99 fit latency, the FP32- and BF16-Hessian fits of the same
+workload (iterations, coefficient difference to the FP64 fit), the
+100,000-individual workload against the oracle's recorded optimum, the
+500-alternative near-separable workload (iterations, line-search
+backtracks, stop reason), the FP64 CPU oracle timed on the host cores over
+a bounded sample, and the continuous-batching server on a stream of uneven
+fits: saturated fits/s (mixed-precision and FP64 Hessians), p50/p99 latency
+under Poisson arrivals, and a batch of 1024 small fits.
 """
 import argparse
 import json
@@ -39,13 +44,10 @@ def log(msg):
 
 
 def hess_kernel_flops(pr):
-    """Useful flops of the Hessian MFMA kernel per launch: 2 N per unique
-    entry of the blocks it forms (beta-beta, beta-gamma, gamma-gamma)."""
-    N, K, p, a = pr.N, pr.K, pr.p, pr.a
-    u_bb = (K - 1) * K // 2 * (p * (p + 1) // 2)
-    u_bg = (K - 1) * p * K * a
-    u_gg = K * (K - 1) // 2 * a * a + K * (a * (a + 1) // 2)
-    return 2.0 * N * (u_bb + u_bg + u_gg)
+    """Useful flops of the beta-beta Hessian kernel per launch: 2 N per
+    unique entry of the (K-1)K/2 blocks of p(p+1)/2 unique entries."""
+    N, K, p = pr.N, pr.K, pr.p
+    return 2.0 * N * ((K - 1) * K // 2) * (p * (p + 1) // 2)
 
 
 def hess_total_flops(pr):
@@ -350,8 +352,8 @@ def serving(n_req, slots, load):
     return out
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "c2_fp64_hessian_traffic.md")
-HESS_SRC = os.path.join(ROOT, "paper_1404_3177_amd", "csrc", "k_hess.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_bb_c3_fp64_traffic.md")
+HESS_SRC = os.path.join(ROOT, "paper_1404_3177_amd", "csrc", "k_bb.hip")
 
 
 def source_digest(path):
@@ -361,7 +363,7 @@ def source_digest(path):
 
 
 def recorded_traffic():
-    """HBM bytes per launch of the Hessian tile kernel from the committed
+    """HBM bytes per launch of the beta-beta kernel from the committed
     counter profile (FETCH_SIZE / WRITE_SIZE, scaled by a plain copy of
     known size), or None when the kernel source changed since."""
     try:
@@ -375,10 +377,11 @@ def recorded_traffic():
     return rec
 
 
-def traffic_probe():
-    """Workload of the traffic profile: a 1 GiB device copy (the counters'
-    calibration), then one C2 Hessian and one fused pass.  Run under
-    rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE)."""
+def traffic_probe(config):
+    """Workload of the counter profiles: a 1 GiB device copy (the HBM
+    counters' calibration), then one Hessian of the workload in each
+    precision (FP64, FP32, BF16; each with its fused pass).  Run under
+    rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE, then the SQ counters)."""
     import torch
     import paper_1404_3177_amd as mnl
     import synth
@@ -388,22 +391,53 @@ def traffic_probe():
     y = x.clone()   # reads 1 GiB, writes 1 GiB
     torch.cuda.synchronize()
     del x, y
-    pr = synth.make_config("c2")
+    pr = synth.make_config(config)
     ctx = mnl.Context(0)
     dp = mnl.Problem.from_numpy(pr, device="cuda:0")
     th = torch.from_numpy(0.5 * pr.theta_true).cuda()
-    ctx.hessian(dp, th, prec="fp64")
-    torch.cuda.synchronize()
-    print(json.dumps({"probe": "done", "hessian_source": source_digest(HESS_SRC)}))
+    for prec in ("fp64", "fp32", "bf16"):
+        ctx.hessian(dp, th, prec=prec)
+        torch.cuda.synchronize()
+    print(json.dumps({"probe": "done", "config": config,
+                      "hessian_source": source_digest(HESS_SRC)}))
+
+
+def rel_err(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def fit_entry(pr, infos, lat, total, prec):
+    """Summary of timed fits: rate, iterations, line search, stop, the
+    beta-beta kernel's rate."""
+    kv = kernel_stats(pr, infos, prec)
+    inf = infos[-1]
+    return {"fits_per_s": len(lat) / total, "ms_per_fit": total / len(lat) * 1e3,
+            "iters": inf["iters"], "ls_iters": inf["ls_iters"],
+            "ls_backtracks": inf["ls_backtracks"],
+            "hess_fp64_retries": inf["hess_fallbacks"],
+            "stop_reason": STOP_NAMES.get(inf["stop_reason"], "?"),
+            "grad_norm": inf["grad_norm"], "loglik": inf["loglik"],
+            "bb_kernel_ms": kv["hess_ms"], "bb_tflops": kv["tflops"],
+            "bb_frac_of_peak": kv["tflops"] / kv["peak"],
+            "peak_tflops": kv["peak"],
+            "phase_ms": {k: inf[k] for k in ("t_loglik_grad", "t_hessian",
+                                              "t_chol", "t_ls")}}
+
+
+def golden_theta(name):
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"fit_{name}.npz")
+    return np.load(path)["theta"] if os.path.exists(path) else None
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000,
@@ -419,7 +453,7 @@ def main():
         sys.exit(2)
 
     if args.traffic_probe:
-        traffic_probe()
+        traffic_probe(args.config)
         return
 
     import numpy as np
@@ -439,57 +473,73 @@ def main():
     info = infos[-1]
     ks = kernel_stats(pr, infos, args.prec)
     log(f"fit: {total / args.steps * 1e3:.2f} ms, iters {info['iters']}, "
-        f"Hessian kernel {ks['hess_ms']:.3f} ms = {ks['tflops']:.2f} TFLOP/s")
-
-    gold_path = os.path.join(ROOT, "tests", "golden", f"fit_{args.config}.npz")
-    coef_err = None
-    if os.path.exists(gold_path):
-        gold = np.load(gold_path)
-        th = theta.cpu().numpy()
-        coef_err = float(np.linalg.norm(th - gold["theta"]) /
-                         np.linalg.norm(gold["theta"]))
+        f"beta-beta kernel {ks['hess_ms']:.3f} ms = {ks['tflops']:.2f} TFLOP/s")
+    th_main = theta.cpu().numpy()
+    gold = golden_theta(args.config)
+    coef_err = rel_err(th_main, gold) if gold is not None else None
 
     variants = {}
     if not args.no_variants and args.prec == "fp64":
         for vp in ("fp32", "bf16"):
             log(f"variant: {vp} Hessian")
-            th_v, inf_v, lat_v, tot_v = time_fits(ctx, dp, max(3, args.steps // 2),
+            th_v, inf_v, lat_v, tot_v = time_fits(ctx, dp, max(3, args.steps),
                                                   1, vp)
-            kv = kernel_stats(pr, inf_v, vp)
-            ent = {"fits_per_s": len(lat_v) / tot_v,
-                   "ms_per_fit": tot_v / len(lat_v) * 1e3,
-                   "iters": inf_v[-1]["iters"],
-                   "hessian_kernel_ms": kv["hess_ms"],
-                   "hessian_tflops": kv["tflops"],
-                   "hessian_frac_of_peak": kv["tflops"] / kv["peak"],
-                   "peak_tflops": kv["peak"],
-                   "grad_norm": inf_v[-1]["grad_norm"],
-                   "stop_reason": inf_v[-1]["stop_reason"]}
-            if os.path.exists(gold_path):
-                ent["coef_rel_err_vs_oracle"] = float(
-                    np.linalg.norm(th_v.cpu().numpy() - gold["theta"]) /
-                    np.linalg.norm(gold["theta"]))
+            ent = fit_entry(pr, inf_v, lat_v, tot_v, vp)
+            ent["workload"] = args.config
+            ent["coef_rel_diff_vs_gpu_fp64_fit"] = rel_err(
+                th_v.cpu().numpy(), th_main)
+            if gold is not None:
+                ent["coef_rel_err_vs_oracle"] = rel_err(th_v.cpu().numpy(),
+                                                        gold)
             variants[f"{vp}_hessian"] = ent
-        log("variant: inexact Newton (Newton-CG, Hessian-vector passes)")
-        th_c, inf_c, lat_c, tot_c = time_fits(ctx, dp, max(3, args.steps // 2),
-                                              1, "fp64", "newton-cg")
-        ic = inf_c[-1]
-        ent = {"fits_per_s": len(lat_c) / tot_c,
-               "ms_per_fit": tot_c / len(lat_c) * 1e3,
-               "iters": ic["iters"], "hessvec_products": ic["cg_iters"],
-               "ms_in_products": ic["t_hessian"],
-               "ms_per_product": ic["t_hessian"] / max(ic["cg_iters"], 1),
-               "grad_norm": ic["grad_norm"], "stop_reason": ic["stop_reason"]}
-        if os.path.exists(gold_path):
-            ent["coef_rel_err_vs_oracle"] = float(
-                np.linalg.norm(th_c.cpu().numpy() - gold["theta"]) /
-                np.linalg.norm(gold["theta"]))
-        variants["newton_cg"] = ent
-
-    methods = None
-    if not args.no_variants:
-        log("fitted-model methods: predict and summary")
-        methods = fitted_methods(ctx, pr, dp, theta)
+        del dp
+        torch.cuda.empty_cache()
+        # the other workloads: 100,000 individuals (oracle optimum on
+        # record), 500 near-separable alternatives, the 2,000-individual
+        # single fit
+        for name, precs, steps in (("c2", ("fp64", "fp32", "bf16"), 5),
+                                   ("c5", ("fp64", "bf16"), 2),
+                                   ("c1", ("fp64",), 20)):
+            pq = synth.make_config(name)
+            dq = mnl.Problem.from_numpy(pq, device="cuda:0")
+            gq = golden_theta(name)
+            for vp in precs:
+                log(f"variant: {name} {vp} Hessian")
+                th_q, inf_q, lat_q, tot_q = time_fits(ctx, dq, steps, 1, vp)
+                ent = fit_entry(pq, inf_q, lat_q, tot_q, vp)
+                ent["workload"] = (f"{name}: N={pq.N} K={pq.K} p={pq.p} "
+                                   f"g={pq.g} a={pq.a} (n_p={pq.n_params})")
+                ent["latency_ms"] = {"p50": percentile(lat_q, 0.5) * 1e3,
+                                     "p99": percentile(lat_q, 0.99) * 1e3}
+                if gq is not None:
+                    ent["coef_rel_err_vs_oracle"] = rel_err(
+                        th_q.cpu().numpy(), gq)
+                variants[f"{name}_{vp}"] = ent
+                if name == "c2" and vp == "fp64":
+                    th_c2, pr_c2, dp_c2 = th_q, pq, dq
+            if name == "c2":
+                log("variant: c2 inexact Newton (Newton-CG, Hessian-vector "
+                    "passes)")
+                th_c, inf_c, lat_c, tot_c = time_fits(ctx, dq, 3, 1, "fp64",
+                                                      "newton-cg")
+                ic = inf_c[-1]
+                ent = {"workload": "c2", "fits_per_s": len(lat_c) / tot_c,
+                       "ms_per_fit": tot_c / len(lat_c) * 1e3,
+                       "iters": ic["iters"], "hessvec_products": ic["cg_iters"],
+                       "ms_in_products": ic["t_hessian"],
+                       "ms_per_product": ic["t_hessian"] / max(ic["cg_iters"], 1),
+                       "grad_norm": ic["grad_norm"],
+                       "stop_reason": STOP_NAMES.get(ic["stop_reason"], "?")}
+                if gq is not None:
+                    ent["coef_rel_err_vs_oracle"] = rel_err(
+                        th_c.cpu().numpy(), gq)
+                variants["c2_newton_cg"] = ent
+                log("fitted-model methods at the c2 optimum")
+                methods = fitted_methods(ctx, pq, dq, th_c2)
+            del dq
+            torch.cuda.empty_cache()
+    else:
+        methods = None
 
     serve = None
     if args.serve_requests > 0:
@@ -529,7 +579,8 @@ def main():
             "frac": ks["tflops"] / ks["peak"],
             "traffic": None,
             "traffic_source": None,
-            "kernel": f"k_hess_tiles<{ {'fp64': 0, 'fp32': 1, 'bf16': 2}[args.prec] }>",
+            "kernel": (f"k_bb<{ {'fp64': 0, 'fp32': 1, 'bf16': 2}[args.prec] },"
+                       f"*> (beta-beta blocks, Khatri-Rao MFMA product)"),
             "kernel_ms": ks["hess_ms"],
             "launches": ks["n_hess"],
             "flops_per_launch": hess_kernel_flops(pr),
@@ -543,7 +594,8 @@ def main():
         "latency_ms": {"p50": percentile(lat, 0.5) * 1e3,
                        "p99": percentile(lat, 0.99) * 1e3},
         "fit": {"iters": info["iters"], "ls_iters": info["ls_iters"],
-                "stop_reason": info["stop_reason"],
+                "ls_backtracks": info["ls_backtracks"],
+                "stop_reason": STOP_NAMES.get(info["stop_reason"], "?"),
                 "grad_norm": info["grad_norm"], "loglik": info["loglik"],
                 "coef_rel_err_vs_oracle": coef_err,
                 "hessian_total_flops": hess_total_flops(pr),
@@ -554,9 +606,9 @@ def main():
         "serving": serve,
         "cpu_baseline": cpu,
     }
-    if args.prec == "fp64" and args.config == "c2":
+    if args.prec == "fp64":
         rec = recorded_traffic()
-        if rec is not None:
+        if rec is not None and rec.get("config") == args.config:
             res["roofline"]["traffic"] = rec["hbm_bytes_per_launch"]
             res["roofline"]["traffic_source"] = os.path.relpath(
                 TRAFFIC_PROFILE, ROOT)

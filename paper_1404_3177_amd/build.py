@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmnl.so")
-SOURCES = ["mnl_api.hip", "mnl_serve.hip", "k_pass.hip", "k_hess.hip",
+SOURCES = ["mnl_api.hip", "mnl_serve.hip", "k_pass.hip", "k_hess.hip", "k_bb.hip",
            "k_chol.hip", "k_collin.hip"]
 OBJDIR = os.path.join(HERE, "_build")
 

@@ -1,0 +1,789 @@
+// Beta-beta blocks of the Hessian (Eq. 10, Sec. 3.3): the bulk of the
+// Hessian and the part the paper's block-symmetric formulation speeds up.
+//
+// For alternatives 1 <= n <= m <= K-1 the block is
+//   H_nm = -X^T W_nm X,  W_nm = diag(w_i P_in (delta_nm - P_im)),
+// H_mn = H_nm^T, and each block is itself symmetric.  All unique entries
+// come from one product whose rows are alternative pairs (n, m) and whose
+// columns are feature pairs a <= b:
+//   C[(n,m)][(a,b)] = sum_i omega_i(n,m) chi_i(a,b),
+//   omega_i(n,m) = w_i P_in (delta_nm - P_im),  chi_i(a,b) = x_ia x_ib,
+// which is half the flops of the blocks' dense products.
+//
+// Neither operand is stored whole:
+//  * chi depends on the data only.  It is formed once per fit, in the MFMA
+//    operand type, in the order the MFMA B operand takes it
+//    (k_xx_frag): per round of KR observations and 16 feature pairs, one
+//    contiguous fragment block.  A workgroup streams its column tile of
+//    it into LDS with asynchronous 16-byte copies (no registers held).
+//  * omega depends on theta.  P is transposed once per Hessian into
+//    observation blocks [N/KR][K][KR] (k_p_blocks); the alternatives a
+//    row tile needs stream into LDS per round (one 256-byte column per
+//    copy instruction), and each wave forms its omega fragments in
+//    registers, in MFMA A-operand order, right before the MFMAs that
+//    consume them.  The rounding to the MFMA type happens after omega is
+//    formed in FP32 (mixed precision) or FP64.
+// A workgroup of 8 waves owns 512 pair rows x 16 TNB feature pairs; every
+// wave runs 64 rows (4 A fragments) x all TNB B fragments, so each B
+// fragment read from LDS feeds 4 MFMAs and each formed A fragment TNB.
+// The observations are split in S contiguous ranges; partial tiles are
+// summed in a fixed order by the assembly kernel (bitwise reproducible).
+#include <algorithm>
+#include <map>
+#include <tuple>
+
+#include "mnl_common.h"
+
+namespace mnl {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int kMaxStage = 128;   // staged alternatives per row tile
+constexpr int kTMA = 4;          // 16-row A fragments per wave
+constexpr int kBlkAlt = 32;      // alternatives per pair block (large K)
+constexpr int kWaves = 8;        // waves per workgroup
+
+// Per precision: T = P / w / omega type, XT = chi type, KR observations per
+// round, RS = LDS row stride of a staged P column (elements; padded so the
+// fragment reads of 16 lanes fall on distinct banks), TNMAX = most B
+// fragments per wave (register budget: kTMA x TNMAX accumulators).
+template <int PREC> struct BBT;
+template <> struct BBT<0> {
+  using T = double;
+  using XT = double;
+  using Acc = d4;
+  static constexpr int KR = 32, RS = 34, TNMAX = 4;
+  __device__ static int out_row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+template <> struct BBT<1> {
+  using T = float;
+  using XT = float;
+  using Acc = f4;
+  static constexpr int KR = 64, RS = 68, TNMAX = 8;
+  __device__ static int out_row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <> struct BBT<2> {
+  using T = float;
+  using XT = __bf16;
+  using Acc = f4;
+  static constexpr int KR = 64, RS = 68, TNMAX = 8;
+  __device__ static int out_row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+struct BBConst {
+  int kr, rs, tnmax, esz, xsz, asz;
+};
+BBConst bb_const(int prec) {
+  if (prec == 0) return {32, 34, 4, 8, 8, 8};
+  if (prec == 1) return {64, 68, 8, 4, 4, 4};
+  return {64, 68, 8, 4, 2, 4};
+}
+
+__host__ __device__ constexpr int al16(int b) { return (b + 15) & ~15; }
+
+// LDS layout of one of the two round buffers: staged P columns (plus one
+// zero column that padding rows read), the round's weights, the B tile.
+struct BBLds {
+  int w, b, bufsz;
+};
+__host__ __device__ inline BBLds bb_lds(int kr, int rs, int esz, int xsz,
+                                        int pcols, int tnb) {
+  BBLds L;
+  L.w = al16((pcols + 1) * rs * esz);
+  L.b = L.w + al16(kr * esz);
+  L.bufsz = al16(L.b + tnb * 16 * kr * xsz);
+  return L;
+}
+
+struct BBTile {
+  int32_t rt, ct, split, ob0, ob1, pad0, pad1, pad2;
+};
+
+struct BBDev {
+  const void *PT;           // [nob][K][KR] T: P by observation blocks
+  const void *WT;           // [nob][KR] T: weights (0 past N)
+  const void *XX;           // [nob][ncgx][16 KR] XT: chi in fragment order
+  const BBTile *tiles;
+  const int32_t *cols;      // [nrt][kMaxStage] staged alternatives
+  const int32_t *ncol;      // [nrt]
+  const uint32_t *rowinfo;  // [Mp] ln | lm << 8 | delta << 16
+  void *part;               // [S][Mp][Np] accumulator type
+  int64_t Mp, Np;
+  int K, pcols, ncgx;
+};
+
+template <int PREC, int TNB>
+__global__ __launch_bounds__(64 * kWaves) void k_bb(BBDev D) {
+  using C = BBT<PREC>;
+  using T = typename C::T;
+  using XT = typename C::XT;
+  using Acc = typename C::Acc;
+  constexpr int KR = C::KR, RS = C::RS;
+  constexpr int XF = 16 * KR;               // chi elements per group/round
+  constexpr int CDW = KR * int(sizeof(T)) / 4;   // dwords per P column: 64
+  static_assert(CDW == 64, "one copy instruction per staged column");
+  constexpr int BCH = TNB * XF * int(sizeof(XT)) / 1024;  // 1 KB B chunks
+  static_assert(TNB * XF * int(sizeof(XT)) % 1024 == 0, "B tile in 1 KB");
+  extern __shared__ double smd[];
+  char *sm = reinterpret_cast<char *>(smd);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const BBTile tl = D.tiles[blockIdx.x];
+  const BBLds L = bb_lds(KR, RS, int(sizeof(T)), int(sizeof(XT)), D.pcols,
+                         TNB);
+  const int ncol = D.ncol[tl.rt];
+  // the tile's staged alternatives, as dword offsets of their P columns
+  // in an observation block, in LDS after the two round buffers: reading
+  // them waits on LDS only, never on the copies in flight
+  int *ctab = reinterpret_cast<int *>(sm + 2 * L.bufsz);
+  for (int c = tid; c < ncol; c += 64 * kWaves)
+    ctab[c] = D.cols[int64_t(tl.rt) * kMaxStage + c] * CDW;
+
+  // the zero column (index pcols) of both buffers, read by padding rows
+  for (int e = tid; e < 2 * RS; e += 64 * kWaves) {
+    const int b = e / RS, o = e - b * RS;
+    reinterpret_cast<T *>(sm + b * L.bufsz)[D.pcols * RS + o] = T(0);
+  }
+  // this lane's A rows (one per fragment): LDS offsets of P_n and P_m
+  int offn[kTMA], offm[kTMA];
+  T dg[kTMA];
+  {
+    const int64_t r0 = int64_t(tl.rt) * (64 * kWaves) + 64 * wv + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < kTMA; ++j) {
+      const uint32_t info = D.rowinfo[r0 + 16 * j];
+      offn[j] = int(info & 0xffu) * RS;
+      offm[j] = int((info >> 8) & 0xffu) * RS;
+      dg[j] = (info >> 16) & 1u ? T(1) : T(0);
+    }
+  }
+
+  // asynchronous copies of round ob into buffer b: each staged P column
+  // and the weights are 64 dwords (one instruction), the B tile is
+  // contiguous in 1 KB pieces
+  const uint32_t *pt32 = static_cast<const uint32_t *>(D.PT);
+  const uint32_t *wt32 = static_cast<const uint32_t *>(D.WT);
+  const char *xx8 = static_cast<const char *>(D.XX);
+  // the wave index as a scalar: the copy loops and their table reads are
+  // then scalar, so waiting for a table entry never waits for the copies
+  const int wvs = __builtin_amdgcn_readfirstlane(wv);
+  auto stage = [&](int b, int ob) {
+    char *buf = sm + b * L.bufsz;
+    const uint32_t *src = pt32 + int64_t(ob) * D.K * CDW;
+    for (int c = wvs; c < ncol; c += kWaves)
+      __builtin_amdgcn_global_load_lds(src + ctab[c] + lane,
+                                       (lds_void_t *)(buf + c * RS * sizeof(T)),
+                                       4, 0, 0);
+    if (wvs == kWaves - 1)
+      __builtin_amdgcn_global_load_lds(wt32 + int64_t(ob) * CDW + lane,
+                                       (lds_void_t *)(buf + L.w), 4, 0, 0);
+    const char *xs =
+        xx8 + (int64_t(ob) * D.ncgx + int64_t(tl.ct) * TNB) * XF * sizeof(XT);
+    for (int q = wvs; q < BCH; q += kWaves)
+      __builtin_amdgcn_global_load_lds(xs + q * 1024 + lane * 16,
+                                       (lds_void_t *)(buf + L.b + q * 1024),
+                                       16, 0, 0);
+  };
+
+  Acc acc[kTMA][TNB];
+#pragma unroll
+  for (int j = 0; j < kTMA; ++j)
+#pragma unroll
+    for (int t = 0; t < TNB; ++t) acc[j][t] = Acc{0, 0, 0, 0};
+
+  __syncthreads();   // column table and zero columns in place
+  stage(0, tl.ob0);
+  __builtin_amdgcn_s_waitcnt(0);   // every counter: this wave's copies landed
+  __syncthreads();
+  int cur = 0;
+  const int kb = lane >> 4;
+  for (int ob = tl.ob0; ob < tl.ob1; ++ob, cur ^= 1) {
+    // the next round streams into the other buffer during this one
+    if (ob + 1 < tl.ob1) stage(cur ^ 1, ob + 1);
+    const char *buf = sm + cur * L.bufsz;
+    const T *Ps = reinterpret_cast<const T *>(buf);
+    const T *Ws = reinterpret_cast<const T *>(buf + L.w);
+    const XT *Bs = reinterpret_cast<const XT *>(buf + L.b);
+    if constexpr (PREC == 2) {
+#pragma unroll
+      for (int ks = 0; ks < KR / 32; ++ks) {
+        // lane: row lane & 15 of each A fragment, observations o .. o + 7
+        const int o = 32 * ks + 8 * kb;
+        const f4 w0 = *reinterpret_cast<const f4 *>(Ws + o);
+        const f4 w1 = *reinterpret_cast<const f4 *>(Ws + o + 4);
+        bf8 bv[TNB];
+#pragma unroll
+        for (int t = 0; t < TNB; ++t)
+          bv[t] = *reinterpret_cast<const bf8 *>(Bs + t * XF + ks * 512 +
+                                                 lane * 8);
+#pragma unroll
+        for (int j = 0; j < kTMA; ++j) {
+          const f4 n0 = *reinterpret_cast<const f4 *>(Ps + offn[j] + o);
+          const f4 n1 = *reinterpret_cast<const f4 *>(Ps + offn[j] + o + 4);
+          const f4 m0 = *reinterpret_cast<const f4 *>(Ps + offm[j] + o);
+          const f4 m1 = *reinterpret_cast<const f4 *>(Ps + offm[j] + o + 4);
+          bf8 av;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            av[e] = (__bf16)((w0[e] * n0[e]) * (dg[j] - m0[e]));
+            av[4 + e] = (__bf16)((w1[e] * n1[e]) * (dg[j] - m1[e]));
+          }
+#pragma unroll
+          for (int t = 0; t < TNB; ++t)
+            acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                av, bv[t], acc[j][t], 0, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll 4
+      for (int ks = 0; ks < KR / 4; ++ks) {
+        // lane: row lane & 15 of each A fragment, observation o
+        const int o = 4 * ks + kb;
+        const T wo = Ws[o];
+        T bv[TNB];
+#pragma unroll
+        for (int t = 0; t < TNB; ++t) bv[t] = Bs[t * XF + ks * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < kTMA; ++j) {
+          const T av = (wo * Ps[offn[j] + o]) * (dg[j] - Ps[offm[j] + o]);
+#pragma unroll
+          for (int t = 0; t < TNB; ++t) {
+            if constexpr (PREC == 0)
+              acc[j][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                  av, bv[t], acc[j][t], 0, 0, 0);
+            else
+              acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                  av, bv[t], acc[j][t], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // the next round's copies have landed and nobody reads this buffer
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+
+  using AT = typename std::conditional<PREC == 0, double, float>::type;
+  AT *base = static_cast<AT *>(D.part) +
+             (int64_t(tl.split) * D.Mp + int64_t(tl.rt) * (64 * kWaves) +
+              64 * wv) * D.Np +
+             int64_t(tl.ct) * TNB * 16;
+#pragma unroll
+  for (int j = 0; j < kTMA; ++j)
+#pragma unroll
+    for (int t = 0; t < TNB; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        base[int64_t(16 * j + C::out_row(lane, r)) * D.Np + 16 * t +
+             (lane & 15)] = AT(acc[j][t][r]);
+}
+
+// chi_i(a,b) = x_ia x_ib in B-fragment order: element index
+// ((ob * ncgx + cg) * NKS + ks) * 64 + lane (times 8 for BF16), holding
+// observation ob KR + ks KSTEP + lane / 16 (+ 8 (lane / 16) + e for BF16,
+// KSTEP 32) and feature pair 16 cg + lane % 16; zero past N and past the
+// last pair.  The product is taken in FP64 and rounded once (BF16: through
+// FP32, as the other mixed operands).
+template <int PREC>
+__global__ __launch_bounds__(256) void k_xx_frag(
+    const double *X, int p, int64_t N, const uint32_t *combo, int64_t ncombo,
+    int ncgx, int64_t nob, typename BBT<PREC>::XT *xx) {
+  using XT = typename BBT<PREC>::XT;
+  constexpr int KR = BBT<PREC>::KR;
+  constexpr int NKS = PREC == 2 ? KR / 32 : KR / 4;
+  const int64_t total = nob * ncgx * NKS * 64;
+  for (int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * 256) {
+    const int l = int(idx & 63);
+    const int64_t gk = idx >> 6;
+    const int ks = int(gk % NKS);
+    const int64_t grp = gk / NKS;
+    const int cg = int(grp % ncgx);
+    const int64_t ob = grp / ncgx;
+    const int64_t col = int64_t(cg) * 16 + (l & 15);
+    int fa = 0, fb = 0;
+    const bool cok = col < ncombo;
+    if (cok) {
+      const uint32_t cq = combo[col];
+      fa = int(cq & 0xffff);
+      fb = int(cq >> 16);
+    }
+    if constexpr (PREC == 2) {
+      const int64_t i0 = ob * KR + 32 * ks + 8 * (l >> 4);
+      bf8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t i = i0 + e;
+        const double x = (cok && i < N) ? X[i * p + fa] * X[i * p + fb] : 0.0;
+        v[e] = (__bf16)float(x);
+      }
+      *reinterpret_cast<bf8 *>(xx + idx * 8) = v;
+    } else {
+      const int64_t i = ob * KR + 4 * ks + (l >> 4);
+      const double x = (cok && i < N) ? X[i * p + fa] * X[i * p + fb] : 0.0;
+      xx[idx] = XT(x);
+    }
+  }
+}
+
+// P [N][K] (FP64) -> PT [nob][K][KR] in T, and the weights (1 when w is
+// NULL, 0 past N) -> WT [nob][KR]; one workgroup per block of KR
+// observations and 64 alternatives, transposed through LDS.
+template <typename T, int KR>
+__global__ __launch_bounds__(256) void k_p_blocks(const double *P,
+                                                  const double *w, int K,
+                                                  int64_t N, T *PT, T *WT) {
+  __shared__ double tile[KR][65];
+  const int64_t ob = blockIdx.x;
+  const int k0 = blockIdx.y * 64;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < KR * 64; e += 256) {
+    const int i = e >> 6, k = e & 63;
+    const int64_t obs = ob * KR + i;
+    tile[i][k] = (obs < N && k0 + k < K) ? P[obs * K + k0 + k] : 0.0;
+  }
+  if (blockIdx.y == 0 && tid < KR) {
+    const int64_t obs = ob * KR + tid;
+    WT[ob * KR + tid] = T(obs < N ? (w ? w[obs] : 1.0) : 0.0);
+  }
+  __syncthreads();
+  for (int e = tid; e < KR * 64; e += 256) {
+    const int k = e / KR, i = e - k * KR;
+    if (k0 + k < K) PT[(ob * K + k0 + k) * KR + i] = T(tile[i][k]);
+  }
+}
+
+// Sum the split partials of a pair row / feature pair entry in a fixed
+// order and write its four places in H (Hessian sign): rows (n, a), (n, b)
+// against columns (m, b), (m, a), and the mirrored ones.
+template <typename AT>
+__global__ void k_bb_assemble(const AT *part, int S, int64_t Mp, int64_t Np,
+                              const int32_t *pair_nm, const uint32_t *combo,
+                              int64_t ncombo, int64_t p, int64_t np,
+                              double *H) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= Mp * ncombo) return;
+  const int64_t r = e / ncombo, q = e - r * ncombo;
+  const int32_t nm = pair_nm[r];
+  if (nm == 0) return;   // padding row
+  double v = 0.0;
+  for (int s = 0; s < S; ++s) v += (double)part[(int64_t(s) * Mp + r) * Np + q];
+  const int n = nm & 0xffff, m = nm >> 16;
+  const int fa = combo[q] & 0xffff, fb = combo[q] >> 16;
+  const int64_t ra = (n - 1) * p + fa, rb = (n - 1) * p + fb;
+  const int64_t ca = (m - 1) * p + fa, cb = (m - 1) * p + fb;
+  v = -v;
+  H[ra * np + cb] = v;
+  H[rb * np + ca] = v;
+  H[cb * np + ra] = v;
+  H[ca * np + rb] = v;
+}
+
+// ---- host plan ------------------------------------------------------------
+
+struct BBPlan {
+  Dims d;
+  int prec = 0, tnb = 1, S = 1, ntiles = 0, pcols = 0, ncgx = 0;
+  int64_t npairs = 0, Mp = 0, Np = 0, ncombo = 0, nob = 0, nrt = 0;
+  size_t lds = 0;
+  std::vector<BBTile> h_tiles;
+  std::vector<int32_t> h_cols, h_ncol, h_pair;
+  std::vector<uint32_t> h_row, h_combo;
+  size_t o_cols = 0, o_ncol = 0, o_row = 0, o_combo = 0, o_pair = 0;
+  size_t dev_bytes = 0;
+  void *dev = nullptr;
+  BBTile *tiles = nullptr;
+  int32_t *cols = nullptr, *ncol = nullptr, *pair = nullptr;
+  uint32_t *row = nullptr, *combo = nullptr;
+};
+
+using BBKey = std::tuple<int64_t, int, int, int>;
+struct BBCache {
+  std::map<BBKey, BBPlan *> plans;
+};
+
+int bb_plan_host(Ctx *c, const Dims &d, int prec, BBPlan *pl) {
+  if (d.p > 255)
+    return set_error(c, MNL_ERR_UNSUPPORTED,
+                     "beta-beta Hessian blocks need p <= 255");
+  if (d.N > (int64_t(1) << 40))
+    return set_error(c, MNL_ERR_UNSUPPORTED, "N too large");
+  pl->d = d;
+  pl->prec = prec;
+  const BBConst bc = bb_const(prec);
+  const int Lk = d.K - 1, p = d.p;
+  const int R = 64 * kWaves;
+  // pair rows: n <= m over alternatives 1..K-1, row-major within blocks of
+  // kBlkAlt alternatives when there are more than a tile can stage; a row
+  // tile closes early (padding rows) when its next pair would need more
+  // than kMaxStage staged alternatives
+  std::vector<std::pair<int, int>> pairs;
+  if (Lk <= kMaxStage) {
+    for (int n = 1; n <= Lk; ++n)
+      for (int m = n; m <= Lk; ++m) pairs.push_back({n, m});
+  } else {
+    const int nb = (Lk + kBlkAlt - 1) / kBlkAlt;
+    for (int bi = 0; bi < nb; ++bi)
+      for (int bj = bi; bj < nb; ++bj)
+        for (int n = 1 + bi * kBlkAlt; n <= std::min(Lk, (bi + 1) * kBlkAlt); ++n)
+          for (int m = std::max(n, 1 + bj * kBlkAlt);
+               m <= std::min(Lk, (bj + 1) * kBlkAlt); ++m)
+            pairs.push_back({n, m});
+  }
+  pl->npairs = int64_t(pairs.size());
+  std::vector<int32_t> row_nm;          // n | m << 16 per row, 0 = padding
+  std::vector<std::vector<int>> tcols;  // staged alternatives per row tile
+  {
+    std::vector<char> in(size_t(d.K), 0);
+    std::vector<int> cur;
+    auto close_tile = [&]() {
+      while (row_nm.size() % R) row_nm.push_back(0);
+      std::sort(cur.begin(), cur.end());
+      tcols.push_back(cur);
+      for (int a : cur) in[a] = 0;
+      cur.clear();
+    };
+    for (auto &pr : pairs) {
+      const int need = (in[pr.first] ? 0 : 1) +
+                       (in[pr.second] || pr.second == pr.first ? 0 : 1);
+      if (int(cur.size()) + need > kMaxStage) close_tile();
+      for (int a : {pr.first, pr.second})
+        if (!in[a]) {
+          in[a] = 1;
+          cur.push_back(a);
+        }
+      row_nm.push_back(pr.first | (pr.second << 16));
+      if (row_nm.size() % R == 0) {
+        std::sort(cur.begin(), cur.end());
+        tcols.push_back(cur);
+        for (int a : cur) in[a] = 0;
+        cur.clear();
+      }
+    }
+    if (row_nm.size() % R) close_tile();
+  }
+  pl->nrt = int64_t(tcols.size());
+  pl->Mp = pl->nrt * R;
+  int pcols = 1;
+  for (auto &tc : tcols) pcols = std::max(pcols, int(tc.size()));
+  pl->pcols = pcols;
+  std::vector<int32_t> cols(size_t(std::max<int64_t>(pl->nrt, 1)) * kMaxStage, 0);
+  std::vector<int32_t> ncol(size_t(std::max<int64_t>(pl->nrt, 1)), 0);
+  std::vector<uint32_t> rowinfo(size_t(std::max<int64_t>(pl->Mp, 1)),
+                                uint32_t(pcols) | (uint32_t(pcols) << 8));
+  for (int64_t t = 0; t < pl->nrt; ++t) {
+    const auto &tc = tcols[t];
+    ncol[t] = int(tc.size());
+    for (size_t q = 0; q < tc.size(); ++q) cols[t * kMaxStage + q] = tc[q];
+    for (int64_t r = t * R; r < (t + 1) * R; ++r) {
+      const int32_t nm = row_nm[r];
+      if (nm == 0) continue;
+      const int n = nm & 0xffff, m = nm >> 16;
+      const uint32_t ln = uint32_t(std::lower_bound(tc.begin(), tc.end(), n) - tc.begin());
+      const uint32_t lm = uint32_t(std::lower_bound(tc.begin(), tc.end(), m) - tc.begin());
+      rowinfo[r] = ln | (lm << 8) | (uint32_t(n == m) << 16);
+    }
+  }
+  // feature pairs a <= b; column groups of 16, TNB groups per tile: the
+  // least padded columns, weighted by the per-tile cost of forming and
+  // staging the A operand (a tile of TNB groups re-forms it once per TNB)
+  std::vector<uint32_t> combo;
+  for (int fa = 0; fa < p; ++fa)
+    for (int fb = fa; fb < p; ++fb)
+      combo.push_back(uint32_t(fa) | (uint32_t(fb) << 16));
+  pl->ncombo = int64_t(combo.size());
+  const int64_t ncg = (pl->ncombo + 15) / 16;
+  int tnb = 1;
+  double best = 1e300;
+  for (int t = 1; t <= bc.tnmax; ++t) {
+    const double cost = double((ncg + t - 1) / t * t) * (1.0 + 0.5 / t);
+    if (cost <= best) {
+      best = cost;
+      tnb = t;
+    }
+  }
+  pl->tnb = tnb;
+  const int64_t nct = (ncg + tnb - 1) / tnb;
+  pl->ncgx = int(nct * tnb);
+  pl->Np = int64_t(pl->ncgx) * 16;
+  pl->nob = (d.N + bc.kr - 1) / bc.kr;
+  const BBLds L = bb_lds(bc.kr, bc.rs, bc.esz, bc.xsz, pcols, tnb);
+  pl->lds = size_t(2) * L.bufsz + kMaxStage * 4;   // + column table
+  if (pl->lds > 160 * 1024)
+    return set_error(c, MNL_ERR_UNSUPPORTED, "beta-beta tile exceeds LDS");
+
+  // observation splits: the count whose workgroups fill the resident slots
+  // (one 8-wave workgroup per CU) best in whole rounds; a larger count
+  // must gain 2 points of fill
+  const int64_t nout = pl->nrt * nct;
+  int S = 1;
+  if (nout > 0) {
+    const int64_t slots = int64_t(device_cus(c));
+    const int64_t max_s = std::max<int64_t>(1, std::min<int64_t>(64, pl->nob / 4));
+    double bestf = -1.0;
+    for (int sc = 1; sc <= max_s; ++sc) {
+      const int64_t wg = sc * nout;
+      const int64_t rounds = (wg + slots - 1) / slots;
+      const double fill = double(wg) / double(rounds * slots);
+      if (fill > bestf + 0.02) {
+        bestf = fill;
+        S = sc;
+      }
+    }
+  }
+  const int64_t chunk = (pl->nob + S - 1) / S;
+  S = int((pl->nob + chunk - 1) / chunk);
+  pl->S = S;
+  // XCD-aware order: workgroup b runs on XCD b % 8, so the tiles of one
+  // observation split get ids of one residue and share that XCD's L2 (the
+  // B column tiles are read by every row tile of the split)
+  std::vector<BBTile> tiles;
+  {
+    std::vector<std::vector<BBTile>> q(8);
+    for (int sp = 0; sp < S; ++sp)
+      for (int64_t ct = 0; ct < nct; ++ct)
+        for (int64_t rt = 0; rt < pl->nrt; ++rt) {
+          BBTile t{};
+          t.rt = int(rt);
+          t.ct = int(ct);
+          t.split = sp;
+          t.ob0 = int(sp * chunk);
+          t.ob1 = int(std::min<int64_t>(pl->nob, (sp + 1) * chunk));
+          q[sp % 8].push_back(t);
+        }
+    size_t pos[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    size_t left = size_t(S) * size_t(nout);
+    while (left) {
+      for (int x = 0; x < 8 && left; ++x) {
+        int src = x;
+        if (pos[src] >= q[src].size()) {
+          size_t most = 0;
+          for (int y = 0; y < 8; ++y)
+            if (q[y].size() - pos[y] > most) {
+              most = q[y].size() - pos[y];
+              src = y;
+            }
+        }
+        tiles.push_back(q[src][pos[src]++]);
+        --left;
+      }
+    }
+  }
+  pl->ntiles = int(tiles.size());
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  pl->o_cols = al(tiles.size() * sizeof(BBTile));
+  pl->o_ncol = al(pl->o_cols + cols.size() * 4);
+  pl->o_row = al(pl->o_ncol + ncol.size() * 4);
+  pl->o_combo = al(pl->o_row + rowinfo.size() * 4);
+  pl->o_pair = al(pl->o_combo + std::max<size_t>(combo.size(), 1) * 4);
+  pl->dev_bytes = al(pl->o_pair + std::max<size_t>(row_nm.size(), 1) * 4);
+  pl->h_tiles = std::move(tiles);
+  pl->h_cols = std::move(cols);
+  pl->h_ncol = std::move(ncol);
+  pl->h_row = std::move(rowinfo);
+  pl->h_combo = std::move(combo);
+  pl->h_pair = std::move(row_nm);
+  return MNL_OK;
+}
+
+int bb_plan_upload(Ctx *c, BBPlan *pl) {
+  if (c->capturing)
+    return set_error(c, MNL_ERR_HIP, "Hessian tables inside a capture");
+  hipError_t e;
+  if (c->pool)
+    e = hipMallocFromPoolAsync(&pl->dev, pl->dev_bytes, c->pool, c->ostream);
+  else
+    e = hipMalloc(&pl->dev, pl->dev_bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    pl->dev = nullptr;
+    return set_error(c, MNL_ERR_OOM, "beta-beta tables");
+  }
+  char *base = static_cast<char *>(pl->dev);
+  pl->tiles = reinterpret_cast<BBTile *>(base);
+  pl->cols = reinterpret_cast<int32_t *>(base + pl->o_cols);
+  pl->ncol = reinterpret_cast<int32_t *>(base + pl->o_ncol);
+  pl->row = reinterpret_cast<uint32_t *>(base + pl->o_row);
+  pl->combo = reinterpret_cast<uint32_t *>(base + pl->o_combo);
+  pl->pair = reinterpret_cast<int32_t *>(base + pl->o_pair);
+  auto up = [&](void *dst, const void *src, size_t n) {
+    if (!n) return hipSuccess;
+    return c->pool ? hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice,
+                                    c->ostream)
+                   : hipMemcpy(dst, src, n, hipMemcpyHostToDevice);
+  };
+  if (up(pl->tiles, pl->h_tiles.data(), pl->h_tiles.size() * sizeof(BBTile)) !=
+          hipSuccess ||
+      up(pl->cols, pl->h_cols.data(), pl->h_cols.size() * 4) != hipSuccess ||
+      up(pl->ncol, pl->h_ncol.data(), pl->h_ncol.size() * 4) != hipSuccess ||
+      up(pl->row, pl->h_row.data(), pl->h_row.size() * 4) != hipSuccess ||
+      up(pl->combo, pl->h_combo.data(), pl->h_combo.size() * 4) != hipSuccess ||
+      up(pl->pair, pl->h_pair.data(), pl->h_pair.size() * 4) != hipSuccess)
+    return set_error(c, MNL_ERR_HIP, "uploading beta-beta tables");
+  return MNL_OK;
+}
+
+void bb_plan_free(Ctx *c, BBPlan *pl) {
+  if (pl->dev) {
+    if (c->pool) (void)hipFreeAsync(pl->dev, c->ostream);
+    else (void)hipFree(pl->dev);
+  }
+  delete pl;
+}
+
+int bb_plan_get(Ctx *c, const Dims &d, int prec, BBPlan **out) {
+  if (!c->bb_cache) c->bb_cache = new BBCache;
+  BBCache *cache = static_cast<BBCache *>(c->bb_cache);
+  BBKey key{d.N, d.K, d.p, prec};
+  auto it = cache->plans.find(key);
+  if (it != cache->plans.end()) {
+    *out = it->second;
+    return MNL_OK;
+  }
+  BBPlan *pl = new BBPlan;
+  int rc = bb_plan_host(c, d, prec, pl);
+  if (rc == MNL_OK) rc = bb_plan_upload(c, pl);
+  if (rc != MNL_OK) {
+    bb_plan_free(c, pl);
+    return rc;
+  }
+  cache->plans[key] = pl;
+  *out = pl;
+  return MNL_OK;
+}
+
+struct BBWs {
+  size_t pt, wt, part, xx;
+};
+BBWs bb_ws_bytes(const BBPlan &pl) {
+  const BBConst bc = bb_const(pl.prec);
+  BBWs w;
+  w.pt = size_t(pl.nob) * pl.d.K * bc.kr * bc.esz;
+  w.wt = size_t(pl.nob) * bc.kr * bc.esz;
+  w.part = size_t(pl.S) * pl.Mp * pl.Np * bc.asz;
+  w.xx = size_t(pl.nob) * pl.ncgx * 16 * bc.kr * bc.xsz;
+  return w;
+}
+
+template <int PREC, int TNB>
+hipError_t launch_bb_tnb(const BBPlan &pl, const BBDev &D, hipStream_t s) {
+  hipError_t e = raise_lds_limit(reinterpret_cast<const void *>(&k_bb<PREC, TNB>),
+                                 int(pl.lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_bb<PREC, TNB>), dim3(pl.ntiles), dim3(64 * kWaves),
+                     pl.lds, s, D);
+  return hipGetLastError();
+}
+
+template <int PREC, int TNB = BBT<PREC>::TNMAX>
+hipError_t launch_bb(const BBPlan &pl, const BBDev &D, hipStream_t s) {
+  if (pl.tnb == TNB) return launch_bb_tnb<PREC, TNB>(pl, D, s);
+  if constexpr (TNB > 1) return launch_bb<PREC, TNB - 1>(pl, D, s);
+  return hipErrorInvalidValue;
+}
+
+template <int PREC>
+int bb_run_prec(Ctx *c, const BBPlan &pl, const HessArgs &h, hipStream_t s) {
+  using C = BBT<PREC>;
+  using T = typename C::T;
+  using XT = typename C::XT;
+  // the call's dims (n_p): one cached plan serves every (g, a) of an (N, K, p)
+  const Dims &d = h.d;
+  const BBWs wb = bb_ws_bytes(pl);
+  void *ptv, *partv, *xxv;
+  MNL_TRY(ws_get(c, S_PT, wb.pt + wb.wt + 256, &ptv));
+  MNL_TRY(ws_get(c, S_BBPART, wb.part, &partv));
+  MNL_TRY(ws_get(c, PREC == 0 ? S_XX : S_XX_LP, wb.xx, &xxv));
+  T *PT = static_cast<T *>(ptv);
+  T *WT = reinterpret_cast<T *>(static_cast<char *>(ptv) +
+                                ((wb.pt + 255) & ~size_t(255)));
+  // chi depends on the data only: formed once per top-level call (a fit
+  // reuses it for all of its Hessians)
+  Ctx::XXState &xs = c->xx[PREC == 0 ? 0 : 1];
+  if (!(xs.X == h.X && xs.N == d.N && xs.p == d.p && xs.prec == PREC &&
+        xs.epoch == c->call_epoch && xs.buf == xxv)) {
+    const int64_t total = pl.nob * pl.ncgx * (PREC == 2 ? C::KR / 32 : C::KR / 4) * 64;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL((k_xx_frag<PREC>), dim3(unsigned(blocks)), dim3(256), 0,
+                       s, h.X, d.p, d.N, pl.combo, pl.ncombo, pl.ncgx, pl.nob,
+                       static_cast<XT *>(xxv));
+    MNL_HIP(c, hipGetLastError());
+    xs.X = h.X;
+    xs.N = d.N;
+    xs.p = d.p;
+    xs.prec = PREC;
+    xs.epoch = c->call_epoch;
+    xs.buf = xxv;
+  }
+  hipLaunchKernelGGL((k_p_blocks<T, C::KR>),
+                     dim3(unsigned(pl.nob), unsigned((d.K + 63) / 64)),
+                     dim3(256), 0, s, h.P, h.w, d.K, d.N, PT, WT);
+  MNL_HIP(c, hipGetLastError());
+  BBDev D;
+  D.PT = PT;
+  D.WT = WT;
+  D.XX = xxv;
+  D.tiles = pl.tiles;
+  D.cols = pl.cols;
+  D.ncol = pl.ncol;
+  D.rowinfo = pl.row;
+  D.part = partv;
+  D.Mp = pl.Mp;
+  D.Np = pl.Np;
+  D.K = d.K;
+  D.pcols = pl.pcols;
+  D.ncgx = pl.ncgx;
+  const bool timed = c->ev_ready;
+  if (timed) MNL_HIP(c, hipEventRecord(c->ev_h0, s));
+  MNL_HIP(c, launch_bb<PREC>(pl, D, s));
+  if (timed) {
+    MNL_HIP(c, hipEventRecord(c->ev_h1, s));
+    c->hess_pending = true;
+  }
+  using AT = typename std::conditional<PREC == 0, double, float>::type;
+  const int64_t n = pl.Mp * pl.ncombo;
+  hipLaunchKernelGGL(k_bb_assemble<AT>, dim3(unsigned((n + 255) / 256)),
+                     dim3(256), 0, s, static_cast<const AT *>(partv), pl.S,
+                     pl.Mp, pl.Np, pl.pair, pl.combo, pl.ncombo, int64_t(d.p),
+                     d.np, h.H);
+  MNL_HIP(c, hipGetLastError());
+  return MNL_OK;
+}
+
+}  // namespace
+
+int bb_run(Ctx *c, const HessArgs &h, hipStream_t s) {
+  const Dims &d = h.d;
+  if (d.K < 2 || d.p < 1) return MNL_OK;
+  BBPlan *pl;
+  MNL_TRY(bb_plan_get(c, d, h.prec, &pl));
+  if (h.prec == 0) return bb_run_prec<0>(c, *pl, h, s);
+  if (h.prec == 1) return bb_run_prec<1>(c, *pl, h, s);
+  return bb_run_prec<2>(c, *pl, h, s);
+}
+
+int bb_footprint(Ctx *c, const Dims &d, int prec, size_t *ws_bytes,
+                 size_t *table_bytes) {
+  *ws_bytes = 0;
+  *table_bytes = 0;
+  if (d.K < 2 || d.p < 1) return MNL_OK;
+  BBPlan pl;
+  MNL_TRY(bb_plan_host(c, d, prec, &pl));
+  const BBWs w = bb_ws_bytes(pl);
+  *ws_bytes = (w.pt + w.wt + 512) + w.part + w.xx;
+  *table_bytes = pl.dev_bytes;
+  return MNL_OK;
+}
+
+void bb_cache_free(Ctx *c) {
+  if (!c->bb_cache) return;
+  BBCache *cache = static_cast<BBCache *>(c->bb_cache);
+  for (auto &kv : cache->plans) bb_plan_free(c, kv.second);
+  delete cache;
+  c->bb_cache = nullptr;
+}
+
+}  // namespace mnl

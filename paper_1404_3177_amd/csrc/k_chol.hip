@@ -18,12 +18,10 @@
 //
 // Large systems factor by outer panels of NBO columns: the 32-wide steps
 // update only the columns of their outer panel (all rows below), then one
-// library GEMM (rocBLAS, atomics off) applies L21 (D L21^T) to the trailing
-// square (the upper triangle it also writes is never read: twice the flops
-// of a symmetric update, yet faster than the library's triangular forms),
-// and a small kernel applies the update to the g row.  Each trailing entry
-// is then read and written once per outer panel instead of once per 32-wide
-// step.
+// FP64-MFMA launch (k_chol_syrk) applies L21 (D L21^T) to the lower
+// triangle of the trailing square by 128 x 128 tiles, and a small kernel
+// applies the update to the g row.  Each trailing entry is then read and
+// written once per outer panel instead of once per 32-wide step.
 //
 // The same factorisation gives the summary's standard errors: with n more
 // rows holding the identity below the g row, the augmented factor leaves
@@ -31,8 +29,6 @@
 // the g row), and diag((-H)^{-1}) = diag(L^{-T} D^{-1} L^{-1}) is
 // sum_k X_ik^2 D_k.
 #include <cmath>
-
-#include <rocblas/rocblas.h>
 
 #include "mnl_common.h"
 
@@ -307,9 +303,113 @@ __global__ __launch_bounds__(256) void k_chol_copy(double *A, int64_t n,
     z[c] = c >= j0p ? prev[n * NBF + (c - j0p)] : A[n * n + c];
 }
 
+// Trailing update of an outer panel on FP64 MFMA:
+//   C[r][c] = beta C[r][c] - sum_k A[r][k] B[c][k],  k < kdim,
+// row-major operands with strides lda, ldb, ldc; r < M, c < Nc.  One
+// workgroup per 128 x 128 tile of C (lower: only tiles with tile row >=
+// tile column, the lower triangle of a symmetric update; the upper part of
+// a diagonal tile is written too and never read), four waves of 64 x 64
+// (4 x 4 MFMA tiles of 16 x 16).  The k extent streams through LDS in
+// chunks of 8 (k-major, so each fragment read is 16 consecutive doubles),
+// the next chunk's loads in registers while this chunk's MFMAs run.
+constexpr int SYT = 128;   // tile edge
+constexpr int SYK = 8;     // k chunk
+constexpr int SYP = SYT + 2;   // LDS row length of a k slice (padding)
+__global__ __launch_bounds__(256, 2) void k_chol_syrk(
+    const double *Amat, int64_t lda, const double *Bmat, int64_t ldb,
+    double *C, int64_t ldc, int64_t M, int64_t Nc, int kdim, double beta,
+    int lower, const int32_t *info) {
+  __shared__ double As[2][SYK][SYP];
+  __shared__ double Bs[2][SYK][SYP];
+  if (info[0]) return;
+  // tile of this workgroup
+  int64_t ti, tj;
+  const int64_t b = blockIdx.x;
+  if (lower) {
+    ti = int64_t((sqrt(8.0 * double(b) + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+    while (ti * (ti + 1) / 2 > b) --ti;
+    tj = b - ti * (ti + 1) / 2;
+  } else {
+    const int64_t tcn = (Nc + SYT - 1) / SYT;
+    ti = b / tcn;
+    tj = b - ti * tcn;
+  }
+  const int64_t r0 = ti * SYT, c0 = tj * SYT;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = (wv >> 1) * 64, wc = (wv & 1) * 64;
+  // loads: thread -> rows (tid >> 2) + 64 u, k pair 2 (tid & 3) of a chunk
+  const int lr = tid >> 2, lk = 2 * (tid & 3);
+  double2 ra[2], rb[2];
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t r = r0 + lr + 64 * u, c = c0 + lr + 64 * u;
+      ra[u] = r < M ? *reinterpret_cast<const double2 *>(Amat + r * lda + kc + lk)
+                    : double2{0.0, 0.0};
+      rb[u] = c < Nc ? *reinterpret_cast<const double2 *>(Bmat + c * ldb + kc + lk)
+                     : double2{0.0, 0.0};
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      As[buf][lk][lr + 64 * u] = ra[u].x;
+      As[buf][lk + 1][lr + 64 * u] = ra[u].y;
+      Bs[buf][lk][lr + 64 * u] = rb[u].x;
+      Bs[buf][lk + 1][lr + 64 * u] = rb[u].y;
+    }
+  };
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  const int nch = kdim / SYK;
+  load(0);
+  store(0);
+  __syncthreads();
+  const int kb = lane >> 4, l16 = lane & 15;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int cur = ch & 1;
+    if (ch + 1 < nch) load((ch + 1) * SYK);
+#pragma unroll
+    for (int ks = 0; ks < SYK / 4; ++ks) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[cur][4 * ks + kb][wr + 16 * i + l16];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[cur][4 * ks + kb][wc + 16 * j + l16];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j],
+                                                           acc[i][j], 0, 0, 0);
+    }
+    if (ch + 1 < nch) store(cur ^ 1);
+    __syncthreads();
+  }
+  // lane holds rows (lane >> 4) + 4 q of each 16 x 16 tile, column lane & 15
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t c = c0 + wc + 16 * j + l16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = r0 + wr + 16 * i + kb + 4 * q;
+        if (r < M && c < Nc) {
+          double *cp = C + r * ldc + c;
+          *cp = beta * *cp - acc[i][j][q];
+        }
+      }
+    }
+}
+
 // Operands of an outer panel's trailing update, columns [J0, J0 + NBO):
 // W[i][k] = L[J1 + i][J0 + k] D_k for the trailing rows i < n - J1 (the
-// library update then forms L21 W^T), and the g row's own update
+// trailing update then forms L21 W^T), and the g row's own update
 // A[n][j] -= sum_k L[j][J0 + k] D_k y_k, one wave per column j, the 256
 // products summed in a fixed order.  Blocks [0, nbw) form W, the rest the
 // g row.
@@ -533,12 +633,6 @@ int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
   double *z = pbuf[1] + nrows * NBF;
   double *floor_p = z + n;
   double *W = floor_p + 8;
-  rocblas_handle hb = nullptr;
-  if (outer) {
-    void *hv;
-    MNL_TRY(blas_get(c, s, &hv));
-    hb = static_cast<rocblas_handle>(hv);
-  }
   hipLaunchKernelGGL(k_floor, dim3(1), dim3(256), 0, s, A, n, g, floor_p,
                      info);
   if (extra) {
@@ -568,9 +662,9 @@ int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
     }
     if (last_outer) break;
     // close the outer panel: its last step's factor into A, the operands of
-    // the trailing update, then A22 -= L21 D L21^T (column-major view of the
-    // row-major buffer; the first panel's trailing block still holds H:
-    // beta = -1 forms A = -H on the way)
+    // the trailing update, then A22 -= L21 D L21^T on the lower triangle
+    // (the first panel's trailing block still holds H: beta = -1 forms
+    // A = -H on the way)
     {
       const int64_t cnt = (nrows - j0p) * NBF;
       const unsigned gr = (unsigned)std::min<int64_t>(1024, (cnt + 255) / 256);
@@ -582,26 +676,22 @@ int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
     const int64_t nbw = (m * NBO + 255) / 256, nbg = (m + 3) / 4;
     hipLaunchKernelGGL(k_outer_prep, dim3((unsigned)(nbw + nbg)), dim3(256), 0,
                        s, A, n, J0, W, nbw, info);
-    const double alpha = -1.0, beta = J0 == 0 ? -1.0 : 1.0;
-    const rocblas_status st = rocblas_dgemm(
-        hb, rocblas_operation_transpose, rocblas_operation_none, rocblas_int(m),
-        rocblas_int(m), rocblas_int(NBO), &alpha, A + J1 * n + J0,
-        rocblas_int(n), W, rocblas_int(NBO), &beta, A + J1 * n + J1,
-        rocblas_int(n));
-    if (st != rocblas_status_success)
-      return set_error(c, MNL_ERR_HIP, "rocblas_dgemm failed (%d)", int(st));
+    const double beta = J0 == 0 ? -1.0 : 1.0;
+    {
+      const int64_t T = (m + SYT - 1) / SYT;
+      hipLaunchKernelGGL(k_chol_syrk, dim3((unsigned)(T * (T + 1) / 2)),
+                         dim3(256), 0, s, A + J1 * n + J0, n, W,
+                         int64_t(NBO), A + J1 * n + J1, n, m, m, NBO, beta, 1,
+                         info);
+    }
     if (extra) {
       // identity rows: X[:, J1:n] -= X[:, J0:J1] (L21 D)^T, the same update
       // as the g row's (these rows are never negated, so beta = 1)
-      const double one = 1.0;
       double *Xr = A + (n + 1) * n;
-      const rocblas_status sx = rocblas_dgemm(
-          hb, rocblas_operation_transpose, rocblas_operation_none,
-          rocblas_int(m), rocblas_int(extra), rocblas_int(NBO), &alpha, W,
-          rocblas_int(NBO), Xr + J0, rocblas_int(n), &one, Xr + J1,
-          rocblas_int(n));
-      if (sx != rocblas_status_success)
-        return set_error(c, MNL_ERR_HIP, "rocblas_dgemm failed (%d)", int(sx));
+      const int64_t T = ((extra + SYT - 1) / SYT) * ((m + SYT - 1) / SYT);
+      hipLaunchKernelGGL(k_chol_syrk, dim3((unsigned)T), dim3(256), 0, s,
+                         Xr + J0, n, W, int64_t(NBO), Xr + J1, n, extra, m,
+                         NBO, 1.0, 0, info);
     }
   }
   {

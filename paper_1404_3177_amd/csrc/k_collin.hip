@@ -267,7 +267,7 @@ int collinear_run(Ctx *c, const Dims &d, const mnl_problem *pr, double tol,
   if (g > 0 && st == rocblas_status_success) {
     const int64_t rows = N * (K - 1);
     MNL_TRY(ws_get(c, S_XX, size_t(rows) * g * 8 + 8, &yv));
-    c->xx_epoch = ~uint64_t(0);   // the X o X cache no longer holds its data
+    c->xx[0].epoch = ~uint64_t(0);   // the FP64 chi no longer holds its data
     hipLaunchKernelGGL(k_ydiff, dim3(grid_for(rows * g)), dim3(256), 0, s,
                        pr->Y, N, K, g, (double *)yv);
     if (rows > 0)

@@ -10,29 +10,18 @@
 //   H_{alpha,alpha}   = -sum_i w_i sum_k P_ik (y_ik - ybar_i)(y_ik - ybar_i)^T
 //
 // Work split (A = -H is accumulated, H written at the end):
-//  * BB tiles (beta-beta, the bulk): one GEMM C = Omega^T (X o X) whose
-//    rows are alternative pairs n <= m (omega_i = w P_n (delta - P_m)) and
-//    whose columns are feature pairs a <= b (x_a x_b).  Both operands are
-//    generated on the fly from LDS-staged P and X, so each block's two
-//    symmetries (H_nm = H_mn^T and X^T W X symmetric) are used and the
-//    per-observation weights W_nm are never stored.
+//  * beta-beta blocks (the bulk): k_bb.hip;
 //  * XG tiles (beta-gamma and gamma-gamma): C = sum_i (w P_n phi_n)(P_m z_m)
 //    for rows over all alternative-specific coefficients and columns over
-//    the gamma coefficients (upper triangle only for gamma-gamma).
+//    the gamma coefficients (upper triangle only for gamma-gamma), on MFMA
+//    (FP64, FP32 or BF16 operands) from LDS-staged P, X and Z, split over
+//    observations; the split partials are summed in a fixed order, so the
+//    result is reproducible;
 //  * per-alternative kernel: the delta_nm parts of the XG blocks
 //    (sum_i w P_n phi_n z_n^T) and all alpha blocks.
-// Tiles of both GEMM kinds run in one launch on MFMA (FP64, FP32 or BF16
-// operands), split over observations; the split partials are summed in a
-// fixed order, so the result is reproducible.
-//  * for large beta-beta products (many pairs x many feature pairs) the two
-//    operands are materialised instead: X o X once per fit and Omega in
-//    chunks of observations, and the product is a plain library GEMM
-//    (rocBLAS, atomics off, chunks accumulated in a fixed order).
 #include <algorithm>
 #include <map>
 #include <tuple>
-
-#include <rocblas/rocblas.h>
 
 #include "mnl_common.h"
 
@@ -642,100 +631,6 @@ __global__ __launch_bounds__(kThreads) void k_hess_alt(
   }
 }
 
-// Materialised beta-beta operands.  Omega rows follow the plan's pair rows
-// (0 entries are padding): om[j][r] = w_i P_in (delta_nm - P_im) for the
-// observations i = i0 + j of one chunk, in the precision the tile kernels
-// use for it (FP64 from P, else FP32 from P32), stored in the operand type
-// with row stride ld (a multiple of 8).  A workgroup stages the P rows and
-// weights of `ob` observations in LDS; each thread owns 8 consecutive pair
-// rows and writes them as one vector per observation.
-template <typename OT, typename CT>
-__global__ __launch_bounds__(256) void k_form_omega(
-    int K, const double *P, const float *P32, const double *w,
-    const int32_t *pair_nm, int64_t nrow, int64_t ld, int64_t i0, int nc,
-    int ob, OT *om) {
-  typedef OT ov8 __attribute__((ext_vector_type(8)));
-  extern __shared__ double smo[];
-  CT *Ps = reinterpret_cast<CT *>(smo);   // [ob][K]
-  CT *Ws = Ps + ob * K;                    // [ob]
-  const int tid = threadIdx.x;
-  const int64_t r0 = (int64_t(blockIdx.x) * 256 + tid) * 8;
-  const bool mine = r0 < ld;
-  int nn[8], mm[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int32_t pm = (mine && r0 + q < nrow) ? pair_nm[r0 + q] : 0;
-    nn[q] = pm & 0xffff;
-    mm[q] = pm >> 16;   // 0 with nn: a padding row
-  }
-  const int nblk = (nc + ob - 1) / ob;
-  for (int bj = blockIdx.y; bj < nblk; bj += gridDim.y) {
-    const int j0 = bj * ob;
-    const int nj = min(ob, nc - j0);
-    const int64_t ib = i0 + j0;
-    __syncthreads();   // the previous block's rows are no longer read
-    for (int e = tid; e < nj * K; e += 256)
-      Ps[e] = P32 ? CT(P32[ib * K + e]) : CT(P[ib * K + e]);
-    for (int e = tid; e < nj; e += 256) Ws[e] = w ? CT(w[ib + e]) : CT(1);
-    __syncthreads();
-    if (!mine) continue;
-    for (int jj = 0; jj < nj; ++jj) {
-      const CT wj = Ws[jj];
-      const CT *Pj = Ps + jj * K;
-      ov8 v;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const bool ok = nn[q] != 0;   // every valid pair row has n >= 1
-        const CT pn = Pj[nn[q]], pmv = Pj[mm[q]];
-        v[q] = ok ? OT(wj * pn * ((nn[q] == mm[q] ? CT(1) : CT(0)) - pmv))
-                  : OT(0);
-      }
-      *reinterpret_cast<ov8 *>(om + int64_t(j0 + jj) * ld + r0) = v;
-    }
-  }
-}
-
-// xx[i][q] = x_ia x_ib for feature pair q = (a, b), row stride ld (a
-// multiple of 8): iteration-invariant.  A workgroup stages the X rows of
-// `ob` observations at a time; each thread owns 8 consecutive pairs.
-template <typename OT, typename CT>
-__global__ __launch_bounds__(256) void k_form_xx(const double *X, int p,
-                                                 const uint32_t *combo,
-                                                 int64_t ncombo, int64_t ld,
-                                                 int64_t N, int ob, OT *xx) {
-  typedef OT ov8 __attribute__((ext_vector_type(8)));
-  extern __shared__ double smx[];   // [ob][p]
-  const int tid = threadIdx.x;
-  const int64_t q0 = (int64_t(blockIdx.x) * 256 + tid) * 8;
-  const bool mine = q0 < ld;
-  int fa[8], fb[8];
-  bool ok[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    ok[q] = mine && q0 + q < ncombo;
-    const uint32_t cq = ok[q] ? combo[q0 + q] : 0u;
-    fa[q] = int(cq & 0xffff);
-    fb[q] = int(cq >> 16);
-  }
-  const int64_t nblk = (N + ob - 1) / ob;
-  for (int64_t bj = blockIdx.y; bj < nblk; bj += gridDim.y) {
-    const int64_t ib = bj * ob;
-    const int nj = int(min<int64_t>(ob, N - ib));
-    __syncthreads();
-    for (int e = tid; e < nj * p; e += 256) smx[e] = X[ib * p + e];
-    __syncthreads();
-    if (!mine) continue;
-    for (int jj = 0; jj < nj; ++jj) {
-      const double *xr = smx + jj * p;
-      ov8 v;
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        v[q] = ok[q] ? OT(CT(xr[fa[q]] * xr[fb[q]])) : OT(0);
-      *reinterpret_cast<ov8 *>(xx + (ib + jj) * ld + q0) = v;
-    }
-  }
-}
-
 // sum the observation splits of the per-alternative sums in a fixed order
 __global__ void k_alt_reduce(const double *alt, int S, int64_t n,
                              double *red) {
@@ -864,8 +759,6 @@ struct Plan {
   int kc_bb = 4, kc_xg = 4, pstride_bb = 1, bb_full = 0;
   int nbuf_bb = 1, nbuf_xg = 1;
   int tn = 1;                    // 16-column MFMA tiles per workgroup tile
-  bool bb_gemm = false;          // beta-beta by materialised operands + GEMM
-  int64_t gemm_nc = 0;           // observations per Omega chunk
   // alt kernel
   int alt_nb = 1, alt_S = 1, alt_nrt = 1, alt_ngrp = 1;
   int64_t alt_chunk = 0;
@@ -889,6 +782,8 @@ struct Cache {
   std::map<Key, Plan *> plans;
 };
 
+}  // namespace
+
 // Compute units of the context's device (256 on MI355X when the device
 // cannot be queried, e.g. for host-only footprint queries).
 int device_cus(Ctx *c) {
@@ -902,6 +797,8 @@ int device_cus(Ctx *c) {
   c->ncu = n;
   return n;
 }
+
+namespace {
 
 // Host part of a plan: tiling, split counts, LDS sizes and the tile tables
 // (in pl's host vectors).  On error the caller deletes pl.
@@ -923,9 +820,8 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
   auto n16_of = [](int64_t ncols) { return (ncols + 15) / 16; };
   int tnu = 1;
   {
-    const int64_t ncombo0 = p > 0 ? int64_t(p) * (p + 1) / 2 : 0;
     const int64_t ncolxg0 = a > 0 ? int64_t(K) * a : 0;
-    for (const int64_t n16 : {n16_of(ncombo0), n16_of(ncolxg0)}) {
+    for (const int64_t n16 : {n16_of(ncolxg0)}) {
       if (n16 == 0) continue;
       const int64_t nct = (n16 + TNMAX - 1) / TNMAX;
       tnu = std::max(tnu, int((n16 + nct - 1) / nct));
@@ -937,80 +833,19 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
     return (n16_of(ncols) + tnu - 1) / tnu;
   };
 
-  // BB rows: pairs n <= m over alternatives 1..K-1.  Row-major, or, when
-  // there are many alternatives, in blocks of (kRows / 16) x 16
-  // alternatives, one block per row tile, so that a tile stages the P
-  // columns of its two blocks only (padding rows are 0)
-  std::vector<int32_t> pair_nm;
-  bool blocked = false;
-  {
-    const int Lk = K - 1, bh = kRows / 16, bw = 16;
-    int64_t rows_blk = 0;
-    for (int bi = 0; 1 + bi * bh <= Lk; ++bi)
-      for (int bj = 0; 1 + bj * bw <= Lk; ++bj)
-        if (1 + bi * bh <= bj * bw + bw) rows_blk += kRows;
-    const double pairs = double(Lk) * (Lk + 1) / 2.0;
-    blocked = p > 0 && Lk > 2 * bw && double(rows_blk) <= 1.15 * pairs;
-    if (blocked) {
-      for (int bi = 0; 1 + bi * bh <= Lk; ++bi)
-        for (int bj = 0; 1 + bj * bw <= Lk; ++bj) {
-          if (1 + bi * bh > bj * bw + bw) continue;
-          for (int dn = 0; dn < bh; ++dn)
-            for (int dm = 0; dm < bw; ++dm) {
-              const int n = 1 + bi * bh + dn, m = 1 + bj * bw + dm;
-              pair_nm.push_back((n <= Lk && m <= Lk && n <= m)
-                                    ? (n | (m << 16)) : 0);
-            }
-        }
-    } else {
-      for (int n = 1; n < K; ++n)
-        for (int m = n; m < K; ++m) pair_nm.push_back(n | (m << 16));
-    }
-  }
-  const int64_t nrow_bb = p > 0 ? int64_t(pair_nm.size()) : 0;
-  std::vector<uint32_t> combo;
-  for (int fa = 0; fa < p; ++fa)
-    for (int fb = fa; fb < p; ++fb) combo.push_back(uint32_t(fa) | (uint32_t(fb) << 16));
-  const int64_t ncombo = int64_t(combo.size());
-  const int64_t nrt_bb = (nrow_bb + kRows - 1) / kRows;
-  int tn_bb = 1;
-  const int64_t nct_bb = col_tiling(ncombo, &tn_bb);
-  const int cw_bb = 16 * tn_bb;
-  std::vector<int32_t> bb_cols(std::max<int64_t>(nrt_bb, 1) * kMaxCols, 0);
-  std::vector<int32_t> bb_ncol(std::max<int64_t>(nrt_bb, 1), 0);
-  std::vector<uint32_t> bb_row(std::max<int64_t>(nrow_bb, 1), 0);
-  pl->bb_full = (!blocked && K <= kMaxCols) ? 1 : 0;
+  // the beta-beta blocks are formed by k_bb.hip: no BB tiles here
+  std::vector<int32_t> pair_nm, bb_cols(kMaxCols, 0), bb_ncol(1, 0);
+  std::vector<uint32_t> combo, bb_row(1, 0);
+  const int64_t nrow_bb = 0, nrt_bb = 0;
   if (K > 4095) {
     return set_error(c, MNL_ERR_UNSUPPORTED, "Hessian tiles need K < 4096");
   }
-  for (int64_t t = 0; t < nrt_bb; ++t) {
-    std::vector<int> alts;
-    const int64_t r1 = std::min<int64_t>(nrow_bb, (t + 1) * kRows);
-    if (pl->bb_full) {
-      for (int k = 0; k < K; ++k) alts.push_back(k);
-    } else {
-      for (int64_t r = t * kRows; r < r1; ++r) {
-        if (pair_nm[r] == 0) continue;
-        alts.push_back(pair_nm[r] & 0xffff);
-        alts.push_back(pair_nm[r] >> 16);
-      }
-    }
-    std::sort(alts.begin(), alts.end());
-    alts.erase(std::unique(alts.begin(), alts.end()), alts.end());
-    bb_ncol[t] = int(alts.size());
-    for (size_t q = 0; q < alts.size(); ++q) bb_cols[t * kMaxCols + q] = alts[q];
-    for (int64_t r = t * kRows; r < r1; ++r) {
-      if (pair_nm[r] == 0) continue;   // padding row: not valid
-      const int n = pair_nm[r] & 0xffff, m = pair_nm[r] >> 16;
-      const uint32_t ln = uint32_t(std::lower_bound(alts.begin(), alts.end(), n) - alts.begin());
-      const uint32_t lm = uint32_t(std::lower_bound(alts.begin(), alts.end(), m) - alts.begin());
-      bb_row[r] = ln | (lm << 12) | (uint32_t(n == m) << 24) | (1u << 25);
-    }
-  }
-  pl->nrow_bb = nrow_bb;
-  pl->ncombo = ncombo;
-  pl->bb_M = nrt_bb * kRows;
-  pl->bb_N = std::max<int64_t>(nct_bb * cw_bb, 16);
+  pl->bb_full = 1;
+  pl->nrow_bb = 0;
+  pl->ncombo = 0;
+  pl->bb_M = 0;
+  pl->bb_N = 16;
+  const int cw_bb = 16 * tnu;
 
   // XG rows: all alternative-specific coefficients; columns: gamma ones
   const int64_t offg = d.off_gamma();
@@ -1025,29 +860,9 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
   pl->xg_M = nrt_xg * kRows;
   pl->xg_N = std::max<int64_t>(nct_xg * cw_xg, 16);
 
-  // large beta-beta products go to a library GEMM on materialised
-  // operands (where it runs faster than the generated-operand tiles:
-  // always for BF16, for FP32 / FP64 with many feature pairs)
-  {
-    const double bbsz = double(nrow_bb) * double(ncombo);
-    pl->bb_gemm = nrow_bb > 0 &&
-                  ((prec == 2 && bbsz >= 1e6) ||
-                   (prec != 2 && ncombo >= 512 && bbsz >= 2e6));
-    if (pl->bb_gemm) {
-      const size_t osz = prec == 2 ? 2 : (prec == 1 ? 4 : 8);
-      int64_t nc = int64_t((size_t(1) << 30) / (size_t(nrow_bb) * osz));
-      nc = std::max<int64_t>(256, nc / 256 * 256);
-      pl->gemm_nc = std::min<int64_t>(nc, d.N);
-    }
-  }
-
   // output tiles, then observation splits
   struct OutTile { int type, row0, col0, tn; };
   std::vector<OutTile> out_tiles;
-  if (!pl->bb_gemm)
-    for (int64_t rt = 0; rt < nrt_bb; ++rt)
-      for (int64_t ct = 0; ct < nct_bb; ++ct)
-        out_tiles.push_back({T_BB, int(rt * kRows), int(ct * cw_bb), tn_bb});
   for (int64_t rt = 0; rt < nrt_xg; ++rt)
     for (int64_t ct = 0; ct < nct_xg; ++ct) {
       const int64_t r0 = rt * kRows, c0 = ct * cw_xg;
@@ -1284,19 +1099,11 @@ int build_plan(Ctx *c, const Dims &d, int prec, Plan **out) {
 struct PartLayout {
   size_t o_xg, o_alt, o_red, total, n_alt;
 };
-// leading dimension of a materialised GEMM operand: a multiple of 8
-// elements, so that 8-element vector stores stay aligned
-int64_t gemm_ld(int64_t n) { return (n + 7) / 8 * 8; }
 
 PartLayout part_layout(const Plan &pl) {
   const Dims &d = pl.d;
   const size_t asz = pl.prec == 0 ? 8 : 4;
-  const size_t osz = pl.prec == 2 ? 2 : asz;
-  // GEMM mode: the product [nrow][ncombo] then one Omega chunk
-  const size_t bytes_bb =
-      pl.bb_gemm ? ((size_t(pl.nrow_bb) * pl.ncombo * asz + 255) & ~size_t(255)) +
-                       size_t(pl.gemm_nc) * gemm_ld(pl.nrow_bb) * osz
-                 : size_t(pl.S) * pl.bb_M * pl.bb_N * asz;
+  const size_t bytes_bb = 0;
   const size_t bytes_xg = size_t(pl.S) * pl.xg_M * pl.xg_N * asz;
   const int nl = d.p + d.a + d.g, nr = d.a + d.g;
   PartLayout L;
@@ -1358,16 +1165,6 @@ template <typename AccT>
 hipError_t launch_assemble(const Plan &pl, const HessArgs &h, void *pbb,
                            void *pxg, const double *alt, hipStream_t s) {
   const Dims &d = pl.d;
-  if (pl.nrow_bb > 0) {
-    // tile partials [S][bb_M][bb_N], or the GEMM product [nrow][ncombo]
-    const int Sb = pl.bb_gemm ? 1 : pl.S;
-    const int64_t Mp = pl.bb_gemm ? pl.nrow_bb : pl.bb_M;
-    const int64_t Np = pl.bb_gemm ? pl.ncombo : pl.bb_N;
-    const int64_t n = pl.nrow_bb * pl.ncombo;
-    hipLaunchKernelGGL(k_assemble_bb<AccT>, dim3((unsigned)((n + 255) / 256)),
-                       dim3(256), 0, s, d, (const AccT *)pbb, Sb, Mp, Np,
-                       pl.pair_nm, pl.bb_combo, pl.nrow_bb, pl.ncombo, h.H);
-  }
   if (pl.nrow_xg > 0) {
     const int64_t n = pl.nrow_xg * pl.ncol_xg;
     hipLaunchKernelGGL(k_assemble_xg<AccT>, dim3((unsigned)((n + 255) / 256)),
@@ -1383,79 +1180,6 @@ hipError_t launch_assemble(const Plan &pl, const HessArgs &h, void *pbb,
 }
 
 }  // namespace
-
-// The beta-beta product by materialised operands: X o X (once per call
-// epoch of the context, reused by every Hessian of a fit), Omega chunk by
-// chunk, C = sum over chunks of (X o X)^T Omega on rocBLAS (column-major:
-// C^T [ncombo x nrow] = XX_chunk [ncombo x nc] * Omega_chunk^T).
-template <typename OT, typename CT>
-int bb_gemm_run(Ctx *c, const Plan &pl, const HessArgs &h, void *cbuf,
-                void *omega, hipStream_t s) {
-  const Dims &d = pl.d;
-  const int64_t nrow = pl.nrow_bb, ncombo = pl.ncombo;
-  const int64_t ldx = gemm_ld(ncombo), ldo = gemm_ld(nrow);
-  void *xxv;
-  MNL_TRY(ws_get(c, S_XX, size_t(d.N) * ldx * sizeof(OT), &xxv));
-  OT *xx = static_cast<OT *>(xxv);
-  if (!(c->xx_X == h.X && c->xx_N == d.N && c->xx_p == d.p &&
-        c->xx_prec == h.prec && c->xx_epoch == c->call_epoch &&
-        c->xx_buf == xxv)) {
-    const int obx = 32;
-    dim3 grid((unsigned)((ldx / 8 + 255) / 256),
-              (unsigned)std::min<int64_t>((d.N + obx - 1) / obx, 8192));
-    hipLaunchKernelGGL((k_form_xx<OT, CT>), grid, dim3(256),
-                       size_t(obx) * d.p * 8, s, h.X, d.p, pl.bb_combo,
-                       ncombo, ldx, d.N, obx, xx);
-    MNL_HIP(c, hipGetLastError());
-    c->xx_X = h.X;
-    c->xx_N = d.N;
-    c->xx_p = d.p;
-    c->xx_prec = h.prec;
-    c->xx_epoch = c->call_epoch;
-    c->xx_buf = xxv;
-  }
-  void *hv;
-  MNL_TRY(blas_get(c, s, &hv));
-  rocblas_handle hb = static_cast<rocblas_handle>(hv);
-  const rocblas_datatype ab =
-      h.prec == 2 ? rocblas_datatype_bf16_r
-                  : (h.prec == 1 ? rocblas_datatype_f32_r
-                                 : rocblas_datatype_f64_r);
-  const rocblas_datatype ct =
-      h.prec == 0 ? rocblas_datatype_f64_r : rocblas_datatype_f32_r;
-  const CT one = CT(1), zero = CT(0);
-  OT *om = static_cast<OT *>(omega);
-  // observations per Omega workgroup: their P rows in at most 64 KB of LDS
-  const int obo = int(std::max<int64_t>(
-      1, std::min<int64_t>(32, (64 * 1024) / (int64_t(d.K) * sizeof(CT) + 8))));
-  const size_t lds_o = size_t(obo) * (d.K + 1) * sizeof(CT);
-  for (int64_t i0 = 0; i0 < d.N; i0 += pl.gemm_nc) {
-    const int nc = int(std::min<int64_t>(pl.gemm_nc, d.N - i0));
-    dim3 grid((unsigned)((ldo / 8 + 255) / 256),
-              (unsigned)std::min<int64_t>((nc + obo - 1) / obo, 8192));
-    hipLaunchKernelGGL((k_form_omega<OT, CT>), grid, dim3(256), lds_o, s, d.K,
-                       h.prec == 0 ? h.P : nullptr,
-                       h.prec == 0 ? nullptr : h.P32, h.w, pl.pair_nm, nrow,
-                       ldo, i0, nc, obo, om);
-    MNL_HIP(c, hipGetLastError());
-    const rocblas_status st = rocblas_gemm_ex(
-        hb, rocblas_operation_none, rocblas_operation_transpose,
-        rocblas_int(ncombo), rocblas_int(nrow), rocblas_int(nc), &one,
-        xx + i0 * ldx, ab, rocblas_int(ldx), om, ab, rocblas_int(ldo),
-        i0 == 0 ? &zero : &one, cbuf, ct, rocblas_int(ncombo), cbuf, ct,
-        rocblas_int(ncombo), ct, rocblas_gemm_algo_standard, 0, 0);
-    if (st != rocblas_status_success)
-      return set_error(c, MNL_ERR_HIP, "rocblas_gemm_ex failed (%d)", int(st));
-  }
-  return MNL_OK;
-}
-
-int hessian_uses_library(Ctx *c, const Dims &d, int prec, bool *uses) {
-  Plan *pl;
-  MNL_TRY(build_plan(c, d, prec, &pl));
-  *uses = pl->bb_gemm;
-  return MNL_OK;
-}
 
 int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   Plan *pl;
@@ -1477,21 +1201,8 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
                        alt);
     MNL_HIP(c, hipGetLastError());
   }
-  // the timed span: the beta-beta GEMM (if any) and the tiles
-  const bool timed = c->ev_ready && (pl->ntiles > 0 || pl->bb_gemm);
-  if (timed) MNL_HIP(c, hipEventRecord(c->ev_h0, s));
-  if (pl->bb_gemm) {
-    // product first, then the Omega chunk buffer (see part_layout)
-    const size_t asz = h.prec == 0 ? 8 : 4;
-    const size_t cbytes =
-        (size_t(pl->nrow_bb) * pl->ncombo * asz + 255) & ~size_t(255);
-    if (h.prec == 0)
-      MNL_TRY((bb_gemm_run<double, double>(c, *pl, h, pbb, wb + cbytes, s)));
-    else if (h.prec == 1)
-      MNL_TRY((bb_gemm_run<float, float>(c, *pl, h, pbb, wb + cbytes, s)));
-    else
-      MNL_TRY((bb_gemm_run<__bf16, float>(c, *pl, h, pbb, wb + cbytes, s)));
-  }
+  // beta-beta blocks (timed: the Hessian's dominant kernel)
+  MNL_TRY(bb_run(c, h, s));
   HessDev hd;
   hd.d = d;
   hd.X = h.X;
@@ -1527,10 +1238,6 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   } else {
     MNL_HIP(c, launch_tiles<2>(*pl, hd, s));
   }
-  if (timed) {
-    MNL_HIP(c, hipEventRecord(c->ev_h1, s));
-    c->hess_pending = true;
-  }
   if (h.prec == 0)
     MNL_HIP(c, (launch_assemble<double>(*pl, h, pbb, pxg, alt, s)));
   else
@@ -1550,11 +1257,10 @@ int hessian_footprint(Ctx *c, const Dims &d, int prec, size_t *part_bytes,
                       size_t *table_bytes) {
   Plan pl;
   MNL_TRY(plan_host(c, d, prec, &pl));
-  *part_bytes = part_layout(pl).total;
-  *table_bytes = pl.dev_bytes;
-  if (pl.bb_gemm)  // X o X of the materialised product (workspace slot S_XX)
-    *table_bytes += size_t(d.N) * gemm_ld(pl.ncombo) *
-                    (prec == 2 ? 2 : (prec == 1 ? 4 : 8));
+  size_t bb_ws = 0, bb_tab = 0;
+  MNL_TRY(bb_footprint(c, d, prec, &bb_ws, &bb_tab));
+  *part_bytes = part_layout(pl).total + bb_ws;
+  *table_bytes = pl.dev_bytes + bb_tab;
   return MNL_OK;
 }
 

@@ -86,6 +86,7 @@ void ctx_release(Ctx *c) {
   }
   c->total_bytes = 0;
   hessian_cache_free(c);
+  bb_cache_free(c);
 }
 
 int blas_get(Ctx *c, hipStream_t s, void **handle) {
@@ -574,11 +575,6 @@ int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
   // whose Hessian and factorisation make no library calls
   bool graph_ok = o.graph != 0 && s != nullptr &&
                   o.method == MNL_METHOD_NEWTON && d.np < 2048 && !one_step;
-  if (graph_ok) {
-    bool lib = false;
-    MNL_TRY(hessian_uses_library(c, d, o.prec, &lib));
-    graph_ok = !lib;
-  }
   if (graph_ok && !c->pinned) {
     if (hipHostMalloc(reinterpret_cast<void **>(&c->pinned), 256) !=
         hipSuccess) {
@@ -666,10 +662,9 @@ int fit_workspace_footprint(Ctx *c, const Dims &d, int prec, size_t *bytes) {
   if (prec != MNL_PREC_FP64) {
     size_t part64 = 0, tab64 = 0;
     MNL_TRY(hessian_footprint(c, d, MNL_PREC_FP64, &part64, &tab64));
-    // the FP64 partials replace the mixed ones (the slot grows), the FP64
-    // tables come on top
-    if (part64 > part) t += al(part64);
-    t += al(tab64);
+    // an upper bound: the FP64 retry's partials, P blocks, chi operand
+    // (a slot of its own) and tables on top of the mixed ones
+    t += al(part64) + al(tab64);
   }
   *bytes = t;
   return MNL_OK;
@@ -743,6 +738,7 @@ int factor_with_identity(Ctx *c, const Dims &d, const mnl_problem *prob,
   return MNL_OK;
 }
 }  // namespace
+
 }  // namespace mnl
 
 using namespace mnl;

@@ -155,10 +155,17 @@ struct HessArgs {
   int prec;
 };
 int hessian_run(Ctx *c, const HessArgs &a, hipStream_t s);
-// Whether the Hessian of this shape and precision calls a library GEMM
-// (such steps are not captured into graphs).
-int hessian_uses_library(Ctx *c, const Dims &d, int prec, bool *uses);
 void hessian_cache_free(Ctx *c);
+// Beta-beta blocks of H (k_bb.hip): written into a.H; the kernel is timed
+// by the context's Hessian events.
+int bb_run(Ctx *c, const HessArgs &a, hipStream_t s);
+// Workspace (P blocks, split partials, chi operand) and table bytes of
+// bb_run for a shape.
+int bb_footprint(Ctx *c, const Dims &d, int prec, size_t *ws_bytes,
+                 size_t *table_bytes);
+void bb_cache_free(Ctx *c);
+// Compute units of the context's device (256 when it cannot be queried).
+int device_cus(Ctx *c);
 // The context's library BLAS handle (rocBLAS, atomics off), bound to
 // stream s; created on first use.
 int blas_get(Ctx *c, hipStream_t s, void **handle);
@@ -240,6 +247,7 @@ struct Ctx {
   bool hess_pending = false, pass_pending = false;
   // host-side caches of Hessian tile tables (keyed by shape)
   void *hess_cache = nullptr;
+  void *bb_cache = nullptr;
   // stream-ordered mode (server slots): device memory comes from `pool`,
   // allocated and freed in the order of `ostream`, the only stream the
   // context's work runs on
@@ -248,13 +256,19 @@ struct Ctx {
   int ncu = 0;   // compute units of `device` (0: not queried yet)
   // library GEMM handle (rocBLAS), created on first use
   void *blas = nullptr;
-  // X o X of the materialised beta-beta product, valid within one call
-  // epoch (one top-level API call: a fit reuses it across its Hessians)
-  uint64_t call_epoch = 0, xx_epoch = ~uint64_t(0);
-  const double *xx_X = nullptr;
-  const void *xx_buf = nullptr;
-  int64_t xx_N = 0;
-  int xx_p = 0, xx_prec = -1;
+  // the beta-beta operand chi = x_a x_b (k_bb.hip), valid within one call
+  // epoch (one top-level API call: a fit reuses it across its Hessians);
+  // [0]: FP64 (workspace slot S_XX), [1]: FP32 / BF16 (slot S_XX_LP).  A
+  // mixed-precision fit's FP64 retries keep their own copy, so a captured
+  // mixed step never reads an operand of the other type
+  uint64_t call_epoch = 0;
+  struct XXState {
+    uint64_t epoch = ~uint64_t(0);
+    const double *X = nullptr;
+    const void *buf = nullptr;
+    int64_t N = 0;
+    int p = 0, prec = -1;
+  } xx[2];
 };
 
 // Raise a kernel's dynamic-LDS limit on the current device to at least
@@ -298,7 +312,10 @@ enum Slot {
   S_HTAB,          // Hessian tile tables
   S_CHOL,          // Cholesky scratch
   S_THETA0,        // zero start
-  S_XX,            // X o X operand of the materialised beta-beta product
+  S_XX,            // chi = x_a x_b operand of the beta-beta product, FP64
+  S_XX_LP,         // the same in FP32 / BF16
+  S_PT,            // P and weights by observation blocks (beta-beta)
+  S_BBPART,        // beta-beta split partials
   S_CG,            // inexact Newton: r, p, H p [np] each, scalars
   S_COLLIN,        // collinearity check: Gram matrices, masks, indices
   S_NSLOTS

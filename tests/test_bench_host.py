@@ -19,19 +19,22 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_hessian_flops_count_unique_entries():
-    # C2: (K-1)K/2 pair rows x p(p+1)/2 feature pairs for beta-beta, all
-    # (K-1)p x K a beta-gamma entries, the gamma-gamma upper blocks
+    # beta-beta kernel: (K-1)K/2 pair rows x p(p+1)/2 feature pairs; the
+    # whole Hessian adds all (K-1)p x K a beta-gamma entries, the
+    # gamma-gamma upper blocks and the alpha rows
     pr = synth.make_config("c2")
     N, K, p, g, a = pr.N, pr.K, pr.p, pr.g, pr.a
     u_bb = 49 * 50 // 2 * (21 * 22 // 2)
     u_bg = 49 * 21 * 50 * 5
     u_gg = 50 * 49 // 2 * 25 + 50 * 15
-    assert bench.hess_kernel_flops(pr) == 2.0 * N * (u_bb + u_bg + u_gg)
+    assert bench.hess_kernel_flops(pr) == 2.0 * N * u_bb
     u_alpha = (K - 1) * p * g + K * a * g + g * (g + 1) // 2
     assert bench.hess_total_flops(pr) == \
         2.0 * N * (u_bb + u_bg + u_gg + u_alpha)
-    # 1.14e11 useful flops per tile-kernel launch at C2
-    assert abs(bench.hess_kernel_flops(pr) - 1.1432e11) < 1e8
+    # the 400,000-individual workload: 4950 x 1326 unique beta-beta
+    # entries, 5.25 TFLOP per launch
+    c3 = synth.make_config("c3", N=10)
+    assert bench.hess_kernel_flops(c3) == 2.0 * 10 * 4950 * 1326
 
 
 def test_pass_bytes_are_the_algorithmic_traffic():

@@ -1,4 +1,6 @@
 """Parity of the GPU block Hessian (Eq. 10) with the FP64 oracle."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -20,7 +22,7 @@ SHAPES = [  # N, K, p, g, a, weights
     (1500, 13, 12, 2, 2, "uniform"),
     (600, 66, 1, 1, 1, None),
     (300, 129, 3, 1, 1, "uniform"),   # many alternatives: blocked pair rows
-    (600, 100, 32, 1, 1, "uniform"),  # many pairs: beta-beta by library GEMM
+    (600, 100, 32, 1, 1, "uniform"),  # several beta-beta row and column tiles
     # 128-column tiles with one, two and several observation rounds per
     # tile and ragged last rounds
     (3001, 9, 21, 1, 3, "uniform"),
@@ -65,6 +67,21 @@ def test_hessian_matches_oracle(ctx, shape, prec):
                                          np.unravel_index(err.argmax(), H.shape))
 
 
+def test_hessians_of_models_sharing_n_k_p_on_one_context(ctx):
+    # the beta-beta plan is cached by (N, K, p) and serves models with other
+    # generic / alternative-specific variables: each Hessian is laid out
+    # with its own n_p
+    base = synth.make_problem(4000, 6, 4, 2, 1, seed=71, weights="uniform")
+    red = dataclasses.replace(base, g=0, Y=np.ascontiguousarray(
+        base.Y[:, :, :0]), theta_true=base.theta_true[:-2])
+    for pr in (base, red, base):
+        th = np.random.default_rng(pr.n_params).normal(0, 0.5, pr.n_params)
+        H = _gpu_h(ctx, pr, th, "fp64")
+        H_ref = R.hessian(th, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
+        err = np.abs(H - H_ref) / hess_scale(pr)
+        assert err.max() <= HESS_TOL["fp64"], (pr.n_params, err.max())
+
+
 def test_hessian_deterministic(ctx):
     import torch
     pr = synth.make_problem(30000, 11, 7, 2, 2, seed=5, weights="uniform")
@@ -75,22 +92,35 @@ def test_hessian_deterministic(ctx):
     assert torch.equal(h1, h2)
 
 
-def test_hessian_c2_full(ctx):
+@pytest.fixture(scope="module")
+def c2_ref():
+    """The oracle's Eq. 10 Hessian of the 100,000-observation workload at
+    half the true coefficients, and the per-entry bound of its terms."""
     pr = synth.make_config("c2")
     th = 0.5 * pr.theta_true
-    H = _gpu_h(ctx, pr, th, "fp64")
-    H_ref = R.hessian(th, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
-    scale = np.abs(H_ref).max()
-    assert np.abs(H - H_ref).max() <= 1e-11 * scale
+    return pr, th, R.hessian(th, pr.X, pr.Y, pr.Z, pr.choice, pr.w), \
+        hess_scale(pr)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_hessian_c2_full(ctx, c2_ref, prec):
+    pr, th, H_ref, S = c2_ref
+    H = _gpu_h(ctx, pr, th, prec)
     assert np.array_equal(H, H.T)
+    if prec == "fp64":
+        scale = np.abs(H_ref).max()
+        assert np.abs(H - H_ref).max() <= 1e-11 * scale
+    err = np.abs(H - H_ref) / S
+    assert err.max() <= HESS_TOL[prec], (prec, err.max())
 
 
 @pytest.mark.parametrize("name,prec", [("c3", "fp64"), ("c5", "fp64"),
-                                       ("c3", "fp32"), ("c3", "bf16")])
+                                       ("c3", "fp32"), ("c3", "bf16"),
+                                       ("c5", "fp32"), ("c5", "bf16")])
 def test_hessian_config_sampled_blocks(ctx, name, prec):
     # full sizes: compare sampled blocks of Eq. 10 computed by the oracle
-    # (c3 takes the library-GEMM route for its beta-beta blocks, with many
-    # Omega chunks in every precision)
+    # (several observation splits, row tiles closed by the staged
+    # alternatives limit at 500 alternatives)
     pr = synth.make_config(name)
     th = 0.5 * pr.theta_true
     H = _gpu_h(ctx, pr, th, prec)

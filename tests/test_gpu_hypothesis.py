@@ -73,11 +73,21 @@ def test_quadform_not_pd(ctx):
 
 
 def test_wald_and_score_tests_match_oracle(ctx):
+    # every statistic at the oracle's estimates (the GPU fits themselves are
+    # compared with those estimates)
+    from paper_1404_3177_amd import Problem
     from paper_1404_3177_amd import hypothesis as hyp
     pr = synth.make_problem(4000, 6, 4, 2, 1, seed=71, weights="uniform")
+    o = R.FitOptions(gtol=1e-10, ftol=0.0)
+    full = R.fit_problem(pr, opts=o)
+    rest = R.fit(pr.X, pr.Y[:, :, :0], pr.Z, pr.choice, pr.w, opts=o)
     dp = device_problem(pr)
-    theta, _ = ctx.fit(dp, gtol=1e-10, ftol=0.0)
-    th = theta.cpu().numpy()
+    theta_g, info = ctx.fit(dp, gtol=1e-10, ftol=0.0)
+    assert info["stop_reason"] == R.STOP_GTOL
+    assert np.linalg.norm(theta_g.cpu().numpy() - full.theta) <= \
+        1e-8 * np.linalg.norm(full.theta)
+    th = full.theta
+    theta = theta_tensor(th)
     V = R.covariance(th, pr.X, pr.Y, pr.Z, pr.w)
     idx = [1, 5, 9, pr.n_params - 1]
     w, df, p = hyp.waldtest(ctx, dp, theta, idx)
@@ -88,12 +98,16 @@ def test_wald_and_score_tests_match_oracle(ctx):
     se, z, _ = ctx.summary(dp, theta)
     w1, _, _ = hyp.waldtest(ctx, dp, theta, [3])
     assert w1 == pytest.approx(float(z[3]) ** 2, rel=1e-12)
-    # score test of the generic coefficients at the fit without them
-    from paper_1404_3177_amd import Problem
+    # the model without the generic variables, fitted on the same context
+    # (its beta-beta plan is the full model's)
     X, Y, Z, c, wt = dp._refs
     red = Problem(X, Y[:, :, :0].contiguous(), Z, c, wt)
-    th_r, _ = ctx.fit(red, gtol=1e-10, ftol=0.0)
-    emb = np.concatenate([th_r.cpu().numpy(), np.zeros(pr.g)])
+    th_r, info_r = ctx.fit(red, gtol=1e-10, ftol=0.0)
+    assert info_r["stop_reason"] == R.STOP_GTOL
+    assert np.linalg.norm(th_r.cpu().numpy() - rest.theta) <= \
+        1e-8 * np.linalg.norm(rest.theta)
+    # score test of the generic coefficients at the restricted estimate
+    emb = np.concatenate([rest.theta, np.zeros(pr.g)])
     s, df, ps = hyp.scoretest(ctx, dp, theta_tensor(emb), pr.g)
     g = R.gradient(emb, pr.X, pr.Y, pr.Z, pr.choice, pr.w)
     Hr = R.hessian(emb, pr.X, pr.Y, pr.Z, None, pr.w)
@@ -101,11 +115,8 @@ def test_wald_and_score_tests_match_oracle(ctx):
     assert s == pytest.approx(sr, rel=1e-8) and ps == pytest.approx(psr, rel=1e-7)
     # likelihood ratio of the same pair of models
     l_full, _, _ = ctx.loglik_grad(dp, theta)
-    l_red, _, _ = ctx.loglik_grad(red, th_r)
+    l_red, _, _ = ctx.loglik_grad(red, theta_tensor(rest.theta))
     lr, _, _ = hyp.lrtest(float(l_full.cpu()[0]), float(l_red.cpu()[0]), pr.g)
-    full = R.fit_problem(pr, opts=R.FitOptions(gtol=1e-10, ftol=0.0))
-    rest = R.fit(pr.X, pr.Y[:, :, :0], pr.Z, pr.choice, pr.w,
-                 opts=R.FitOptions(gtol=1e-10, ftol=0.0))
     lrr, _, _ = R.lr_test(full.loglik, rest.loglik, pr.g)
     assert lr == pytest.approx(lrr, abs=1e-7)
 

@@ -71,7 +71,7 @@ def test_pass_is_deterministic(ctx):
     assert torch.equal(l1, l2) and torch.equal(g1, g2)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c5"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c5"])
 def test_pass_config_sizes(ctx, name):
     pr = synth.make_config(name)
     th = pr.theta_true * 0.5
