@@ -215,6 +215,23 @@ const char *mnl_last_error(const mnl_ctx *ctx);
 int mnl_loglik_grad(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
                     double *loglik, double *grad, double *P, void *stream);
 
+/* mnl_loglik_grad for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, bitwise, with no hipMalloc,
+ * hipFree or allocating library call.  Its scratch (the pass's
+ * per-workgroup partial rows, n_wg x (n_p + 1) doubles, n_wg <= 768) is a
+ * static device buffer of MNL_NOALLOC_SCRATCH_BYTES per GPU, held from the
+ * library's load until the process ends; shapes needing more return
+ * MNL_ERR_UNSUPPORTED before anything is enqueued.  Every call on one GPU
+ * shares that buffer: calls that overlap on one device (other streams,
+ * other contexts or threads) race and must be ordered by the caller.
+ * Arguments and layouts as for mnl_loglik_grad; the context is only read
+ * (its device and its error message). */
+#define MNL_NOALLOC_SCRATCH_BYTES (32u << 20)
+int mnl_loglik_grad_noalloc(mnl_ctx *ctx, const mnl_problem *prob,
+                            const double *theta, double *loglik, double *grad,
+                            double *P, void *stream);
+
 /* Full Hessian at theta (Eq. 10), Hessian sign (negative semidefinite).
  *   theta   [n_p] device, input.
  *   prec    mnl_prec of the contraction.

@@ -170,6 +170,22 @@ class Context:
             _stream_handle(stream)))
         return l, g, P
 
+    def loglik_grad_noalloc(self, prob: Problem, theta, want_P: bool = False,
+                            stream=None):
+        """loglik_grad through mnl_loglik_grad_noalloc: no device
+        allocation by the library (the outputs here are torch tensors)."""
+        import torch
+        dev = prob.device
+        l = torch.empty(1, dtype=torch.float64, device=dev)
+        g = torch.empty(prob.n_params, dtype=torch.float64, device=dev)
+        P = torch.empty(prob.N, prob.K, dtype=torch.float64, device=dev) \
+            if want_P else None
+        self._check(self.lib.mnl_loglik_grad_noalloc(
+            self.h, ctypes.byref(prob.c), theta.data_ptr(), l.data_ptr(),
+            g.data_ptr(), P.data_ptr() if P is not None else None,
+            _stream_handle(stream)))
+        return l, g, P
+
     def hessian(self, prob: Problem, theta, prec="fp64", stream=None):
         import torch
         n = prob.n_params

@@ -28,7 +28,8 @@ METHOD = {"newton": 0, "newton-cg": 1}
 EXPORTS = [
     "mnl_version", "mnl_strerror", "mnl_default_opts", "mnl_num_params",
     "mnl_create", "mnl_destroy", "mnl_workspace_bytes", "mnl_last_error",
-    "mnl_loglik_grad", "mnl_hessian", "mnl_newton_step", "mnl_fit",
+    "mnl_loglik_grad", "mnl_loglik_grad_noalloc", "mnl_hessian",
+    "mnl_newton_step", "mnl_fit",
     "mnl_hessvec", "mnl_collinear", "mnl_select_columns", "mnl_predict",
     "mnl_stderr", "mnl_covariance", "mnl_quadform", "mnl_chi2_sf",
     "mnl_lrtest",
@@ -138,6 +139,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mnl_last_error.restype = ctypes.c_char_p
     prob = ctypes.POINTER(MnlProblem)
     lib.mnl_loglik_grad.argtypes = [P, prob, P, P, P, P, P]
+    lib.mnl_loglik_grad_noalloc.argtypes = [P, prob, P, P, P, P, P]
     lib.mnl_hessian.argtypes = [P, prob, P, I32, P, P]
     lib.mnl_newton_step.argtypes = [P, prob, P, ctypes.POINTER(MnlFitOpts),
                                     ctypes.POINTER(MnlFitInfo), P]
@@ -171,7 +173,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mnl_server_wait.argtypes = [P, ctypes.POINTER(MnlServerResult), I32,
                                     ctypes.c_double, ctypes.POINTER(I32)]
     lib.mnl_server_get_stats.argtypes = [P, ctypes.POINTER(MnlServerStats)]
-    for name in ("mnl_create", "mnl_loglik_grad", "mnl_hessian",
+    for name in ("mnl_create", "mnl_loglik_grad", "mnl_loglik_grad_noalloc",
+                 "mnl_hessian",
                  "mnl_newton_step", "mnl_fit", "mnl_hessvec", "mnl_predict",
                  "mnl_collinear", "mnl_select_columns", "mnl_covariance",
                  "mnl_quadform",

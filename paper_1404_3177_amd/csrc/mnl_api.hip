@@ -739,6 +739,38 @@ int factor_with_identity(Ctx *c, const Dims &d, const mnl_problem *prob,
 }
 }  // namespace
 
+// Static device scratch of the entry point that allocates nothing
+// (mnl_loglik_grad_noalloc): the fused pass's per-workgroup partial rows.
+// Every device the library runs on holds its own copy from the module's
+// load until the process ends.  Host code never passes the array's name to
+// a kernel: its device address on each device comes from
+// hipGetSymbolAddress (scratch_setup, called by mnl_create with the device
+// current) and is kept per device.
+constexpr size_t kScratchBytes = MNL_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchBytes / 8];
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxDevices] = {};
+
+int scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return MNL_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (scratch_ptr[device]) return MNL_OK;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return MNL_ERR_HIP;
+  }
+  scratch_ptr[device] = p;
+  return MNL_OK;
+}
+
+void *scratch_get(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  return scratch_ptr[device];
+}
+
 }  // namespace mnl
 
 using namespace mnl;
@@ -790,6 +822,9 @@ int mnl_create(mnl_ctx **ctx, int device) {
   }
   if (device < 0 || device >= n) return MNL_ERR_ARG;
   if (hipSetDevice(device) != hipSuccess) return MNL_ERR_HIP;
+  // this device's address of the static scratch (with the device current)
+  const int rs = scratch_setup(device);
+  if (rs != MNL_OK) return rs;
   mnl_ctx *h = new mnl_ctx;
   h->c.device = device;
   h->c.bufs.resize(S_NSLOTS);
@@ -847,6 +882,44 @@ int mnl_loglik_grad(mnl_ctx *ctx, const mnl_problem *prob, const double *theta,
   MNL_HIP(c, launch_pass(plan, A, s));
   MNL_HIP(c, launch_pass_reduce(plan, (double *)partial, loglik, grad, d.np,
                                 s));
+  return MNL_OK;
+}
+
+int mnl_loglik_grad_noalloc(mnl_ctx *ctx, const mnl_problem *prob,
+                            const double *theta, double *loglik, double *grad,
+                            double *P, void *stream) {
+  if (!ctx) return MNL_ERR_ARG;
+  Ctx *c = &ctx->c;
+  Dims d;
+  MNL_TRY(check_problem(c, prob, &d));
+  if (!theta || !loglik) return set_error(c, MNL_ERR_ARG, "NULL output");
+  MNL_HIP(c, hipSetDevice(c->device));
+  PassPlan plan;
+  int rc = pass_plan(d, &plan);
+  if (rc != MNL_OK) return set_error(c, rc, "shape beyond pass limits");
+  const size_t need = size_t(plan.grid) * size_t(plan.stride) * 8;
+  if (need > kScratchBytes)
+    return set_error(c, MNL_ERR_UNSUPPORTED,
+                     "the pass needs %zu bytes of scratch (%d workgroup rows "
+                     "of %lld values), more than the %zu-byte static buffer",
+                     need, plan.grid, (long long)plan.stride, kScratchBytes);
+  void *sp = scratch_get(c->device);
+  if (!sp) return set_error(c, MNL_ERR_HIP, "no scratch address for device");
+  PassArgs A;
+  A.d = d;
+  A.X = prob->X;
+  A.Y = prob->Y;
+  A.Z = prob->Z;
+  A.w = prob->w;
+  A.choice = prob->choice;
+  A.theta = theta;
+  A.P = P;
+  A.P32 = nullptr;
+  A.Ybar = nullptr;
+  A.partial = static_cast<double *>(sp);
+  hipStream_t s = (hipStream_t)stream;
+  MNL_HIP(c, launch_pass(plan, A, s));
+  MNL_HIP(c, launch_pass_reduce(plan, A.partial, loglik, grad, d.np, s));
   return MNL_OK;
 }
 
