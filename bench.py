@@ -412,14 +412,20 @@ def fit_entry(pr, infos, lat, total, prec):
     beta-beta kernel's rate."""
     kv = kernel_stats(pr, infos, prec)
     inf = infos[-1]
+    if inf["hess_fallbacks"] > 0:
+        # the kernel average mixes this precision's launches with the FP64
+        # retries': no rate for the precision itself
+        kv = dict(kv, tflops=float("nan"))
     return {"fits_per_s": len(lat) / total, "ms_per_fit": total / len(lat) * 1e3,
             "iters": inf["iters"], "ls_iters": inf["ls_iters"],
             "ls_backtracks": inf["ls_backtracks"],
             "hess_fp64_retries": inf["hess_fallbacks"],
             "stop_reason": STOP_NAMES.get(inf["stop_reason"], "?"),
             "grad_norm": inf["grad_norm"], "loglik": inf["loglik"],
-            "bb_kernel_ms": kv["hess_ms"], "bb_tflops": kv["tflops"],
-            "bb_frac_of_peak": kv["tflops"] / kv["peak"],
+            "bb_kernel_ms": kv["hess_ms"],
+            "bb_tflops": kv["tflops"] if kv["tflops"] == kv["tflops"] else None,
+            "bb_frac_of_peak": (kv["tflops"] / kv["peak"]
+                                if kv["tflops"] == kv["tflops"] else None),
             "peak_tflops": kv["peak"],
             "phase_ms": {k: inf[k] for k in ("t_loglik_grad", "t_hessian",
                                               "t_chol", "t_ls")}}
