@@ -7,8 +7,9 @@
 // come from one product whose rows are alternative pairs (n, m) and whose
 // columns are feature pairs a <= b:
 //   C[(n,m)][(a,b)] = sum_i omega_i(n,m) chi_i(a,b),
-//   omega_i(n,m) = w_i P_in (delta_nm - P_im),  chi_i(a,b) = x_ia x_ib,
-// which is half the flops of the blocks' dense products.
+//   omega_i(n,m) = P_in (delta_nm - P_im),  chi_i(a,b) = w_i x_ia x_ib,
+// which is half the flops of the blocks' dense products (the observation
+// weight rides with the data-only operand).
 //
 // Neither operand is stored whole:
 //  * chi depends on the data only.  It is formed once per fit, in the MFMA
@@ -86,15 +87,14 @@ BBConst bb_const(int prec) {
 __host__ __device__ constexpr int al16(int b) { return (b + 15) & ~15; }
 
 // LDS layout of one of the two round buffers: staged P columns (plus one
-// zero column that padding rows read), the round's weights, the B tile.
+// zero column that padding rows read), then the B tile.
 struct BBLds {
-  int w, b, bufsz;
+  int b, bufsz;
 };
 __host__ __device__ inline BBLds bb_lds(int kr, int rs, int esz, int xsz,
                                         int pcols, int tnb) {
   BBLds L;
-  L.w = al16((pcols + 1) * rs * esz);
-  L.b = L.w + al16(kr * esz);
+  L.b = al16((pcols + 1) * rs * esz);
   L.bufsz = al16(L.b + tnb * 16 * kr * xsz);
   return L;
 }
@@ -105,7 +105,6 @@ struct BBTile {
 
 struct BBDev {
   const void *PT;           // [nob][K][KR] T: P by observation blocks
-  const void *WT;           // [nob][KR] T: weights (0 past N)
   const void *XX;           // [nob][ncgx][16 KR] XT: chi in fragment order
   const BBTile *tiles;
   const int32_t *cols;      // [nrt][kMaxStage] staged alternatives
@@ -162,10 +161,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_bb(BBDev D) {
   }
 
   // asynchronous copies of round ob into buffer b: each staged P column
-  // and the weights are 64 dwords (one instruction), the B tile is
-  // contiguous in 1 KB pieces
+  // is 64 dwords (one instruction), the B tile is contiguous in 1 KB pieces
   const uint32_t *pt32 = static_cast<const uint32_t *>(D.PT);
-  const uint32_t *wt32 = static_cast<const uint32_t *>(D.WT);
   const char *xx8 = static_cast<const char *>(D.XX);
   // the wave index as a scalar: the copy loops and their table reads are
   // then scalar, so waiting for a table entry never waits for the copies
@@ -177,9 +174,6 @@ __global__ __launch_bounds__(64 * kWaves) void k_bb(BBDev D) {
       __builtin_amdgcn_global_load_lds(src + ctab[c] + lane,
                                        (lds_void_t *)(buf + c * RS * sizeof(T)),
                                        4, 0, 0);
-    if (wvs == kWaves - 1)
-      __builtin_amdgcn_global_load_lds(wt32 + int64_t(ob) * CDW + lane,
-                                       (lds_void_t *)(buf + L.w), 4, 0, 0);
     const char *xs =
         xx8 + (int64_t(ob) * D.ncgx + int64_t(tl.ct) * TNB) * XF * sizeof(XT);
     for (int q = wvs; q < BCH; q += kWaves)
@@ -205,15 +199,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_bb(BBDev D) {
     if (ob + 1 < tl.ob1) stage(cur ^ 1, ob + 1);
     const char *buf = sm + cur * L.bufsz;
     const T *Ps = reinterpret_cast<const T *>(buf);
-    const T *Ws = reinterpret_cast<const T *>(buf + L.w);
     const XT *Bs = reinterpret_cast<const XT *>(buf + L.b);
     if constexpr (PREC == 2) {
 #pragma unroll
       for (int ks = 0; ks < KR / 32; ++ks) {
         // lane: row lane & 15 of each A fragment, observations o .. o + 7
         const int o = 32 * ks + 8 * kb;
-        const f4 w0 = *reinterpret_cast<const f4 *>(Ws + o);
-        const f4 w1 = *reinterpret_cast<const f4 *>(Ws + o + 4);
         bf8 bv[TNB];
 #pragma unroll
         for (int t = 0; t < TNB; ++t)
@@ -228,8 +219,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_bb(BBDev D) {
           bf8 av;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            av[e] = (__bf16)((w0[e] * n0[e]) * (dg[j] - m0[e]));
-            av[4 + e] = (__bf16)((w1[e] * n1[e]) * (dg[j] - m1[e]));
+            av[e] = (__bf16)(n0[e] * (dg[j] - m0[e]));
+            av[4 + e] = (__bf16)(n1[e] * (dg[j] - m1[e]));
           }
 #pragma unroll
           for (int t = 0; t < TNB; ++t)
@@ -242,13 +233,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_bb(BBDev D) {
       for (int ks = 0; ks < KR / 4; ++ks) {
         // lane: row lane & 15 of each A fragment, observation o
         const int o = 4 * ks + kb;
-        const T wo = Ws[o];
         T bv[TNB];
 #pragma unroll
         for (int t = 0; t < TNB; ++t) bv[t] = Bs[t * XF + ks * 64 + lane];
 #pragma unroll
         for (int j = 0; j < kTMA; ++j) {
-          const T av = (wo * Ps[offn[j] + o]) * (dg[j] - Ps[offm[j] + o]);
+          const T av = Ps[offn[j] + o] * (dg[j] - Ps[offm[j] + o]);
 #pragma unroll
           for (int t = 0; t < TNB; ++t) {
             if constexpr (PREC == 0)
@@ -281,16 +271,16 @@ __global__ __launch_bounds__(64 * kWaves) void k_bb(BBDev D) {
              (lane & 15)] = AT(acc[j][t][r]);
 }
 
-// chi_i(a,b) = x_ia x_ib in B-fragment order: element index
+// chi_i(a,b) = w_i x_ia x_ib in B-fragment order: element index
 // ((ob * ncgx + cg) * NKS + ks) * 64 + lane (times 8 for BF16), holding
 // observation ob KR + ks KSTEP + lane / 16 (+ 8 (lane / 16) + e for BF16,
 // KSTEP 32) and feature pair 16 cg + lane % 16; zero past N and past the
-// last pair.  The product is taken in FP64 and rounded once (BF16: through
-// FP32, as the other mixed operands).
+// last pair; w NULL reads as ones.  The product is taken in FP64 and
+// rounded once (BF16: through FP32, as the other mixed operands).
 template <int PREC>
 __global__ __launch_bounds__(256) void k_xx_frag(
-    const double *X, int p, int64_t N, const uint32_t *combo, int64_t ncombo,
-    int ncgx, int64_t nob, typename BBT<PREC>::XT *xx) {
+    const double *X, const double *w, int p, int64_t N, const uint32_t *combo,
+    int64_t ncombo, int ncgx, int64_t nob, typename BBT<PREC>::XT *xx) {
   using XT = typename BBT<PREC>::XT;
   constexpr int KR = BBT<PREC>::KR;
   constexpr int NKS = PREC == 2 ? KR / 32 : KR / 4;
@@ -317,25 +307,27 @@ __global__ __launch_bounds__(256) void k_xx_frag(
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int64_t i = i0 + e;
-        const double x = (cok && i < N) ? X[i * p + fa] * X[i * p + fb] : 0.0;
+        const double x = (cok && i < N)
+                             ? (w ? w[i] : 1.0) * X[i * p + fa] * X[i * p + fb]
+                             : 0.0;
         v[e] = (__bf16)float(x);
       }
       *reinterpret_cast<bf8 *>(xx + idx * 8) = v;
     } else {
       const int64_t i = ob * KR + 4 * ks + (l >> 4);
-      const double x = (cok && i < N) ? X[i * p + fa] * X[i * p + fb] : 0.0;
+      const double x = (cok && i < N)
+                           ? (w ? w[i] : 1.0) * X[i * p + fa] * X[i * p + fb]
+                           : 0.0;
       xx[idx] = XT(x);
     }
   }
 }
 
-// P [N][K] (FP64) -> PT [nob][K][KR] in T, and the weights (1 when w is
-// NULL, 0 past N) -> WT [nob][KR]; one workgroup per block of KR
-// observations and 64 alternatives, transposed through LDS.
+// P [N][K] (FP64) -> PT [nob][K][KR] in T (0 past N); one workgroup per
+// block of KR observations and 64 alternatives, transposed through LDS.
 template <typename T, int KR>
-__global__ __launch_bounds__(256) void k_p_blocks(const double *P,
-                                                  const double *w, int K,
-                                                  int64_t N, T *PT, T *WT) {
+__global__ __launch_bounds__(256) void k_p_blocks(const double *P, int K,
+                                                  int64_t N, T *PT) {
   __shared__ double tile[KR][65];
   const int64_t ob = blockIdx.x;
   const int k0 = blockIdx.y * 64;
@@ -344,10 +336,6 @@ __global__ __launch_bounds__(256) void k_p_blocks(const double *P,
     const int i = e >> 6, k = e & 63;
     const int64_t obs = ob * KR + i;
     tile[i][k] = (obs < N && k0 + k < K) ? P[obs * K + k0 + k] : 0.0;
-  }
-  if (blockIdx.y == 0 && tid < KR) {
-    const int64_t obs = ob * KR + tid;
-    WT[ob * KR + tid] = T(obs < N ? (w ? w[obs] : 1.0) : 0.0);
   }
   __syncthreads();
   for (int e = tid; e < KR * 64; e += 256) {
@@ -656,13 +644,12 @@ int bb_plan_get(Ctx *c, const Dims &d, int prec, BBPlan **out) {
 }
 
 struct BBWs {
-  size_t pt, wt, part, xx;
+  size_t pt, part, xx;
 };
 BBWs bb_ws_bytes(const BBPlan &pl) {
   const BBConst bc = bb_const(pl.prec);
   BBWs w;
   w.pt = size_t(pl.nob) * pl.d.K * bc.kr * bc.esz;
-  w.wt = size_t(pl.nob) * bc.kr * bc.esz;
   w.part = size_t(pl.S) * pl.Mp * pl.Np * bc.asz;
   w.xx = size_t(pl.nob) * pl.ncgx * 16 * bc.kr * bc.xsz;
   return w;
@@ -694,24 +681,23 @@ int bb_run_prec(Ctx *c, const BBPlan &pl, const HessArgs &h, hipStream_t s) {
   const Dims &d = h.d;
   const BBWs wb = bb_ws_bytes(pl);
   void *ptv, *partv, *xxv;
-  MNL_TRY(ws_get(c, S_PT, wb.pt + wb.wt + 256, &ptv));
+  MNL_TRY(ws_get(c, S_PT, wb.pt, &ptv));
   MNL_TRY(ws_get(c, S_BBPART, wb.part, &partv));
   MNL_TRY(ws_get(c, PREC == 0 ? S_XX : S_XX_LP, wb.xx, &xxv));
   T *PT = static_cast<T *>(ptv);
-  T *WT = reinterpret_cast<T *>(static_cast<char *>(ptv) +
-                                ((wb.pt + 255) & ~size_t(255)));
   // chi depends on the data only: formed once per top-level call (a fit
   // reuses it for all of its Hessians)
   Ctx::XXState &xs = c->xx[PREC == 0 ? 0 : 1];
-  if (!(xs.X == h.X && xs.N == d.N && xs.p == d.p && xs.prec == PREC &&
-        xs.epoch == c->call_epoch && xs.buf == xxv)) {
+  if (!(xs.X == h.X && xs.w == h.w && xs.N == d.N && xs.p == d.p &&
+        xs.prec == PREC && xs.epoch == c->call_epoch && xs.buf == xxv)) {
     const int64_t total = pl.nob * pl.ncgx * (PREC == 2 ? C::KR / 32 : C::KR / 4) * 64;
     const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
     hipLaunchKernelGGL((k_xx_frag<PREC>), dim3(unsigned(blocks)), dim3(256), 0,
-                       s, h.X, d.p, d.N, pl.combo, pl.ncombo, pl.ncgx, pl.nob,
-                       static_cast<XT *>(xxv));
+                       s, h.X, h.w, d.p, d.N, pl.combo, pl.ncombo, pl.ncgx,
+                       pl.nob, static_cast<XT *>(xxv));
     MNL_HIP(c, hipGetLastError());
     xs.X = h.X;
+    xs.w = h.w;
     xs.N = d.N;
     xs.p = d.p;
     xs.prec = PREC;
@@ -720,11 +706,10 @@ int bb_run_prec(Ctx *c, const BBPlan &pl, const HessArgs &h, hipStream_t s) {
   }
   hipLaunchKernelGGL((k_p_blocks<T, C::KR>),
                      dim3(unsigned(pl.nob), unsigned((d.K + 63) / 64)),
-                     dim3(256), 0, s, h.P, h.w, d.K, d.N, PT, WT);
+                     dim3(256), 0, s, h.P, d.K, d.N, PT);
   MNL_HIP(c, hipGetLastError());
   BBDev D;
   D.PT = PT;
-  D.WT = WT;
   D.XX = xxv;
   D.tiles = pl.tiles;
   D.cols = pl.cols;
@@ -773,7 +758,7 @@ int bb_footprint(Ctx *c, const Dims &d, int prec, size_t *ws_bytes,
   BBPlan pl;
   MNL_TRY(bb_plan_host(c, d, prec, &pl));
   const BBWs w = bb_ws_bytes(pl);
-  *ws_bytes = (w.pt + w.wt + 512) + w.part + w.xx;
+  *ws_bytes = (w.pt + 256) + w.part + w.xx;
   *table_bytes = pl.dev_bytes;
   return MNL_OK;
 }

@@ -264,7 +264,7 @@ struct Ctx {
   uint64_t call_epoch = 0;
   struct XXState {
     uint64_t epoch = ~uint64_t(0);
-    const double *X = nullptr;
+    const double *X = nullptr, *w = nullptr;
     const void *buf = nullptr;
     int64_t N = 0;
     int p = 0, prec = -1;
@@ -314,7 +314,7 @@ enum Slot {
   S_THETA0,        // zero start
   S_XX,            // chi = x_a x_b operand of the beta-beta product, FP64
   S_XX_LP,         // the same in FP32 / BF16
-  S_PT,            // P and weights by observation blocks (beta-beta)
+  S_PT,            // P by observation blocks (beta-beta)
   S_BBPART,        // beta-beta split partials
   S_CG,            // inexact Newton: r, p, H p [np] each, scalars
   S_COLLIN,        // collinearity check: Gram matrices, masks, indices
