@@ -34,27 +34,24 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int kThreads = 256;    // small kernels
-constexpr int kMaxCols = 512;    // staged alternatives per BB row tile
-
-enum TileType { T_BB = 0, T_XG = 1 };
 
 struct Tile {
-  int32_t type, row0, col0, split;
-  int32_t obs0, obs1, tn, pad1;   // tn: 16-column MFMA tiles of this tile
+  int32_t row0, col0, split, obs0;
+  int32_t obs1, pad0, pad1, pad2;
 };
 
 // MFMA traits --------------------------------------------------------------
-// T: staged input type; OT: operand type in LDS; KCB / KCX: most
-// observations per round for BB / XG tiles (a multiple of KSTEP, the
-// observations per MFMA); TN: most 16-column MFMA tiles per wave; NW: waves
-// per workgroup (16 rows each), chosen so that accumulators plus operands
-// fit the register file at NW / 4 waves per SIMD.
+// T: staged input type; OT: operand type in LDS; KCX: most observations per
+// round (a multiple of KSTEP, the observations per MFMA); TN: most
+// 16-column MFMA tiles per wave; NW: waves per workgroup (16 rows each),
+// chosen so that accumulators plus operands fit the register file at
+// NW / 4 waves per SIMD.
 template <int PREC> struct MF;
 template <> struct MF<0> {
   using T = double;
   using OT = double;
   using Acc = d4;
-  static constexpr int KSTEP = 4, KCB = 32, KCX = 32, TN = 8, NW = 16;
+  static constexpr int KSTEP = 4, KCX = 32, TN = 8, NW = 16;
   __device__ static int out_row(int l, int r) { return (l >> 4) + 4 * r; }
   __device__ static Acc zero() { return Acc{0, 0, 0, 0}; }
 };
@@ -62,7 +59,7 @@ template <> struct MF<1> {
   using T = float;
   using OT = float;
   using Acc = f4;
-  static constexpr int KSTEP = 4, KCB = 32, KCX = 16, TN = 16, NW = 8;
+  static constexpr int KSTEP = 4, KCX = 16, TN = 16, NW = 8;
   __device__ static int out_row(int l, int r) { return 4 * (l >> 4) + r; }
   __device__ static Acc zero() { return Acc{0, 0, 0, 0}; }
 };
@@ -70,7 +67,7 @@ template <> struct MF<2> {
   using T = float;
   using OT = __bf16;
   using Acc = f4;
-  static constexpr int KSTEP = 32, KCB = 64, KCX = 32, TN = 16, NW = 8;
+  static constexpr int KSTEP = 32, KCX = 32, TN = 16, NW = 8;
   __device__ static int out_row(int l, int r) { return 4 * (l >> 4) + r; }
   __device__ static Acc zero() { return Acc{0, 0, 0, 0}; }
 };
@@ -81,64 +78,40 @@ struct HessDev {
   const double *P;
   const float *P32;
   const Tile *tiles;
-  // BB tables
-  const int32_t *bb_cols;    // [n_row_tiles][kMaxCols]
-  const int32_t *bb_ncol;    // [n_row_tiles]
-  const uint32_t *bb_row;    // per pair row: ln | lm << 12 | diag << 24 | valid << 25
-  const uint32_t *bb_combo;  // per combo col: a | b << 16
-  int64_t bb_M, bb_N;        // padded partial dims
-  int64_t xg_M, xg_N;
-  void *part_bb, *part_xg;   // [S][M][N] accumulator type
-  int64_t nrow_bb, ncombo;   // valid rows / cols
-  int64_t nrow_xg, ncol_xg;
-  int kc_bb, kc_xg;          // observations per round
-  int nbuf_bb, nbuf_xg;      // raw input buffers (2: next round streams in)
-  int pstride_bb;            // staged P columns per observation (BB)
-  int bb_full;               // BB stages whole P rows (K <= kMaxCols)
+  int64_t xg_M, xg_N;        // padded partial dims
+  void *part_xg;             // [S][M][N] accumulator type
+  int64_t nrow_xg, ncol_xg;  // valid rows / cols
+  int kc_xg;                 // observations per round
+  int nbuf_xg;               // raw input buffers (2: next round streams in)
 };
-
-template <typename T>
-__device__ inline T ldg_op(const double *p64, const float *p32, int64_t idx);
-template <>
-__device__ inline double ldg_op<double>(const double *p64, const float *,
-                                        int64_t idx) {
-  return p64[idx];
-}
-template <>
-__device__ inline float ldg_op<float>(const double *p64, const float *p32,
-                                      int64_t idx) {
-  return p32 ? p32[idx] : (float)p64[idx];
-}
 
 __host__ __device__ constexpr int align16(int bytes) {
   return (bytes + 15) & ~15;
 }
 
 // LDS layout of one workgroup (bytes); shared by the kernel and the host.
-// The raw region is P columns, X, Z and w of one round, back to back.
+// The raw region of a round is P rows, X, Z and w, back to back.
 struct TileLds {
-  // raw inputs of a round: P columns and Z (operand precision; P as P /
-  // P32 are stored) and X and w in FP64; two buffers
+  // raw inputs of a round: P rows and Z in the staged type (P as P or P32
+  // are stored), X and w in FP64; one or two buffers
   int rx, rz, rw, rawsz;
-  int raw0, tab, opa, opb, total;
+  int raw0, opa, opb, total;
 };
 
 template <int PREC>
-__host__ __device__ inline TileLds tile_lds(int type, int KC, int K, int p,
-                                            int a, int bn, int pcols,
-                                            int nbuf) {
+__host__ __device__ inline TileLds tile_lds(int KC, int K, int p, int a,
+                                            int bn, int nbuf) {
   using M = MF<PREC>;
   constexpr int kRows = 16 * M::NW;
   const int tsz = sizeof(typename M::T), osz = sizeof(typename M::OT);
   const int kp = PREC == 2 ? KC + 8 : KC;   // padded k extent (bf16 rows)
   TileLds L;
-  L.rx = align16(KC * pcols * tsz);
+  L.rx = align16(KC * K * tsz);
   L.rz = L.rx + KC * p * 8;
-  L.rw = L.rz + (type == 0 ? 0 : align16(KC * K * a * tsz));
+  L.rw = L.rz + align16(KC * K * a * tsz);
   L.rawsz = align16(L.rw + KC * 8);
   int o = 0;
   L.raw0 = o; o += nbuf * L.rawsz;
-  L.tab = o;  o = align16(o + (kRows + bn + pcols) * 4);
   L.opa = o;  o = align16(o + kRows * kp * osz);
   L.opb = o;  o = align16(o + bn * kp * osz);
   L.total = o;
@@ -154,12 +127,13 @@ __device__ inline void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Generated-operand GEMM over a tile list.  Per round of KC observations:
-// the raw inputs (P columns, X, Z, w) sit in LDS; the workgroup forms the
-// A tile (64 rows x KC) and the B tile (16 tn columns x KC) in the MFMA
-// operand type, then each wave runs 16 rows x 16 tn columns of MFMAs from
-// LDS.  Several workgroups share a CU, so one's loads overlap another's
-// MFMAs.
+// Generated-operand GEMM over the XG tile list.  Per round of KC
+// observations: the raw inputs (P rows, X, Z, w) sit in LDS; the workgroup
+// forms the A tile (rows: alternative-specific coefficients (n, feature),
+// w P_n phi_n) and the B tile (16 tn gamma columns (m, c), P_m z_mc) in the
+// MFMA operand type, then each wave runs 16 rows x 16 tn columns of MFMAs
+// from LDS.  Several workgroups share a CU, so one's loads overlap
+// another's MFMAs.
 template <int PREC, int TNV>
 __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
   using M = MF<PREC>;
@@ -174,54 +148,27 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
   const int K = d.K, p = d.p, a = d.a;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int bn = 16 * TNV;
-  const bool is_bb = tile.type == T_BB;
-  const int KC = is_bb ? H.kc_bb : H.kc_xg;
+  const int KC = H.kc_xg;
   const int kp = PREC == 2 ? KC + 8 : KC;
-  const int nbuf = is_bb ? H.nbuf_bb : H.nbuf_xg;
-  const TileLds L = tile_lds<PREC>(tile.type, KC, K, p, a, bn,
-                                   is_bb ? H.pstride_bb : K, nbuf);
-  uint32_t *tab = reinterpret_cast<uint32_t *>(smb + L.tab);
+  const int nbuf = H.nbuf_xg;
+  const TileLds L = tile_lds<PREC>(KC, K, p, a, bn, nbuf);
   OT *opa = reinterpret_cast<OT *>(smb + L.opa);
   OT *opb = reinterpret_cast<OT *>(smb + L.opb);
-  const int pstride = is_bb ? H.pstride_bb : K;
-  const bool gather = is_bb && !H.bb_full;
-  // raw buffer b of the round: P columns, then X, Z, w (FP64)
+  // raw buffer b of the round: P rows, then X, Z, w (FP64)
   auto rawp = [&](int b) {
     return reinterpret_cast<T *>(smb + L.raw0 + b * L.rawsz);
   };
   auto rawd = [&](int b, int off) {
     return reinterpret_cast<double *>(smb + L.raw0 + b * L.rawsz + off);
   };
-
-  // tile tables: BB row info and feature pairs, cached in LDS
-  int ncol = K;
-  const int32_t *cols = nullptr;
-  if (is_bb) {
-    const int rt = tile.row0 / kRows;
-    ncol = H.bb_ncol[rt];
-    cols = H.bb_cols + int64_t(rt) * kMaxCols;
-    for (int r = tid; r < kRows; r += NT) {
-      const int row = tile.row0 + r;
-      tab[r] = row < H.nrow_bb ? H.bb_row[row] : 0u;
-    }
-    for (int c = tid; c < bn; c += NT) {
-      const int col = tile.col0 + c;
-      tab[kRows + c] = col < H.ncombo ? H.bb_combo[col] : 0xffffffffu;
-    }
-    if (gather)
-      for (int c = tid; c < ncol; c += NT) tab[kRows + bn + c] = cols[c];
-  }
-  // staged P columns per observation of this tile
-  const int pst = gather ? ncol : pstride;
-  const uint32_t *colt = tab + kRows + bn;
   // start from zeros in both raw buffers: the slots past the last
   // observation keep stale (finite) values that meet a zero weight
   for (int e = tid; e < nbuf * L.rawsz / 4; e += NT)
     reinterpret_cast<uint32_t *>(smb + L.raw0)[e] = 0u;
-  __syncthreads();  // tile tables and zeroed buffers visible to every thread
+  __syncthreads();
   // stage one round of raw inputs into buffer b: the contiguous blocks (P
   // rows, X, Z) stream straight into LDS asynchronously, split over the
-  // waves in 64-dword pieces; gathered P columns and w are copied directly
+  // waves in 64-dword pieces; converted values and w are copied directly
   auto stage = [&](int b, int i0, int nobs) {
     auto wg_copy = [&](const void *src, void *dst, int ndw) {
       const uint32_t *s32 = static_cast<const uint32_t *>(src);
@@ -234,52 +181,24 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
       }
     };
     T *Pw = rawp(b);
-    if (gather && (PREC == 0 || H.P32)) {
-      // the tile's columns of each row, [obs][ncol] in LDS, element by
-      // element (dword by dword) straight into LDS
-      constexpr int DW = sizeof(T) / 4;
-      const uint32_t *b32 =
-          PREC == 0 ? reinterpret_cast<const uint32_t *>(H.P)
-                    : reinterpret_cast<const uint32_t *>(H.P32);
-      const int ndw = nobs * ncol * DW;
-      char *d8 = reinterpret_cast<char *>(Pw);
-      for (int c0 = 64 * wv; c0 < ndw; c0 += 64 * (NT / 64)) {
-        const int t = c0 + lane;
-        if (t < ndw) {
-          const int e = t / DW, hf = t - e * DW;
-          const int j = e / ncol, c = e - j * ncol;
-          __builtin_amdgcn_global_load_lds(
-              b32 + (int64_t(i0 + j) * K + int(colt[c])) * DW + hf,
-              (lds_void_t *)(d8 + 4 * c0), 4, 0, 0);
-        }
-      }
-    } else if (gather) {
-      for (int e = tid; e < nobs * ncol; e += NT) {
-        const int j = e / ncol, c = e - j * ncol;
-        Pw[j * pst + c] = ldg_op<T>(H.P, H.P32, int64_t(i0 + j) * K + colt[c]);
-      }
-    } else if (PREC == 0 || !H.P32) {
-      if (PREC == 0) {
-        wg_copy(H.P + int64_t(i0) * K, Pw, 2 * nobs * K);
-      } else {
-        for (int e = tid; e < nobs * K; e += NT)
-          Pw[e] = T(H.P[int64_t(i0) * K + e]);
-      }
-    } else {
+    if constexpr (PREC == 0) {
+      wg_copy(H.P + int64_t(i0) * K, Pw, 2 * nobs * K);
+    } else if (H.P32) {
       wg_copy(H.P32 + int64_t(i0) * K, Pw, nobs * K);
+    } else {
+      for (int e = tid; e < nobs * K; e += NT)
+        Pw[e] = T(H.P[int64_t(i0) * K + e]);
     }
     wg_copy(H.X + int64_t(i0) * p, rawd(b, L.rx), 2 * nobs * p);
-    if (!is_bb) {
-      if constexpr (PREC == 0) {
-        wg_copy(H.Z + int64_t(i0) * K * a, rawd(b, L.rz), 2 * nobs * K * a);
-      } else {
-        T *Zw = reinterpret_cast<T *>(smb + L.raw0 + b * L.rawsz + L.rz);
-        const int za = K * a;
-        batched_copy<8>(
-            nobs * za, tid, NT,
-            [&](int e) { return T(H.Z[int64_t(i0) * za + e]); },
-            [&](int e, T v) { Zw[e] = v; });
-      }
+    if constexpr (PREC == 0) {
+      wg_copy(H.Z + int64_t(i0) * K * a, rawd(b, L.rz), 2 * nobs * K * a);
+    } else {
+      T *Zw = reinterpret_cast<T *>(smb + L.raw0 + b * L.rawsz + L.rz);
+      const int za = K * a;
+      batched_copy<8>(
+          nobs * za, tid, NT,
+          [&](int e) { return T(H.Z[int64_t(i0) * za + e]); },
+          [&](int e, T v) { Zw[e] = v; });
     }
     double *Ww = rawd(b, L.rw);
     for (int e = tid; e < KC; e += NT)
@@ -292,19 +211,13 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
 
   stage(0, tile.obs0, min(KC, tile.obs1 - tile.obs0));
   __syncthreads();
-  // per-thread operand roles, fixed for the tile (no division in the loop)
+  // per-thread operand roles, fixed for the tile (no division in the loop):
+  // A row: beta_n feature f (rows below (K-1) p) or gamma_n variable
   const int nb_rows = int(int64_t(K - 1) * p);
   const int ra = tid & (kRows - 1), ka0 = tid / kRows;  // NT / kRows = 4
   bool a_ok = false, a_z = false;
-  int a_ln = 0, a_lm = 0, a_f = 0;
-  T a_dg = T(0);
-  if (is_bb) {
-    const uint32_t ri = tab[ra];
-    a_ok = (ri >> 25) & 1;
-    a_ln = ri & 0xfff;
-    a_lm = (ri >> 12) & 0xfff;
-    a_dg = (ri >> 24) & 1 ? T(1) : T(0);
-  } else {
+  int a_ln = 0, a_f = 0;
+  {
     const int row = tile.row0 + ra;
     if (row < H.nrow_xg) {
       a_ok = true;
@@ -326,17 +239,10 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
   bool b_ok = false;
   int b_f1 = 0, b_f2 = 0;
   if (cbx < bn) {
-    if (is_bb) {
-      const uint32_t ci = tab[kRows + cbx];
-      b_ok = ci != 0xffffffffu;
-      b_f1 = int(ci & 0xffff);
-      b_f2 = int(ci >> 16);
-    } else {
-      const int col = tile.col0 + cbx;
-      b_ok = col < H.ncol_xg;
-      b_f1 = col / a;
-      b_f2 = col;
-    }
+    const int col = tile.col0 + cbx;
+    b_ok = col < H.ncol_xg;
+    b_f1 = col / a;
+    b_f2 = col;
   }
   int cur = 0;
   for (int i0 = tile.obs0; i0 < tile.obs1;
@@ -350,12 +256,8 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
     // A: thread -> row ra, observations ka0, ka0 + 4, ...
     if (a_ok) {
       for (int k = ka0; k < KC; k += NT / kRows) {
-        T v;
-        if (is_bb)
-          v = T(Ws[k]) * Ps[k * pst + a_ln] * (a_dg - Ps[k * pst + a_lm]);
-        else
-          v = T(Ws[k]) * Ps[k * pst + a_ln] *
-              T(a_z ? Zs[k * K * a + a_f] : Xs[k * p + a_f]);
+        const T v = T(Ws[k]) * Ps[k * K + a_ln] *
+                    T(a_z ? Zs[k * K * a + a_f] : Xs[k * p + a_f]);
         if constexpr (PREC == 2) opa[ra * kp + k] = (__bf16)v;
         else opa[k * kRows + ra] = v;
       }
@@ -368,11 +270,7 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
     // B: thread -> column cbx, observations kb0, kb0 + kbs, ...
     if (cbx < bn) {
       for (int k = kb0; k < KC; k += kbs) {
-        T v = T(0);
-        if (b_ok) {
-          if (is_bb) v = T(Xs[k * p + b_f1] * Xs[k * p + b_f2]);
-          else v = Ps[k * pst + b_f1] * T(Zs[k * K * a + b_f2]);
-        }
+        const T v = b_ok ? Ps[k * K + b_f1] * T(Zs[k * K * a + b_f2]) : T(0);
         if constexpr (PREC == 2) opb[cbx * kp + k] = (__bf16)v;
         else opb[k * bn + cbx] = v;
       }
@@ -440,18 +338,9 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
 
   // epilogue: this split's partial tile
   using AccT = typename std::conditional<PREC == 0, double, float>::type;
-  AccT *part;
-  int64_t Mp, Np;
-  if (is_bb) {
-    part = reinterpret_cast<AccT *>(H.part_bb);
-    Mp = H.bb_M;
-    Np = H.bb_N;
-  } else {
-    part = reinterpret_cast<AccT *>(H.part_xg);
-    Mp = H.xg_M;
-    Np = H.xg_N;
-  }
-  AccT *base = part + (int64_t(tile.split) * Mp + tile.row0 + 16 * wv) * Np +
+  AccT *part = reinterpret_cast<AccT *>(H.part_xg);
+  AccT *base = part +
+               (int64_t(tile.split) * H.xg_M + tile.row0 + 16 * wv) * H.xg_N +
                tile.col0;
 #pragma unroll
   for (int t = 0; t < TNM; ++t) {
@@ -459,7 +348,7 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
     for (int r = 0; r < 4; ++r) {
       const int orow = M::out_row(lane, r);
       const int ocol = 16 * t + (lane & 15);
-      base[int64_t(orow) * Np + ocol] = acc[t][r];
+      base[int64_t(orow) * H.xg_N + ocol] = acc[t][r];
     }
   }
 }
@@ -650,29 +539,6 @@ __global__ void k_alt_reduce(const double *alt, int S, int64_t n,
 // ---- assembly into H (Hessian sign) ----------------------------------------------
 
 template <typename AccT>
-__global__ void k_assemble_bb(Dims d, const AccT *part, int S, int64_t Mp,
-                              int64_t Np, const int32_t *pair_nm,
-                              const uint32_t *combo, int64_t nrow,
-                              int64_t ncombo, double *Hm) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= nrow * ncombo) return;
-  const int64_t r = e / ncombo, q = e - (e / ncombo) * ncombo;
-  double v = 0.0;
-  for (int s = 0; s < S; ++s) v += (double)part[(int64_t(s) * Mp + r) * Np + q];
-  if (pair_nm[r] == 0) return;  // padding row of a pair block
-  const int n = pair_nm[r] & 0xffff, m = pair_nm[r] >> 16;
-  const int fa = combo[q] & 0xffff, fb = combo[q] >> 16;
-  const int64_t np = d.np, p = d.p;
-  const int64_t ra = (n - 1) * p + fa, rb = (n - 1) * p + fb;
-  const int64_t ca = (m - 1) * p + fa, cb = (m - 1) * p + fb;
-  v = -v;
-  Hm[ra * np + cb] = v;
-  Hm[rb * np + ca] = v;
-  Hm[cb * np + ra] = v;
-  Hm[ca * np + rb] = v;
-}
-
-template <typename AccT>
 __global__ void k_assemble_xg(Dims d, const AccT *part, int S, int64_t Mp,
                               int64_t Np, const double *alt, int Salt,
                               double *Hm) {
@@ -751,13 +617,11 @@ __global__ void k_assemble_alpha(Dims d, const double *alt, int Salt,
 struct Plan {
   Dims d;
   int prec;
-  int S = 1;                     // observation splits of the GEMM tiles
+  int S = 1;                     // observation splits of the XG tiles
   int ntiles = 0;
-  int64_t bb_M = 0, bb_N = 0, xg_M = 0, xg_N = 0;
-  int64_t nrow_bb = 0, ncombo = 0, nrow_xg = 0, ncol_xg = 0;
+  int64_t xg_M = 0, xg_N = 0, nrow_xg = 0, ncol_xg = 0;
   size_t lds = 0;
-  int kc_bb = 4, kc_xg = 4, pstride_bb = 1, bb_full = 0;
-  int nbuf_bb = 1, nbuf_xg = 1;
+  int kc_xg = 4, nbuf_xg = 1;
   int tn = 1;                    // 16-column MFMA tiles per workgroup tile
   // alt kernel
   int alt_nb = 1, alt_S = 1, alt_nrt = 1, alt_ngrp = 1;
@@ -767,14 +631,9 @@ struct Plan {
   // tables: host copies (kept until the plan is freed, so an asynchronous
   // upload never reads freed memory) and one device allocation
   std::vector<Tile> h_tiles;
-  std::vector<int32_t> h_cols, h_ncol, h_pair;
-  std::vector<uint32_t> h_row, h_combo;
-  size_t o_cols = 0, o_ncol = 0, o_row = 0, o_combo = 0, o_pair = 0;
   void *dev = nullptr;
   size_t dev_bytes = 0;
   Tile *tiles = nullptr;
-  int32_t *bb_cols = nullptr, *bb_ncol = nullptr, *pair_nm = nullptr;
-  uint32_t *bb_row = nullptr, *bb_combo = nullptr;
 };
 
 using Key = std::tuple<int64_t, int, int, int, int, int>;
@@ -800,75 +659,55 @@ int device_cus(Ctx *c) {
 
 namespace {
 
-// Host part of a plan: tiling, split counts, LDS sizes and the tile tables
-// (in pl's host vectors).  On error the caller deletes pl.
+// Host part of a plan: tiling, split counts, LDS sizes and the tile list
+// (in pl's host vector).  On error the caller deletes pl.
 int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
-  if (d.p > 255 || d.K > 32767)
-    return set_error(c, MNL_ERR_UNSUPPORTED, "Hessian tiles need p <= 255");
+  if (d.p > 255 || d.K > 4095)
+    return set_error(c, MNL_ERR_UNSUPPORTED,
+                     "Hessian tiles need p <= 255 and K < 4096");
   pl->d = d;
   pl->prec = prec;
   const int KSTEP = prec == 2 ? 32 : 4;
   const int kRows = 16 * (prec == 0 ? MF<0>::NW : (prec == 1 ? MF<1>::NW : MF<2>::NW));
   const int NT = 4 * kRows;
-  const int KCB0 = prec == 0 ? MF<0>::KCB : (prec == 1 ? MF<1>::KCB : MF<2>::KCB);
   const int KCX0 = prec == 0 ? MF<0>::KCX : (prec == 1 ? MF<1>::KCX : MF<2>::KCX);
   const int TNMAX = prec == 0 ? MF<0>::TN : (prec == 1 ? MF<1>::TN : MF<2>::TN);
   const int K = d.K, p = d.p, a = d.a, g = d.g;
-  // column tiling: one width (tn 16-column MFMA tiles) for both tile kinds,
-  // as the kernel is specialised on it; per kind, as few tiles of padding as
-  // possible with at most TNMAX per workgroup tile, and the wider of the two
+  // column tiling: tn 16-column MFMA tiles per workgroup tile (the kernel
+  // is specialised on it), as few tiles of padding as possible with at most
+  // TNMAX per workgroup tile
   auto n16_of = [](int64_t ncols) { return (ncols + 15) / 16; };
   int tnu = 1;
   {
-    const int64_t ncolxg0 = a > 0 ? int64_t(K) * a : 0;
-    for (const int64_t n16 : {n16_of(ncolxg0)}) {
-      if (n16 == 0) continue;
+    const int64_t n16 = n16_of(a > 0 ? int64_t(K) * a : 0);
+    if (n16 > 0) {
       const int64_t nct = (n16 + TNMAX - 1) / TNMAX;
       tnu = std::max(tnu, int((n16 + nct - 1) / nct));
     }
   }
   pl->tn = tnu;
-  auto col_tiling = [&](int64_t ncols, int *tn_out) -> int64_t {
-    *tn_out = tnu;
-    return (n16_of(ncols) + tnu - 1) / tnu;
-  };
-
-  // the beta-beta blocks are formed by k_bb.hip: no BB tiles here
-  std::vector<int32_t> pair_nm, bb_cols(kMaxCols, 0), bb_ncol(1, 0);
-  std::vector<uint32_t> combo, bb_row(1, 0);
-  const int64_t nrow_bb = 0, nrt_bb = 0;
-  if (K > 4095) {
-    return set_error(c, MNL_ERR_UNSUPPORTED, "Hessian tiles need K < 4096");
-  }
-  pl->bb_full = 1;
-  pl->nrow_bb = 0;
-  pl->ncombo = 0;
-  pl->bb_M = 0;
-  pl->bb_N = 16;
-  const int cw_bb = 16 * tnu;
 
   // XG rows: all alternative-specific coefficients; columns: gamma ones
   const int64_t offg = d.off_gamma();
   const int64_t nrow_xg = a > 0 ? offg + int64_t(K) * a : 0;
   const int64_t ncol_xg = a > 0 ? int64_t(K) * a : 0;
   const int64_t nrt_xg = (nrow_xg + kRows - 1) / kRows;
-  int tn_xg = 1;
-  const int64_t nct_xg = col_tiling(ncol_xg, &tn_xg);
-  const int cw_xg = 16 * tn_xg;
+  const int64_t nct_xg = (n16_of(ncol_xg) + tnu - 1) / tnu;
+  const int cw_xg = 16 * tnu;
   pl->nrow_xg = nrow_xg;
   pl->ncol_xg = ncol_xg;
   pl->xg_M = nrt_xg * kRows;
   pl->xg_N = std::max<int64_t>(nct_xg * cw_xg, 16);
 
   // output tiles, then observation splits
-  struct OutTile { int type, row0, col0, tn; };
+  struct OutTile { int row0, col0; };
   std::vector<OutTile> out_tiles;
   for (int64_t rt = 0; rt < nrt_xg; ++rt)
     for (int64_t ct = 0; ct < nct_xg; ++ct) {
       const int64_t r0 = rt * kRows, c0 = ct * cw_xg;
       // gamma-gamma below the diagonal is mirrored, not computed
       if (r0 >= offg && r0 > offg + c0 + cw_xg - 1) continue;
-      out_tiles.push_back({T_XG, int(r0), int(c0), tn_xg});
+      out_tiles.push_back({int(r0), int(c0)});
     }
   const int64_t nout = int64_t(out_tiles.size());
   int S = 1;
@@ -891,8 +730,9 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
       }
     }
   }
+  // split boundaries at multiples of 64 (BF16) or 32 observations
   int64_t chunk = (d.N + S - 1) / S;
-  const int KCR = std::max(KCB0, KCX0);
+  const int KCR = prec == 2 ? 64 : 32;
   chunk = (chunk + KCR - 1) / KCR * KCR;
   S = int((d.N + chunk - 1) / chunk);
   pl->S = S;
@@ -904,10 +744,8 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
     for (int sp = 0; sp < S; ++sp)
       for (auto &ot : out_tiles) {
         Tile t{};
-        t.type = ot.type;
         t.row0 = ot.row0;
         t.col0 = ot.col0;
-        t.tn = ot.tn;
         t.split = sp;
         t.obs0 = int(sp * chunk);
         t.obs1 = int(std::min<int64_t>(d.N, (sp + 1) * chunk));
@@ -934,44 +772,35 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
   }
   pl->ntiles = int(tiles.size());
 
-  // observations per round: as many as the prefetch registers and LDS
-  // allow (a multiple of the MFMA's observation count)
-  int max_ncol = 0;
-  for (int64_t t = 0; t < nrt_bb; ++t) max_ncol = std::max(max_ncol, bb_ncol[t]);
-  pl->pstride_bb = std::max(max_ncol, 1);
-  auto lds_of = [&](int type, int kc, int bn, int nbuf) -> size_t {
-    const int pc = type == T_BB ? pl->pstride_bb : K;
-    if (prec == 0) return tile_lds<0>(type, kc, K, p, a, bn, pc, nbuf).total;
-    if (prec == 1) return tile_lds<1>(type, kc, K, p, a, bn, pc, nbuf).total;
-    return tile_lds<2>(type, kc, K, p, a, bn, pc, nbuf).total;
+  auto lds_of = [&](int kc, int bn, int nbuf) -> size_t {
+    if (prec == 0) return tile_lds<0>(kc, K, p, a, bn, nbuf).total;
+    if (prec == 1) return tile_lds<1>(kc, K, p, a, bn, nbuf).total;
+    return tile_lds<2>(kc, K, p, a, bn, nbuf).total;
   };
   // observations per round: the largest multiple of the MFMA's observation
   // count that keeps LDS small enough for several workgroups per CU
   // (double-buffered raw inputs if they fit; one buffer otherwise)
-  auto pick_kc = [&](int type, int kc0, int bn, int *nbuf) -> int {
+  auto pick_kc = [&](int kc0, int bn, int *nbuf) -> int {
     // 16-wave workgroups own a CU; 8-wave ones share it with a second
     const size_t budget = kRows >= 192 ? size_t(150 * 1024) : size_t(78 * 1024);
     for (int nb2 = 2; nb2 >= 1; --nb2) {
       for (int kc = kc0; kc >= KSTEP; kc -= KSTEP) {
-        if (lds_of(type, kc, bn, nb2) <= budget) {
+        if (lds_of(kc, bn, nb2) <= budget) {
           *nbuf = nb2;
           return kc;
         }
       }
     }
     *nbuf = 1;
-    return lds_of(type, KSTEP, bn, 1) > 150 * 1024 ? 0 : KSTEP;
+    return lds_of(KSTEP, bn, 1) > 150 * 1024 ? 0 : KSTEP;
   };
-  pl->nbuf_bb = pl->nbuf_xg = 1;
-  pl->kc_bb = nrow_bb ? pick_kc(T_BB, KCB0, cw_bb, &pl->nbuf_bb) : KSTEP;
-  pl->kc_xg = nrow_xg ? pick_kc(T_XG, KCX0, cw_xg, &pl->nbuf_xg) : KSTEP;
-  if (pl->kc_bb == 0 || pl->kc_xg == 0) {
+  pl->nbuf_xg = 1;
+  pl->kc_xg = nrow_xg ? pick_kc(KCX0, cw_xg, &pl->nbuf_xg) : KSTEP;
+  if (pl->kc_xg == 0) {
     return set_error(c, MNL_ERR_UNSUPPORTED,
                      "Hessian tile exceeds LDS (p=%d K=%d a=%d)", p, K, a);
   }
-  pl->lds = std::max(
-      nrow_bb ? lds_of(T_BB, pl->kc_bb, cw_bb, pl->nbuf_bb) : size_t(0),
-      nrow_xg ? lds_of(T_XG, pl->kc_xg, cw_xg, pl->nbuf_xg) : size_t(0));
+  pl->lds = nrow_xg ? lds_of(pl->kc_xg, cw_xg, pl->nbuf_xg) : size_t(0);
 
   // per-alternative kernel
   pl->need_alt = (a + g) > 0;
@@ -1007,24 +836,14 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
       return set_error(c, MNL_ERR_UNSUPPORTED, "per-alternative tile too big");
   }
 
-  // table layout (one allocation)
-  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  pl->o_cols = al(tiles.size() * sizeof(Tile));
-  pl->o_ncol = al(pl->o_cols + bb_cols.size() * 4);
-  pl->o_row = al(pl->o_ncol + bb_ncol.size() * 4);
-  pl->o_combo = al(pl->o_row + bb_row.size() * 4);
-  pl->o_pair = al(pl->o_combo + std::max<size_t>(combo.size(), 1) * 4);
-  pl->dev_bytes = al(pl->o_pair + std::max<size_t>(pair_nm.size(), 1) * 4);
+  // the tile list (one allocation)
+  pl->dev_bytes = (std::max<size_t>(tiles.size(), 1) * sizeof(Tile) + 255) &
+                  ~size_t(255);
   pl->h_tiles = std::move(tiles);
-  pl->h_cols = std::move(bb_cols);
-  pl->h_ncol = std::move(bb_ncol);
-  pl->h_row = std::move(bb_row);
-  pl->h_combo = std::move(combo);
-  pl->h_pair = std::move(pair_nm);
   return MNL_OK;
 }
 
-// Device copy of a plan's tables.  A context in stream-ordered mode takes
+// Device copy of a plan's tile list.  A context in stream-ordered mode takes
 // the memory from its pool and uploads on its stream; otherwise the upload
 // is synchronous.
 int plan_upload(Ctx *c, Plan *pl) {
@@ -1040,13 +859,7 @@ int plan_upload(Ctx *c, Plan *pl) {
     pl->dev = nullptr;
     return set_error(c, MNL_ERR_OOM, "Hessian tables");
   }
-  char *base = static_cast<char *>(pl->dev);
-  pl->tiles = reinterpret_cast<Tile *>(base);
-  pl->bb_cols = reinterpret_cast<int32_t *>(base + pl->o_cols);
-  pl->bb_ncol = reinterpret_cast<int32_t *>(base + pl->o_ncol);
-  pl->bb_row = reinterpret_cast<uint32_t *>(base + pl->o_row);
-  pl->bb_combo = reinterpret_cast<uint32_t *>(base + pl->o_combo);
-  pl->pair_nm = reinterpret_cast<int32_t *>(base + pl->o_pair);
+  pl->tiles = static_cast<Tile *>(pl->dev);
   auto up = [&](void *dst, const void *src, size_t n) {
     if (!n) return hipSuccess;
     return c->pool ? hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice,
@@ -1054,13 +867,7 @@ int plan_upload(Ctx *c, Plan *pl) {
                    : hipMemcpy(dst, src, n, hipMemcpyHostToDevice);
   };
   if (up(pl->tiles, pl->h_tiles.data(), pl->h_tiles.size() * sizeof(Tile)) !=
-          hipSuccess ||
-      up(pl->bb_cols, pl->h_cols.data(), pl->h_cols.size() * 4) != hipSuccess ||
-      up(pl->bb_ncol, pl->h_ncol.data(), pl->h_ncol.size() * 4) != hipSuccess ||
-      up(pl->bb_row, pl->h_row.data(), pl->h_row.size() * 4) != hipSuccess ||
-      up(pl->bb_combo, pl->h_combo.data(), pl->h_combo.size() * 4) !=
-          hipSuccess ||
-      up(pl->pair_nm, pl->h_pair.data(), pl->h_pair.size() * 4) != hipSuccess)
+      hipSuccess)
     return set_error(c, MNL_ERR_HIP, "uploading Hessian tables");
   return MNL_OK;
 }
@@ -1103,13 +910,12 @@ struct PartLayout {
 PartLayout part_layout(const Plan &pl) {
   const Dims &d = pl.d;
   const size_t asz = pl.prec == 0 ? 8 : 4;
-  const size_t bytes_bb = 0;
   const size_t bytes_xg = size_t(pl.S) * pl.xg_M * pl.xg_N * asz;
   const int nl = d.p + d.a + d.g, nr = d.a + d.g;
   PartLayout L;
   L.n_alt = pl.need_alt ? size_t(d.K) * nl * nr : 0;
   const size_t bytes_alt = size_t(pl.alt_S) * L.n_alt * 8;
-  L.o_xg = (bytes_bb + 255) & ~size_t(255);
+  L.o_xg = 0;
   L.o_alt = (L.o_xg + bytes_xg + 255) & ~size_t(255);
   L.o_red = (L.o_alt + bytes_alt + 255) & ~size_t(255);
   L.total = L.o_red + L.n_alt * 8 + 256;
@@ -1162,8 +968,8 @@ hipError_t launch_alt(const Plan &pl, const HessArgs &h, double *part,
 }
 
 template <typename AccT>
-hipError_t launch_assemble(const Plan &pl, const HessArgs &h, void *pbb,
-                           void *pxg, const double *alt, hipStream_t s) {
+hipError_t launch_assemble(const Plan &pl, const HessArgs &h, void *pxg,
+                           const double *alt, hipStream_t s) {
   const Dims &d = pl.d;
   if (pl.nrow_xg > 0) {
     const int64_t n = pl.nrow_xg * pl.ncol_xg;
@@ -1190,7 +996,7 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   void *ws;
   MNL_TRY(ws_get(c, S_HPART, L.total, &ws));
   char *wb = static_cast<char *>(ws);
-  void *pbb = wb, *pxg = wb + L.o_xg;
+  void *pxg = wb + L.o_xg;
   double *alt_part = reinterpret_cast<double *>(wb + L.o_alt);
   double *alt = reinterpret_cast<double *>(wb + L.o_red);
 
@@ -1211,26 +1017,13 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   hd.P = h.P;
   hd.P32 = h.prec == 0 ? nullptr : h.P32;
   hd.tiles = pl->tiles;
-  hd.bb_cols = pl->bb_cols;
-  hd.bb_ncol = pl->bb_ncol;
-  hd.bb_row = pl->bb_row;
-  hd.bb_combo = pl->bb_combo;
-  hd.bb_M = pl->bb_M;
-  hd.bb_N = pl->bb_N;
   hd.xg_M = pl->xg_M;
   hd.xg_N = pl->xg_N;
-  hd.part_bb = pbb;
   hd.part_xg = pxg;
-  hd.nrow_bb = pl->nrow_bb;
-  hd.ncombo = pl->ncombo;
   hd.nrow_xg = pl->nrow_xg;
   hd.ncol_xg = pl->ncol_xg;
-  hd.kc_bb = pl->kc_bb;
   hd.kc_xg = pl->kc_xg;
-  hd.nbuf_bb = pl->nbuf_bb;
   hd.nbuf_xg = pl->nbuf_xg;
-  hd.pstride_bb = pl->pstride_bb;
-  hd.bb_full = pl->bb_full;
   if (h.prec == 0) {
     MNL_HIP(c, launch_tiles<0>(*pl, hd, s));
   } else if (h.prec == 1) {
@@ -1239,9 +1032,9 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
     MNL_HIP(c, launch_tiles<2>(*pl, hd, s));
   }
   if (h.prec == 0)
-    MNL_HIP(c, (launch_assemble<double>(*pl, h, pbb, pxg, alt, s)));
+    MNL_HIP(c, (launch_assemble<double>(*pl, h, pxg, alt, s)));
   else
-    MNL_HIP(c, (launch_assemble<float>(*pl, h, pbb, pxg, alt, s)));
+    MNL_HIP(c, (launch_assemble<float>(*pl, h, pxg, alt, s)));
   return MNL_OK;
 }
 
