@@ -129,20 +129,25 @@ typedef struct {
     int32_t method;            /* mnl_method of the Newton direction       */
     int32_t cg_maxiter;        /* NEWTON_CG: Hessian-vector products per
                                   iteration at most, >= 1                  */
-    int32_t graph;             /* nonzero: from the second iteration on,
-                                  each Newton step (Hessian, factorisation,
+    int32_t graph;             /* > 0: from the second iteration on, each
+                                  Newton step (Hessian, factorisation,
                                   full-step trial) is captured once per
                                   parity of the alternating buffers into a
-                                  HIP graph and replayed.  Needs a
-                                  non-default stream; NEWTON_CG, shapes on
-                                  library GEMMs (large beta-beta products,
-                                  n_p >= 2048), the default stream and
+                                  HIP graph and replayed; 0: eager steps;
+                                  < 0 (MNL_GRAPH_AUTO, the default): graph
+                                  steps for n_p <= MNL_GRAPH_AUTO_MAX_NP,
+                                  where launches dominate a step.  Needs a
+                                  non-default stream; NEWTON_CG, n_p >=
+                                  2048, the default stream and
                                   mnl_newton_step run eagerly.  Growth of
                                   the workspace (the first FP64 retry of a
                                   mixed Hessian) drops the captured steps,
                                   which are captured again.  Results are
                                   bitwise the same.                        */
 } mnl_fit_opts;
+
+#define MNL_GRAPH_AUTO (-1)
+#define MNL_GRAPH_AUTO_MAX_NP 512
 
 /* Report of a fit or of one Newton step (mnlogit's est.stat). Times in ms:
  * t_* are host wall times of the phases; t_hess_kernel and t_pass_kernel

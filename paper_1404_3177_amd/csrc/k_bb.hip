@@ -24,9 +24,10 @@
 //    registers, in MFMA A-operand order, right before the MFMAs that
 //    consume them.  The rounding to the MFMA type happens after omega is
 //    formed in FP32 (mixed precision) or FP64.
-// A workgroup of 8 waves owns 512 pair rows x 16 TNB feature pairs; every
-// wave runs 64 rows (4 A fragments) x all TNB B fragments, so each B
-// fragment read from LDS feeds 4 MFMAs and each formed A fragment TNB.
+// A workgroup of NWV waves (8, or 4 for few pair rows) owns 64 NWV pair rows
+// x 16 TNB feature pairs; every wave runs 64 rows (4 A fragments) x all TNB
+// B fragments, so each B fragment read from LDS feeds 4 MFMAs and each
+// formed A fragment TNB.
 // The observations are split in S contiguous ranges; partial tiles are
 // summed in a fixed order by the assembly kernel (bitwise reproducible).
 #include <algorithm>
@@ -46,7 +47,6 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 constexpr int kMaxStage = 128;   // staged alternatives per row tile
 constexpr int kTMA = 4;          // 16-row A fragments per wave
 constexpr int kBlkAlt = 32;      // alternatives per pair block (large K)
-constexpr int kWaves = 8;        // waves per workgroup
 
 // Per precision: T = P / w / omega type, XT = chi type, KR observations per
 // round, RS = LDS row stride of a staged P column (elements; padded so the
@@ -115,8 +115,9 @@ struct BBDev {
   int K, pcols, ncgx;
 };
 
-template <int PREC, int TNB>
-__global__ __launch_bounds__(64 * kWaves) void k_bb(BBDev D) {
+template <int PREC, int TNB, int NWV>
+__global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
+  constexpr int kWaves = NWV;
   using C = BBT<PREC>;
   using T = typename C::T;
   using XT = typename C::XT;
@@ -374,7 +375,7 @@ __global__ void k_bb_assemble(const AT *part, int S, int64_t Mp, int64_t Np,
 
 struct BBPlan {
   Dims d;
-  int prec = 0, tnb = 1, S = 1, ntiles = 0, pcols = 0, ncgx = 0;
+  int prec = 0, tnb = 1, nw = 8, S = 1, ntiles = 0, pcols = 0, ncgx = 0;
   int64_t npairs = 0, Mp = 0, Np = 0, ncombo = 0, nob = 0, nrt = 0;
   size_t lds = 0;
   std::vector<BBTile> h_tiles;
@@ -403,7 +404,14 @@ int bb_plan_host(Ctx *c, const Dims &d, int prec, BBPlan *pl) {
   pl->prec = prec;
   const BBConst bc = bb_const(prec);
   const int Lk = d.K - 1, p = d.p;
-  const int R = 64 * kWaves;
+  // workgroups of 8 waves (512 pair rows), or of 4 when that pads at least
+  // 10% fewer rows (few alternatives; two such workgroups share a CU)
+  {
+    const int64_t np = int64_t(Lk) * (Lk + 1) / 2;
+    const int64_t r8 = (np + 511) / 512 * 512, r4 = (np + 255) / 256 * 256;
+    pl->nw = (Lk <= kMaxStage && r4 < 0.9 * double(r8)) ? 4 : 8;
+  }
+  const int R = 64 * pl->nw;
   // pair rows: n <= m over alternatives 1..K-1, row-major within blocks of
   // kBlkAlt alternatives when there are more than a tile can stage; a row
   // tile closes early (padding rows) when its next pair would need more
@@ -504,12 +512,15 @@ int bb_plan_host(Ctx *c, const Dims &d, int prec, BBPlan *pl) {
     return set_error(c, MNL_ERR_UNSUPPORTED, "beta-beta tile exceeds LDS");
 
   // observation splits: the count whose workgroups fill the resident slots
-  // (one 8-wave workgroup per CU) best in whole rounds; a larger count
-  // must gain 2 points of fill
+  // (one 8-wave or two 4-wave workgroups per CU, as LDS allows) best in
+  // whole rounds; a larger count must gain 2 points of fill
   const int64_t nout = pl->nrt * nct;
   int S = 1;
   if (nout > 0) {
-    const int64_t slots = int64_t(device_cus(c));
+    const int per_cu = std::max<int>(
+        1, std::min<int>(pl->nw == 4 ? 2 : 1,
+                         int((160 * 1024) / std::max<size_t>(pl->lds, 1))));
+    const int64_t slots = int64_t(device_cus(c)) * per_cu;
     const int64_t max_s = std::max<int64_t>(1, std::min<int64_t>(64, pl->nob / 4));
     double bestf = -1.0;
     for (int sc = 1; sc <= max_s; ++sc) {
@@ -655,14 +666,20 @@ BBWs bb_ws_bytes(const BBPlan &pl) {
   return w;
 }
 
-template <int PREC, int TNB>
-hipError_t launch_bb_tnb(const BBPlan &pl, const BBDev &D, hipStream_t s) {
-  hipError_t e = raise_lds_limit(reinterpret_cast<const void *>(&k_bb<PREC, TNB>),
-                                 int(pl.lds));
+template <int PREC, int TNB, int NWV>
+hipError_t launch_bb_nw(const BBPlan &pl, const BBDev &D, hipStream_t s) {
+  hipError_t e = raise_lds_limit(
+      reinterpret_cast<const void *>(&k_bb<PREC, TNB, NWV>), int(pl.lds));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_bb<PREC, TNB>), dim3(pl.ntiles), dim3(64 * kWaves),
+  hipLaunchKernelGGL((k_bb<PREC, TNB, NWV>), dim3(pl.ntiles), dim3(64 * NWV),
                      pl.lds, s, D);
   return hipGetLastError();
+}
+
+template <int PREC, int TNB>
+hipError_t launch_bb_tnb(const BBPlan &pl, const BBDev &D, hipStream_t s) {
+  return pl.nw == 4 ? launch_bb_nw<PREC, TNB, 4>(pl, D, s)
+                    : launch_bb_nw<PREC, TNB, 8>(pl, D, s);
 }
 
 template <int PREC, int TNB = BBT<PREC>::TNMAX>

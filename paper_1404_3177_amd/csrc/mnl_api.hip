@@ -572,9 +572,12 @@ int fit_impl(Ctx *c, const mnl_problem *prob, double *theta,
   info->t_loglik_grad = now_ms() - t0;
   const double gnorm0 = gnorm;   // scale of the inexact Newton forcing term
   // captured steps: only on a non-default stream, for exact Newton steps
-  // whose Hessian and factorisation make no library calls
-  bool graph_ok = o.graph != 0 && s != nullptr &&
-                  o.method == MNL_METHOD_NEWTON && d.np < 2048 && !one_step;
+  // below the outer-panel factorisation's size; by default only for small
+  // fits, whose steps are launch-bound
+  const bool graph_on =
+      o.graph > 0 || (o.graph < 0 && d.np <= MNL_GRAPH_AUTO_MAX_NP);
+  bool graph_ok = graph_on && s != nullptr && o.method == MNL_METHOD_NEWTON &&
+                  d.np < 2048 && !one_step;
   if (graph_ok && !c->pinned) {
     if (hipHostMalloc(reinterpret_cast<void **>(&c->pinned), 256) !=
         hipSuccess) {
@@ -804,7 +807,7 @@ void mnl_default_opts(mnl_fit_opts *o) {
   o->validate = 0;
   o->method = MNL_METHOD_NEWTON;
   o->cg_maxiter = 250;
-  o->graph = 0;
+  o->graph = MNL_GRAPH_AUTO;
 }
 
 int64_t mnl_num_params(int32_t K, int32_t p, int32_t g, int32_t a) {

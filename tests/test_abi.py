@@ -98,6 +98,8 @@ def test_default_method_is_exact_newton(lib):
     o = _lib.MnlFitOpts()
     lib.mnl_default_opts(ctypes.byref(o))
     assert o.method == 0 and o.cg_maxiter == 250 and o.validate == 0
+    # graph-captured steps for small fits only (MNL_GRAPH_AUTO)
+    assert o.graph == -1
 
 
 def test_struct_layouts_match_header():

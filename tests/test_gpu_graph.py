@@ -34,7 +34,8 @@ def test_graph_fit_equals_eager_fit(ctx, stream, shape, prec):
     N, K, p, g, a, wk = shape
     pr = synth.make_problem(N, K, p, g, a, seed=900 + K, weights=wk)
     dp = device_problem(pr)
-    t_e, i_e = ctx.fit(dp, gtol=GTOL, ftol=0.0, prec=prec, stream=stream)
+    t_e, i_e = ctx.fit(dp, gtol=GTOL, ftol=0.0, prec=prec, graph=0,
+                       stream=stream)
     # two graph fits in a row: the graphs of one fit never serve the next
     for _ in range(2):
         t_g, i_g = ctx.fit(dp, gtol=GTOL, ftol=0.0, prec=prec, graph=1,
@@ -46,6 +47,22 @@ def test_graph_fit_equals_eager_fit(ctx, stream, shape, prec):
         # every step after the first was a replay
         assert i_g["graph_steps"] == i_g["iters"] - 1 and \
             i_e["graph_steps"] == 0
+
+
+def test_default_captures_small_fits_only(ctx, stream):
+    # MNL_GRAPH_AUTO (the default): graph steps for n_p <= 512 on a
+    # non-default stream, eager steps above, bitwise the eager results
+    import torch
+    for shape, small in (((2000, 10, 6, 1, 0), True),
+                         ((20000, 30, 20, 2, 1), False)):
+        pr = synth.make_problem(*shape, seed=950 + shape[1])
+        dp = device_problem(pr)
+        assert (pr.n_params <= 512) == small
+        t_e, i_e = ctx.fit(dp, gtol=GTOL, ftol=0.0, graph=0, stream=stream)
+        t_a, i_a = ctx.fit(dp, gtol=GTOL, ftol=0.0, stream=stream)
+        stream.synchronize()
+        assert torch.equal(t_a, t_e)
+        assert i_a["graph_steps"] == (i_a["iters"] - 1 if small else 0)
 
 
 def test_graph_fit_with_backtracking_matches_oracle(ctx, stream):
@@ -72,7 +89,8 @@ def test_graph_option_falls_back_where_it_cannot_capture(ctx, stream):
     assert torch.equal(t_e, t_g) and i_g["graph_steps"] == 0
     pr = synth.make_problem(3000, 43, 50, 1, 1, seed=120, weights="uniform")
     dp = device_problem(pr)
-    t_e, i_e = ctx.fit(dp, gtol=GTOL, ftol=0.0, maxiter=2, stream=stream)
+    t_e, i_e = ctx.fit(dp, gtol=GTOL, ftol=0.0, maxiter=2, graph=0,
+                       stream=stream)
     t_g, i_g = ctx.fit(dp, gtol=GTOL, ftol=0.0, maxiter=2, graph=1,
                        stream=stream)
     stream.synchronize()
@@ -89,7 +107,7 @@ def test_graph_fit_with_fp64_retries_equals_eager_fit(ctx, stream):
                             weights="int")
     dp = device_problem(pr)
     t_e, i_e = ctx.fit(dp, gtol=GTOL, ftol=0.0, prec="bf16", maxiter=12,
-                       stream=stream)
+                       graph=0, stream=stream)
     t_g, i_g = ctx.fit(dp, gtol=GTOL, ftol=0.0, prec="bf16", maxiter=12,
                        graph=1, stream=stream)
     stream.synchronize()
@@ -134,7 +152,7 @@ def test_graph_option_is_ignored_by_newton_cg_and_single_steps(ctx, stream):
     import torch
     pr = synth.make_problem(3000, 8, 5, 1, 1, seed=47, weights="uniform")
     dp = device_problem(pr)
-    t_e, i_e = ctx.fit(dp, gtol=GTOL, ftol=0.0, method="newton-cg",
+    t_e, i_e = ctx.fit(dp, gtol=GTOL, ftol=0.0, method="newton-cg", graph=0,
                        stream=stream)
     t_g, i_g = ctx.fit(dp, gtol=GTOL, ftol=0.0, method="newton-cg", graph=1,
                        stream=stream)
