@@ -271,6 +271,46 @@ int mnl_fit(mnl_ctx *ctx, const mnl_problem *prob, const double *theta0,
             const mnl_fit_opts *opts, double *theta_out, mnl_fit_info *info,
             void *stream);
 
+/* Many small Newton-Raphson fits at once (Sec. 3.1: Eqs. 2-6, 9 and 10 and
+ * the halving line search, the stop rules of mnl_fit), one workgroup per
+ * fit of a persistent kernel that takes fits from a device work list.  A
+ * fit's state (theta, gradient, -H and its L D L^T factor) stays on chip
+ * for the whole fit; every sum runs in an order fixed by the fit's own
+ * shape, so each result is bitwise the same whatever else is in the batch.
+ * The arithmetic differs from mnl_fit's kernels in rounding only.
+ *   probs      host array [nfits] of problems with DEVICE data.
+ *   theta0     host array [nfits] of device [n_p] starts, or NULL (zeros);
+ *              a NULL entry is a zero start.
+ *   opts       host array [nfits], NULL = defaults for all.  Each must ask
+ *              for FP64 Newton steps without validation (prec FP64, method
+ *              NEWTON, validate 0; graph and cg_maxiter are ignored), else
+ *              MNL_ERR_UNSUPPORTED.
+ *   theta_out  host array [nfits] of device [n_p] outputs (may equal the
+ *              fit's theta0).
+ *   info       host array [nfits], output: iters, ls_iters, ls_backtracks,
+ *              stop_reason, n_hess, n_pass, loglik, grad_norm and
+ *              loglik_diff as from mnl_fit; t_total is the batch's wall
+ *              time; t_loglik_grad, t_hessian, t_chol and t_ls are the
+ *              fit's own phases timed on the device's constant-rate clock
+ *              by its workgroup; the other times and counters are 0.
+ * Shape limits (MNL_ERR_UNSUPPORTED beyond them): K <= 64, n_p <= 128,
+ * and the fit's LDS layout (A = -H with row stride n_p | 1, six vectors
+ * of n_p, and 16 staged observations of p + K a + K g values, K
+ * probabilities, g means and (K-1) p + K a products) within 160 KiB.  Nothing is written for a call that fails its
+ * checks.  Not capturable into a HIP graph (host copies of the work
+ * list).  Synchronises `stream`. */
+int mnl_fit_batch(mnl_ctx *ctx, int32_t nfits, const mnl_problem *probs,
+                  const double *const *theta0, const mnl_fit_opts *opts,
+                  double *const *theta_out, mnl_fit_info *info,
+                  void *stream);
+
+/* 1 if a fit of this shape (sizes only) with these options (NULL =
+ * defaults) is one the server runs through mnl_fit_batch: within its
+ * limits, FP64 Newton without validation, and N n_p^2 <= MNL_BATCH_MAX_WORK
+ * (a fit the size of one workgroup); else 0. */
+#define MNL_BATCH_MAX_WORK (((int64_t)1) << 26)
+int mnl_batch_eligible(const mnl_problem *shape, const mnl_fit_opts *opts);
+
 /* Hessian-vector product H(theta) v (Eq. 10's H, never formed): one fused
  * pass for P at theta, then one pass of v through -sum_i w_i J_i^T
  * (diag P_i - P_i P_i^T) J_i, J_i = dU_i/dtheta.  prob->choice is not read
@@ -403,6 +443,12 @@ int mnl_lrtest(double loglik_full, double loglik_restricted, int32_t df,
  * each slot runs its fit on a HIP stream of its own, so the fits' kernels
  * overlap on the device.  Every fit's reductions use partitions fixed by
  * its own shape, so its result is bitwise the same alone and in any mix.
+ * Small fits run together: a slot that admits a request the batched
+ * kernel takes (mnl_batch_eligible) also admits the eligible requests
+ * queued right behind it, in arrival order, up to max_group and the
+ * budget, and runs the group as one mnl_fit_batch; such a request's
+ * result is bitwise the same as mnl_fit_batch of it alone (the other
+ * requests run through mnl_fit's path, bitwise the same as mnl_fit).
  * A request whose footprint exceeds the whole budget is refused at submit.
  * Device memory comes from a stream-ordered pool owned by the server; the
  * budget bounds the bytes that admitted fits have requested from it.
@@ -420,8 +466,11 @@ typedef struct {
                                   waits host_fit_ms and returns theta = 0
                                   (stop_reason MNL_STOP_NONE, no
                                   iterations); hbm_budget must be > 0      */
-    int32_t reserved;
-    double host_fit_ms;        /* host_only: time each "fit" takes          */
+    int32_t max_group;         /* most requests one slot runs together
+                                  through mnl_fit_batch; 0 = 1024, 1 = one
+                                  request per slot, >= 0                   */
+    double host_fit_ms;        /* host_only: time each "fit" (or group of
+                                  fits) takes                              */
 } mnl_server_opts;
 
 /* One finished request (mnl_server_wait).  Times in ms on the server clock

@@ -26,7 +26,7 @@ from ._lib import (METHOD, MnlError, MnlFitInfo, MnlFitOpts,  # noqa
                    STOP_NONE, STOP_NONFINITE, STOP_NOT_PD)
 
 __all__ = ["Context", "Problem", "HostProblem", "Server", "num_params",
-           "default_opts", "fit_footprint", "chi2_sf", "lr_stat", "MnlError"]
+           "batch_eligible", "default_opts", "fit_footprint", "chi2_sf", "lr_stat", "MnlError"]
 
 
 def num_params(K: int, p: int, g: int, a: int) -> int:
@@ -47,6 +47,15 @@ def lr_stat(loglik_full: float, loglik_restricted: float, df: int):
     if rc != 0:
         raise MnlError(rc, "mnl_lrtest failed")
     return stat.value, p.value
+
+
+def batch_eligible(N: int, K: int, p: int, g: int, a: int, **opts) -> bool:
+    """Whether the server runs a fit of this shape with these options
+    through the batched kernel (mnl_batch_eligible)."""
+    o = Context._opts(**opts)
+    shape = MnlProblem(N=N, K=K, p=p, g=g, a=a)
+    return bool(_lib.load().mnl_batch_eligible(ctypes.byref(shape),
+                                               ctypes.byref(o)))
 
 
 def default_opts() -> dict:
@@ -219,6 +228,30 @@ class Context:
             _stream_handle(stream)))
         return theta, info.as_dict()
 
+    def fit_batch(self, probs, theta0s=None, opts=None, stream=None):
+        """Many small fits in one persistent kernel (mnl_fit_batch); probs
+        is a list of Problems, theta0s None or a list of tensors / None,
+        opts None (defaults), one dict for all, or a list of dicts.
+        Returns ([theta tensors], [info dicts])."""
+        import torch
+        n = len(probs)
+        pa = (MnlProblem * max(n, 1))(*[pr.c for pr in probs])
+        if opts is None or isinstance(opts, dict):
+            one = self._opts(**(opts or {}))
+            oa = (MnlFitOpts * max(n, 1))(*([one] * n))
+        else:
+            oa = (MnlFitOpts * max(n, 1))(*[self._opts(**o) for o in opts])
+        thetas = [torch.empty(pr.n_params, dtype=torch.float64,
+                              device=pr.device) for pr in probs]
+        ta = (ctypes.c_void_p * max(n, 1))(*[t.data_ptr() for t in thetas])
+        t0 = None
+        if theta0s is not None:
+            t0 = (ctypes.c_void_p * max(n, 1))(
+                *[t.data_ptr() if t is not None else None for t in theta0s])
+        infos = (MnlFitInfo * max(n, 1))()
+        self._check(self.lib.mnl_fit_batch(
+            self.h, n, pa, t0, oa, ta, infos, _stream_handle(stream)))
+        return thetas, [infos[i].as_dict() for i in range(n)]
 
     def collinear(self, prob: Problem, tol: float = 1e-6, stream=None):
         """Keep masks (numpy bool) of the X, Y and Z variables."""
@@ -375,10 +408,12 @@ class Server:
     server clock, now_ms())."""
 
     def __init__(self, slots: int = 8, hbm_budget: int = 0, device: int = 0,
-                 host_only: bool = False, host_fit_ms: float = 0.0):
+                 host_only: bool = False, host_fit_ms: float = 0.0,
+                 max_group: int = 0):
         self.lib = _lib.load()
         o = MnlServerOpts(device=device, slots=slots, hbm_budget=hbm_budget,
                           host_only=1 if host_only else 0,
+                          max_group=int(max_group),
                           host_fit_ms=float(host_fit_ms))
         h = ctypes.c_void_p()
         rc = self.lib.mnl_server_create(ctypes.byref(h), ctypes.byref(o))

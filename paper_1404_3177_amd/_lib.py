@@ -29,7 +29,7 @@ EXPORTS = [
     "mnl_version", "mnl_strerror", "mnl_default_opts", "mnl_num_params",
     "mnl_create", "mnl_destroy", "mnl_workspace_bytes", "mnl_last_error",
     "mnl_loglik_grad", "mnl_loglik_grad_noalloc", "mnl_hessian",
-    "mnl_newton_step", "mnl_fit",
+    "mnl_newton_step", "mnl_fit", "mnl_fit_batch", "mnl_batch_eligible",
     "mnl_hessvec", "mnl_collinear", "mnl_select_columns", "mnl_predict",
     "mnl_stderr", "mnl_covariance", "mnl_quadform", "mnl_chi2_sf",
     "mnl_lrtest",
@@ -80,7 +80,7 @@ class MnlFitInfo(ctypes.Structure):
 class MnlServerOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32),
                 ("hbm_budget", ctypes.c_size_t),
-                ("host_only", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("host_only", ctypes.c_int32), ("max_group", ctypes.c_int32),
                 ("host_fit_ms", ctypes.c_double)]
 
 
@@ -145,6 +145,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                     ctypes.POINTER(MnlFitInfo), P]
     lib.mnl_fit.argtypes = [P, prob, P, ctypes.POINTER(MnlFitOpts), P,
                             ctypes.POINTER(MnlFitInfo), P]
+    lib.mnl_fit_batch.argtypes = [P, I32, prob, P, ctypes.POINTER(MnlFitOpts),
+                                  P, ctypes.POINTER(MnlFitInfo), P]
+    lib.mnl_batch_eligible.argtypes = [prob, ctypes.POINTER(MnlFitOpts)]
+    lib.mnl_batch_eligible.restype = ctypes.c_int
     lib.mnl_hessvec.argtypes = [P, prob, P, P, P, P]
     lib.mnl_collinear.argtypes = [P, prob, ctypes.c_double, P, P, P, P]
     lib.mnl_covariance.argtypes = [P, prob, P, P, I32, P, P]
@@ -175,7 +179,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mnl_server_get_stats.argtypes = [P, ctypes.POINTER(MnlServerStats)]
     for name in ("mnl_create", "mnl_loglik_grad", "mnl_loglik_grad_noalloc",
                  "mnl_hessian",
-                 "mnl_newton_step", "mnl_fit", "mnl_hessvec", "mnl_predict",
+                 "mnl_newton_step", "mnl_fit", "mnl_fit_batch", "mnl_hessvec",
+                 "mnl_predict",
                  "mnl_collinear", "mnl_select_columns", "mnl_covariance",
                  "mnl_quadform",
                  "mnl_stderr",

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmnl.so")
 SOURCES = ["mnl_api.hip", "mnl_serve.hip", "k_pass.hip", "k_hess.hip", "k_bb.hip",
-           "k_chol.hip", "k_collin.hip"]
+           "k_chol.hip", "k_collin.hip", "k_small.hip"]
 OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [

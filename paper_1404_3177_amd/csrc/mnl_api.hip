@@ -1196,4 +1196,33 @@ int mnl_fit(mnl_ctx *ctx, const mnl_problem *prob, const double *theta0,
   return rc;
 }
 
+int mnl_fit_batch(mnl_ctx *ctx, int32_t nfits, const mnl_problem *probs,
+                  const double *const *theta0, const mnl_fit_opts *opts,
+                  double *const *theta_out, mnl_fit_info *info,
+                  void *stream) {
+  if (!ctx) return MNL_ERR_ARG;
+  Ctx *c = &ctx->c;
+  ++c->call_epoch;
+  return small_fit_run(c, nfits, probs, theta0, opts, theta_out, info,
+                       (hipStream_t)stream);
+}
+
+int mnl_batch_eligible(const mnl_problem *shape, const mnl_fit_opts *opts) {
+  if (!shape) return 0;
+  mnl_fit_opts o;
+  if (opts) o = *opts;
+  else mnl_default_opts(&o);
+  Ctx c;
+  if (check_opts(&c, &o) != MNL_OK) return 0;
+  // only the sizes matter: stand-in pointers pass the NULL checks
+  static const double dummy = 0.0;
+  static const int32_t dummy_c = 0;
+  mnl_problem pr = *shape;
+  pr.X = pr.Y = pr.Z = &dummy;
+  pr.choice = &dummy_c;
+  Dims d;
+  if (check_problem(&c, &pr, &d) != MNL_OK) return 0;
+  return batch_eligible(d, o) ? 1 : 0;
+}
+
 }  // extern "C"

@@ -224,6 +224,23 @@ int select_columns_run(Ctx *c, const Dims &d, const mnl_problem *pr,
                        const int32_t *keep_z, double *X_out, double *Y_out,
                        double *Z_out, hipStream_t s);
 
+// ---- batched small fits (k_small.hip) ---------------------------------------
+// Whether one workgroup can hold a fit of this shape (LDS and register
+// limits of k_fit_small).
+bool small_fit_shape_ok(const Dims &d);
+// Fit nfits problems (device data) with one persistent kernel; opts may be
+// NULL (defaults), else nfits entries, each FP64 Newton without validation.
+// Synchronises s.
+int small_fit_run(Ctx *c, int nfits, const mnl_problem *probs,
+                  const double *const *theta0, const mnl_fit_opts *opts,
+                  double *const *theta_out, mnl_fit_info *infos,
+                  hipStream_t s);
+// Whether the server runs a fit of this shape and options through
+// small_fit_run (mnl_batch_eligible).
+bool batch_eligible(const Dims &d, const mnl_fit_opts &o);
+// Workspace bytes (slot S_BATCH) of a batch of nfits fits.
+size_t small_fit_workspace_bytes(int nfits);
+
 // Context ---------------------------------------------------------------------
 struct Ctx {
   int device = 0;
@@ -318,6 +335,7 @@ enum Slot {
   S_BBPART,        // beta-beta split partials
   S_CG,            // inexact Newton: r, p, H p [np] each, scalars
   S_COLLIN,        // collinearity check: Gram matrices, masks, indices
+  S_BATCH,         // batched small fits: descriptors, options, reports
   S_NSLOTS
 };
 

@@ -10,7 +10,11 @@
 // request that arrives while others run starts as soon as a slot and memory
 // are free.  The arithmetic of a fit depends only on its own shape and data
 // (fixed reduction partitions), never on the slot or on the other fits.
-// A host-only mode runs the same scheduler with no device (admitted
+// Small fits run in groups: a slot that admits a request the batched kernel
+// takes (batch_eligible) also admits the eligible requests right behind it
+// at the head of the queue (arrival order kept, up to max_group and the
+// budget) and runs them as one small_fit_run, a persistent kernel with one
+// workgroup per fit.  A host-only mode runs the same scheduler with no device (admitted
 // requests wait a given time instead of fitting), so admission, slot and
 // budget accounting can be tested anywhere.
 #include <algorithm>
@@ -57,7 +61,10 @@ struct Request {
   Dims d;
   double t_arrival;
   size_t footprint;
+  bool batch;              // runs through small_fit_run
 };
+
+constexpr int kDefaultGroup = 1024;
 
 }  // namespace
 }  // namespace mnl
@@ -65,6 +72,7 @@ struct Request {
 struct mnl_server {
   int device = 0;
   size_t budget = 0;
+  int max_group = 1;
   bool host_only = false;
   double host_fit_ms = 0.0;
   hipMemPool_t pool = nullptr;
@@ -146,21 +154,111 @@ void run_request(mnl_server *sv, mnl_server::Slot *sl, const Request &r,
   res->status = rc;
 }
 
+// Run an admitted group of batch-eligible requests as one small_fit_run:
+// one pool allocation holds every request's data and, at its end, all the
+// thetas (one copy back).  Fills res[0 .. n).
+void run_group(mnl_server::Slot *sl, const std::vector<Request> &g,
+               mnl_server_result *res) {
+  Ctx *c = &sl->ctx;
+  hipStream_t s = sl->stream;
+  const int n = int(g.size());
+  std::vector<size_t> off(n + 1), toff(n + 1);
+  std::vector<DataLayout> L(n);
+  off[0] = 0;
+  toff[0] = 0;
+  for (int f = 0; f < n; ++f) {
+    L[f] = data_layout(g[f].d, g[f].hp.w != nullptr);
+    off[f + 1] = off[f] + L[f].oT;   // data only; thetas go at the end
+    toff[f + 1] = toff[f] + size_t(g[f].d.np);
+  }
+  const size_t bytes = off[n] + al(toff[n] * 8);
+  void *buf = nullptr;
+  int rc = MNL_OK;
+  auto hip_fail = [&](hipError_t e, const char *what) {
+    (void)hipGetLastError();
+    if (rc == MNL_OK)
+      rc = set_error(c, MNL_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+  };
+  hipError_t e = hipMallocFromPoolAsync(&buf, bytes, c->pool, s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    rc = set_error(c, MNL_ERR_OOM, "group data copy of %zu bytes", bytes);
+  }
+  char *b = static_cast<char *>(buf);
+  double *thetas = rc == MNL_OK ? reinterpret_cast<double *>(b + off[n])
+                                : nullptr;
+  std::vector<mnl_problem> dp(n);
+  std::vector<const double *> th0(n, nullptr);
+  std::vector<double *> th(n, nullptr);
+  std::vector<mnl_fit_opts> opts(n);
+  std::vector<mnl_fit_info> infos(n);
+  auto h2d = [&](size_t o, const void *src, size_t nb) -> void * {
+    if (rc != MNL_OK || nb == 0 || src == nullptr) return nullptr;
+    hipError_t e2 = hipMemcpyAsync(b + o, src, nb, hipMemcpyHostToDevice, s);
+    if (e2 != hipSuccess) hip_fail(e2, "host-to-device copy");
+    return b + o;
+  };
+  for (int f = 0; f < n && rc == MNL_OK; ++f) {
+    const Request &r = g[f];
+    const Dims &d = r.d;
+    const size_t N = size_t(d.N), K = size_t(d.K), o = off[f];
+    dp[f] = r.hp;
+    dp[f].X = (const double *)h2d(o + L[f].oX, r.hp.X, N * d.p * 8);
+    dp[f].Y = (const double *)h2d(o + L[f].oY, r.hp.Y, N * K * d.g * 8);
+    dp[f].Z = (const double *)h2d(o + L[f].oZ, r.hp.Z, N * K * d.a * 8);
+    dp[f].choice = (const int32_t *)h2d(o + L[f].oC, r.hp.choice, N * 4);
+    dp[f].w = r.hp.w ? (const double *)h2d(o + L[f].oW, r.hp.w, N * 8)
+                     : nullptr;
+    th[f] = thetas + toff[f];
+    // a start is copied into the theta slot itself (NULL: zeros)
+    if (r.theta0) th0[f] = (const double *)h2d(off[n] + toff[f] * 8,
+                                               r.theta0, size_t(d.np) * 8);
+    opts[f] = r.opts;
+  }
+  if (rc == MNL_OK)
+    rc = small_fit_run(c, n, dp.data(), th0.data(), opts.data(), th.data(),
+                       infos.data(), s);
+  std::vector<double> hth;
+  if (rc == MNL_OK) {
+    hth.resize(toff[n]);
+    e = hipMemcpyAsync(hth.data(), thetas, toff[n] * 8, hipMemcpyDeviceToHost,
+                       s);
+    if (e != hipSuccess) hip_fail(e, "device-to-host copy");
+  }
+  ctx_release(c);
+  if (buf) (void)hipFreeAsync(buf, s);
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) hip_fail(e, "stream synchronize");
+  for (int f = 0; f < n; ++f) {
+    res[f].status = rc;
+    if (rc == MNL_OK) {
+      res[f].info = infos[f];
+      std::memcpy(g[f].theta_out, hth.data() + toff[f],
+                  size_t(g[f].d.np) * 8);
+    }
+  }
+}
+
 // host-only mode: the request "runs" for host_fit_ms and returns theta = 0
-void run_request_host(mnl_server *sv, const Request &r,
-                      mnl_server_result *res) {
-  res->status = MNL_OK;
+// (a group together: its fits run at once, as in one batched launch)
+void run_group_host(mnl_server *sv, const std::vector<Request> &g,
+                    mnl_server_result *res) {
   std::this_thread::sleep_for(
       std::chrono::duration<double, std::milli>(sv->host_fit_ms));
-  std::memset(r.theta_out, 0, size_t(r.d.np) * 8);
-  res->info.stop_reason = MNL_STOP_NONE;
+  for (size_t f = 0; f < g.size(); ++f) {
+    res[f].status = MNL_OK;
+    std::memset(g[f].theta_out, 0, size_t(g[f].d.np) * 8);
+    res[f].info.stop_reason = MNL_STOP_NONE;
+  }
 }
 
 void slot_main(mnl_server *sv, int i) {
   mnl_server::Slot *sl = sv->slots[i];
   if (!sv->host_only) (void)hipSetDevice(sv->device);
+  std::vector<Request> grp;
+  std::vector<mnl_server_result> res;
   for (;;) {
-    Request r;
+    grp.clear();
     double t_admit = 0.0;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
@@ -170,31 +268,44 @@ void slot_main(mnl_server *sv, int i) {
                                 sv->budget);
       });
       if (sv->stop) return;
-      r = sv->queue.front();
-      sv->queue.pop_front();
-      sv->in_use += r.footprint;
+      // the head of the queue, and with a batch-eligible head the eligible
+      // requests right behind it while they fit (never one further back)
+      do {
+        const Request &r = sv->queue.front();
+        grp.push_back(r);
+        sv->queue.pop_front();
+        sv->in_use += r.footprint;
+      } while (grp[0].batch && int(grp.size()) < sv->max_group &&
+               !sv->queue.empty() && sv->queue.front().batch &&
+               sv->in_use + sv->queue.front().footprint <= sv->budget);
       sv->peak_in_use = std::max(sv->peak_in_use, sv->in_use);
-      sv->running += 1;
+      sv->running += int(grp.size());
       sv->max_running = std::max(sv->max_running, sv->running);
       // taken under the lock: admission times follow the queue order
       t_admit = now_ms();
     }
-    mnl_server_result res;
-    std::memset(&res, 0, sizeof res);
-    res.id = r.id;
-    res.slot = i;
-    res.t_arrival = r.t_arrival;
-    res.t_admit = t_admit;
-    res.footprint = r.footprint;
-    if (sv->host_only) run_request_host(sv, r, &res);
-    else run_request(sv, sl, r, &res);
-    res.t_done = now_ms();
+    res.assign(grp.size(), mnl_server_result{});
+    for (size_t f = 0; f < grp.size(); ++f) {
+      std::memset(&res[f], 0, sizeof res[f]);
+      res[f].id = grp[f].id;
+      res[f].slot = i;
+      res[f].t_arrival = grp[f].t_arrival;
+      res[f].t_admit = t_admit;
+      res[f].footprint = grp[f].footprint;
+    }
+    if (sv->host_only) run_group_host(sv, grp, res.data());
+    else if (grp[0].batch) run_group(sl, grp, res.data());
+    else run_request(sv, sl, grp[0], &res[0]);
+    const double t_done = now_ms();
     {
       std::lock_guard<std::mutex> lk(sv->mu);
-      sv->in_use -= r.footprint;
-      sv->running -= 1;
-      sv->completed += 1;
-      sv->done.push_back(res);
+      for (size_t f = 0; f < grp.size(); ++f) {
+        res[f].t_done = t_done;
+        sv->in_use -= grp[f].footprint;
+        sv->done.push_back(res[f]);
+      }
+      sv->running -= int(grp.size());
+      sv->completed += int64_t(grp.size());
     }
     // freed memory may admit the next request on any idle slot
     sv->cv_work.notify_all();
@@ -235,11 +346,13 @@ int64_t mnl_fit_footprint(const mnl_problem *shape, int32_t prec) {
 int mnl_server_create(mnl_server **out, const mnl_server_opts *o) {
   if (!out || !o) return MNL_ERR_ARG;
   *out = nullptr;
-  if (o->slots < 1 || o->slots > 256) return MNL_ERR_ARG;
+  if (o->slots < 1 || o->slots > 256 || o->max_group < 0) return MNL_ERR_ARG;
+  const int max_group = o->max_group == 0 ? kDefaultGroup : o->max_group;
   if (o->host_only) {
     if (o->hbm_budget == 0 || !(o->host_fit_ms >= 0.0)) return MNL_ERR_ARG;
     mnl_server *sv = new mnl_server;
     sv->host_only = true;
+    sv->max_group = max_group;
     sv->host_fit_ms = o->host_fit_ms;
     sv->budget = o->hbm_budget;
     for (int i = 0; i < o->slots; ++i)
@@ -258,6 +371,7 @@ int mnl_server_create(mnl_server **out, const mnl_server_opts *o) {
   if (hipSetDevice(o->device) != hipSuccess) return MNL_ERR_HIP;
   mnl_server *sv = new mnl_server;
   sv->device = o->device;
+  sv->max_group = max_group;
   sv->budget = o->hbm_budget;
   if (sv->budget == 0) {
     size_t fr = 0, tot = 0;
@@ -351,6 +465,7 @@ int mnl_server_submit(mnl_server *sv, const mnl_problem *prob,
     const int64_t f = footprint_of(c, prob, r.opts.prec);
     if (f < 0) return MNL_ERR_UNSUPPORTED;
     r.footprint = size_t(f);
+    r.batch = batch_eligible(r.d, r.opts);
   }
   if (r.footprint > sv->budget) return MNL_ERR_OOM;
   r.hp = *prob;

@@ -134,6 +134,19 @@ def test_server_null_arguments_are_rejected(lib):
     assert lib.mnl_server_now_ms() >= t0
 
 
+def test_batch_entry_points_without_a_device(lib):
+    from paper_1404_3177_amd import _lib
+    assert lib.mnl_fit_batch(None, 0, None, None, None, None, None,
+                             None) == -1
+    assert lib.mnl_batch_eligible(None, None) == 0
+    shape = _lib.MnlProblem(N=2000, K=10, p=6, g=1, a=0)
+    assert lib.mnl_batch_eligible(ctypes.byref(shape), None) == 1
+    o = _lib.MnlFitOpts()
+    lib.mnl_default_opts(ctypes.byref(o))
+    o.maxiter = -1   # invalid options are never eligible
+    assert lib.mnl_batch_eligible(ctypes.byref(shape), ctypes.byref(o)) == 0
+
+
 def _footprint(N, K, p, g, a, prec="fp64", weights=False):
     import paper_1404_3177_amd as mnl
     return mnl.fit_footprint(N, K, p, g, a, prec, weights)

@@ -1,6 +1,7 @@
 """Continuous-batching server on the GPU: served fits against the FP64 oracle,
-bitwise identity of each result alone and in a mix, admission by device
-footprint, requests joining a running mix, and error reports."""
+bitwise identity of each result alone and in a mix (with and without
+grouped small fits), admission by device footprint, requests joining a
+running mix, and error reports."""
 import numpy as np
 import pytest
 
@@ -28,9 +29,9 @@ def problems():
             for i, (N, K, p, g, a, wk) in enumerate(MIX)]
 
 
-def serve(probs, slots, prec="fp64", budget=0, **opts):
+def serve(probs, slots, prec="fp64", budget=0, max_group=0, **opts):
     import paper_1404_3177_amd as mnl
-    srv = mnl.Server(slots=slots, hbm_budget=budget)
+    srv = mnl.Server(slots=slots, hbm_budget=budget, max_group=max_group)
     try:
         hps = [mnl.HostProblem.from_numpy(pr, pinned=(i % 2 == 0))
                for i, pr in enumerate(probs)]
@@ -47,12 +48,19 @@ def serve(probs, slots, prec="fp64", budget=0, **opts):
 
 @pytest.fixture(scope="module")
 def alone():
-    """Each problem fitted on its own through mnl_fit (device data)."""
+    """Each problem fitted on its own (device data): through mnl_fit_batch
+    when the server groups such fits, else through mnl_fit."""
     import paper_1404_3177_amd as mnl
     ctx = mnl.Context(0)
     out = []
     for pr in problems():
-        theta, info = ctx.fit(device_problem(pr), gtol=GTOL, ftol=0.0)
+        dp = device_problem(pr)
+        if mnl.batch_eligible(pr.N, pr.K, pr.p, pr.g, pr.a, gtol=GTOL,
+                              ftol=0.0):
+            th, info = ctx.fit_batch([dp], opts=dict(gtol=GTOL, ftol=0.0))
+            theta, info = th[0], info[0]
+        else:
+            theta, info = ctx.fit(dp, gtol=GTOL, ftol=0.0)
         out.append((theta.cpu().numpy(), info))
     return out
 
@@ -70,10 +78,13 @@ def test_served_fits_match_the_oracle():
         assert err <= 1e-8, (pr.name, err)
 
 
-@pytest.mark.parametrize("slots", [1, 5, 12])
-def test_each_result_is_bitwise_the_same_alone_and_in_the_mix(alone, slots):
-    res, st = serve(problems(), slots=slots)
-    assert st["max_running"] <= slots
+@pytest.mark.parametrize("slots,max_group", [(1, 0), (5, 0), (12, 1),
+                                             (3, 4)])
+def test_each_result_is_bitwise_the_same_alone_and_in_the_mix(alone, slots,
+                                                              max_group):
+    res, st = serve(problems(), slots=slots, max_group=max_group)
+    if max_group == 1:
+        assert st["max_running"] <= slots
     if slots > 1:
         assert st["max_running"] > 1  # the fits did overlap
     for (theta, info), r in zip(alone, res):
@@ -124,7 +135,7 @@ def test_admission_respects_the_memory_budget():
 def test_requests_join_a_running_mix():
     import paper_1404_3177_amd as mnl
     probs = problems()
-    srv = mnl.Server(slots=4)
+    srv = mnl.Server(slots=4, max_group=1)
     try:
         hps = [mnl.HostProblem.from_numpy(pr) for pr in probs]
         first = [srv.submit(h, gtol=GTOL, ftol=0.0) for h in hps[:8]]
