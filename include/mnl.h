@@ -293,10 +293,11 @@ int mnl_fit(mnl_ctx *ctx, const mnl_problem *prob, const double *theta0,
  *              time; t_loglik_grad, t_hessian, t_chol and t_ls are the
  *              fit's own phases timed on the device's constant-rate clock
  *              by its workgroup; the other times and counters are 0.
- * Shape limits (MNL_ERR_UNSUPPORTED beyond them): K <= 64, n_p <= 128,
- * and the fit's LDS layout (A = -H with row stride n_p | 1, six vectors
- * of n_p, and 16 staged observations of p + K a + K g values, K
- * probabilities, g means and (K-1) p + K a products) within 160 KiB.  Nothing is written for a call that fails its
+ * Shape limits (MNL_ERR_UNSUPPORTED beyond them): K <= 64, g <= 8,
+ * n_p <= 128, and the fit's LDS layout (A = -H with row stride n_p | 1,
+ * five vectors of n_p, and for 4 observations two staged copies of their
+ * p + K a + K g values, weight and choice, and K + g + g (g+1)/2 +
+ * (K-1) p + K a per-observation products) within 160 KiB.  Nothing is written for a call that fails its
  * checks.  Not capturable into a HIP graph (host copies of the work
  * list).  Synchronises `stream`. */
 int mnl_fit_batch(mnl_ctx *ctx, int32_t nfits, const mnl_problem *probs,

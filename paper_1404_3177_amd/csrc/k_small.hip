@@ -25,20 +25,26 @@ namespace {
 
 constexpr int kSmThreads = 256;  // 4 waves
 constexpr int kSmWaves = kSmThreads / 64;
-constexpr int kSmK = 64, kSmNP = 128;
-constexpr size_t kSmLdsMax = 160 * 1024;
-constexpr size_t kSmLdsTwo = 80 * 1024;   // two workgroups per CU
+constexpr int kSmK = 64, kSmG = 8, kSmNP = 128;
+// dynamic LDS of a workgroup at most: 160 KiB less room for the kernel's
+// static LDS (the work-list slot)
+constexpr size_t kSmLdsMax = 160 * 1024 - 256;
+constexpr int kSmChMax = 64, kSmChMin = 4;   // observations per chunk
 
 // A fit of the work list with its LDS layout (offsets in doubles).
 struct SmallFit {
   int64_t N;
-  int K, p, g, a, np, nbg;   // nbg: beta and gamma coefficients
+  int K, p, g, a, np, nbg, npair;   // nbg: beta and gamma coefficients;
+                                    // npair: g (g + 1) / 2
+  int nbgp;                  // nbg rounded up to a multiple of 16
   int ch;                    // observations per staged chunk
   int seg;                   // lanes per observation (power of two >= K)
   int ld;                    // row stride of A
-  int drow;                  // doubles per staged observation
   int oA, oTh, oG, oDl, oTr, oTg, oPart, oRed, oAlt, oFoff;
-  int oRow, oW, oCh, oP, oYb, oU;
+  int oBuf0, oBuf1;          // two staged chunks, each laid out as:
+  int bX, bZ, bY, bW, bC;    // X [ch][p], Z [ch][K a], Y [ch][K g], w [ch],
+                             // choice [ch] (int32), as in global memory
+  int oP, oQ, oS, oU;        // per-chunk products (see chunk_eval)
   int lds_doubles, pad;
   const double *X, *Y, *Z, *w;
   const int32_t *choice;
@@ -65,77 +71,90 @@ __device__ inline double seg_sum(double v, int seg) {
   for (int o = seg >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
-// sum over the lanes that share lane % seg (one per observation slot)
-__device__ inline double across_segs(double v, int seg) {
-  for (int o = seg; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
-  return v;
+
+// Asynchronous copy of n dwords from global memory into LDS by the whole
+// workgroup: 64-dword blocks go round-robin to the waves, and each lane's
+// dword lands straight in LDS (no registers).  A wave's copies have landed
+// after its s_waitcnt vmcnt(0).
+__device__ inline void wg_copy_lds(const void *src, double *dst, int n) {
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t *s = static_cast<const uint32_t *>(src);
+  char *dc = reinterpret_cast<char *>(dst);
+  for (int c = wv * 64; c < n; c += kSmThreads)
+    if (c + lane < n)
+      __builtin_amdgcn_global_load_lds(s + c + lane,
+                                       (lds_void_t *)(dc + 4 * c), 4, 0, 0);
 }
 
-// Stage observations i0 .. i0 + nobs - 1 into LDS: row j = [x_j (p) |
-// z_j (K a) | y_j (K g)], the weight and the choice.  Rows past nobs are
-// left as they are (never read).
-__device__ void stage_chunk(const SmallFit &F, int64_t i0, int nobs,
-                            double *sm) {
-  const int tid = threadIdx.x;
-  const int p = F.p, Ka = F.K * F.a, Kg = F.K * F.g, dr = F.drow;
-  double *row = sm + F.oRow;
-  if (p)
-    batched_copy<4>(nobs * p, tid, kSmThreads,
-                    [&](int e) { return F.X[i0 * p + e]; },
-                    [&](int e, double v) {
-                      const int j = e / p;
-                      row[j * dr + (e - j * p)] = v;
-                    });
-  if (Ka)
-    batched_copy<4>(nobs * Ka, tid, kSmThreads,
-                    [&](int e) { return F.Z[i0 * Ka + e]; },
-                    [&](int e, double v) {
-                      const int j = e / Ka;
-                      row[j * dr + p + (e - j * Ka)] = v;
-                    });
-  if (Kg)
-    batched_copy<4>(nobs * Kg, tid, kSmThreads,
-                    [&](int e) { return F.Y[i0 * Kg + e]; },
-                    [&](int e, double v) {
-                      const int j = e / Kg;
-                      row[j * dr + p + Ka + (e - j * Kg)] = v;
-                    });
-  int *chs = reinterpret_cast<int *>(sm + F.oCh);
-  for (int j = tid; j < F.ch; j += kSmThreads) {
-    sm[F.oW + j] = j < nobs ? (F.w ? F.w[i0 + j] : 1.0) : 0.0;
-    chs[j] = j < nobs ? F.choice[i0 + j] : -1;
+// Start staging observations i0 .. i0 + nobs - 1 into buffer b.  Without
+// weights the buffer's w holds ones, written once per fit.
+__device__ inline void issue_chunk(const SmallFit &F, int64_t i0, int nobs,
+                                   double *b) {
+  const int p = F.p, Ka = F.K * F.a, Kg = F.K * F.g;
+  if (p) wg_copy_lds(F.X + i0 * p, b + F.bX, 2 * nobs * p);
+  if (Ka) wg_copy_lds(F.Z + i0 * Ka, b + F.bZ, 2 * nobs * Ka);
+  if (Kg) wg_copy_lds(F.Y + i0 * Kg, b + F.bY, 2 * nobs * Kg);
+  if (F.w) wg_copy_lds(F.w + i0, b + F.bW, 2 * nobs);
+  wg_copy_lds(F.choice + i0, b + F.bC, nobs);
+}
+
+// Run body(i0, nobs, buffer) over the chunks of the fit's observations in
+// order, the next chunk's copy in flight while the current one is used.
+template <typename Body>
+__device__ inline void for_chunks(const SmallFit &F, double *sm, Body body) {
+  const int64_t N = F.N, ch = F.ch;
+  const int nch = int((N + ch - 1) / ch);
+  auto nob = [&](int c) { return int(min(ch, N - int64_t(c) * ch)); };
+  issue_chunk(F, 0, nob(0), sm + F.oBuf0);
+  for (int c = 0; c < nch; ++c) {
+    // chunk c has landed, and every wave is done with chunk c - 1, whose
+    // buffer the next copy overwrites
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (c + 1 < nch)
+      issue_chunk(F, int64_t(c + 1) * ch, nob(c + 1),
+                  sm + ((c + 1) & 1 ? F.oBuf1 : F.oBuf0));
+    body(nob(c), sm + (c & 1 ? F.oBuf1 : F.oBuf0));
   }
+  __syncthreads();
 }
 
 // One staged chunk at theta th: for each observation the utilities of
-// Eq. 1 (base alternative's beta = 0) and the softmax (Eqs. 2-3), then
-// either (HESS) P, U_r = P_{alt(r)} phi_r for the beta / gamma coefficients
-// and Ybar = sum_k P_k y_k into LDS, or the residuals R_jk = w_j (delta_{k,
-// c_j} - P_jk) of the gradient (Eq. 9) into LDS and the observation's
-// weighted log-likelihood term (Eq. 5) into *lacc of the chosen
-// alternative's lane.  Wave v, lane l takes observation slot l / seg of
-// the wave's q = 64 / seg, alternative l % seg.
+// Eq. 1 (base alternative's beta = 0) and the softmax (Eqs. 2-3).  Wave v,
+// lane l takes observation slot l / seg of the wave's q = 64 / seg,
+// alternative k = l % seg.  Then, into LDS:
+//  HESS: U_r = P_{alt(r)} phi_r for the beta / gamma coefficients (phi:
+//        the x or z value of coefficient r) [ch][nbg], Ybar = sum_k P_k y_k
+//        [ch][g], and S_uv = sum_k P_k (y_k - Ybar)_u (y_k - Ybar)_v [ch]
+//        [npair] (u >= v);
+//  else: the residuals R_k = w (delta_{k,c} - P_k) of the gradient
+//        (Eq. 9) [ch][K] and their generic sums Ra_v = sum_k R_k y_kv
+//        [ch][g]; the observation's weighted log-likelihood term (Eq. 5)
+//        goes to *lacc of the chosen alternative's lane.
 template <bool HESS>
 __device__ void chunk_eval(const SmallFit &F, const double *th, int nobs,
-                           double *sm, double *lacc) {
+                           const double *b, double *sm, double *lacc) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int K = F.K, p = F.p, g = F.g, a = F.a, seg = F.seg;
   const int q = 64 / seg, k = lane & (seg - 1);
   const bool alt = k < K;
-  const int *chs = reinterpret_cast<const int *>(sm + F.oCh);
+  const double *Xs = b + F.bX, *Zs = b + F.bZ, *Ys = b + F.bY, *Ws = b + F.bW;
+  const int *Cs = reinterpret_cast<const int *>(b + F.bC);
   const double *thg = th + (K - 1) * p, *tha = thg + K * a;
   for (int j0 = wv * q; j0 < F.ch; j0 += kSmWaves * q) {
     const int j = j0 + lane / seg;
-    const bool obs = j < nobs;
-    const double *rj = sm + F.oRow + j * F.drow;
+    const bool on = j < nobs && alt;
+    const double *xj = Xs + j * p, *zk = Zs + (j * K + k) * a,
+                 *yk = Ys + (j * K + k) * g;
     double u = 0.0;
-    if (obs && alt) {
+    if (on) {
       if (k >= 1) {
         const double *bk = th + (k - 1) * p;
-        for (int c = 0; c < p; ++c) u = fma(rj[c], bk[c], u);
+#pragma unroll 4
+        for (int c = 0; c < p; ++c) u = fma(xj[c], bk[c], u);
       }
-      for (int c = 0; c < a; ++c) u = fma(rj[p + k * a + c], thg[k * a + c], u);
-      const double *yk = rj + p + K * a + k * g;
+      for (int c = 0; c < a; ++c) u = fma(zk[c], thg[k * a + c], u);
       for (int c = 0; c < g; ++c) u = fma(yk[c], tha[c], u);
     }
     if (!alt) u = -INFINITY;
@@ -143,40 +162,57 @@ __device__ void chunk_eval(const SmallFit &F, const double *th, int nobs,
     const double e = alt ? exp(u - m) : 0.0;
     const double s = seg_sum(e, seg);
     const double P = e / s;
+    const bool row = j < F.ch && k == 0;   // one lane writes per observation
     if (HESS) {
-      if (j < F.ch && alt) {
-        sm[F.oP + j * K + k] = P;
-        double *uj = sm + F.oU + j * F.nbg;
+      if (on) {
+        double *uj = sm + F.oU + j * F.nbgp;
         if (k >= 1)
-          for (int c = 0; c < p; ++c) uj[(k - 1) * p + c] = P * rj[c];
+          for (int c = 0; c < p; ++c) uj[(k - 1) * p + c] = P * xj[c];
         for (int c = 0; c < a; ++c)
-          uj[(K - 1) * p + k * a + c] = P * rj[p + k * a + c];
+          uj[(K - 1) * p + k * a + c] = P * zk[c];
       }
-      for (int c = 0; c < g; ++c) {
-        const double t =
-            seg_sum(obs && alt ? P * rj[p + K * a + k * g + c] : 0.0, seg);
-        if (j < F.ch && k == 0) sm[F.oYb + j * g + c] = t;
+      double yb[kSmG];
+#pragma unroll
+      for (int v = 0; v < kSmG; ++v) {
+        if (v >= g) break;
+        yb[v] = seg_sum(on ? P * yk[v] : 0.0, seg);
+        if (row) sm[F.oQ + j * g + v] = yb[v];
       }
-    } else if (obs && alt) {
-      const double w = sm[F.oW + j];
-      const int ci = chs[j];
-      if (k == ci) *lacc = fma(w, u - (m + log(s)), *lacc);
-      sm[F.oP + j * K + k] = w * ((k == ci ? 1.0 : 0.0) - P);
+      int pi = 0;
+#pragma unroll
+      for (int v = 0; v < kSmG; ++v) {
+        if (v >= g) break;
+#pragma unroll
+        for (int w2 = 0; w2 <= v; ++w2, ++pi) {
+          const double t = seg_sum(
+              on ? P * (yk[v] - yb[v]) * (yk[w2] - yb[w2]) : 0.0, seg);
+          if (row) sm[F.oS + j * F.npair + pi] = t;
+        }
+      }
+    } else {
+      const int ci = Cs[j < F.ch ? j : 0];
+      const double w = on ? Ws[j] : 0.0;
+      if (on && k == ci) *lacc = fma(w, u - (m + log(s)), *lacc);
+      const double r = on ? w * ((k == ci ? 1.0 : 0.0) - P) : 0.0;
+      if (on) sm[F.oP + j * K + k] = r;
+      for (int v = 0; v < g; ++v) {
+        const double t = seg_sum(on ? r * yk[v] : 0.0, seg);
+        if (row) sm[F.oQ + j * g + v] = t;
+      }
     }
   }
 }
 
 // The fused pass at theta th (LDS): l into *l_out, the gradient into grad
 // (LDS).  Thread t < n_p owns gradient entry t and adds each chunk's
-// observations in order (beta_k,c: sum_j R_jk x_jc; gamma_k,c: sum_j R_jk
-// z_jkc; alpha_c: sum_j sum_k R_jk y_jkc); l is summed over the lanes by a
-// fixed butterfly, then over the waves in wave order.
+// observations in order (beta_k,v: sum_j R_jk x_jv; gamma_k,v: sum_j R_jk
+// z_jkv; alpha_v: sum_j Ra_jv); l is summed over the lanes by a fixed
+// butterfly, then over the waves in wave order.
 __device__ void small_pass(const SmallFit &F, const double *th, double *grad,
                            double *l_out, double *sm) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int K = F.K, p = F.p, g = F.g, a = F.a, np = F.np, dr = F.drow;
-  const double *R = sm + F.oP, *row = sm + F.oRow;
-  // what entry tid of the gradient reads: R column and row offset
+  const int K = F.K, p = F.p, g = F.g, a = F.a, np = F.np, Ka = K * a;
+  const double *R = sm + F.oP, *Ra = sm + F.oQ;
   int kind = 3, kk = 0, off = 0;
   if (tid < (K - 1) * p) {
     kind = 0;
@@ -184,33 +220,31 @@ __device__ void small_pass(const SmallFit &F, const double *th, double *grad,
     off = tid % p;
   } else if (tid < F.nbg) {
     kind = 1;
-    const int c = tid - (K - 1) * p;
-    kk = c / a;
-    off = p + c;
+    off = tid - (K - 1) * p;
+    kk = off / a;
   } else if (tid < np) {
     kind = 2;
-    off = p + K * a + (tid - F.nbg);
+    off = tid - F.nbg;
   }
   double gacc = 0.0, lacc = 0.0;
-  for (int64_t i0 = 0; i0 < F.N; i0 += F.ch) {
-    const int nobs = int(F.N - i0 < F.ch ? F.N - i0 : F.ch);
-    stage_chunk(F, i0, nobs, sm);
+  for_chunks(F, sm, [&](int nobs, const double *b) {
+    chunk_eval<false>(F, th, nobs, b, sm, &lacc);
     __syncthreads();
-    chunk_eval<false>(F, th, nobs, sm, &lacc);
-    __syncthreads();
-    if (kind < 2) {
-      for (int j = 0; j < nobs; ++j)
-        gacc = fma(R[j * K + kk], row[j * dr + off], gacc);
+    double t = gacc;
+    if (kind == 0) {
+      const double *Xs = b + F.bX + off;
+#pragma unroll 8
+      for (int j = 0; j < nobs; ++j) t = fma(R[j * K + kk], Xs[j * p], t);
+    } else if (kind == 1) {
+      const double *Zs = b + F.bZ + off;
+#pragma unroll 8
+      for (int j = 0; j < nobs; ++j) t = fma(R[j * K + kk], Zs[j * Ka], t);
     } else if (kind == 2) {
-      for (int j = 0; j < nobs; ++j) {
-        double t = 0.0;
-        for (int k = 0; k < K; ++k)
-          t = fma(R[j * K + k], row[j * dr + off + k * g], t);
-        gacc += t;
-      }
+#pragma unroll 8
+      for (int j = 0; j < nobs; ++j) t += Ra[j * g + off];
     }
-    __syncthreads();
-  }
+    gacc = t;
+  });
   double *part = sm + F.oPart;
   const double lw = seg_sum(lacc, 64);
   if (lane == 0) part[wv] = lw;
@@ -251,64 +285,112 @@ __device__ inline void tri_rc(int e, int *r, int *c) {
   *c = e - rr * (rr + 1) / 2;
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 // A = -H of Eq. 10 into the lower triangle of the LDS matrix.  With U_r =
-// P_{alt(r)} phi_r (phi: the x or z value of coefficient r) the beta /
-// gamma entries are sum_i w U_r (delta phi_c - U_c) (delta: same
-// alternative); the alpha rows use the centred form: sum_i w U_c
-// (y_{alt(c), v} - ybar_v) and sum_i w sum_k P_k (y_k - ybar)_v
-// (y_k - ybar)_u.  Thread t owns entries t, t + 256, ... and adds each
-// chunk's observations in order.
+// P_{alt(r)} phi_r (phi: the x or z value of coefficient r), the beta /
+// gamma block is sum_i w [delta_{alt(r),alt(c)} U_r phi_c - U_r U_c]: the
+// second term, U^T diag(w) U, is a dense product run on FP64 MFMA (16 x 16
+// tiles of the lower triangle, four observations per k-step, one tile
+// pair per wave at a time, accumulated in place in A chunk by chunk); the
+// first term (pairs of one alternative), the alpha rows in the centred form
+// (w U_c (y_{alt(c), v} - Ybar_v)) and the alpha-alpha block (w S_uv) are
+// sums that thread t adds entry by entry (entries t, t + 256, ...).  Every
+// entry's terms are added in observation order.
 __device__ void small_hessian(const SmallFit &F, const double *th,
                               double *sm) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int K = F.K, p = F.p, g = F.g, a = F.a, np = F.np, nbg = F.nbg;
-  const int ntri = np * (np + 1) / 2, dr = F.drow, yoff = p + K * a;
-  const int *calt = reinterpret_cast<const int *>(sm + F.oAlt);
+  const int nb = (K - 1) * p, Ka = K * a, Kg = K * g, npair = F.npair;
+  const int nbp = F.nbgp, LD = F.ld;
+  const int T = nbp / 16, ntp = T * (T + 1) / 2;
+  // scalar entries: same-alternative pairs of alternative 0 (gamma_0),
+  // then of alternatives 1 .. K-1 (beta_k then gamma_k), then alpha rows
+  const int B = p + a, t0 = a * (a + 1) / 2, tb = B * (B + 1) / 2;
+  const int n_same = t0 + (K - 1) * tb, n_sc = n_same + g * nbg + npair;
   const int *cfoff = reinterpret_cast<const int *>(sm + F.oFoff);
+  const int *calt = reinterpret_cast<const int *>(sm + F.oAlt);
   double *Am = sm + F.oA;
-  const double *W = sm + F.oW, *U = sm + F.oU, *row = sm + F.oRow,
-               *Pc = sm + F.oP, *Yb = sm + F.oYb;
-  double unused = 0.0;
-  for (int64_t i0 = 0; i0 < F.N; i0 += F.ch) {
-    const int nobs = int(F.N - i0 < F.ch ? F.N - i0 : F.ch);
-    stage_chunk(F, i0, nobs, sm);
+  const double *U = sm + F.oU, *Yb = sm + F.oQ, *S = sm + F.oS;
+  for (int e = tid; e < np * LD; e += kSmThreads) Am[e] = 0.0;
+  const int kb = lane >> 4, l16 = lane & 15;
+  for_chunks(F, sm, [&](int nobs, const double *b) {
+    chunk_eval<true>(F, th, nobs, b, sm, nullptr);
     __syncthreads();
-    chunk_eval<true>(F, th, nobs, sm, &unused);
-    __syncthreads();
-    for (int e = tid; e < ntri; e += kSmThreads) {
-      int r, c;
-      tri_rc(e, &r, &c);
-      double *dst = Am + r * F.ld + c;
-      double s = i0 == 0 ? 0.0 : *dst;
-      if (r < nbg) {
-        if (calt[r] == calt[c]) {
-          const int fo = cfoff[c];
-          for (int j = 0; j < nobs; ++j)
-            s = fma(W[j] * U[j * nbg + r], row[j * dr + fo] - U[j * nbg + c], s);
-        } else {
-          for (int j = 0; j < nobs; ++j)
-            s = fma(-W[j] * U[j * nbg + r], U[j * nbg + c], s);
-        }
-      } else if (c < nbg) {
-        const int v = r - nbg, yo = yoff + calt[c] * g + v;
-        for (int j = 0; j < nobs; ++j)
-          s = fma(W[j] * U[j * nbg + c], row[j * dr + yo] - Yb[j * g + v], s);
-      } else {
-        const int vr = r - nbg, vc = c - nbg;
-        for (int j = 0; j < nobs; ++j) {
-          const double *yj = row + j * dr + yoff;
-          const double br = Yb[j * g + vr], bc = Yb[j * g + vc];
-          double t = 0.0;
-          for (int kk = 0; kk < K; ++kk)
-            t = fma(Pc[j * K + kk] * (yj[kk * g + vr] - br),
-                    yj[kk * g + vc] - bc, t);
-          s = fma(W[j], t, s);
-        }
+    const double *W = b + F.bW;
+    // dense part: A -= U^T diag(w) U on the lower tile pairs
+    for (int tp = wv; tp < ntp; tp += kSmWaves) {
+      int ti, tj;
+      tri_rc(tp, &ti, &tj);
+      const int rb = 16 * ti, cb = 16 * tj;
+      d4 acc;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = rb + kb + 4 * q, c = cb + l16;
+        acc[q] = r < nbg && c < nbg ? Am[r * LD + c] : 0.0;
       }
-      *dst = s;
+      for (int j0 = 0; j0 < nobs; j0 += 4) {
+        const int j = j0 + kb;
+        const bool in = j < nobs;
+        const double av = in ? -W[j] * U[j * nbp + rb + l16] : 0.0;
+        const double bv = in ? U[j * nbp + cb + l16] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = rb + kb + 4 * q, c = cb + l16;
+        if (r < nbg && c < nbg) Am[r * LD + c] = acc[q];
+      }
     }
     __syncthreads();
-  }
+    for (int e = tid; e < n_sc; e += kSmThreads) {
+      int r, c;
+      double s;
+      if (e < n_same) {
+        // sum_j w U_r phi_c over a pair of one alternative
+        int k, lr, lc;
+        if (e < t0) {
+          k = 0;
+          tri_rc(e, &lr, &lc);
+          r = nb + lr;
+          c = nb + lc;
+        } else {
+          k = 1 + (e - t0) / tb;
+          tri_rc((e - t0) % tb, &lr, &lc);
+          r = lr < p ? (k - 1) * p + lr : nb + k * a + (lr - p);
+          c = lc < p ? (k - 1) * p + lc : nb + k * a + (lc - p);
+        }
+        s = Am[r * LD + c];
+        const double *Ur = U + r;
+        const double *ph = c < nb ? b + F.bX + cfoff[c] : b + F.bZ + cfoff[c];
+        const int st = c < nb ? p : Ka;
+#pragma unroll 4
+        for (int j = 0; j < nobs; ++j)
+          s = fma(W[j] * Ur[j * nbp], ph[j * st], s);
+      } else if (e < n_same + g * nbg) {
+        const int e2 = e - n_same, v = e2 / nbg;
+        c = e2 - v * nbg;
+        r = nbg + v;
+        s = Am[r * LD + c];
+        const double *Uc = U + c;
+        const double *y = b + F.bY + calt[c] * g + v, *yb = Yb + v;
+#pragma unroll 4
+        for (int j = 0; j < nobs; ++j)
+          s = fma(W[j] * Uc[j * nbp], y[j * Kg] - yb[j * g], s);
+      } else {
+        int vr, vc;
+        tri_rc(e - n_same - g * nbg, &vr, &vc);
+        r = nbg + vr;
+        c = nbg + vc;
+        s = Am[r * LD + c];
+        const double *Sp = S + vr * (vr + 1) / 2 + vc;
+#pragma unroll 4
+        for (int j = 0; j < nobs; ++j) s = fma(W[j], Sp[j * npair], s);
+      }
+      Am[r * LD + c] = s;
+    }
+  });
 }
 
 // L D L^T of A (lower triangle in place: D on the diagonal, the unit
@@ -395,14 +477,23 @@ __global__ __launch_bounds__(kSmThreads, 2) void k_fit_small(
     int *cfoff = reinterpret_cast<int *>(sm + F.oFoff);
     for (int j = tid; j < np; j += kSmThreads) {
       th[j] = F.theta0 ? F.theta0[j] : 0.0;
+      // alternative of the coefficient and its offset in an x or z row
       if (j < (F.K - 1) * F.p) {
         calt[j] = 1 + j / F.p;
         cfoff[j] = j % F.p;
       } else if (j < F.nbg) {
         const int c = j - (F.K - 1) * F.p;
         calt[j] = c / F.a;
-        cfoff[j] = F.p + c;
+        cfoff[j] = c;
       }
+    }
+    if (!F.w)
+      for (int j = tid; j < F.ch; j += kSmThreads)
+        sm[F.oBuf0 + F.bW + j] = sm[F.oBuf1 + F.bW + j] = 1.0;
+    // the padding columns of U stay zero (the MFMA tiles read them)
+    for (int e = tid; e < F.ch * (F.nbgp - F.nbg); e += kSmThreads) {
+      const int j = e / (F.nbgp - F.nbg);
+      sm[F.oU + j * F.nbgp + F.nbg + (e - j * (F.nbgp - F.nbg))] = 0.0;
     }
     __syncthreads();
     double *lv = sm + F.oRed + kSmThreads - 1;   // a pass's l
@@ -517,10 +608,11 @@ int small_layout(const Dims &d, int ch, SmallFit *F) {
   F->a = a;
   F->np = np;
   F->nbg = (K - 1) * p + K * a;
+  F->nbgp = (F->nbg + 15) / 16 * 16;
+  F->npair = g * (g + 1) / 2;
   F->ch = ch;
   F->seg = pow2_at_least(K);
   F->ld = np | 1;
-  F->drow = p + K * a + K * g;
   int o = 0;
   F->oA = o;    o += ev(np * F->ld);
   F->oTh = o;   o += ev(np);
@@ -532,12 +624,18 @@ int small_layout(const Dims &d, int ch, SmallFit *F) {
   F->oRed = o;  o += kSmThreads;
   F->oAlt = o;  o += ev((np + 1) / 2);
   F->oFoff = o; o += ev((np + 1) / 2);
-  F->oRow = o;  o += ev(ch * F->drow);
-  F->oW = o;    o += ev(ch);
-  F->oCh = o;   o += ev((ch + 1) / 2);
+  int bo = 0;
+  F->bX = bo;   bo += ev(ch * p);
+  F->bZ = bo;   bo += ev(ch * K * a);
+  F->bY = bo;   bo += ev(ch * K * g);
+  F->bW = bo;   bo += ev(ch);
+  F->bC = bo;   bo += ev((ch + 1) / 2);
+  F->oBuf0 = o; o += bo;
+  F->oBuf1 = o; o += bo;
   F->oP = o;    o += ev(ch * K);
-  F->oYb = o;   o += ev(ch * g);
-  F->oU = o;    o += ev(ch * F->nbg);
+  F->oQ = o;    o += ev(ch * g);
+  F->oS = o;    o += ev(ch * F->npair);
+  F->oU = o;    o += ch * F->nbgp;
   F->lds_doubles = o;
   return o;
 }
@@ -545,9 +643,9 @@ int small_layout(const Dims &d, int ch, SmallFit *F) {
 }  // namespace
 
 bool small_fit_shape_ok(const Dims &d) {
-  if (d.K > kSmK || d.np > kSmNP) return false;
+  if (d.K > kSmK || d.g > kSmG || d.np > kSmNP) return false;
   SmallFit F;
-  return size_t(small_layout(d, 16, &F)) * 8 <= kSmLdsMax;
+  return size_t(small_layout(d, kSmChMin, &F)) * 8 <= kSmLdsMax;
 }
 
 bool batch_eligible(const Dims &d, const mnl_fit_opts &o) {
@@ -573,6 +671,15 @@ int small_fit_run(Ctx *c, int nfits, const mnl_problem *probs,
   if (nfits == 0) return MNL_OK;
   MNL_HIP(c, hipSetDevice(c->device));
   const double t_start = now_ms();
+  // workgroups per CU that registers allow; a fit's chunk is the largest
+  // whose layout leaves room for that many (a function of the shape alone)
+  const void *kern = reinterpret_cast<const void *>(&k_fit_small);
+  MNL_HIP(c, raise_lds_limit(kern, int(kSmLdsMax)));
+  int occ_regs = 0;
+  MNL_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_regs, kern,
+                                                          kSmThreads, 0));
+  const size_t lds_each = (kSmLdsMax + 256) / size_t(std::max(occ_regs, 1)) -
+                          256;
   std::vector<SmallFit> h(nfits);
   std::vector<SmallOpts> ho(nfits);
   size_t lds = 0;
@@ -596,10 +703,9 @@ int small_fit_run(Ctx *c, int nfits, const mnl_problem *probs,
     if (!theta_out[f])
       return set_error(c, MNL_ERR_ARG, "NULL theta_out of fit %d", f);
     SmallFit &F = h[f];
-    // the largest chunk that keeps two workgroups per CU, else the
-    // smallest
-    int ch = 64;
-    while (ch > 16 && size_t(small_layout(d, ch, &F)) * 8 > kSmLdsTwo) ch /= 2;
+    int ch = kSmChMax;
+    while (ch > kSmChMin && size_t(small_layout(d, ch, &F)) * 8 > lds_each)
+      ch /= 2;
     small_layout(d, ch, &F);
     F.N = d.N;
     F.pad = 0;
@@ -632,10 +738,10 @@ int small_fit_run(Ctx *c, int nfits, const mnl_problem *probs,
                             size_t(nfits) * sizeof(SmallOpts),
                             hipMemcpyHostToDevice, s));
   MNL_HIP(c, hipMemsetAsync(b + o_cnt, 0, sizeof(int), s));
-  MNL_HIP(c, raise_lds_limit(reinterpret_cast<const void *>(&k_fit_small),
-                             int(lds)));
-  const int per_cu = lds <= kSmLdsTwo ? 2 : 1;
-  const int grid = std::min(nfits, device_cus(c) * per_cu);
+  int per_cu = 0;
+  MNL_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern,
+                                                          kSmThreads, lds));
+  const int grid = std::min(nfits, device_cus(c) * std::max(per_cu, 1));
   hipLaunchKernelGGL(k_fit_small, dim3(grid), dim3(kSmThreads), lds, s,
                      reinterpret_cast<const SmallFit *>(b), nfits,
                      reinterpret_cast<const SmallOpts *>(b + o_opt),
