@@ -21,6 +21,12 @@ HIPCC_FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 
+# per-source additions: the batched-fit kernel keeps every phase of a fit
+# in one persistent loop, where hoisting loop-invariant constants (the exp
+# and log polynomials, addresses) out of the phases holds them in registers
+# across all phases; without that the kernel fits three workgroups per CU
+SOURCE_FLAGS = {"k_small.hip": ["-mllvm", "-disable-machine-licm"]}
+
 
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc",
@@ -39,7 +45,8 @@ def build(verbose: bool = False) -> str:
     procs = []
     for src in SOURCES:
         obj = os.path.join(OBJDIR, src.replace(".hip", ".o"))
-        cmd = [cc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *HIPCC_FLAGS, *SOURCE_FLAGS.get(src, []), "-c",
+               os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, obj, subprocess.Popen(

@@ -39,7 +39,6 @@ struct SmallFit {
   int nbgp;                  // nbg rounded up to a multiple of 16
   int ch;                    // observations per staged chunk
   int seg;                   // lanes per observation (power of two >= K)
-  int ld;                    // row stride of A
   int oA, oTh, oG, oDl, oTr, oTg, oPart, oRed, oAlt, oFoff;
   int oBuf0, oBuf1;          // two staged chunks, each laid out as:
   int bX, bZ, bY, bW, bC;    // X [ch][p], Z [ch][K a], Y [ch][K g], w [ch],
@@ -276,6 +275,9 @@ __device__ double small_sumsq(const double *v, int n, double *sm,
   return r;
 }
 
+// Offset of entry (r, c), r >= c, of a row-major packed lower triangle.
+__device__ inline int tix(int r, int c) { return r * (r + 1) / 2 + c; }
+
 // Packed lower-triangle index e -> (r, c), r >= c, row-major.
 __device__ inline void tri_rc(int e, int *r, int *c) {
   int rr = int((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
@@ -303,7 +305,7 @@ __device__ void small_hessian(const SmallFit &F, const double *th,
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int K = F.K, p = F.p, g = F.g, a = F.a, np = F.np, nbg = F.nbg;
   const int nb = (K - 1) * p, Ka = K * a, Kg = K * g, npair = F.npair;
-  const int nbp = F.nbgp, LD = F.ld;
+  const int nbp = F.nbgp;
   const int T = nbp / 16, ntp = T * (T + 1) / 2;
   // scalar entries: same-alternative pairs of alternative 0 (gamma_0),
   // then of alternatives 1 .. K-1 (beta_k then gamma_k), then alpha rows
@@ -313,7 +315,7 @@ __device__ void small_hessian(const SmallFit &F, const double *th,
   const int *calt = reinterpret_cast<const int *>(sm + F.oAlt);
   double *Am = sm + F.oA;
   const double *U = sm + F.oU, *Yb = sm + F.oQ, *S = sm + F.oS;
-  for (int e = tid; e < np * LD; e += kSmThreads) Am[e] = 0.0;
+  for (int e = tid; e < np * (np + 1) / 2; e += kSmThreads) Am[e] = 0.0;
   const int kb = lane >> 4, l16 = lane & 15;
   for_chunks(F, sm, [&](int nobs, const double *b) {
     chunk_eval<true>(F, th, nobs, b, sm, nullptr);
@@ -324,23 +326,26 @@ __device__ void small_hessian(const SmallFit &F, const double *th,
       int ti, tj;
       tri_rc(tp, &ti, &tj);
       const int rb = 16 * ti, cb = 16 * tj;
+      // the lane's A-operand row and B-operand column exist (the region
+      // past nbg holds the pass's residuals, not zeros)
+      const bool ra = rb + l16 < nbg, ca = cb + l16 < nbg;
       d4 acc;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r = rb + kb + 4 * q, c = cb + l16;
-        acc[q] = r < nbg && c < nbg ? Am[r * LD + c] : 0.0;
+        acc[q] = r < nbg && c <= r ? Am[tix(r, c)] : 0.0;
       }
       for (int j0 = 0; j0 < nobs; j0 += 4) {
         const int j = j0 + kb;
         const bool in = j < nobs;
-        const double av = in ? -W[j] * U[j * nbp + rb + l16] : 0.0;
-        const double bv = in ? U[j * nbp + cb + l16] : 0.0;
+        const double av = in && ra ? -W[j] * U[j * nbp + rb + l16] : 0.0;
+        const double bv = in && ca ? U[j * nbp + cb + l16] : 0.0;
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r = rb + kb + 4 * q, c = cb + l16;
-        if (r < nbg && c < nbg) Am[r * LD + c] = acc[q];
+        if (r < nbg && c <= r) Am[tix(r, c)] = acc[q];
       }
     }
     __syncthreads();
@@ -361,7 +366,7 @@ __device__ void small_hessian(const SmallFit &F, const double *th,
           r = lr < p ? (k - 1) * p + lr : nb + k * a + (lr - p);
           c = lc < p ? (k - 1) * p + lc : nb + k * a + (lc - p);
         }
-        s = Am[r * LD + c];
+        s = Am[tix(r, c)];
         const double *Ur = U + r;
         const double *ph = c < nb ? b + F.bX + cfoff[c] : b + F.bZ + cfoff[c];
         const int st = c < nb ? p : Ka;
@@ -372,7 +377,7 @@ __device__ void small_hessian(const SmallFit &F, const double *th,
         const int e2 = e - n_same, v = e2 / nbg;
         c = e2 - v * nbg;
         r = nbg + v;
-        s = Am[r * LD + c];
+        s = Am[tix(r, c)];
         const double *Uc = U + c;
         const double *y = b + F.bY + calt[c] * g + v, *yb = Yb + v;
 #pragma unroll 4
@@ -383,12 +388,12 @@ __device__ void small_hessian(const SmallFit &F, const double *th,
         tri_rc(e - n_same - g * nbg, &vr, &vc);
         r = nbg + vr;
         c = nbg + vc;
-        s = Am[r * LD + c];
+        s = Am[tix(r, c)];
         const double *Sp = S + vr * (vr + 1) / 2 + vc;
 #pragma unroll 4
         for (int j = 0; j < nobs; ++j) s = fma(W[j], Sp[j * npair], s);
       }
-      Am[r * LD + c] = s;
+      Am[tix(r, c)] = s;
     }
   });
 }
@@ -400,10 +405,10 @@ __device__ void small_hessian(const SmallFit &F, const double *th,
 // a pivot is not above the floor or not finite (A is then garbage).
 __device__ bool small_solve(const SmallFit &F, double *sm) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int n = F.np, LD = F.ld;
+  const int n = F.np;
   double *A = sm + F.oA, *red = sm + F.oRed;
   double m = 0.0;
-  for (int j = tid; j < n; j += kSmThreads) m = fmax(m, A[j * LD + j]);
+  for (int j = tid; j < n; j += kSmThreads) m = fmax(m, A[tix(j, j)]);
   red[tid] = m;
   __syncthreads();
   for (int h = kSmThreads / 2; h > 0; h >>= 1) {
@@ -413,7 +418,7 @@ __device__ bool small_solve(const SmallFit &F, double *sm) {
   const double floor = double(n) * 2.220446049250313e-16 * red[0];
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    const double d = A[k * LD + k];
+    const double d = A[tix(k, k)];
     if (!(d > floor) || !isfinite(d)) return false;   // uniform
     const int m2 = n - k - 1, cnt = m2 * (m2 + 1) / 2;
     const double rd = 1.0 / d;
@@ -421,10 +426,10 @@ __device__ bool small_solve(const SmallFit &F, double *sm) {
       int r, c;
       tri_rc(e, &r, &c);
       const int i = k + 1 + r, j = k + 1 + c;
-      A[i * LD + j] = fma(-A[i * LD + k] * rd, A[j * LD + k], A[i * LD + j]);
+      A[tix(i, j)] = fma(-A[tix(i, k)] * rd, A[tix(j, k)], A[tix(i, j)]);
     }
     __syncthreads();
-    for (int i = k + 1 + tid; i < n; i += kSmThreads) A[i * LD + k] *= rd;
+    for (int i = k + 1 + tid; i < n; i += kSmThreads) A[tix(i, k)] *= rd;
     __syncthreads();
   }
   const double *gv = sm + F.oG;
@@ -432,18 +437,18 @@ __device__ bool small_solve(const SmallFit &F, double *sm) {
   if (wv == 0) {
     for (int i = 0; i < n; ++i) {
       double s = 0.0;
-      for (int j = lane; j < i; j += 64) s = fma(A[i * LD + j], x[j], s);
+      for (int j = lane; j < i; j += 64) s = fma(A[tix(i, j)], x[j], s);
       s = seg_sum(s, 64);
       if (lane == 0) x[i] = gv[i] - s;
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
       __builtin_amdgcn_wave_barrier();
     }
-    for (int i = lane; i < n; i += 64) x[i] /= A[i * LD + i];
+    for (int i = lane; i < n; i += 64) x[i] /= A[tix(i, i)];
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     __builtin_amdgcn_wave_barrier();
     for (int i = n - 1; i >= 0; --i) {
       double s = 0.0;
-      for (int j = i + 1 + lane; j < n; j += 64) s = fma(A[j * LD + i], x[j], s);
+      for (int j = i + 1 + lane; j < n; j += 64) s = fma(A[tix(j, i)], x[j], s);
       s = seg_sum(s, 64);
       if (lane == 0) x[i] -= s;
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
@@ -454,7 +459,16 @@ __device__ bool small_solve(const SmallFit &F, double *sm) {
   return true;
 }
 
-__global__ __launch_bounds__(kSmThreads, 2) void k_fit_small(
+// The descriptor's address, hidden from the optimiser: each phase reads the
+// fields it needs (scalar loads) instead of values derived from them for
+// every phase being kept live across the whole iteration loop.
+__device__ inline const SmallFit &fresh(const SmallFit *p) {
+  uint64_t v = reinterpret_cast<uint64_t>(p);
+  asm volatile("" : "+s"(v));
+  return *reinterpret_cast<const SmallFit *>(v);
+}
+
+__global__ __launch_bounds__(kSmThreads, 3) void k_fit_small(
     const SmallFit *fits, int nfits, const SmallOpts *opts, SmallInfo *info,
     int *counter) {
   extern __shared__ double sm[];
@@ -468,7 +482,8 @@ __global__ __launch_bounds__(kSmThreads, 2) void k_fit_small(
     const int f = __builtin_amdgcn_readfirstlane(next);
     __syncthreads();
     if (f >= nfits) return;
-    const SmallFit F = fits[f];
+    const SmallFit *Fp = fits + f;
+    const SmallFit &F = fresh(Fp);
     const SmallOpts o = opts[f];
     const int np = F.np;
     double *th = sm + F.oTh, *gr = sm + F.oG, *dl = sm + F.oDl,
@@ -490,21 +505,16 @@ __global__ __launch_bounds__(kSmThreads, 2) void k_fit_small(
     if (!F.w)
       for (int j = tid; j < F.ch; j += kSmThreads)
         sm[F.oBuf0 + F.bW + j] = sm[F.oBuf1 + F.bW + j] = 1.0;
-    // the padding columns of U stay zero (the MFMA tiles read them)
-    for (int e = tid; e < F.ch * (F.nbgp - F.nbg); e += kSmThreads) {
-      const int j = e / (F.nbgp - F.nbg);
-      sm[F.oU + j * F.nbgp + F.nbg + (e - j * (F.nbgp - F.nbg))] = 0.0;
-    }
     __syncthreads();
     double *lv = sm + F.oRed + kSmThreads - 1;   // a pass's l
     double l = 0.0, dlast = NAN, gnorm = 0.0;
     int iters = 0, ls_iters = 0, backtracks = 0, n_hess = 0, n_pass = 1;
     int reason = MNL_STOP_NONE;
     uint64_t tk0 = wall_clock64(), tk_hess = 0, tk_chol = 0, tk_ls = 0;
-    small_pass(F, th, gr, lv, sm);
+    small_pass(fresh(Fp), th, gr, lv, sm);
     l = *lv;
     __syncthreads();
-    gnorm = sqrt(small_sumsq(gr, np, sm, F));
+    gnorm = sqrt(small_sumsq(gr, np, sm, fresh(Fp)));
     const uint64_t tk_first = wall_clock64() - tk0;
     for (;;) {
       if (!isfinite(l) || !isfinite(gnorm)) {
@@ -520,11 +530,11 @@ __global__ __launch_bounds__(kSmThreads, 2) void k_fit_small(
         break;
       }
       const uint64_t tk1 = wall_clock64();
-      small_hessian(F, th, sm);
+      small_hessian(fresh(Fp), th, sm);
       n_hess += 1;
       const uint64_t tk2 = wall_clock64();
       tk_hess += tk2 - tk1;
-      const bool pd = small_solve(F, sm);
+      const bool pd = small_solve(fresh(Fp), sm);
       const uint64_t tk3 = wall_clock64();
       tk_chol += tk3 - tk2;
       if (!pd) {
@@ -538,7 +548,7 @@ __global__ __launch_bounds__(kSmThreads, 2) void k_fit_small(
       for (int trial = 1; trial <= o.ls_max + 1; ++trial) {
         for (int j = tid; j < np; j += kSmThreads) tr[j] = fma(t, dl[j], th[j]);
         __syncthreads();
-        small_pass(F, tr, tg, lv, sm);
+        small_pass(fresh(Fp), tr, tg, lv, sm);
         lt = *lv;
         __syncthreads();
         n_pass += 1;
@@ -564,13 +574,13 @@ __global__ __launch_bounds__(kSmThreads, 2) void k_fit_small(
       iters += 1;
       dlast = lt - l;
       l = lt;
-      gnorm = sqrt(small_sumsq(gr, np, sm, F));
+      gnorm = sqrt(small_sumsq(gr, np, sm, fresh(Fp)));
       if (fabs(dlast) < o.ftol) {
         reason = MNL_STOP_FTOL;
         break;
       }
     }
-    for (int j = tid; j < np; j += kSmThreads) F.theta[j] = th[j];
+    for (int j = tid; j < np; j += kSmThreads) fresh(Fp).theta[j] = th[j];
     if (tid == 0) {
       SmallInfo r;
       r.iters = iters;
@@ -612,9 +622,8 @@ int small_layout(const Dims &d, int ch, SmallFit *F) {
   F->npair = g * (g + 1) / 2;
   F->ch = ch;
   F->seg = pow2_at_least(K);
-  F->ld = np | 1;
   int o = 0;
-  F->oA = o;    o += ev(np * F->ld);
+  F->oA = o;    o += ev(np * (np + 1) / 2);
   F->oTh = o;   o += ev(np);
   F->oG = o;    o += ev(np);
   F->oDl = o;   o += ev(np);
@@ -632,10 +641,11 @@ int small_layout(const Dims &d, int ch, SmallFit *F) {
   F->bC = bo;   bo += ev((ch + 1) / 2);
   F->oBuf0 = o; o += bo;
   F->oBuf1 = o; o += bo;
-  F->oP = o;    o += ev(ch * K);
+  // the pass's residuals and the Hessian's U products share a region
+  F->oP = F->oU = o;
+  o += std::max(ev(ch * K), ch * F->nbgp);
   F->oQ = o;    o += ev(ch * g);
   F->oS = o;    o += ev(ch * F->npair);
-  F->oU = o;    o += ch * F->nbgp;
   F->lds_doubles = o;
   return o;
 }
