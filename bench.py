@@ -349,7 +349,43 @@ def serving(n_req, slots, load):
     out["c1_batch_1024_fp64"] = serve_run(
         [mnl.HostProblem.from_numpy(p, pinned=True) for p in c1], slots,
         "fp64")
+    out["c1_batch_1024_fp64"]["path"] = (
+        "server: host data, one group of batch-eligible requests per slot "
+        "admission, mnl_fit_batch (one workgroup per fit)")
+    out["c1_fit_batch_1024_device"] = fit_batch_run(c1)
     return out
+
+
+def fit_batch_run(probs, reps=3):
+    """The same fits through mnl_fit_batch on device-resident data (one
+    persistent launch, no host copies): fits/s of the best of reps, and the
+    per-fit device phase times of the workgroups."""
+    import numpy as np
+    import torch
+    import paper_1404_3177_amd as mnl
+    ctx = mnl.Context(0)
+    dps = [mnl.Problem.from_numpy(p) for p in probs]
+    s = torch.cuda.Stream()
+    best, infos = None, None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, infos = ctx.fit_batch(dps, opts=dict(gtol=GTOL, ftol=0.0),
+                                 stream=s)
+        dt = time.perf_counter() - t
+        best = dt if best is None else min(best, dt)
+    stops = {}
+    for i in infos:
+        k = STOP_NAMES.get(i["stop_reason"], "error")
+        stops[k] = stops.get(k, 0) + 1
+    return {"fits": len(probs), "fits_per_s": len(probs) / best,
+            "ms_per_batch": best * 1e3,
+            "iters_mean": float(np.mean([i["iters"] for i in infos])),
+            "stop_reasons": stops,
+            "fit_device_ms_mean": {
+                k: float(np.mean([i[k] for i in infos]))
+                for k in ("t_loglik_grad", "t_hessian", "t_chol", "t_ls")},
+            "path": "mnl_fit_batch, device data, one launch"}
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_bb_c3_fp64_traffic.md")
