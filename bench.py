@@ -488,6 +488,9 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the workload of the counter profile")
+    ap.add_argument("--batch-probe", action="store_true",
+                    help="only run 1024 small fits through mnl_fit_batch "
+                         "(the workload of the batched-kernel profile)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the "
@@ -496,6 +499,12 @@ def main():
 
     if args.traffic_probe:
         traffic_probe(args.config)
+        return
+    if args.batch_probe:
+        import synth
+        c1 = [synth.make_problem(2000, 10, 6, 1, 0, seed=1000 + i,
+                                 coef_sd=0.5) for i in range(1024)]
+        print(json.dumps(fit_batch_run(c1)), flush=True)
         return
 
     import numpy as np
