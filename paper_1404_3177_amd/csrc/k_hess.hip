@@ -369,11 +369,13 @@ template <int NRT>
 __global__ __launch_bounds__(kThreads) void k_hess_alt(
     Dims d, const double *X, const double *Y, const double *Z,
     const double *w, const double *P, const double *Ybar, int nb, int ngrp,
-    int64_t obs_chunk, double *out /* [S][K][nl][nr] */) {
+    int64_t obs_chunk, int xr, double *out /* [S][K][nl][nr] */) {
   constexpr int NQ = NRT == 1 ? 8 : (NRT == 2 ? 4 : (NRT <= 4 ? 2 : 1));
   extern __shared__ double sm[];
-  const int K = d.K, p = d.p, g = d.g, a = d.a;
-  const int nl = p + a + g, nr = a + g;
+  // xr = p: every row of L; xr = 0: only the z and y rows (the x rows come
+  // from k_hess_altx), written at their places p.. of the output rows
+  const int K = d.K, p = xr, g = d.g, a = d.a, pf = d.p;
+  const int nl = p + a + g, nr = a + g, nlf = pf + a + g, lo = pf - p;
   const int grp = blockIdx.x % ngrp, split = blockIdx.x / ngrp;
   const int n0 = grp * nb;
   const int nbe = min(nb, K - n0);
@@ -404,7 +406,7 @@ __global__ __launch_bounds__(kThreads) void k_hess_alt(
                                            (lds_void_t *)(d8 + 4 * c), 4, 0, 0);
       }
     };
-    wg_copy(X + i0 * p, B, 2 * nobs * p);
+    if (p) wg_copy(X + i0 * p, B, 2 * nobs * p);
     wg_copy(Ybar + i0 * g, B + oB, 2 * nobs * g);
     if (w) wg_copy(w + i0, B + oW, 2 * nobs);
     // per observation, the slices of the workgroup's alternatives
@@ -507,16 +509,139 @@ __global__ __launch_bounds__(kThreads) void k_hess_alt(
   for (int jq = 0; jq < NQ; ++jq) {
     const int q = wv + 4 * jq;
     if (q >= nbe) continue;
-    double *ob = out + ((int64_t(split) * K + n0 + q) * nl) * nr;
+    double *ob = out + ((int64_t(split) * K + n0 + q) * nlf) * nr;
     const int r = lane & 15;
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int l = 16 * rt + (lane >> 4) + 4 * i;
-        if (l < nl && r < nr) ob[l * nr + r] = acc[jq][rt][i];
+        if (l < nl && r < nr) ob[(l + lo) * nr + r] = acc[jq][rt][i];
       }
     }
+  }
+}
+
+// The x rows of the per-alternative sums for all alternatives at once:
+//   out[n][l][r] = sum_i x_il (w_i P_in R_in[r]),  l < p,
+// a product X^T B' over the observations with B' columns (n, r) packed 16
+// to an MFMA tile (K (a + g) columns), B' formed in registers from P, the
+// z / y values, Ybar and w staged in LDS.  One workgroup of 8 waves per
+// observation range reads X and Y once; wave v owns column tiles 4 v ..
+// 4 v + 3 and all NRT 16-row tiles of X, so per k-step each A fragment
+// feeds 4 MFMAs and each formed B fragment NRT.
+constexpr int kAxThreads = 512;
+template <int NRT>
+__global__ __launch_bounds__(kAxThreads) void k_hess_altx(
+    Dims d, const double *X, const double *Y, const double *Z,
+    const double *w, const double *P, const double *Ybar, int rb,
+    int64_t obs_chunk, double *out /* [S][K][nl][nr] */) {
+  extern __shared__ double sm[];
+  const int K = d.K, p = d.p, g = d.g, a = d.a;
+  const int nr = a + g, nl = p + a + g, Ka = K * a, Kg = K * g;
+  const int split = blockIdx.x;
+  const int64_t i_begin = int64_t(split) * obs_chunk;
+  const int64_t i_end = min(d.N, i_begin + obs_chunk);
+  // two buffers: Xs [rb][p], Ps [rb][K], Zs [rb][K a], Ys [rb][K g],
+  // Yb [rb][g], Ws [rb] (0 past the range), then one zero slot
+  const int oP = rb * p, oZ = oP + rb * K, oY = oZ + rb * Ka,
+            oB = oY + rb * Kg, oW = oB + rb * g, o0 = oW + rb, bsz = o0 + 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int e = tid; e < 2 * bsz; e += kAxThreads) sm[e] = 0.0;
+  __syncthreads();
+  auto stage = [&](int b, int64_t i0) {
+    double *B = sm + b * bsz;
+    const int nobs = (int)min<int64_t>(rb, i_end - i0);
+    auto wg_copy = [&](const double *src, double *dst, int ndw) {
+      const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src);
+      char *d8 = reinterpret_cast<char *>(dst);
+      for (int c = 64 * wv; c < ndw; c += kAxThreads)
+        if (c + lane < ndw)
+          __builtin_amdgcn_global_load_lds(s32 + c + lane,
+                                           (lds_void_t *)(d8 + 4 * c), 4, 0, 0);
+    };
+    wg_copy(X + i0 * p, B, 2 * nobs * p);
+    wg_copy(P + i0 * K, B + oP, 2 * nobs * K);
+    if (a) wg_copy(Z + i0 * Ka, B + oZ, 2 * nobs * Ka);
+    if (g) {
+      wg_copy(Y + i0 * Kg, B + oY, 2 * nobs * Kg);
+      wg_copy(Ybar + i0 * g, B + oB, 2 * nobs * g);
+    }
+    if (w) wg_copy(w + i0, B + oW, 2 * nobs);
+    // unit weights without w, zero weights past the range
+    if (tid < rb && (!w || tid >= nobs)) B[oW + tid] = tid < nobs ? 1.0 : 0.0;
+  };
+  // this lane's B columns (one per column tile): alternative, the offset of
+  // its z or y value in an observation row, the Ybar offset (zero slot for
+  // z), as offsets base + observation * stride so the loop has no branch
+  const int kb = lane >> 4, l16 = lane & 15;
+  int cP[4], cR[4], cRs[4], cY[4], cYs[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int col = 64 * wv + 16 * t + l16;
+    cP[t] = o0; cR[t] = o0; cRs[t] = 0; cY[t] = o0; cYs[t] = 0;
+    if (col < K * nr) {
+      const int n = col / nr, r = col - n * nr;
+      cP[t] = oP + n;
+      if (r < a) {
+        cR[t] = oZ + n * a + r; cRs[t] = Ka;
+      } else {
+        cR[t] = oY + n * g + (r - a); cRs[t] = Kg;
+        cY[t] = oB + (r - a); cYs[t] = g;
+      }
+    }
+  }
+  int cX[NRT];
+#pragma unroll
+  for (int rt = 0; rt < NRT; ++rt) cX[rt] = 16 * rt + l16;
+  d4 acc[NRT][4];
+#pragma unroll
+  for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[rt][t] = d4{0, 0, 0, 0};
+  const int nround = (int)((i_end - i_begin + rb - 1) / rb);
+  if (nround > 0) stage(0, i_begin);
+  for (int t0 = 0; t0 < nround; ++t0) {
+    const int cur = t0 & 1;
+    // this round's copies landed and every wave is done with the buffer
+    // the next copies overwrite
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (t0 + 1 < nround) stage(cur ^ 1, i_begin + int64_t(t0 + 1) * rb);
+    const double *B = sm + cur * bsz;
+    for (int ks = 0; ks < rb / 4; ++ks) {
+      const int o = 4 * ks + kb;
+      const double wo = B[oW + o];
+      double av[NRT], bv[4];
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt)
+        av[rt] = B[cX[rt] < p ? o * p + cX[rt] : o0];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        bv[t] = wo * B[cP[t] == o0 ? o0 : cP[t] + o * K] *
+                (B[cR[t] + o * cRs[t]] - B[cY[t] + o * cYs[t]]);
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          acc[rt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rt], bv[t],
+                                                            acc[rt][t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int col = 64 * wv + 16 * t + l16;
+    if (col >= K * nr) continue;
+    const int n = col / nr, r = col - n * nr;
+    double *ob = out + ((int64_t(split) * K + n) * nl) * nr + r;
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int l = 16 * rt + kb + 4 * i;
+        if (l < p) ob[l * nr] = acc[rt][t][i];
+      }
   }
 }
 
@@ -628,6 +753,10 @@ struct Plan {
   int64_t alt_chunk = 0;
   size_t alt_lds = 0;
   bool need_alt = false;
+  // x rows of the per-alternative sums in k_hess_altx (else in k_hess_alt)
+  bool altx = false;
+  int altx_nrt = 1, altx_rb = 8;
+  size_t altx_lds = 0;
   // tables: host copies (kept until the plan is freed, so an asynchronous
   // upload never reads freed memory) and one device allocation
   std::vector<Tile> h_tiles;
@@ -805,10 +934,34 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
   // per-alternative kernel
   pl->need_alt = (a + g) > 0;
   if (pl->need_alt) {
-    const int nl = p + a + g, nr = a + g;
+    const int nr = a + g;
     if (nr > kAltNR)
       return set_error(c, MNL_ERR_UNSUPPORTED,
                        "more than %d alternative-varying variables", kAltNR);
+    // the x rows go to k_hess_altx when its columns (alternative, r) fit
+    // one workgroup's 32 column tiles, p <= 64 and its staged rounds fit
+    // in LDS; then k_hess_alt keeps the z and y rows (one row tile)
+    // It pays when the X rows that the one-kernel path reads once per group
+    // of alternatives outweigh the second read of the z and y data:
+    // (groups - 1) p > K (a + g) values per observation
+    pl->altx = false;
+    const int nrt1 = (p + a + g + 15) / 16;
+    const int nb1 = 4 * (nrt1 == 1 ? 8 : (nrt1 == 2 ? 4 : (nrt1 <= 4 ? 2 : 1)));
+    const int64_t groups1 = (K + nb1 - 1) / nb1;
+    if (p >= 1 && p <= 64 && int64_t(K) * nr <= 8 * 4 * 16 &&
+        (groups1 - 1) * p > int64_t(K) * nr) {
+      for (int rb = 8; rb >= 4 && !pl->altx; rb -= 4) {
+        const size_t bsz = size_t(rb) * (p + K + size_t(K) * (a + g) + g + 1) + 1;
+        if (2 * bsz * 8 <= 150 * 1024) {
+          pl->altx = true;
+          pl->altx_rb = rb;
+          pl->altx_lds = 2 * bsz * 8;
+          pl->altx_nrt = (p + 15) / 16;
+        }
+      }
+    }
+    const int pr = pl->altx ? 0 : p;   // rows of L taken from X in k_hess_alt
+    const int nl = pr + a + g;
     int nrt = (nl + 15) / 16;
     if (nrt > 8)
       return set_error(c, MNL_ERR_UNSUPPORTED, "more than 128 features");
@@ -821,11 +974,21 @@ int plan_host(Ctx *c, const Dims &d, int prec, Plan *pl) {
     // one round of resident workgroups (at most 3 per CU: register and
     // LDS limits), split evenly over the alternative groups
     pl->alt_lds = 2 * (size_t(kAltTB) *
-                           (p + size_t(nb) * a + size_t(nb) * g + g + nb + 1) +
+                           (pr + size_t(nb) * a + size_t(nb) * g + g + nb + 1) +
                        1) * 8;
     const int wpc = int(std::max<size_t>(
         1, std::min<size_t>(3, (160 * 1024) / pl->alt_lds)));
-    int Sa = std::max(1, wpc * device_cus(c) / ngrp);
+    // the x-row kernel shares the observation ranges: one range per its
+    // resident workgroups
+    // (two resident workgroups per CU for one row tile of X, whose
+    // registers allow that, else one)
+    const int xpc =
+        pl->altx && pl->altx_nrt == 1
+            ? int(std::max<size_t>(1, std::min<size_t>(
+                                          2, (160 * 1024) / pl->altx_lds)))
+            : 1;
+    int Sa = pl->altx ? xpc * device_cus(c)
+                      : std::max(1, wpc * device_cus(c) / ngrp);
     Sa = int(std::min<int64_t>(Sa, std::max<int64_t>(1, d.N / 64)));
     int64_t ch = (d.N + Sa - 1) / Sa;
     ch = (ch + kAltTB - 1) / kAltTB * kAltTB;
@@ -949,8 +1112,31 @@ hipError_t launch_alt_nrt(const Plan &pl, const HessArgs &h, double *part,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_hess_alt<NRT>), dim3(pl.alt_ngrp * pl.alt_S),
                      dim3(kThreads), pl.alt_lds, s, pl.d, h.X, h.Y, h.Z, h.w,
-                     h.P, h.Ybar, pl.alt_nb, pl.alt_ngrp, pl.alt_chunk, part);
+                     h.P, h.Ybar, pl.alt_nb, pl.alt_ngrp, pl.alt_chunk,
+                     pl.altx ? 0 : pl.d.p, part);
   return hipGetLastError();
+}
+
+template <int NRT>
+hipError_t launch_altx_nrt(const Plan &pl, const HessArgs &h, double *part,
+                           hipStream_t s) {
+  hipError_t e = raise_lds_limit(
+      reinterpret_cast<const void *>(&k_hess_altx<NRT>), (int)pl.altx_lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_hess_altx<NRT>), dim3(pl.alt_S), dim3(kAxThreads),
+                     pl.altx_lds, s, pl.d, h.X, h.Y, h.Z, h.w, h.P, h.Ybar,
+                     pl.altx_rb, pl.alt_chunk, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_altx(const Plan &pl, const HessArgs &h, double *part,
+                       hipStream_t s) {
+  switch (pl.altx_nrt) {
+    case 1: return launch_altx_nrt<1>(pl, h, part, s);
+    case 2: return launch_altx_nrt<2>(pl, h, part, s);
+    case 3: return launch_altx_nrt<3>(pl, h, part, s);
+    default: return launch_altx_nrt<4>(pl, h, part, s);
+  }
 }
 
 hipError_t launch_alt(const Plan &pl, const HessArgs &h, double *part,
@@ -1001,6 +1187,7 @@ int hessian_run(Ctx *c, const HessArgs &h, hipStream_t s) {
   double *alt = reinterpret_cast<double *>(wb + L.o_red);
 
   if (pl->need_alt) {
+    if (pl->altx) MNL_HIP(c, launch_altx(*pl, h, alt_part, s));
     MNL_HIP(c, launch_alt(*pl, h, alt_part, s));
     hipLaunchKernelGGL(k_alt_reduce, dim3((unsigned)((n_alt + 255) / 256)),
                        dim3(256), 0, s, alt_part, pl->alt_S, int64_t(n_alt),

@@ -172,3 +172,17 @@ def test_fit_footprint_covers_data_and_grows_with_the_shape(lib):
     assert _footprint(N, 1, p, g, a) == -1
     assert _footprint(0, K, p, g, a) == -1
     assert lib.mnl_fit_footprint(None, 0) == -1
+
+
+def test_plans_of_every_kernel_path_build_on_the_host(lib):
+    # shapes on both sides of the Hessian kernels' switches (the x rows of
+    # the per-alternative sums in their own kernel for p <= 64 and
+    # K (a + g) <= 512; outer-panel factorisation; no alternative-varying
+    # data): each plan is built on the host by the footprint query
+    shapes = [(1000, 5, 3, 2, 1), (1000, 5, 70, 2, 1), (1000, 200, 3, 2, 1),
+              (400_000, 100, 51, 5, 0), (100_000, 50, 21, 5, 5),
+              (1000, 3, 0, 2, 2), (500, 40, 20, 0, 16), (2000, 8, 64, 3, 3),
+              (2000, 8, 65, 3, 3), (50_000, 500, 11, 0, 0)]
+    for sh in shapes:
+        for prec in ("fp64", "fp32", "bf16"):
+            assert _footprint(*sh, prec) > 0, (sh, prec)

@@ -29,6 +29,11 @@ SHAPES = [  # N, K, p, g, a, weights
     (4000, 25, 4, 1, 5, None),
     (20, 9, 21, 1, 3, None),
     (45, 9, 21, 0, 2, "int"),
+    # the x rows of the per-alternative sums in their own kernel (many
+    # groups of alternatives against little alternative-varying data),
+    # ragged rounds and observation ranges
+    (2003, 30, 40, 1, 0, None),
+    (1001, 30, 40, 1, 1, "uniform"),
 ]
 
 
