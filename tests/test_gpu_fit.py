@@ -89,7 +89,7 @@ def test_newton_steps_follow_oracle_trajectory(ctx):
                                    (3000, 49, 48, 0, 0, None)])
 def test_newton_step_large_system_matches_oracle(ctx, shape):
     # n_p >= 2048 (2,144 ragged, 2,304 a whole number of outer panels): the
-    # factorisation runs by outer panels with library trailing updates
+    # factorisation runs by outer panels with FP64-MFMA trailing updates
     N, K, p, g, a, wk = shape
     pr = synth.make_problem(N, K, p, g, a, seed=77 + K, weights=wk)
     assert pr.n_params >= 2048
