@@ -229,7 +229,9 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
                 av, bv[t], acc[j][t], 0, 0, 0);
         }
       }
-    } else {
+    } else if constexpr (PREC == 0 && TNB == 4) {
+      // (the widest FP64 tile: its registers leave no room to hold the
+      // next step's operands; measured slower that way)
 #pragma unroll 4
       for (int ks = 0; ks < KR / 4; ++ks) {
         // lane: row lane & 15 of each A fragment, observation o
@@ -241,6 +243,35 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
         for (int j = 0; j < kTMA; ++j) {
           const T av = Ps[offn[j] + o] * (dg[j] - Ps[offm[j] + o]);
 #pragma unroll
+          for (int t = 0; t < TNB; ++t)
+            acc[j][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                av, bv[t], acc[j][t], 0, 0, 0);
+        }
+      }
+    } else {
+      // operands one k-step ahead: the LDS reads of step ks + 1 are in
+      // flight while step ks's MFMAs run (lane: row lane & 15 of each A
+      // fragment, observation 4 ks + lane / 16)
+      T bv[TNB], pn[kTMA], pm[kTMA];
+      auto load = [&](int ks, T *b, T *n, T *m) {
+        const int o = 4 * ks + kb;
+#pragma unroll
+        for (int t = 0; t < TNB; ++t) b[t] = Bs[t * XF + ks * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < kTMA; ++j) {
+          n[j] = Ps[offn[j] + o];
+          m[j] = Ps[offm[j] + o];
+        }
+      };
+      load(0, bv, pn, pm);
+#pragma unroll
+      for (int ks = 0; ks < KR / 4; ++ks) {
+        T bv2[TNB], pn2[kTMA], pm2[kTMA];
+        if (ks + 1 < KR / 4) load(ks + 1, bv2, pn2, pm2);
+#pragma unroll
+        for (int j = 0; j < kTMA; ++j) {
+          const T av = pn[j] * (dg[j] - pm[j]);
+#pragma unroll
           for (int t = 0; t < TNB; ++t) {
             if constexpr (PREC == 0)
               acc[j][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
@@ -248,6 +279,15 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
             else
               acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                   av, bv[t], acc[j][t], 0, 0, 0);
+          }
+        }
+        if (ks + 1 < KR / 4) {
+#pragma unroll
+          for (int t = 0; t < TNB; ++t) bv[t] = bv2[t];
+#pragma unroll
+          for (int j = 0; j < kTMA; ++j) {
+            pn[j] = pn2[j];
+            pm[j] = pm2[j];
           }
         }
       }
