@@ -57,7 +57,7 @@ template <> struct BBT<0> {
   using T = double;
   using XT = double;
   using Acc = d4;
-  static constexpr int KR = 32, RS = 34, TNMAX = 4;
+  static constexpr int KR = 32, RS = 34, TNMAX = 5;
   __device__ static int out_row(int l, int r) { return (l >> 4) + 4 * r; }
 };
 template <> struct BBT<1> {
@@ -79,7 +79,7 @@ struct BBConst {
   int kr, rs, tnmax, esz, xsz, asz;
 };
 BBConst bb_const(int prec) {
-  if (prec == 0) return {32, 34, 4, 8, 8, 8};
+  if (prec == 0) return {32, 34, 5, 8, 8, 8};
   if (prec == 1) return {64, 68, 8, 4, 4, 4};
   return {64, 68, 8, 4, 2, 4};
 }
@@ -229,23 +229,60 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
                 av, bv[t], acc[j][t], 0, 0, 0);
         }
       }
-    } else if constexpr (PREC == 0 && TNB == 4) {
-      // (the widest FP64 tile: its registers leave no room to hold the
-      // next step's operands; measured slower that way)
-#pragma unroll 4
+    } else if constexpr (TNB >= 3) {
+      // one k-step of software pipeline with the instruction order fixed
+      // (scheduling barriers): the LDS reads of step ks + 1 go out between
+      // the first three MFMAs of step ks, and its A fragments are formed
+      // between the last four, at least five MFMAs after those reads; a
+      // wave then waits on LDS only at the start of a round
+      constexpr int NQ = kTMA * TNB;
+      T bv[TNB], av[kTMA];
+      {
+#pragma unroll
+        for (int t = 0; t < TNB; ++t) bv[t] = Bs[t * XF + lane];
+#pragma unroll
+        for (int j = 0; j < kTMA; ++j)
+          av[j] = Ps[offn[j] + kb] * (dg[j] - Ps[offm[j] + kb]);
+      }
+#pragma unroll
       for (int ks = 0; ks < KR / 4; ++ks) {
-        // lane: row lane & 15 of each A fragment, observation o
-        const int o = 4 * ks + kb;
-        T bv[TNB];
+        const bool more = ks + 1 < KR / 4;
+        const int o = 4 * (ks + 1) + kb;
+        T bn[TNB], pn[kTMA], pm[kTMA], an[kTMA];
 #pragma unroll
-        for (int t = 0; t < TNB; ++t) bv[t] = Bs[t * XF + ks * 64 + lane];
-#pragma unroll
-        for (int j = 0; j < kTMA; ++j) {
-          const T av = Ps[offn[j] + o] * (dg[j] - Ps[offm[j] + o]);
-#pragma unroll
-          for (int t = 0; t < TNB; ++t)
+        for (int q = 0; q < NQ; ++q) {
+          const int j = q / TNB, t = q % TNB;
+          __builtin_amdgcn_sched_barrier(0);
+          if constexpr (PREC == 0)
             acc[j][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                av, bv[t], acc[j][t], 0, 0, 0);
+                av[j], bv[t], acc[j][t], 0, 0, 0);
+          else
+            acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                av[j], bv[t], acc[j][t], 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
+          if (more) {
+            if (q == 0) {
+#pragma unroll
+              for (int u = 0; u < TNB; ++u)
+                bn[u] = Bs[u * XF + (ks + 1) * 64 + lane];
+            } else if (q == 1) {
+#pragma unroll
+              for (int i = 0; i < kTMA; ++i) pn[i] = Ps[offn[i] + o];
+            } else if (q == 2) {
+#pragma unroll
+              for (int i = 0; i < kTMA; ++i) pm[i] = Ps[offm[i] + o];
+            } else if (q >= NQ - kTMA) {
+              const int i = q - (NQ - kTMA);
+              an[i] = pn[i] * (dg[i] - pm[i]);
+            }
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (more) {
+#pragma unroll
+          for (int j = 0; j < kTMA; ++j) av[j] = an[j];
+#pragma unroll
+          for (int t = 0; t < TNB; ++t) bv[t] = bn[t];
         }
       }
     } else {
