@@ -190,6 +190,14 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
     for (int t = 0; t < TNB; ++t) acc[j][t] = Acc{0, 0, 0, 0};
 
   __syncthreads();   // column table and zero columns in place
+  // this wave's staged columns (wvs, wvs + NWV, ...): lane i holds the
+  // dword offset of its i-th, read from LDS once, so that a copy during
+  // the MFMAs takes its offset with a lane read instead of an LDS read
+  // and the wait behind it
+  constexpr int CPW = kMaxStage / kWaves;   // most columns per wave
+  static_assert(CPW <= 64, "one lane per column");
+  const int nmine = ncol > wvs ? (ncol - wvs + kWaves - 1) / kWaves : 0;
+  const int mycol = lane < nmine ? ctab[wvs + kWaves * lane] : 0;
   stage(0, tl.ob0);
   __builtin_amdgcn_s_waitcnt(0);   // every counter: this wave's copies landed
   __syncthreads();
@@ -197,7 +205,8 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
   const int kb = lane >> 4;
   for (int ob = tl.ob0; ob < tl.ob1; ++ob, cur ^= 1) {
     // the next round streams into the other buffer during this one
-    if (ob + 1 < tl.ob1) stage(cur ^ 1, ob + 1);
+    constexpr bool kSpread = PREC == 0 && TNB >= 3;
+    if (!kSpread && ob + 1 < tl.ob1) stage(cur ^ 1, ob + 1);
     const char *buf = sm + cur * L.bufsz;
     const T *Ps = reinterpret_cast<const T *>(buf);
     const XT *Bs = reinterpret_cast<const XT *>(buf + L.b);
@@ -235,7 +244,20 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
       // the first three MFMAs of step ks, and its A fragments are formed
       // between the last four, at least five MFMAs after those reads; a
       // wave then waits on LDS only at the start of a round
-      constexpr int NQ = kTMA * TNB;
+      constexpr int NQ = kTMA * TNB, NKS = KR / 4, NHALF = NKS / 2;
+      // FP64: the next round's copies go out over the first half of the
+      // round, between MFMAs (step ks < NHALF issues this wave's columns
+      // CPK ks .. CPK ks + CPK - 1 and B pieces BPK ks .. BPK ks + BPK - 1);
+      // the 2x faster FP32 MFMAs hide them less well than one block of
+      // copies at the start of the round (measured)
+      constexpr int CPK = (CPW + NHALF - 1) / NHALF;
+      constexpr int BPW = (BCH + kWaves - 1) / kWaves;
+      constexpr int BPK = (BPW + NHALF - 1) / NHALF;
+      const bool copy = kSpread && ob + 1 < tl.ob1;
+      char *nbuf = sm + (cur ^ 1) * L.bufsz;
+      const uint32_t *nsrc = pt32 + int64_t(ob + 1) * D.K * CDW;
+      const char *nxs = xx8 + (int64_t(ob + 1) * D.ncgx + int64_t(tl.ct) * TNB) *
+                                  XF * sizeof(XT);
       T bv[TNB], av[kTMA];
       {
 #pragma unroll
@@ -260,6 +282,27 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
             acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                 av[j], bv[t], acc[j][t], 0, 0, 0);
           __builtin_amdgcn_sched_barrier(0);
+          if (ks < NHALF && q == 3 && copy) {
+#pragma unroll
+            for (int u = 0; u < CPK; ++u) {
+              const int i = CPK * ks + u;
+              if (i < CPW && i < nmine)
+                __builtin_amdgcn_global_load_lds(
+                    nsrc + __builtin_amdgcn_readlane(mycol, i) + lane,
+                    (lds_void_t *)(nbuf + (wvs + kWaves * i) * RS * sizeof(T)),
+                    4, 0, 0);
+            }
+          }
+          if (ks < NHALF && q == 4 && copy) {
+#pragma unroll
+            for (int u = 0; u < BPK; ++u) {
+              const int m = wvs + kWaves * (BPK * ks + u);
+              if (m < BCH)
+                __builtin_amdgcn_global_load_lds(
+                    nxs + m * 1024 + lane * 16,
+                    (lds_void_t *)(nbuf + L.b + m * 1024), 16, 0, 0);
+            }
+          }
           if (more) {
             if (q == 0) {
 #pragma unroll
