@@ -34,6 +34,11 @@ SHAPES = [  # N, K, p, g, a, weights
     # ragged rounds and observation ranges
     (2003, 30, 40, 1, 0, None),
     (1001, 30, 40, 1, 1, "uniform"),
+    # three B fragments per wave: 128 staged alternatives in 8-wave tiles
+    # (every wave's copy slots in use), 4-wave tiles, two row tiles
+    (700, 129, 8, 1, 1, "uniform"),
+    (1100, 12, 9, 0, 0, None),
+    (900, 40, 8, 1, 0, None),
 ]
 
 
