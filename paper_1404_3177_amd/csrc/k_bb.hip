@@ -18,9 +18,10 @@
 //    contiguous fragment block.  A workgroup streams its column tile of
 //    it into LDS with asynchronous 16-byte copies (no registers held).
 //  * omega depends on theta.  P is transposed once per Hessian into
-//    observation blocks [N/KR][K][KR] (k_p_blocks); the alternatives a
-//    row tile needs stream into LDS per round (one 256-byte column per
-//    copy instruction), and each wave forms its omega fragments in
+//    observation blocks [N/KR][K][RS] (k_p_blocks), each column padded as
+//    its copy in LDS; the alternatives a row tile needs stream into LDS
+//    per round, each run of consecutive alternatives in 1 KB pieces of
+//    16-byte copies, and each wave forms its omega fragments in
 //    registers, in MFMA A-operand order, right before the MFMAs that
 //    consume them.  The rounding to the MFMA type happens after omega is
 //    formed in FP32 (mixed precision) or FP64.
@@ -45,6 +46,10 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int kMaxStage = 128;   // staged alternatives per row tile
+// copy pieces per row tile: each run of consecutive staged alternatives
+// goes to LDS in 1 KB pieces (at most 34 full pieces for 128 columns, plus
+// one partial piece per run)
+constexpr int kMaxPieces = 192;
 constexpr int kTMA = 4;          // 16-row A fragments per wave
 constexpr int kBlkAlt = 32;      // alternatives per pair block (large K)
 
@@ -104,11 +109,14 @@ struct BBTile {
 };
 
 struct BBDev {
-  const void *PT;           // [nob][K][KR] T: P by observation blocks
+  const void *PT;           // [nob][K][RS] T: P by observation blocks,
+                            // each column padded as in LDS
   const void *XX;           // [nob][ncgx][16 KR] XT: chi in fragment order
   const BBTile *tiles;
-  const int32_t *cols;      // [nrt][kMaxStage] staged alternatives
-  const int32_t *ncol;      // [nrt]
+  const int32_t *pieces;    // [nrt][kMaxPieces][2] copy pieces: source
+                            // dword offset in an observation block, LDS
+                            // byte offset | 16-byte lanes << 24
+  const int32_t *npiece;    // [nrt]
   const uint32_t *rowinfo;  // [Mp] ln | lm << 8 | delta << 16
   void *part;               // [S][Mp][Np] accumulator type
   int64_t Mp, Np;
@@ -124,8 +132,6 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
   using Acc = typename C::Acc;
   constexpr int KR = C::KR, RS = C::RS;
   constexpr int XF = 16 * KR;               // chi elements per group/round
-  constexpr int CDW = KR * int(sizeof(T)) / 4;   // dwords per P column: 64
-  static_assert(CDW == 64, "one copy instruction per staged column");
   constexpr int BCH = TNB * XF * int(sizeof(XT)) / 1024;  // 1 KB B chunks
   static_assert(TNB * XF * int(sizeof(XT)) % 1024 == 0, "B tile in 1 KB");
   extern __shared__ double smd[];
@@ -134,13 +140,22 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
   const BBTile tl = D.tiles[blockIdx.x];
   const BBLds L = bb_lds(KR, RS, int(sizeof(T)), int(sizeof(XT)), D.pcols,
                          TNB);
-  const int ncol = D.ncol[tl.rt];
-  // the tile's staged alternatives, as dword offsets of their P columns
-  // in an observation block, in LDS after the two round buffers: reading
-  // them waits on LDS only, never on the copies in flight
-  int *ctab = reinterpret_cast<int *>(sm + 2 * L.bufsz);
-  for (int c = tid; c < ncol; c += 64 * kWaves)
-    ctab[c] = D.cols[int64_t(tl.rt) * kMaxStage + c] * CDW;
+  // the wave index as a scalar: the copy loops are then scalar
+  const int wvs = __builtin_amdgcn_readfirstlane(wv);
+  // this wave's copy pieces of the tile's staged P columns (pieces wvs,
+  // wvs + NWV, ...): lane i holds the i-th, so a copy takes its offsets
+  // with a lane read and no memory wait
+  constexpr int PPW = kMaxPieces / kWaves;   // most pieces per wave
+  static_assert(PPW <= 64, "one lane per piece");
+  const int npc = D.npiece[tl.rt];
+  const int npw = npc > wvs ? (npc - wvs + kWaves - 1) / kWaves : 0;
+  int psrc = 0, pdst = 0;
+  if (lane < npw) {
+    const int32_t *pe =
+        D.pieces + (int64_t(tl.rt) * kMaxPieces + wvs + kWaves * lane) * 2;
+    psrc = pe[0];
+    pdst = pe[1];
+  }
 
   // the zero column (index pcols) of both buffers, read by padding rows
   for (int e = tid; e < 2 * RS; e += 64 * kWaves) {
@@ -161,20 +176,25 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
     }
   }
 
-  // asynchronous copies of round ob into buffer b: each staged P column
-  // is 64 dwords (one instruction), the B tile is contiguous in 1 KB pieces
+  // asynchronous copies of round ob into buffer b: the staged P columns
+  // (laid out in HBM as in LDS) and the B tile go in 1 KB pieces of
+  // 16-byte lanes
   const uint32_t *pt32 = static_cast<const uint32_t *>(D.PT);
   const char *xx8 = static_cast<const char *>(D.XX);
-  // the wave index as a scalar: the copy loops and their table reads are
-  // then scalar, so waiting for a table entry never waits for the copies
-  const int wvs = __builtin_amdgcn_readfirstlane(wv);
+  constexpr int PDW = RS * int(sizeof(T)) / 4;   // dwords per padded column
+  static_assert(RS * int(sizeof(T)) % 16 == 0, "16-byte column pieces");
+  auto piece = [&](char *buf, const uint32_t *src, int i) {
+    const int ps = __builtin_amdgcn_readlane(psrc, i);
+    const int pd = __builtin_amdgcn_readlane(pdst, i);
+    if (lane < (pd >> 24))
+      __builtin_amdgcn_global_load_lds(src + ps + 4 * lane,
+                                       (lds_void_t *)(buf + (pd & 0xffffff)),
+                                       16, 0, 0);
+  };
   auto stage = [&](int b, int ob) {
     char *buf = sm + b * L.bufsz;
-    const uint32_t *src = pt32 + int64_t(ob) * D.K * CDW;
-    for (int c = wvs; c < ncol; c += kWaves)
-      __builtin_amdgcn_global_load_lds(src + ctab[c] + lane,
-                                       (lds_void_t *)(buf + c * RS * sizeof(T)),
-                                       4, 0, 0);
+    const uint32_t *src = pt32 + int64_t(ob) * D.K * PDW;
+    for (int i = 0; i < npw; ++i) piece(buf, src, i);
     const char *xs =
         xx8 + (int64_t(ob) * D.ncgx + int64_t(tl.ct) * TNB) * XF * sizeof(XT);
     for (int q = wvs; q < BCH; q += kWaves)
@@ -189,15 +209,7 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
 #pragma unroll
     for (int t = 0; t < TNB; ++t) acc[j][t] = Acc{0, 0, 0, 0};
 
-  __syncthreads();   // column table and zero columns in place
-  // this wave's staged columns (wvs, wvs + NWV, ...): lane i holds the
-  // dword offset of its i-th, read from LDS once, so that a copy during
-  // the MFMAs takes its offset with a lane read instead of an LDS read
-  // and the wait behind it
-  constexpr int CPW = kMaxStage / kWaves;   // most columns per wave
-  static_assert(CPW <= 64, "one lane per column");
-  const int nmine = ncol > wvs ? (ncol - wvs + kWaves - 1) / kWaves : 0;
-  const int mycol = lane < nmine ? ctab[wvs + kWaves * lane] : 0;
+  __syncthreads();   // zero columns in place
   stage(0, tl.ob0);
   __builtin_amdgcn_s_waitcnt(0);   // every counter: this wave's copies landed
   __syncthreads();
@@ -246,16 +258,18 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
       // wave then waits on LDS only at the start of a round
       constexpr int NQ = kTMA * TNB, NKS = KR / 4, NHALF = NKS / 2;
       // FP64: the next round's copies go out over the first half of the
-      // round, between MFMAs (step ks < NHALF issues this wave's columns
+      // round, between MFMAs (step ks < NHALF issues this wave's P pieces
       // CPK ks .. CPK ks + CPK - 1 and B pieces BPK ks .. BPK ks + BPK - 1);
       // the 2x faster FP32 MFMAs hide them less well than one block of
       // copies at the start of the round (measured)
-      constexpr int CPK = (CPW + NHALF - 1) / NHALF;
+      // (at most 4 pieces per step; a wave's pieces past 4 NHALF, which
+      // only many short runs of alternatives give, go out in one loop)
+      constexpr int CPK = std::min(4, (PPW + NHALF - 1) / NHALF);
       constexpr int BPW = (BCH + kWaves - 1) / kWaves;
       constexpr int BPK = (BPW + NHALF - 1) / NHALF;
       const bool copy = kSpread && ob + 1 < tl.ob1;
       char *nbuf = sm + (cur ^ 1) * L.bufsz;
-      const uint32_t *nsrc = pt32 + int64_t(ob + 1) * D.K * CDW;
+      const uint32_t *nsrc = pt32 + int64_t(ob + 1) * D.K * PDW;
       const char *nxs = xx8 + (int64_t(ob + 1) * D.ncgx + int64_t(tl.ct) * TNB) *
                                   XF * sizeof(XT);
       T bv[TNB], av[kTMA];
@@ -286,12 +300,10 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
 #pragma unroll
             for (int u = 0; u < CPK; ++u) {
               const int i = CPK * ks + u;
-              if (i < CPW && i < nmine)
-                __builtin_amdgcn_global_load_lds(
-                    nsrc + __builtin_amdgcn_readlane(mycol, i) + lane,
-                    (lds_void_t *)(nbuf + (wvs + kWaves * i) * RS * sizeof(T)),
-                    4, 0, 0);
+              if (i < PPW && i < npw) piece(nbuf, nsrc, i);
             }
+            if (ks == 0)
+              for (int i = CPK * NHALF; i < npw; ++i) piece(nbuf, nsrc, i);
           }
           if (ks < NHALF && q == 4 && copy) {
 #pragma unroll
@@ -444,9 +456,11 @@ __global__ __launch_bounds__(256) void k_xx_frag(
   }
 }
 
-// P [N][K] (FP64) -> PT [nob][K][KR] in T (0 past N); one workgroup per
-// block of KR observations and 64 alternatives, transposed through LDS.
-template <typename T, int KR>
+// P [N][K] (FP64) -> PT [nob][K][RS] in T (0 past N; the RS - KR padding
+// entries of a column are not written), the layout of the staged columns
+// in LDS; one workgroup per block of KR observations and 64 alternatives,
+// transposed through LDS.
+template <typename T, int KR, int RS>
 __global__ __launch_bounds__(256) void k_p_blocks(const double *P, int K,
                                                   int64_t N, T *PT) {
   __shared__ double tile[KR][65];
@@ -461,7 +475,7 @@ __global__ __launch_bounds__(256) void k_p_blocks(const double *P, int K,
   __syncthreads();
   for (int e = tid; e < KR * 64; e += 256) {
     const int k = e / KR, i = e - k * KR;
-    if (k0 + k < K) PT[(ob * K + k0 + k) * KR + i] = T(tile[i][k]);
+    if (k0 + k < K) PT[(ob * K + k0 + k) * RS + i] = T(tile[i][k]);
   }
 }
 
@@ -499,13 +513,13 @@ struct BBPlan {
   int64_t npairs = 0, Mp = 0, Np = 0, ncombo = 0, nob = 0, nrt = 0;
   size_t lds = 0;
   std::vector<BBTile> h_tiles;
-  std::vector<int32_t> h_cols, h_ncol, h_pair;
+  std::vector<int32_t> h_pieces, h_npiece, h_pair;
   std::vector<uint32_t> h_row, h_combo;
-  size_t o_cols = 0, o_ncol = 0, o_row = 0, o_combo = 0, o_pair = 0;
+  size_t o_pieces = 0, o_npiece = 0, o_row = 0, o_combo = 0, o_pair = 0;
   size_t dev_bytes = 0;
   void *dev = nullptr;
   BBTile *tiles = nullptr;
-  int32_t *cols = nullptr, *ncol = nullptr, *pair = nullptr;
+  int32_t *pieces = nullptr, *npiece = nullptr, *pair = nullptr;
   uint32_t *row = nullptr, *combo = nullptr;
 };
 
@@ -586,14 +600,32 @@ int bb_plan_host(Ctx *c, const Dims &d, int prec, BBPlan *pl) {
   int pcols = 1;
   for (auto &tc : tcols) pcols = std::max(pcols, int(tc.size()));
   pl->pcols = pcols;
-  std::vector<int32_t> cols(size_t(std::max<int64_t>(pl->nrt, 1)) * kMaxStage, 0);
-  std::vector<int32_t> ncol(size_t(std::max<int64_t>(pl->nrt, 1)), 0);
+  // copy pieces of each row tile: runs of consecutive staged alternatives
+  // (contiguous in the padded P blocks and in LDS) cut into 1 KB pieces
+  std::vector<int32_t> pieces(size_t(std::max<int64_t>(pl->nrt, 1)) * kMaxPieces * 2, 0);
+  std::vector<int32_t> npiece(size_t(std::max<int64_t>(pl->nrt, 1)), 0);
+  const int colb = bc.rs * bc.esz;   // bytes per padded column
   std::vector<uint32_t> rowinfo(size_t(std::max<int64_t>(pl->Mp, 1)),
                                 uint32_t(pcols) | (uint32_t(pcols) << 8));
   for (int64_t t = 0; t < pl->nrt; ++t) {
     const auto &tc = tcols[t];
-    ncol[t] = int(tc.size());
-    for (size_t q = 0; q < tc.size(); ++q) cols[t * kMaxStage + q] = tc[q];
+    int np = 0;
+    for (size_t q0 = 0; q0 < tc.size();) {
+      size_t q1 = q0 + 1;
+      while (q1 < tc.size() && tc[q1] == tc[q1 - 1] + 1) ++q1;
+      const int64_t bytes = int64_t(q1 - q0) * colb;
+      for (int64_t off = 0; off < bytes; off += 1024, ++np) {
+        if (np >= kMaxPieces)
+          return set_error(c, MNL_ERR_UNSUPPORTED, "beta-beta copy pieces");
+        const int64_t nb = std::min<int64_t>(1024, bytes - off);
+        pieces[(t * kMaxPieces + np) * 2] =
+            int32_t((int64_t(tc[q0]) * colb + off) / 4);
+        pieces[(t * kMaxPieces + np) * 2 + 1] =
+            int32_t((int64_t(q0) * colb + off) | ((nb / 16) << 24));
+      }
+      q0 = q1;
+    }
+    npiece[t] = np;
     for (int64_t r = t * R; r < (t + 1) * R; ++r) {
       const int32_t nm = row_nm[r];
       if (nm == 0) continue;
@@ -627,7 +659,7 @@ int bb_plan_host(Ctx *c, const Dims &d, int prec, BBPlan *pl) {
   pl->Np = int64_t(pl->ncgx) * 16;
   pl->nob = (d.N + bc.kr - 1) / bc.kr;
   const BBLds L = bb_lds(bc.kr, bc.rs, bc.esz, bc.xsz, pcols, tnb);
-  pl->lds = size_t(2) * L.bufsz + kMaxStage * 4;   // + column table
+  pl->lds = size_t(2) * L.bufsz;
   if (pl->lds > 160 * 1024)
     return set_error(c, MNL_ERR_UNSUPPORTED, "beta-beta tile exceeds LDS");
 
@@ -693,15 +725,15 @@ int bb_plan_host(Ctx *c, const Dims &d, int prec, BBPlan *pl) {
   }
   pl->ntiles = int(tiles.size());
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  pl->o_cols = al(tiles.size() * sizeof(BBTile));
-  pl->o_ncol = al(pl->o_cols + cols.size() * 4);
-  pl->o_row = al(pl->o_ncol + ncol.size() * 4);
+  pl->o_pieces = al(tiles.size() * sizeof(BBTile));
+  pl->o_npiece = al(pl->o_pieces + pieces.size() * 4);
+  pl->o_row = al(pl->o_npiece + npiece.size() * 4);
   pl->o_combo = al(pl->o_row + rowinfo.size() * 4);
   pl->o_pair = al(pl->o_combo + std::max<size_t>(combo.size(), 1) * 4);
   pl->dev_bytes = al(pl->o_pair + std::max<size_t>(row_nm.size(), 1) * 4);
   pl->h_tiles = std::move(tiles);
-  pl->h_cols = std::move(cols);
-  pl->h_ncol = std::move(ncol);
+  pl->h_pieces = std::move(pieces);
+  pl->h_npiece = std::move(npiece);
   pl->h_row = std::move(rowinfo);
   pl->h_combo = std::move(combo);
   pl->h_pair = std::move(row_nm);
@@ -723,8 +755,8 @@ int bb_plan_upload(Ctx *c, BBPlan *pl) {
   }
   char *base = static_cast<char *>(pl->dev);
   pl->tiles = reinterpret_cast<BBTile *>(base);
-  pl->cols = reinterpret_cast<int32_t *>(base + pl->o_cols);
-  pl->ncol = reinterpret_cast<int32_t *>(base + pl->o_ncol);
+  pl->pieces = reinterpret_cast<int32_t *>(base + pl->o_pieces);
+  pl->npiece = reinterpret_cast<int32_t *>(base + pl->o_npiece);
   pl->row = reinterpret_cast<uint32_t *>(base + pl->o_row);
   pl->combo = reinterpret_cast<uint32_t *>(base + pl->o_combo);
   pl->pair = reinterpret_cast<int32_t *>(base + pl->o_pair);
@@ -736,8 +768,8 @@ int bb_plan_upload(Ctx *c, BBPlan *pl) {
   };
   if (up(pl->tiles, pl->h_tiles.data(), pl->h_tiles.size() * sizeof(BBTile)) !=
           hipSuccess ||
-      up(pl->cols, pl->h_cols.data(), pl->h_cols.size() * 4) != hipSuccess ||
-      up(pl->ncol, pl->h_ncol.data(), pl->h_ncol.size() * 4) != hipSuccess ||
+      up(pl->pieces, pl->h_pieces.data(), pl->h_pieces.size() * 4) != hipSuccess ||
+      up(pl->npiece, pl->h_npiece.data(), pl->h_npiece.size() * 4) != hipSuccess ||
       up(pl->row, pl->h_row.data(), pl->h_row.size() * 4) != hipSuccess ||
       up(pl->combo, pl->h_combo.data(), pl->h_combo.size() * 4) != hipSuccess ||
       up(pl->pair, pl->h_pair.data(), pl->h_pair.size() * 4) != hipSuccess)
@@ -780,7 +812,7 @@ struct BBWs {
 BBWs bb_ws_bytes(const BBPlan &pl) {
   const BBConst bc = bb_const(pl.prec);
   BBWs w;
-  w.pt = size_t(pl.nob) * pl.d.K * bc.kr * bc.esz;
+  w.pt = size_t(pl.nob) * pl.d.K * bc.rs * bc.esz;
   w.part = size_t(pl.S) * pl.Mp * pl.Np * bc.asz;
   w.xx = size_t(pl.nob) * pl.ncgx * 16 * bc.kr * bc.xsz;
   return w;
@@ -841,7 +873,7 @@ int bb_run_prec(Ctx *c, const BBPlan &pl, const HessArgs &h, hipStream_t s) {
     xs.epoch = c->call_epoch;
     xs.buf = xxv;
   }
-  hipLaunchKernelGGL((k_p_blocks<T, C::KR>),
+  hipLaunchKernelGGL((k_p_blocks<T, C::KR, C::RS>),
                      dim3(unsigned(pl.nob), unsigned((d.K + 63) / 64)),
                      dim3(256), 0, s, h.P, d.K, d.N, PT);
   MNL_HIP(c, hipGetLastError());
@@ -849,8 +881,8 @@ int bb_run_prec(Ctx *c, const BBPlan &pl, const HessArgs &h, hipStream_t s) {
   D.PT = PT;
   D.XX = xxv;
   D.tiles = pl.tiles;
-  D.cols = pl.cols;
-  D.ncol = pl.ncol;
+  D.pieces = pl.pieces;
+  D.npiece = pl.npiece;
   D.rowinfo = pl.row;
   D.part = partv;
   D.Mp = pl.Mp;
