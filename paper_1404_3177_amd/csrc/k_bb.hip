@@ -217,7 +217,7 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
   const int kb = lane >> 4;
   for (int ob = tl.ob0; ob < tl.ob1; ++ob, cur ^= 1) {
     // the next round streams into the other buffer during this one
-    constexpr bool kSpread = PREC == 0 && TNB >= 3;
+    constexpr bool kSpread = PREC != 2 && TNB >= 3;
     if (!kSpread && ob + 1 < tl.ob1) stage(cur ^ 1, ob + 1);
     const char *buf = sm + cur * L.bufsz;
     const T *Ps = reinterpret_cast<const T *>(buf);
@@ -257,17 +257,15 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
       // between the last four, at least five MFMAs after those reads; a
       // wave then waits on LDS only at the start of a round
       constexpr int NQ = kTMA * TNB, NKS = KR / 4, NHALF = NKS / 2;
-      // FP64: the next round's copies go out over the first half of the
-      // round, between MFMAs (step ks < NHALF issues this wave's P pieces
-      // CPK ks .. CPK ks + CPK - 1 and B pieces BPK ks .. BPK ks + BPK - 1);
-      // the 2x faster FP32 MFMAs hide them less well than one block of
-      // copies at the start of the round (measured)
+      // the next round's copies go out over the first half of the round,
+      // between MFMAs: step ks < NHALF issues this wave's P pieces
+      // CPK ks .. CPK ks + CPK - 1 and B pieces BPK ks .. BPK ks + BPK - 1
       // (at most 4 pieces per step; a wave's pieces past 4 NHALF, which
       // only many short runs of alternatives give, go out in one loop)
       constexpr int CPK = std::min(4, (PPW + NHALF - 1) / NHALF);
       constexpr int BPW = (BCH + kWaves - 1) / kWaves;
       constexpr int BPK = (BPW + NHALF - 1) / NHALF;
-      const bool copy = kSpread && ob + 1 < tl.ob1;
+      const bool copy = ob + 1 < tl.ob1;
       char *nbuf = sm + (cur ^ 1) * L.bufsz;
       const uint32_t *nsrc = pt32 + int64_t(ob + 1) * D.K * PDW;
       const char *nxs = xx8 + (int64_t(ob + 1) * D.ncgx + int64_t(tl.ct) * TNB) *
