@@ -306,19 +306,30 @@ __global__ __launch_bounds__(256) void k_chol_copy(double *A, int64_t n,
 // Trailing update of an outer panel on FP64 MFMA:
 //   C[r][c] = beta C[r][c] - sum_k A[r][k] B[c][k],  k < kdim,
 // row-major operands with strides lda, ldb, ldc; r < M, c < Nc.  One
-// workgroup per 128 x 128 tile of C (lower: only tiles with tile row >=
+// workgroup per TE x TE tile of C (lower: only tiles with tile row >=
 // tile column, the lower triangle of a symmetric update; the upper part of
-// a diagonal tile is written too and never read), four waves of 64 x 64
-// (4 x 4 MFMA tiles of 16 x 16).  The k extent streams through LDS in
-// chunks of 8 (k-major, so each fragment read is 16 consecutive doubles),
-// the next chunk's loads in registers while this chunk's MFMAs run.
-constexpr int SYT = 128;   // tile edge
-constexpr int SYK = 8;     // k chunk
-constexpr int SYP = SYT + 2;   // LDS row length of a k slice (padding)
-__global__ __launch_bounds__(256, 2) void k_chol_syrk(
+// a diagonal tile is written too and never read), four waves of TE/2 x
+// TE/2 (16 x 16 MFMA tiles).  The k extent streams through LDS in chunks
+// of SYK (k-major, so each fragment read is 16 consecutive doubles), the
+// next chunk's loads in registers while this chunk's MFMAs run.  128-wide
+// tiles read each operand half as often; 64-wide ones split a small
+// trailing square over more workgroups (the launch takes whichever needs
+// fewer rounds of MFMA work).
+template <int TE>
+struct SyrkCfg {
+  static constexpr int SYK = TE == 128 ? 8 : 16;   // k chunk
+  static constexpr int SYP = TE + 2;   // LDS row length of a k slice
+  static constexpr int NF = TE / 32;   // 16-wide fragments per wave edge
+  static constexpr int NU = TE / (512 / SYK);   // row passes of a load
+};
+template <int TE>
+__global__ __launch_bounds__(256, TE == 128 ? 2 : 4) void k_chol_syrk(
     const double *Amat, int64_t lda, const double *Bmat, int64_t ldb,
     double *C, int64_t ldc, int64_t M, int64_t Nc, int kdim, double beta,
     int lower, const int32_t *info) {
+  using Cf = SyrkCfg<TE>;
+  constexpr int SYK = Cf::SYK, SYP = Cf::SYP, NF = Cf::NF, NU = Cf::NU;
+  static_assert(NU >= 1 && NU * (512 / SYK) == TE, "load passes");
   __shared__ double As[2][SYK][SYP];
   __shared__ double Bs[2][SYK][SYP];
   if (info[0]) return;
@@ -331,20 +342,22 @@ __global__ __launch_bounds__(256, 2) void k_chol_syrk(
     while (ti * (ti + 1) / 2 > b) --ti;
     tj = b - ti * (ti + 1) / 2;
   } else {
-    const int64_t tcn = (Nc + SYT - 1) / SYT;
+    const int64_t tcn = (Nc + TE - 1) / TE;
     ti = b / tcn;
     tj = b - ti * tcn;
   }
-  const int64_t r0 = ti * SYT, c0 = tj * SYT;
+  const int64_t r0 = ti * TE, c0 = tj * TE;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wr = (wv >> 1) * 64, wc = (wv & 1) * 64;
-  // loads: thread -> rows (tid >> 2) + 64 u, k pair 2 (tid & 3) of a chunk
-  const int lr = tid >> 2, lk = 2 * (tid & 3);
-  double2 ra[2], rb[2];
+  const int wr = (wv >> 1) * (TE / 2), wc = (wv & 1) * (TE / 2);
+  // loads: thread -> rows tid / (SYK / 2) + (512 / SYK) u, k pair
+  // 2 (tid % (SYK / 2)) of a chunk
+  constexpr int KP = SYK / 2, RP = 256 / KP;
+  const int lr = tid / KP, lk = 2 * (tid % KP);
+  double2 ra[NU], rb[NU];
   auto load = [&](int kc) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int64_t r = r0 + lr + 64 * u, c = c0 + lr + 64 * u;
+    for (int u = 0; u < NU; ++u) {
+      const int64_t r = r0 + lr + RP * u, c = c0 + lr + RP * u;
       ra[u] = r < M ? *reinterpret_cast<const double2 *>(Amat + r * lda + kc + lk)
                     : double2{0.0, 0.0};
       rb[u] = c < Nc ? *reinterpret_cast<const double2 *>(Bmat + c * ldb + kc + lk)
@@ -353,18 +366,18 @@ __global__ __launch_bounds__(256, 2) void k_chol_syrk(
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      As[buf][lk][lr + 64 * u] = ra[u].x;
-      As[buf][lk + 1][lr + 64 * u] = ra[u].y;
-      Bs[buf][lk][lr + 64 * u] = rb[u].x;
-      Bs[buf][lk + 1][lr + 64 * u] = rb[u].y;
+    for (int u = 0; u < NU; ++u) {
+      As[buf][lk][lr + RP * u] = ra[u].x;
+      As[buf][lk + 1][lr + RP * u] = ra[u].y;
+      Bs[buf][lk][lr + RP * u] = rb[u].x;
+      Bs[buf][lk + 1][lr + RP * u] = rb[u].y;
     }
   };
-  d4 acc[4][4];
+  d4 acc[NF][NF];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NF; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0, 0, 0, 0};
+    for (int j = 0; j < NF; ++j) acc[i][j] = d4{0, 0, 0, 0};
   const int nch = kdim / SYK;
   load(0);
   store(0);
@@ -375,15 +388,15 @@ __global__ __launch_bounds__(256, 2) void k_chol_syrk(
     if (ch + 1 < nch) load((ch + 1) * SYK);
 #pragma unroll
     for (int ks = 0; ks < SYK / 4; ++ks) {
-      double av[4], bv[4];
+      double av[NF], bv[NF];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[cur][4 * ks + kb][wr + 16 * i + l16];
+      for (int i = 0; i < NF; ++i) av[i] = As[cur][4 * ks + kb][wr + 16 * i + l16];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[cur][4 * ks + kb][wc + 16 * j + l16];
+      for (int j = 0; j < NF; ++j) bv[j] = Bs[cur][4 * ks + kb][wc + 16 * j + l16];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < NF; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < NF; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j],
                                                            acc[i][j], 0, 0, 0);
     }
@@ -392,9 +405,9 @@ __global__ __launch_bounds__(256, 2) void k_chol_syrk(
   }
   // lane holds rows (lane >> 4) + 4 q of each 16 x 16 tile, column lane & 15
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NF; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < NF; ++j) {
       const int64_t c = c0 + wc + 16 * j + l16;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -405,6 +418,34 @@ __global__ __launch_bounds__(256, 2) void k_chol_syrk(
         }
       }
     }
+}
+
+// Launch the trailing update with the tile edge that finishes first: the
+// rounds of resident workgroups (two 128-wide or four 64-wide per CU)
+// times the MFMA work a round puts on a CU (a 64-wide tile is a quarter
+// of a 128-wide one).
+hipError_t launch_syrk(Ctx *c, const double *Amat, int64_t lda,
+                       const double *Bmat, int64_t ldb, double *C,
+                       int64_t ldc, int64_t M, int64_t Nc, int kdim,
+                       double beta, int lower, const int32_t *info,
+                       hipStream_t s) {
+  const int64_t cus = device_cus(c);
+  auto tiles = [&](int64_t te) {
+    const int64_t tr = (M + te - 1) / te, tc = (Nc + te - 1) / te;
+    return lower ? tr * (tr + 1) / 2 : tr * tc;
+  };
+  const int64_t t128 = tiles(128), t64 = tiles(64);
+  const int64_t w128 = 8 * ((t128 + 2 * cus - 1) / (2 * cus));
+  const int64_t w64 = 4 * ((t64 + 4 * cus - 1) / (4 * cus));
+  if (w64 < w128)
+    hipLaunchKernelGGL(k_chol_syrk<64>, dim3((unsigned)t64), dim3(256), 0, s,
+                       Amat, lda, Bmat, ldb, C, ldc, M, Nc, kdim, beta, lower,
+                       info);
+  else
+    hipLaunchKernelGGL(k_chol_syrk<128>, dim3((unsigned)t128), dim3(256), 0,
+                       s, Amat, lda, Bmat, ldb, C, ldc, M, Nc, kdim, beta,
+                       lower, info);
+  return hipGetLastError();
 }
 
 // Operands of an outer panel's trailing update, columns [J0, J0 + NBO):
@@ -677,21 +718,14 @@ int chol_solve_run(Ctx *c, double *A, int64_t n, const double *g,
     hipLaunchKernelGGL(k_outer_prep, dim3((unsigned)(nbw + nbg)), dim3(256), 0,
                        s, A, n, J0, W, nbw, info);
     const double beta = J0 == 0 ? -1.0 : 1.0;
-    {
-      const int64_t T = (m + SYT - 1) / SYT;
-      hipLaunchKernelGGL(k_chol_syrk, dim3((unsigned)(T * (T + 1) / 2)),
-                         dim3(256), 0, s, A + J1 * n + J0, n, W,
-                         int64_t(NBO), A + J1 * n + J1, n, m, m, NBO, beta, 1,
-                         info);
-    }
+    MNL_HIP(c, launch_syrk(c, A + J1 * n + J0, n, W, int64_t(NBO),
+                           A + J1 * n + J1, n, m, m, NBO, beta, 1, info, s));
     if (extra) {
       // identity rows: X[:, J1:n] -= X[:, J0:J1] (L21 D)^T, the same update
       // as the g row's (these rows are never negated, so beta = 1)
       double *Xr = A + (n + 1) * n;
-      const int64_t T = ((extra + SYT - 1) / SYT) * ((m + SYT - 1) / SYT);
-      hipLaunchKernelGGL(k_chol_syrk, dim3((unsigned)T), dim3(256), 0, s,
-                         Xr + J0, n, W, int64_t(NBO), Xr + J1, n, extra, m,
-                         NBO, 1.0, 0, info);
+      MNL_HIP(c, launch_syrk(c, Xr + J0, n, W, int64_t(NBO), Xr + J1, n,
+                             extra, m, NBO, 1.0, 0, info, s));
     }
   }
   {
