@@ -200,9 +200,15 @@ __global__ __launch_bounds__(64 * MF<PREC>::NW) void k_hess_tiles(HessDev H) {
           [&](int e) { return T(H.Z[int64_t(i0) * za + e]); },
           [&](int e, T v) { Zw[e] = v; });
     }
+    // w streams in like the rest: a plain load here would make the
+    // compiler wait for every copy in flight before storing it
     double *Ww = rawd(b, L.rw);
-    for (int e = tid; e < KC; e += NT)
-      Ww[e] = e < nobs ? (H.w ? H.w[i0 + e] : 1.0) : 0.0;
+    if (H.w) {
+      wg_copy(H.w + i0, Ww, 2 * nobs);
+      for (int e = nobs + tid; e < KC; e += NT) Ww[e] = 0.0;
+    } else {
+      for (int e = tid; e < KC; e += NT) Ww[e] = e < nobs ? 1.0 : 0.0;
+    }
   };
 
   typename M::Acc acc[TNM];
