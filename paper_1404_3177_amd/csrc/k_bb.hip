@@ -175,6 +175,11 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
       dg[j] = (info >> 16) & 1u ? T(1) : T(0);
     }
   }
+  // fragments with no diagonal pair in any row of this wave (wave-uniform)
+  bool offd[kTMA];
+#pragma unroll
+  for (int j = 0; j < kTMA; ++j)
+    offd[j] = __builtin_amdgcn_ballot_w64(dg[j] != T(0)) == 0;
 
   // asynchronous copies of round ob into buffer b: the staged P columns
   // (laid out in HBM as in LDS) and the B tile go in 1 KB pieces of
@@ -223,6 +228,9 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
     const T *Ps = reinterpret_cast<const T *>(buf);
     const XT *Bs = reinterpret_cast<const XT *>(buf + L.b);
     if constexpr (PREC == 2) {
+      // forming omega is the BF16 kernel's VALU load: a fragment none of
+      // whose rows is a diagonal pair (n = m, delta = 1) takes
+      // omega = -(P_n P_m), one product per element instead of two ops
 #pragma unroll
       for (int ks = 0; ks < KR / 32; ++ks) {
         // lane: row lane & 15 of each A fragment, observations o .. o + 7
@@ -239,10 +247,18 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
           const f4 m0 = *reinterpret_cast<const f4 *>(Ps + offm[j] + o);
           const f4 m1 = *reinterpret_cast<const f4 *>(Ps + offm[j] + o + 4);
           bf8 av;
+          if (offd[j]) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            av[e] = (__bf16)(n0[e] * (dg[j] - m0[e]));
-            av[4 + e] = (__bf16)(n1[e] * (dg[j] - m1[e]));
+            for (int e = 0; e < 4; ++e) {
+              av[e] = (__bf16)(-(n0[e] * m0[e]));
+              av[4 + e] = (__bf16)(-(n1[e] * m1[e]));
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              av[e] = (__bf16)(n0[e] * (dg[j] - m0[e]));
+              av[4 + e] = (__bf16)(n1[e] * (dg[j] - m1[e]));
+            }
           }
 #pragma unroll
           for (int t = 0; t < TNB; ++t)
