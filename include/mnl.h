@@ -196,9 +196,14 @@ void mnl_default_opts(mnl_fit_opts *opts);
 int64_t mnl_num_params(int32_t K, int32_t p, int32_t g, int32_t a);
 
 /* Create a context on HIP device `device`.  *ctx receives the handle.
- * Returns MNL_ERR_ARG for ctx == NULL or an invalid device, MNL_ERR_HIP if
- * the device cannot be selected. */
-int mnl_create(mnl_ctx **ctx, int device);
+ * The library owns the context's device workspace and grows it on demand;
+ * workspace_bytes caps it: a call that would grow the workspace past that
+ * many bytes fails with MNL_ERR_OOM (the same as a failed device
+ * allocation) and the workspace keeps what it held.  0: no cap.  The cap
+ * covers the workspace (mnl_workspace_bytes), not the small per-shape plan
+ * tables.  Returns MNL_ERR_ARG for ctx == NULL or an invalid device,
+ * MNL_ERR_HIP if the device cannot be selected. */
+int mnl_create(mnl_ctx **ctx, int device, size_t workspace_bytes);
 
 /* Free the context and its workspace (NULL is ignored).  Waits for the
  * context's outstanding work. */

@@ -119,12 +119,13 @@ class Problem:
 
 
 class Context:
-    """One library context (device workspace) on a HIP device."""
+    """One library context (device workspace) on a HIP device;
+    workspace_bytes caps the workspace (0: no cap)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, workspace_bytes: int = 0):
         self.lib = _lib.load()
         h = ctypes.c_void_p()
-        rc = self.lib.mnl_create(ctypes.byref(h), device)
+        rc = self.lib.mnl_create(ctypes.byref(h), device, int(workspace_bytes))
         if rc != 0:
             raise MnlError(rc, "mnl_create failed")
         self.h = h

@@ -130,7 +130,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mnl_default_opts.restype = None
     lib.mnl_num_params.argtypes = [I32, I32, I32, I32]
     lib.mnl_num_params.restype = I64
-    lib.mnl_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+    lib.mnl_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.c_size_t]
     lib.mnl_destroy.argtypes = [P]
     lib.mnl_destroy.restype = None
     lib.mnl_workspace_bytes.argtypes = [P]

@@ -39,6 +39,11 @@ int ws_get(Ctx *c, int slot, size_t bytes, void **ptr) {
   if (b.bytes < bytes) {
     if (c->capturing)
       return set_error(c, MNL_ERR_HIP, "workspace growth inside a capture");
+    if (c->ws_cap && c->total_bytes - b.bytes + bytes > c->ws_cap)
+      return set_error(c, MNL_ERR_OOM,
+                       "workspace of %zu bytes would exceed the context's "
+                       "cap of %zu bytes",
+                       c->total_bytes - b.bytes + bytes, c->ws_cap);
     // captured steps hold the workspace's addresses: a buffer that moves
     // (a mixed-precision fit's FP64 retry grows the Hessian partials, for
     // one) makes them stale, so they are dropped and captured again
@@ -815,7 +820,7 @@ int64_t mnl_num_params(int32_t K, int32_t p, int32_t g, int32_t a) {
   return int64_t(K - 1) * p + int64_t(K) * a + g;
 }
 
-int mnl_create(mnl_ctx **ctx, int device) {
+int mnl_create(mnl_ctx **ctx, int device, size_t workspace_bytes) {
   if (!ctx) return MNL_ERR_ARG;
   *ctx = nullptr;
   int n = 0;
@@ -831,6 +836,7 @@ int mnl_create(mnl_ctx **ctx, int device) {
   mnl_ctx *h = new mnl_ctx;
   h->c.device = device;
   h->c.bufs.resize(S_NSLOTS);
+  h->c.ws_cap = workspace_bytes;
   *ctx = h;
   return MNL_OK;
 }

@@ -247,6 +247,7 @@ struct Ctx {
   std::string last_error;
   std::vector<Buf> bufs;
   size_t total_bytes = 0;
+  size_t ws_cap = 0;   // most bytes the workspace may hold (0: no cap)
   // HIP events bracketing the Hessian MFMA kernel and the fused pass
   // kernel on the caller's stream (read after the driver's next sync)
   hipEvent_t ev_h0 = nullptr, ev_h1 = nullptr, ev_p0 = nullptr,

@@ -74,7 +74,7 @@ def test_strerror_and_version(lib):
 
 def test_null_context_is_rejected(lib):
     # argument errors are caught before any device call
-    assert lib.mnl_create(None, 0) == -1
+    assert lib.mnl_create(None, 0, 0) == -1
     assert lib.mnl_loglik_grad(None, None, None, None, None, None, None) == -1
     assert lib.mnl_fit(None, None, None, None, None, None, None) == -1
     assert lib.mnl_workspace_bytes(None) == 0

@@ -115,6 +115,27 @@ def test_fit_is_deterministic(ctx):
     assert torch.equal(t1, t2) and i1["iters"] == i2["iters"]
 
 
+def test_workspace_cap(ctx):
+    # a context whose workspace cap is below what the fit needs refuses it
+    # (OOM) without growing past the cap; a cap of exactly the need gives
+    # the same fit bit for bit
+    import torch
+    import paper_1404_3177_amd as mnl
+    pr = synth.make_problem(20000, 12, 6, 2, 1, seed=9, weights="uniform")
+    dp = device_problem(pr)
+    fresh = mnl.Context(0)
+    t_ref, _ = fresh.fit(dp, gtol=GTOL, ftol=0.0)
+    need = fresh.workspace_bytes
+    small = mnl.Context(0, workspace_bytes=need // 2)
+    with pytest.raises(mnl.MnlError) as err:
+        small.fit(dp, gtol=GTOL, ftol=0.0)
+    assert err.value.code == -2
+    assert small.workspace_bytes <= need // 2
+    exact = mnl.Context(0, workspace_bytes=need)
+    t, _ = exact.fit(dp, gtol=GTOL, ftol=0.0)
+    assert torch.equal(t, t_ref) and exact.workspace_bytes <= need
+
+
 def test_fit_from_start_and_resume(ctx):
     pr = synth.make_problem(3000, 5, 3, 1, 1, seed=41)
     dp = device_problem(pr)
