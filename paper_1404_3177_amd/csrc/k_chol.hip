@@ -429,6 +429,8 @@ hipError_t launch_syrk(Ctx *c, const double *Amat, int64_t lda,
                        int64_t ldc, int64_t M, int64_t Nc, int kdim,
                        double beta, int lower, const int32_t *info,
                        hipStream_t s) {
+  // both tile edges take the k extent in whole chunks (8 or 16)
+  if (kdim % 16) return hipErrorInvalidValue;
   const int64_t cus = device_cus(c);
   auto tiles = [&](int64_t te) {
     const int64_t tr = (M + te - 1) / te, tc = (Nc + te - 1) / te;
