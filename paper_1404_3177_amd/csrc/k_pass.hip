@@ -219,6 +219,18 @@ k_pass(PassArgs A, int64_t stride) {
 #pragma unroll
       for (int c = 0; c < CAP; ++c)
         yv[c] = (c < g && own) ? yr[lane * g + c] : 0.0;
+      // alternatives 64..127 (one more chunk): their y values load with
+      // the first chunk's, one round trip for both, instead of being read
+      // from memory in each loop below
+      // (kernels held to three waves per SIMD have no registers for it)
+      constexpr bool kY2 = !HV && CAP >= 8 && !(NTW <= 2 && CAP <= 8);
+      constexpr int C2 = kY2 ? CAP : 1;
+      const bool two = kY2 && K > kWave && K <= 2 * kWave;
+      double yv2[C2];
+#pragma unroll
+      for (int c = 0; c < C2; ++c)
+        yv2[c] = (two && c < g && kWave + lane < K)
+                     ? yr[(kWave + lane) * g + c] : 0.0;
       double m = -INFINITY;
       {
         double u = -INFINITY;
@@ -239,7 +251,13 @@ k_pass(PassArgs A, int64_t stride) {
         if (k < K) {
           double u = ui[k];
           for (int c = 0; c < a; ++c) u = fma(zr[k * a + c], gam[k * a + c], u);
-          for (int c = 0; c < g; ++c) u = fma(yr[k * g + c], alf[c], u);
+          if (two) {
+#pragma unroll
+            for (int c = 0; c < C2; ++c)
+              if (c < g) u = fma(yv2[c], alf[c], u);
+          } else {
+            for (int c = 0; c < g; ++c) u = fma(yr[k * g + c], alf[c], u);
+          }
           ui[k] = u;
           m = fmax(m, u);
         }
@@ -335,9 +353,15 @@ k_pass(PassArgs A, int64_t stride) {
           const int k = k0 + lane;
           if (k < K) {
             const double P = ui[k] * inv;
+            if (two) {
 #pragma unroll
-            for (int c = 0; c < CAP; ++c)
-              if (c < g) part[c] = fma(P, yr[k * g + c], part[c]);
+              for (int c = 0; c < C2; ++c)
+                if (c < g) part[c] = fma(P, yv2[c], part[c]);
+            } else {
+#pragma unroll
+              for (int c = 0; c < CAP; ++c)
+                if (c < g) part[c] = fma(P, yr[k * g + c], part[c]);
+            }
           }
         }
         // all g sums at once: the 64 x CAP partial values go through this
