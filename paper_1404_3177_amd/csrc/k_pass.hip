@@ -84,6 +84,7 @@ __device__ inline double wave_max(double v) {
 struct Lay {  // LDS layout, offsets in doubles
   int Kp, p16, cap;
   int xs, us, ws, gz, gam, alf, red, ch, ysc, lg;
+  int yb, ys;     // y-row buffers (two per wave) and their stride
   int total;
 };
 
@@ -93,7 +94,7 @@ __host__ __device__ inline int pass_cap(const Dims &d) {
   return mx <= 4 ? 4 : (mx <= 8 ? 8 : 16);
 }
 
-__host__ __device__ inline Lay make_lay(const Dims &d) {
+__host__ __device__ inline Lay make_lay(const Dims &d, bool yl = false) {
   Lay L;
   L.Kp = (d.K + 15) & ~15;
   L.p16 = (d.p + 15) & ~15;
@@ -111,6 +112,11 @@ __host__ __device__ inline Lay make_lay(const Dims &d) {
   // every CAP values, so the transposed reads hit distinct banks
   L.ysc = o; o += d.g > 0 ? kWaves * L.cap * (kWave + kWave / L.cap) : 0;
   L.lg = o;  o += 2 * kTB;                    // max and sum per observation
+  // y rows of one observation (K g values), two buffers per wave: the
+  // wave's next observation streams in while the current one is used
+  L.ys = (d.K * d.g + 1) & ~1;
+  o = (o + 1) & ~1;
+  L.yb = o;  o += yl ? kWaves * 2 * L.ys : 0;
   L.total = o;
   return L;
 }
@@ -120,14 +126,17 @@ __host__ __device__ inline Lay make_lay(const Dims &d) {
 // no register is spent on z, gamma or the gamma gradient).  With NTW <= 2
 // and CAP <= 8 the kernel is held to 168 VGPRs for three waves per SIMD:
 // more loads in flight per CU outweigh the few registers spilled.
-template <int NTW, int CAP, bool ZR, bool HV>
+// YL: the y rows reach the wave through LDS, copied asynchronously one
+// observation ahead (K g even, Y 16-byte aligned); otherwise each
+// observation reads them from global memory when it starts.
+template <int NTW, int CAP, bool ZR, bool HV, bool YL>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(NTW <= 2 && CAP <= 8 ? 3 : 1))) void
 k_pass(PassArgs A, int64_t stride) {
   constexpr int CZ = ZR ? CAP : 1;
   extern __shared__ double sm[];
   const Dims d = A.d;
-  const Lay L = make_lay(d);
+  const Lay L = make_lay(d, YL);
   const int K = d.K, p = d.p, g = d.g, a = d.a, Kp = L.Kp, p16 = L.p16;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   double *xs = sm + L.xs, *us = sm + L.us, *ws = sm + L.ws, *gz = sm + L.gz,
@@ -161,6 +170,24 @@ k_pass(PassArgs A, int64_t stride) {
   }
 
   const int64_t ntiles = (d.N + kTB - 1) / kTB;
+  // y rows through LDS: 16-byte copies of observation gn into buffer b of
+  // this wave (no registers held while they are in flight)
+  double *ybuf = sm + L.yb + wv * 2 * L.ys;
+  const int nyb = K * g * 8;
+  auto ycopy = [&](int64_t gn, int b) {
+    const uint32_t *src =
+        reinterpret_cast<const uint32_t *>(A.Y + gn * int64_t(K) * g);
+    char *dst = reinterpret_cast<char *>(ybuf + b * L.ys);
+    for (int o = 0; o < nyb; o += 1024)
+      if (o + 16 * lane < nyb)
+        __builtin_amdgcn_global_load_lds(src + o / 4 + 4 * lane,
+                                         (lds_void_t *)(dst + o), 16, 0, 0);
+  };
+  int ypar = 0;
+  if constexpr (YL) {
+    const int64_t g0 = int64_t(blockIdx.x) * kTB + wv;
+    if (g0 < d.N) ycopy(g0, 0);
+  }
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t i0 = t * kTB;
     const int nobs = (int)((d.N - i0) < kTB ? (d.N - i0) : kTB);
@@ -208,7 +235,26 @@ k_pass(PassArgs A, int64_t stride) {
       const double wi = ws[i];
       const int ci = chs[i];
       const int64_t gi = i0 + i;
-      const double *yr = A.Y + gi * K * g;
+      const double *yr;
+      if constexpr (YL) {
+        // this observation's rows have landed (the wave's only memory
+        // operations since their copy are its own stores); the copy of the
+        // wave's next observation, in this tile or its first of the next,
+        // goes to the other buffer
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        int64_t gn = -1;
+        if (i + kWaves < nobs) {
+          gn = gi + kWaves;
+        } else if (t + gridDim.x < ntiles) {
+          const int64_t fn = (t + gridDim.x) * kTB + wv;
+          if (fn < d.N) gn = fn;
+        }
+        if (gn >= 0) ycopy(gn, ypar ^ 1);
+        yr = ybuf + ypar * L.ys;
+        ypar ^= 1;
+      } else {
+        yr = A.Y + gi * K * g;
+      }
       const double *zr = A.Z + gi * Ka;
       double *ui = us + i * Kp;
       double zv[CZ], yv[CAP];
@@ -534,22 +580,52 @@ int pass_plan(const Dims &d, PassPlan *plan) {
   const int gmax =
       (ntw <= 2 && L.cap <= 8 && 3 * plan->lds_bytes <= 160 * 1024) ? 768
                                                                      : 512;
+  // two workgroups per CU with eight value slots: the y rows go through
+  // LDS when both workgroups' buffers fit
+  plan->yl = 0;
+  if (gmax == 512 && L.cap == 8 && d.g > 0 && (d.K * d.g) % 2 == 0) {
+    const Lay Ly = make_lay(d, true);
+    if (2 * size_t(Ly.total) * 8 <= 160 * 1024) {
+      plan->yl = 1;
+      plan->lds_bytes = size_t(Ly.total) * 8;
+    }
+  }
   plan->grid = (int)(ntiles < gmax ? ntiles : gmax);
   plan->stride = 1 + d.np;
   return MNL_OK;
 }
 
+namespace {
+template <int J, int C, bool Z, bool H, bool Y>
+hipError_t launch_pass_k(const PassPlan &plan, const PassArgs &a,
+                         hipStream_t s) {
+  const size_t lds = plan.lds_bytes;
+  hipError_t e = raise_lds_limit(
+      reinterpret_cast<const void *>(&k_pass<J, C, Z, H, Y>), (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_pass<J, C, Z, H, Y>), dim3(plan.grid),
+                     dim3(kThreads), lds, s, a, plan.stride);
+  return hipSuccess;
+}
+// the y rows go through LDS where the plan allows it and Y is 16-byte
+// aligned (the Hessian-vector mode reads them from global memory)
+template <int J, int C, bool Z, bool H>
+hipError_t launch_pass_y(const PassPlan &plan, const PassArgs &a,
+                         hipStream_t s) {
+  if constexpr (C == 8 && !H) {
+    if (plan.yl && (reinterpret_cast<uintptr_t>(a.Y) & 15) == 0)
+      return launch_pass_k<J, C, Z, H, true>(plan, a, s);
+  }
+  return launch_pass_k<J, C, Z, H, false>(plan, a, s);
+}
+}  // namespace
+
 hipError_t launch_pass(const PassPlan &plan, const PassArgs &a,
                        hipStream_t s) {
-  dim3 grid(plan.grid), block(kThreads);
-  const size_t lds = plan.lds_bytes;
 #define MNL_PASS_LAUNCH3(J, C, Z, H)                                          \
   do {                                                                        \
-    hipError_t e_ = raise_lds_limit(                                          \
-        reinterpret_cast<const void *>(&k_pass<J, C, Z, H>), (int)lds);       \
+    hipError_t e_ = launch_pass_y<J, C, Z, H>(plan, a, s);                    \
     if (e_ != hipSuccess) return e_;                                          \
-    hipLaunchKernelGGL((k_pass<J, C, Z, H>), grid, block, lds, s, a,          \
-                       plan.stride);                                          \
   } while (0)
 #define MNL_PASS_LAUNCH2(J, C, Z)                                             \
   do {                                                                        \

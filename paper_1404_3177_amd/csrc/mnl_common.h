@@ -92,6 +92,7 @@ struct PassPlan {
   int grid;          // workgroups (fixed by the shape: deterministic sums)
   int ntw;           // beta-gradient MFMA tiles per wave (power of two)
   int cap;           // register slots for one alternative's z / y values
+  int yl;            // 1: y rows staged through LDS one observation ahead
   size_t lds_bytes;
   int64_t stride;    // doubles per workgroup partial row
 };

@@ -76,3 +76,25 @@ def test_pass_config_sizes(ctx, name):
     pr = synth.make_config(name)
     th = pr.theta_true * 0.5
     _check(ctx, pr, th)
+
+
+# Shapes whose kernels stage each observation's y rows through LDS one
+# observation ahead (two workgroups per CU, eight value slots, K g even):
+# several tiles per workgroup with a ragged last tile, K past one and past
+# two waves, with and without Z; and one with K g odd, which reads y from
+# global memory instead.
+LDS_ROW_SHAPES = [
+    (9001, 60, 40, 5, 0, "uniform"),
+    (20011, 100, 51, 6, 0, None),
+    (5000, 40, 60, 5, 3, "uniform"),
+    (3000, 130, 20, 1, 5, None),
+    (9003, 61, 40, 5, 2, None),
+]
+
+
+@pytest.mark.parametrize("shape", LDS_ROW_SHAPES)
+def test_pass_staged_rows(ctx, shape):
+    N, K, p, g, a, wk = shape
+    pr = synth.make_problem(N, K, p, g, a, seed=200 + K, weights=wk)
+    th = np.random.default_rng(K).normal(0, 0.3, pr.n_params)
+    _check(ctx, pr, th)
