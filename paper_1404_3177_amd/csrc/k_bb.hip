@@ -50,7 +50,11 @@ constexpr int kMaxStage = 128;   // staged alternatives per row tile
 // goes to LDS in 1 KB pieces (at most 34 full pieces for 128 columns, plus
 // one partial piece per run)
 constexpr int kMaxPieces = 192;
-constexpr int kTMA = 4;          // 16-row A fragments per wave
+// A fragments (16 pair rows each) per wave: 4, or 3 where 384-row tiles
+// pad the pair rows and columns less (FP64, 8-wave tiles; up to 6 B
+// fragments then)
+constexpr int kTMA = 4;
+constexpr int kTNMax3 = 6;
 constexpr int kBlkAlt = 32;      // alternatives per pair block (large K)
 
 // Per precision: T = P / w / omega type, XT = chi type, KR observations per
@@ -123,9 +127,10 @@ struct BBDev {
   int K, pcols, ncgx;
 };
 
-template <int PREC, int TNB, int NWV>
+template <int PREC, int TNB, int NWV, int TMA>
 __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
   constexpr int kWaves = NWV;
+  constexpr int RW = 16 * TMA;               // pair rows per wave
   using C = BBT<PREC>;
   using T = typename C::T;
   using XT = typename C::XT;
@@ -163,12 +168,12 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
     reinterpret_cast<T *>(sm + b * L.bufsz)[D.pcols * RS + o] = T(0);
   }
   // this lane's A rows (one per fragment): LDS offsets of P_n and P_m
-  int offn[kTMA], offm[kTMA];
-  T dg[kTMA];
+  int offn[TMA], offm[TMA];
+  T dg[TMA];
   {
-    const int64_t r0 = int64_t(tl.rt) * (64 * kWaves) + 64 * wv + (lane & 15);
+    const int64_t r0 = int64_t(tl.rt) * (RW * kWaves) + RW * wv + (lane & 15);
 #pragma unroll
-    for (int j = 0; j < kTMA; ++j) {
+    for (int j = 0; j < TMA; ++j) {
       const uint32_t info = D.rowinfo[r0 + 16 * j];
       offn[j] = int(info & 0xffu) * RS;
       offm[j] = int((info >> 8) & 0xffu) * RS;
@@ -176,9 +181,9 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
     }
   }
   // fragments with no diagonal pair in any row of this wave (wave-uniform)
-  bool offd[kTMA];
+  bool offd[TMA];
 #pragma unroll
-  for (int j = 0; j < kTMA; ++j)
+  for (int j = 0; j < TMA; ++j)
     offd[j] = __builtin_amdgcn_ballot_w64(dg[j] != T(0)) == 0;
 
   // asynchronous copies of round ob into buffer b: the staged P columns
@@ -208,9 +213,9 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
                                        16, 0, 0);
   };
 
-  Acc acc[kTMA][TNB];
+  Acc acc[TMA][TNB];
 #pragma unroll
-  for (int j = 0; j < kTMA; ++j)
+  for (int j = 0; j < TMA; ++j)
 #pragma unroll
     for (int t = 0; t < TNB; ++t) acc[j][t] = Acc{0, 0, 0, 0};
 
@@ -241,7 +246,7 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
           bv[t] = *reinterpret_cast<const bf8 *>(Bs + t * XF + ks * 512 +
                                                  lane * 8);
 #pragma unroll
-        for (int j = 0; j < kTMA; ++j) {
+        for (int j = 0; j < TMA; ++j) {
           const f4 n0 = *reinterpret_cast<const f4 *>(Ps + offn[j] + o);
           const f4 n1 = *reinterpret_cast<const f4 *>(Ps + offn[j] + o + 4);
           const f4 m0 = *reinterpret_cast<const f4 *>(Ps + offm[j] + o);
@@ -272,7 +277,7 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
       // the first three MFMAs of step ks, and its A fragments are formed
       // between the last four, at least five MFMAs after those reads; a
       // wave then waits on LDS only at the start of a round
-      constexpr int NQ = kTMA * TNB, NKS = KR / 4, NHALF = NKS / 2;
+      constexpr int NQ = TMA * TNB, NKS = KR / 4, NHALF = NKS / 2;
       // the next round's copies go out over the first half of the round,
       // between MFMAs: step ks < NHALF issues this wave's P pieces
       // CPK ks .. CPK ks + CPK - 1 and B pieces BPK ks .. BPK ks + BPK - 1
@@ -286,19 +291,19 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
       const uint32_t *nsrc = pt32 + int64_t(ob + 1) * D.K * PDW;
       const char *nxs = xx8 + (int64_t(ob + 1) * D.ncgx + int64_t(tl.ct) * TNB) *
                                   XF * sizeof(XT);
-      T bv[TNB], av[kTMA];
+      T bv[TNB], av[TMA];
       {
 #pragma unroll
         for (int t = 0; t < TNB; ++t) bv[t] = Bs[t * XF + lane];
 #pragma unroll
-        for (int j = 0; j < kTMA; ++j)
+        for (int j = 0; j < TMA; ++j)
           av[j] = Ps[offn[j] + kb] * (dg[j] - Ps[offm[j] + kb]);
       }
 #pragma unroll
       for (int ks = 0; ks < KR / 4; ++ks) {
         const bool more = ks + 1 < KR / 4;
         const int o = 4 * (ks + 1) + kb;
-        T bn[TNB], pn[kTMA], pm[kTMA], an[kTMA];
+        T bn[TNB], pn[TMA], pm[TMA], an[TMA];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           const int j = q / TNB, t = q % TNB;
@@ -336,12 +341,12 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
                 bn[u] = Bs[u * XF + (ks + 1) * 64 + lane];
             } else if (q == 1) {
 #pragma unroll
-              for (int i = 0; i < kTMA; ++i) pn[i] = Ps[offn[i] + o];
+              for (int i = 0; i < TMA; ++i) pn[i] = Ps[offn[i] + o];
             } else if (q == 2) {
 #pragma unroll
-              for (int i = 0; i < kTMA; ++i) pm[i] = Ps[offm[i] + o];
-            } else if (q >= NQ - kTMA) {
-              const int i = q - (NQ - kTMA);
+              for (int i = 0; i < TMA; ++i) pm[i] = Ps[offm[i] + o];
+            } else if (q >= NQ - TMA) {
+              const int i = q - (NQ - TMA);
               an[i] = pn[i] * (dg[i] - pm[i]);
             }
           }
@@ -349,7 +354,7 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
         __builtin_amdgcn_sched_barrier(0);
         if (more) {
 #pragma unroll
-          for (int j = 0; j < kTMA; ++j) av[j] = an[j];
+          for (int j = 0; j < TMA; ++j) av[j] = an[j];
 #pragma unroll
           for (int t = 0; t < TNB; ++t) bv[t] = bn[t];
         }
@@ -358,13 +363,13 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
       // operands one k-step ahead: the LDS reads of step ks + 1 are in
       // flight while step ks's MFMAs run (lane: row lane & 15 of each A
       // fragment, observation 4 ks + lane / 16)
-      T bv[TNB], pn[kTMA], pm[kTMA];
+      T bv[TNB], pn[TMA], pm[TMA];
       auto load = [&](int ks, T *b, T *n, T *m) {
         const int o = 4 * ks + kb;
 #pragma unroll
         for (int t = 0; t < TNB; ++t) b[t] = Bs[t * XF + ks * 64 + lane];
 #pragma unroll
-        for (int j = 0; j < kTMA; ++j) {
+        for (int j = 0; j < TMA; ++j) {
           n[j] = Ps[offn[j] + o];
           m[j] = Ps[offm[j] + o];
         }
@@ -372,10 +377,10 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
       load(0, bv, pn, pm);
 #pragma unroll
       for (int ks = 0; ks < KR / 4; ++ks) {
-        T bv2[TNB], pn2[kTMA], pm2[kTMA];
+        T bv2[TNB], pn2[TMA], pm2[TMA];
         if (ks + 1 < KR / 4) load(ks + 1, bv2, pn2, pm2);
 #pragma unroll
-        for (int j = 0; j < kTMA; ++j) {
+        for (int j = 0; j < TMA; ++j) {
           const T av = pn[j] * (dg[j] - pm[j]);
 #pragma unroll
           for (int t = 0; t < TNB; ++t) {
@@ -391,7 +396,7 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
 #pragma unroll
           for (int t = 0; t < TNB; ++t) bv[t] = bv2[t];
 #pragma unroll
-          for (int j = 0; j < kTMA; ++j) {
+          for (int j = 0; j < TMA; ++j) {
             pn[j] = pn2[j];
             pm[j] = pm2[j];
           }
@@ -405,11 +410,11 @@ __global__ __launch_bounds__(64 * NWV, 2) void k_bb(BBDev D) {
 
   using AT = typename std::conditional<PREC == 0, double, float>::type;
   AT *base = static_cast<AT *>(D.part) +
-             (int64_t(tl.split) * D.Mp + int64_t(tl.rt) * (64 * kWaves) +
-              64 * wv) * D.Np +
+             (int64_t(tl.split) * D.Mp + int64_t(tl.rt) * (RW * kWaves) +
+              RW * wv) * D.Np +
              int64_t(tl.ct) * TNB * 16;
 #pragma unroll
-  for (int j = 0; j < kTMA; ++j)
+  for (int j = 0; j < TMA; ++j)
 #pragma unroll
     for (int t = 0; t < TNB; ++t)
 #pragma unroll
@@ -523,7 +528,8 @@ __global__ void k_bb_assemble(const AT *part, int S, int64_t Mp, int64_t Np,
 
 struct BBPlan {
   Dims d;
-  int prec = 0, tnb = 1, nw = 8, S = 1, ntiles = 0, pcols = 0, ncgx = 0;
+  int prec = 0, tnb = 1, nw = 8, tma = kTMA, S = 1, ntiles = 0, pcols = 0,
+      ncgx = 0;
   int64_t npairs = 0, Mp = 0, Np = 0, ncombo = 0, nob = 0, nrt = 0;
   size_t lds = 0;
   std::vector<BBTile> h_tiles;
@@ -559,7 +565,6 @@ int bb_plan_host(Ctx *c, const Dims &d, int prec, BBPlan *pl) {
     const int64_t r8 = (np + 511) / 512 * 512, r4 = (np + 255) / 256 * 256;
     pl->nw = (Lk <= kMaxStage && r4 < 0.9 * double(r8)) ? 4 : 8;
   }
-  const int R = 64 * pl->nw;
   // pair rows: n <= m over alternatives 1..K-1, row-major within blocks of
   // kBlkAlt alternatives when there are more than a tile can stage; a row
   // tile closes early (padding rows) when its next pair would need more
@@ -578,9 +583,10 @@ int bb_plan_host(Ctx *c, const Dims &d, int prec, BBPlan *pl) {
             pairs.push_back({n, m});
   }
   pl->npairs = int64_t(pairs.size());
-  std::vector<int32_t> row_nm;          // n | m << 16 per row, 0 = padding
-  std::vector<std::vector<int>> tcols;  // staged alternatives per row tile
-  {
+  // rows of R pairs per tile: row_nm gets n | m << 16 per row (0 =
+  // padding), tcols the staged alternatives of each tile
+  auto tile_rows = [&](int R, std::vector<int32_t> &row_nm,
+                       std::vector<std::vector<int>> &tcols) {
     std::vector<char> in(size_t(d.K), 0);
     std::vector<int> cur;
     auto close_tile = [&]() {
@@ -608,6 +614,50 @@ int bb_plan_host(Ctx *c, const Dims &d, int prec, BBPlan *pl) {
       }
     }
     if (row_nm.size() % R) close_tile();
+  };
+  // feature pairs a <= b; column groups of 16, TNB groups per tile: the
+  // least padded columns, weighted by the per-tile cost of forming and
+  // staging the A operand (a tile of TNB groups re-forms it once per TNB)
+  std::vector<uint32_t> combo;
+  for (int fa = 0; fa < p; ++fa)
+    for (int fb = fa; fb < p; ++fb)
+      combo.push_back(uint32_t(fa) | (uint32_t(fb) << 16));
+  pl->ncombo = int64_t(combo.size());
+  const int64_t ncg = (pl->ncombo + 15) / 16;
+  auto pick_tnb = [&](int lo, int hi) {
+    int tnb = lo;
+    double best = 1e300;
+    for (int t = lo; t <= hi; ++t) {
+      const double cost = double((ncg + t - 1) / t * t) * (1.0 + 0.5 / t);
+      if (cost <= best) {
+        best = cost;
+        tnb = t;
+      }
+    }
+    return tnb;
+  };
+  std::vector<int32_t> row_nm;
+  std::vector<std::vector<int>> tcols;
+  int R = 16 * kTMA * pl->nw;
+  tile_rows(R, row_nm, tcols);
+  int tnb = pick_tnb(1, bc.tnmax);
+  // FP64 8-wave tiles: three A fragments per wave (384 rows, up to six B
+  // fragments) when that pads the pair rows times columns at least 2% less
+  if (prec == 0 && pl->nw == 8) {
+    std::vector<int32_t> row3;
+    std::vector<std::vector<int>> tc3;
+    const int R3 = 16 * 3 * pl->nw;
+    tile_rows(R3, row3, tc3);
+    const int tnb3 = pick_tnb(3, kTNMax3);
+    const double w4 = double(row_nm.size()) * double((ncg + tnb - 1) / tnb * tnb);
+    const double w3 = double(row3.size()) * double((ncg + tnb3 - 1) / tnb3 * tnb3);
+    if (w3 <= 0.98 * w4) {
+      pl->tma = 3;
+      R = R3;
+      tnb = tnb3;
+      row_nm.swap(row3);
+      tcols.swap(tc3);
+    }
   }
   pl->nrt = int64_t(tcols.size());
   pl->Mp = pl->nrt * R;
@@ -647,24 +697,6 @@ int bb_plan_host(Ctx *c, const Dims &d, int prec, BBPlan *pl) {
       const uint32_t ln = uint32_t(std::lower_bound(tc.begin(), tc.end(), n) - tc.begin());
       const uint32_t lm = uint32_t(std::lower_bound(tc.begin(), tc.end(), m) - tc.begin());
       rowinfo[r] = ln | (lm << 8) | (uint32_t(n == m) << 16);
-    }
-  }
-  // feature pairs a <= b; column groups of 16, TNB groups per tile: the
-  // least padded columns, weighted by the per-tile cost of forming and
-  // staging the A operand (a tile of TNB groups re-forms it once per TNB)
-  std::vector<uint32_t> combo;
-  for (int fa = 0; fa < p; ++fa)
-    for (int fb = fa; fb < p; ++fb)
-      combo.push_back(uint32_t(fa) | (uint32_t(fb) << 16));
-  pl->ncombo = int64_t(combo.size());
-  const int64_t ncg = (pl->ncombo + 15) / 16;
-  int tnb = 1;
-  double best = 1e300;
-  for (int t = 1; t <= bc.tnmax; ++t) {
-    const double cost = double((ncg + t - 1) / t * t) * (1.0 + 0.5 / t);
-    if (cost <= best) {
-      best = cost;
-      tnb = t;
     }
   }
   pl->tnb = tnb;
@@ -832,23 +864,33 @@ BBWs bb_ws_bytes(const BBPlan &pl) {
   return w;
 }
 
-template <int PREC, int TNB, int NWV>
+template <int PREC, int TNB, int NWV, int TMA>
 hipError_t launch_bb_nw(const BBPlan &pl, const BBDev &D, hipStream_t s) {
   hipError_t e = raise_lds_limit(
-      reinterpret_cast<const void *>(&k_bb<PREC, TNB, NWV>), int(pl.lds));
+      reinterpret_cast<const void *>(&k_bb<PREC, TNB, NWV, TMA>), int(pl.lds));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_bb<PREC, TNB, NWV>), dim3(pl.ntiles), dim3(64 * NWV),
-                     pl.lds, s, D);
+  hipLaunchKernelGGL((k_bb<PREC, TNB, NWV, TMA>), dim3(pl.ntiles),
+                     dim3(64 * NWV), pl.lds, s, D);
   return hipGetLastError();
 }
 
 template <int PREC, int TNB>
 hipError_t launch_bb_tnb(const BBPlan &pl, const BBDev &D, hipStream_t s) {
-  return pl.nw == 4 ? launch_bb_nw<PREC, TNB, 4>(pl, D, s)
-                    : launch_bb_nw<PREC, TNB, 8>(pl, D, s);
+  if constexpr (PREC == 0 && TNB >= 3 && TNB <= kTNMax3) {
+    if (pl.tma == 3)
+      return pl.nw == 8 ? launch_bb_nw<PREC, TNB, 8, 3>(pl, D, s)
+                        : hipErrorInvalidValue;
+  }
+  if constexpr (TNB <= BBT<PREC>::TNMAX) {
+    if (pl.tma == kTMA)
+      return pl.nw == 4 ? launch_bb_nw<PREC, TNB, 4, kTMA>(pl, D, s)
+                        : launch_bb_nw<PREC, TNB, 8, kTMA>(pl, D, s);
+  }
+  return hipErrorInvalidValue;
 }
 
-template <int PREC, int TNB = BBT<PREC>::TNMAX>
+template <int PREC,
+          int TNB = (PREC == 0 ? kTNMax3 : BBT<PREC>::TNMAX)>
 hipError_t launch_bb(const BBPlan &pl, const BBDev &D, hipStream_t s) {
   if (pl.tnb == TNB) return launch_bb_tnb<PREC, TNB>(pl, D, s);
   if constexpr (TNB > 1) return launch_bb<PREC, TNB - 1>(pl, D, s);

@@ -39,6 +39,9 @@ SHAPES = [  # N, K, p, g, a, weights
     (700, 129, 8, 1, 1, "uniform"),
     (1100, 12, 9, 0, 0, None),
     (900, 40, 8, 1, 0, None),
+    # FP64 tiles of three A fragments per wave (384 pair rows) and six B
+    # fragments: nine row tiles, the last one part padding; ragged rounds
+    (3001, 80, 13, 1, 0, None),
 ]
 
 
