@@ -51,10 +51,10 @@ constexpr int kMaxStage = 128;   // staged alternatives per row tile
 // one partial piece per run)
 constexpr int kMaxPieces = 192;
 // A fragments (16 pair rows each) per wave: 4, or 3 where 384-row tiles
-// pad the pair rows and columns less (FP64, 8-wave tiles; up to 6 B
-// fragments then)
+// pad the pair rows and columns less (FP64 and FP32 8-wave tiles; up to 6
+// B fragments then in FP64, 8 in FP32)
 constexpr int kTMA = 4;
-constexpr int kTNMax3 = 6;
+constexpr int tnmax3(int prec) { return prec == 0 ? 6 : 8; }
 constexpr int kBlkAlt = 32;      // alternatives per pair block (large K)
 
 // Per precision: T = P / w / omega type, XT = chi type, KR observations per
@@ -641,14 +641,14 @@ int bb_plan_host(Ctx *c, const Dims &d, int prec, BBPlan *pl) {
   int R = 16 * kTMA * pl->nw;
   tile_rows(R, row_nm, tcols);
   int tnb = pick_tnb(1, bc.tnmax);
-  // FP64 8-wave tiles: three A fragments per wave (384 rows, up to six B
-  // fragments) when that pads the pair rows times columns at least 2% less
-  if (prec == 0 && pl->nw == 8) {
+  // FP64 / FP32 8-wave tiles: three A fragments per wave (384 rows) when
+  // that pads the pair rows times columns at least 2% less
+  if (prec != 2 && pl->nw == 8) {
     std::vector<int32_t> row3;
     std::vector<std::vector<int>> tc3;
     const int R3 = 16 * 3 * pl->nw;
     tile_rows(R3, row3, tc3);
-    const int tnb3 = pick_tnb(3, kTNMax3);
+    const int tnb3 = pick_tnb(3, tnmax3(prec));
     const double w4 = double(row_nm.size()) * double((ncg + tnb - 1) / tnb * tnb);
     const double w3 = double(row3.size()) * double((ncg + tnb3 - 1) / tnb3 * tnb3);
     if (w3 <= 0.98 * w4) {
@@ -876,7 +876,7 @@ hipError_t launch_bb_nw(const BBPlan &pl, const BBDev &D, hipStream_t s) {
 
 template <int PREC, int TNB>
 hipError_t launch_bb_tnb(const BBPlan &pl, const BBDev &D, hipStream_t s) {
-  if constexpr (PREC == 0 && TNB >= 3 && TNB <= kTNMax3) {
+  if constexpr (PREC != 2 && TNB >= 3 && TNB <= tnmax3(PREC)) {
     if (pl.tma == 3)
       return pl.nw == 8 ? launch_bb_nw<PREC, TNB, 8, 3>(pl, D, s)
                         : hipErrorInvalidValue;
@@ -890,7 +890,7 @@ hipError_t launch_bb_tnb(const BBPlan &pl, const BBDev &D, hipStream_t s) {
 }
 
 template <int PREC,
-          int TNB = (PREC == 0 ? kTNMax3 : BBT<PREC>::TNMAX)>
+          int TNB = (PREC == 0 ? tnmax3(0) : BBT<PREC>::TNMAX)>
 hipError_t launch_bb(const BBPlan &pl, const BBDev &D, hipStream_t s) {
   if (pl.tnb == TNB) return launch_bb_tnb<PREC, TNB>(pl, D, s);
   if constexpr (TNB > 1) return launch_bb<PREC, TNB - 1>(pl, D, s);
