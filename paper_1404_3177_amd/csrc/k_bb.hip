@@ -51,10 +51,10 @@ constexpr int kMaxStage = 128;   // staged alternatives per row tile
 // one partial piece per run)
 constexpr int kMaxPieces = 192;
 // A fragments (16 pair rows each) per wave: 4, or 3 where 384-row tiles
-// pad the pair rows and columns less (FP64 and FP32 8-wave tiles; up to 6
+// pad the pair rows and columns less (FP64 and FP32 8-wave tiles; up to 7
 // B fragments then in FP64, 8 in FP32)
 constexpr int kTMA = 4;
-constexpr int tnmax3(int prec) { return prec == 0 ? 6 : 8; }
+constexpr int tnmax3(int prec) { return prec == 0 ? 7 : 8; }
 constexpr int kBlkAlt = 32;      // alternatives per pair block (large K)
 
 // Per precision: T = P / w / omega type, XT = chi type, KR observations per
