@@ -51,10 +51,11 @@ constexpr int kMaxStage = 128;   // staged alternatives per row tile
 // one partial piece per run)
 constexpr int kMaxPieces = 192;
 // A fragments (16 pair rows each) per wave: 4, or 3 where 384-row tiles
-// pad the pair rows and columns less (FP64 and FP32 8-wave tiles; up to 7
-// B fragments then in FP64, 8 in FP32)
+// pad the pair rows and columns less (8-wave tiles; up to 7 B fragments
+// then in FP64, 8 in FP32 and 12 in BF16, whose formed omega fragments
+// then feed more MFMAs each)
 constexpr int kTMA = 4;
-constexpr int tnmax3(int prec) { return prec == 0 ? 7 : 8; }
+constexpr int tnmax3(int prec) { return prec == 0 ? 7 : (prec == 1 ? 8 : 12); }
 constexpr int kBlkAlt = 32;      // alternatives per pair block (large K)
 
 // Per precision: T = P / w / omega type, XT = chi type, KR observations per
@@ -641,9 +642,9 @@ int bb_plan_host(Ctx *c, const Dims &d, int prec, BBPlan *pl) {
   int R = 16 * kTMA * pl->nw;
   tile_rows(R, row_nm, tcols);
   int tnb = pick_tnb(1, bc.tnmax);
-  // FP64 / FP32 8-wave tiles: three A fragments per wave (384 rows) when
-  // that pads the pair rows times columns at least 2% less
-  if (prec != 2 && pl->nw == 8) {
+  // 8-wave tiles: three A fragments per wave (384 rows) when that pads the
+  // pair rows times columns at least 2% less
+  if (pl->nw == 8) {
     std::vector<int32_t> row3;
     std::vector<std::vector<int>> tc3;
     const int R3 = 16 * 3 * pl->nw;
@@ -876,7 +877,7 @@ hipError_t launch_bb_nw(const BBPlan &pl, const BBDev &D, hipStream_t s) {
 
 template <int PREC, int TNB>
 hipError_t launch_bb_tnb(const BBPlan &pl, const BBDev &D, hipStream_t s) {
-  if constexpr (PREC != 2 && TNB >= 3 && TNB <= tnmax3(PREC)) {
+  if constexpr (TNB >= 3 && TNB <= tnmax3(PREC)) {
     if (pl.tma == 3)
       return pl.nw == 8 ? launch_bb_nw<PREC, TNB, 8, 3>(pl, D, s)
                         : hipErrorInvalidValue;
@@ -889,8 +890,8 @@ hipError_t launch_bb_tnb(const BBPlan &pl, const BBDev &D, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-template <int PREC,
-          int TNB = (PREC == 0 ? tnmax3(0) : BBT<PREC>::TNMAX)>
+template <int PREC, int TNB = (tnmax3(PREC) > BBT<PREC>::TNMAX
+                                  ? tnmax3(PREC) : BBT<PREC>::TNMAX)>
 hipError_t launch_bb(const BBPlan &pl, const BBDev &D, hipStream_t s) {
   if (pl.tnb == TNB) return launch_bb_tnb<PREC, TNB>(pl, D, s);
   if constexpr (TNB > 1) return launch_bb<PREC, TNB - 1>(pl, D, s);
