@@ -52,10 +52,10 @@ constexpr int kMaxStage = 128;   // staged alternatives per row tile
 constexpr int kMaxPieces = 192;
 // A fragments (16 pair rows each) per wave: 4, or 3 where 384-row tiles
 // pad the pair rows and columns less (8-wave tiles; up to 7 B fragments
-// then in FP64, 8 in FP32 and 12 in BF16, whose formed omega fragments
-// then feed more MFMAs each)
+// then in FP64 and 12 in FP32 and BF16, LDS allowing, so that a formed
+// omega fragment feeds more MFMAs)
 constexpr int kTMA = 4;
-constexpr int tnmax3(int prec) { return prec == 0 ? 7 : (prec == 1 ? 8 : 12); }
+constexpr int tnmax3(int prec) { return prec == 0 ? 7 : 12; }
 constexpr int kBlkAlt = 32;      // alternatives per pair block (large K)
 
 // Per precision: T = P / w / omega type, XT = chi type, KR observations per
@@ -649,10 +649,20 @@ int bb_plan_host(Ctx *c, const Dims &d, int prec, BBPlan *pl) {
     std::vector<std::vector<int>> tc3;
     const int R3 = 16 * 3 * pl->nw;
     tile_rows(R3, row3, tc3);
-    const int tnb3 = pick_tnb(3, tnmax3(prec));
+    int pc3 = 1;
+    for (auto &tc : tc3) pc3 = std::max(pc3, int(tc.size()));
+    // the most B fragments whose two round buffers fit in LDS
+    int hi3 = tnmax3(prec);
+    while (hi3 > 3 &&
+           2 * size_t(bb_lds(bc.kr, bc.rs, bc.esz, bc.xsz, pc3, hi3).bufsz) >
+               160 * 1024)
+      --hi3;
+    const int tnb3 = pick_tnb(3, hi3);
     const double w4 = double(row_nm.size()) * double((ncg + tnb - 1) / tnb * tnb);
     const double w3 = double(row3.size()) * double((ncg + tnb3 - 1) / tnb3 * tnb3);
-    if (w3 <= 0.98 * w4) {
+    if (2 * size_t(bb_lds(bc.kr, bc.rs, bc.esz, bc.xsz, pc3, tnb3).bufsz) <=
+            160 * 1024 &&
+        w3 <= 0.98 * w4) {
       pl->tma = 3;
       R = R3;
       tnb = tnb3;
