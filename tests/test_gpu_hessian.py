@@ -42,6 +42,10 @@ SHAPES = [  # N, K, p, g, a, weights
     # FP64 tiles of three A fragments per wave (384 pair rows) and six B
     # fragments: nine row tiles, the last one part padding; ragged rounds
     (3001, 80, 13, 1, 0, None),
+    # three A fragments with 128 staged alternatives per row tile: twelve
+    # FP32 B fragments would not fit LDS beside them (six are taken), BF16
+    # takes twelve
+    (300, 129, 19, 1, 1, "uniform"),
 ]
 
 
