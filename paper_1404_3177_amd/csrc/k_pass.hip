@@ -237,10 +237,11 @@ k_pass(PassArgs A, int64_t stride) {
       const int64_t gi = i0 + i;
       const double *yr;
       if constexpr (YL) {
-        // this observation's rows have landed (the wave's only memory
-        // operations since their copy are its own stores); the copy of the
-        // wave's next observation, in this tile or its first of the next,
-        // goes to the other buffer
+        // wait for every vector memory operation of the wave, this
+        // observation's row copies among them (also the previous
+        // observation's stores, and at a tile's first observation the
+        // tile's loads); the copy of the wave's next observation, in this
+        // tile or its first of the next, goes to the other buffer
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         int64_t gn = -1;
         if (i + kWaves < nobs) {
